@@ -1,0 +1,297 @@
+/*
+ * nqs.h -- C ABI of libnqs: the hot path of neural-quantum-state variational
+ * Monte Carlo for a real restricted Boltzmann machine (RBM) on spin-1/2
+ * lattices, following the problem statement of the NetKet 3 paper
+ * (arXiv 2112.10526): Hilbert space + Hamiltonian -> variational state (model
+ * + Metropolis sampler) -> expectation values and gradient -> quantum
+ * geometric tensor (QGT) solve -> stochastic-reconfiguration (SR) update.
+ *
+ * Conventions shared by every call
+ *  - Every call returns an int status (nqs_status).  On failure the context
+ *    records a message readable with nqs_last_error(); no exception crosses
+ *    the ABI.  A failed call leaves device buffers it did not finish writing
+ *    in an unspecified state, and leaves the context usable.
+ *  - One context = one variational state bound to one HIP device and one HIP
+ *    stream.  Kernels are launched asynchronously on that stream; calls that
+ *    return host scalars (statistics, acceptance, solver info) synchronise the
+ *    stream before returning.  A context may be used by one host thread at a
+ *    time; different contexts are independent.
+ *  - Device memory: the library never allocates device memory.  The caller
+ *    allocates one workspace of nqs_workspace_bytes() bytes (e.g. a PyTorch
+ *    uint8 tensor) and binds it with nqs_bind_workspace(); every internal
+ *    buffer lives inside it.  Pointers documented as "device" must point to
+ *    device memory on the context's device; "host" pointers to host memory.
+ *    Input arrays are read during the call (host arrays are copied in) and
+ *    remain owned by the caller.
+ *  - Spin configurations are int8 with values +1 / -1, one row of n_sites
+ *    bytes per configuration (paper, section on Hilbert spaces: spin-1/2
+ *    local states in the sigma^z basis).
+ *  - Parameters cross the boundary as float64 in the packed layout
+ *    [a (n_sites, if visible bias) | b (n_hidden, if hidden bias) |
+ *     W (n_hidden x n_sites, row-major; W[j*n_sites+i] couples hidden unit j
+ *     to site i)], the contiguous parameter layout the paper uses for its
+ *    dense Jacobian.  The RBM amplitude is
+ *        ln psi(s) = sum_i a_i s_i + sum_j ln cosh(b_j + sum_i W_ji s_i)
+ *    (paper, table of models, RBM: a dense layer followed by a nonlinearity
+ *    with alpha * N features).
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nqs_ctx nqs_ctx;
+
+typedef enum {
+    NQS_OK = 0,
+    NQS_EINVAL = 1,    /* bad argument, size or bond index */
+    NQS_ENOMEM = 2,    /* workspace missing or too small */
+    NQS_EDEVICE = 3,   /* HIP runtime error */
+    NQS_ENUMERIC = 4,  /* non-finite parameter, energy or solver scalar */
+    NQS_ENOTCONV = 5,  /* CG hit maxiter; the direction is still written */
+    NQS_ESTATE = 6     /* call out of order (e.g. no Hamiltonian set yet) */
+} nqs_status;
+
+typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2 } nqs_precision;
+typedef enum { NQS_RULE_LOCAL = 0, NQS_RULE_EXCHANGE = 1 } nqs_rule;
+typedef enum { NQS_QGT_ONTHEFLY = 0, NQS_QGT_JACOBIAN_DENSE = 1 } nqs_qgt;
+
+/* Monte Carlo statistics of the local energies (paper, estimating
+ * observables: sample mean with 1/N_s normalisation). */
+typedef struct {
+    double mean;        /* (1/N_s) sum_k E(s_k) */
+    double variance;    /* (1/N_s) sum_k (E(s_k) - mean)^2 */
+    double error;       /* sqrt(variance / N_s) */
+    double acceptance;  /* accepted / proposed moves in the last nqs_sample */
+} nqs_stats;
+
+/* Result of one SR linear solve. */
+typedef struct {
+    int iterations;       /* CG iterations performed */
+    int converged;        /* 1 if ||r|| <= tol * ||f|| */
+    double rel_residual;  /* ||r|| / ||f|| from the CG recurrence */
+} nqs_sr_info;
+
+/* Settings of one fused VMC step. */
+typedef struct {
+    nqs_qgt qgt;        /* QGT representation for the SR solve */
+    double diag_shift;  /* epsilon in (S + epsilon I) delta = f */
+    double lr;          /* eta in p <- p - eta delta */
+    double cg_tol;      /* relative residual tolerance */
+    int cg_maxiter;     /* <= 0: min(P, 10000) */
+} nqs_step_cfg;
+
+/* What one VMC step reports back to the host. */
+typedef struct {
+    nqs_stats energy;
+    nqs_sr_info sr;
+    int status;         /* status of this context's step (batched calls) */
+} nqs_step_report;
+
+/* ------------------------------------------------------------------------- */
+/* Context lifetime                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device` that launches on `hip_stream` (a
+ * hipStream_t; NULL = the device's null stream).  *out receives the handle,
+ * owned by the caller until nqs_destroy().  Errors: NQS_EINVAL (out NULL or
+ * bad device), NQS_EDEVICE. */
+int nqs_create(nqs_ctx** out, int device, void* hip_stream);
+
+/* Release the context (the workspace stays owned by the caller). */
+void nqs_destroy(nqs_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none); owned by the
+ * context, valid until the next call on it.  ctx NULL gives a static text. */
+const char* nqs_last_error(const nqs_ctx* ctx);
+
+/* Rebind the context to another stream (hipStream_t) of the same device. */
+int nqs_set_stream(nqs_ctx* ctx, void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Problem definition                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Transverse-field Ising model (paper, transverse-field Ising equation):
+ *     H = J sum_<ab> sz_a sz_b - h sum_i sx_i .
+ * bonds: host int32 [n_bonds][2], site pairs, each bond listed once (the
+ * array is copied in).  Errors: NQS_EINVAL for n_sites < 2, n_bonds < 1 or a
+ * site index outside [0, n_sites) or a bond joining a site to itself. */
+int nqs_set_tfim(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bonds,
+                 double J, double h);
+
+/* Heisenberg model with Pauli matrices (paper, Heisenberg operator):
+ *     H = J sum_<ab> (sx_a sx_b + sy_a sy_b + sz_a sz_b) .
+ * sublattice: host int8 [n_sites] of 0/1 labels or NULL.  When given, the
+ * Marshall-rotated operator U H U^dagger, U = prod over label-1 sites of
+ * sz, is used: its off-diagonal element on bond (a, b) is 2J (-1)^(l_a+l_b),
+ * so on a bipartite lattice it is sign-free and a real RBM can represent its
+ * ground state.  Same errors as nqs_set_tfim. */
+int nqs_set_heisenberg(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bonds,
+                       double J, const int8_t* sublattice);
+
+/* RBM ansatz with n_hidden = alpha * n_sites hidden units (paper, table of
+ * models).  visible_bias / hidden_bias switch a and b on or off.  prec
+ * selects the arithmetic of the sampler, local energies and QGT products:
+ * NQS_FP64 everywhere FP64; NQS_FP32 FP32 with FP64 means and CG inner
+ * products; NQS_BF16 the Wσ+b contraction on BF16 MFMA with FP32
+ * accumulation (W split into two BF16 terms), the rest as NQS_FP32.
+ * Requires a Hamiltonian.  Errors: NQS_EINVAL (n_hidden < 1, bad prec),
+ * NQS_ESTATE. */
+int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,
+                nqs_precision prec);
+
+/* Number P of packed parameters. 0 before nqs_set_rbm. */
+size_t nqs_num_params(const nqs_ctx* ctx);
+
+/* Metropolis sampler (paper, Monte Carlo samplers section).
+ * rule NQS_RULE_LOCAL flips one site per proposal (MetropolisLocal);
+ * NQS_RULE_EXCHANGE swaps the two spins of one bond of the Hamiltonian's
+ * bond list (MetropolisExchange, conserves magnetisation).  n_chains chains
+ * each record samples_per_chain samples per nqs_sample(), one every
+ * sweep_size proposals; chains persist across calls.  Random numbers come
+ * from Philox4x32-10 keyed by `seed`; the draw for proposal p of chain c has
+ * counter (p lo, p hi, c, 0); chain starts use counter tag 1.
+ * total_sz_zero starts every chain in the zero-magnetisation sector
+ * (required for the exchange rule on a Heisenberg model).
+ * Errors: NQS_EINVAL, NQS_ESTATE (no model). */
+int nqs_set_sampler(nqs_ctx* ctx, nqs_rule rule, int n_chains, int samples_per_chain,
+                    int sweep_size, uint64_t seed, int total_sz_zero);
+
+/* Choose the QGT representation whose buffers the workspace must hold:
+ * NQS_QGT_ONTHEFLY (default; no Jacobian stored) or NQS_QGT_JACOBIAN_DENSE
+ * (stores the centred Jacobian [N_s][P] and the dense matrix [P][P], both in
+ * FP32 for NQS_FP32/NQS_BF16 and FP64 for NQS_FP64; paper, QGT
+ * implementation differences).  Must precede nqs_workspace_bytes(). */
+int nqs_set_qgt(nqs_ctx* ctx, nqs_qgt kind);
+
+/* Bytes of device workspace the current configuration needs (0 if the
+ * configuration is incomplete).  This is the context's HBM footprint. */
+size_t nqs_workspace_bytes(const nqs_ctx* ctx);
+
+/* Bind caller-owned device memory (>= nqs_workspace_bytes, 256-byte aligned)
+ * and initialise tables and chains.  The memory must stay valid until the
+ * context is destroyed or rebound.  Errors: NQS_ENOMEM (too small or NULL),
+ * NQS_EINVAL (misaligned), NQS_ESTATE (incomplete configuration). */
+int nqs_bind_workspace(nqs_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------------------- */
+/* Parameters, chains and checkpoints                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Copy P float64 parameters in (host or device pointer) and rebuild the
+ * derived tables.  Errors: NQS_ENUMERIC if any value is not finite. */
+int nqs_set_params(nqs_ctx* ctx, const double* p, int on_device);
+int nqs_get_params(nqs_ctx* ctx, double* p, int on_device);
+
+/* Restart every chain from its Philox start configuration and reset the
+ * proposal counter to 0. */
+int nqs_reset_chains(nqs_ctx* ctx);
+
+/* Current chain configurations, int8 [n_chains][n_sites] (host or device). */
+int nqs_get_chains(nqs_ctx* ctx, int8_t* out, int on_device);
+int nqs_set_chains(nqs_ctx* ctx, const int8_t* in, int on_device);
+
+/* Number of proposals every chain has made since its start. */
+uint64_t nqs_proposal_count(const nqs_ctx* ctx);
+
+/* Checkpoint blob (host memory): parameters, chains and proposal counter.
+ * With blob NULL, *bytes receives the size.  nqs_set_state restores it
+ * exactly, so a resumed run continues bit-for-bit. */
+int nqs_get_state(nqs_ctx* ctx, void* blob, size_t* bytes);
+int nqs_set_state(nqs_ctx* ctx, const void* blob, size_t bytes);
+
+/* ------------------------------------------------------------------------- */
+/* The hot path                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Metropolis-Hastings sampling (paper, Monte Carlo samplers section): every
+ * chain makes n_discard_segments * sweep_size proposals that are not
+ * recorded, then samples_per_chain * sweep_size proposals, recording its
+ * configuration after every sweep_size of them.  A proposal s -> s' is
+ * accepted iff u < |psi(s')/psi(s)|^2 with u uniform in [0,1) (53 bits from
+ * the draw's words 1 and 2); the site (local rule) or bond (exchange rule)
+ * is floor(word0 * n / 2^32).  The amplitude ratio uses the hidden
+ * pre-activations theta = W s + b, updated per accepted move and recomputed
+ * from s after every recorded sample.
+ * samples_out: device int8 [n_chains][samples_per_chain][n_sites] or NULL
+ * (the context keeps its own copy for nqs_expect_and_grad either way).
+ * accept_log: device uint8 [n_chains][samples_per_chain*sweep_size] (1 =
+ * accepted) or NULL; discarded proposals are not logged.
+ * acceptance: host, receives the accepted fraction of the recorded
+ * proposals, or NULL (then the call does not synchronise). */
+int nqs_sample(nqs_ctx* ctx, int n_discard_segments, int8_t* samples_out,
+               uint8_t* accept_log, double* acceptance);
+
+/* Replace the context's current sample batch by n_samples configurations
+ * (device int8 [n_samples][n_sites]; n_samples must equal n_chains *
+ * samples_per_chain), so that estimators and the SR solve can be run on an
+ * identical batch. */
+int nqs_load_samples(nqs_ctx* ctx, const int8_t* samples, int64_t n_samples);
+
+/* Local energies (paper, local-estimator equation):
+ *     E(s) = sum_{s'} <s|H|s'> psi(s') / psi(s),
+ * with the connected s' enumerated on the device (all single flips for the
+ * TFIM, all antiparallel bonds for Heisenberg).  s: device int8 [n][n_sites];
+ * eloc_out: device float64 [n].  Any n >= 0. */
+int nqs_local_energy(nqs_ctx* ctx, const int8_t* s, int64_t n, double* eloc_out);
+
+/* ln psi(s) for n configurations.  out: device, float64 [n] for NQS_FP64,
+ * float32 [n] otherwise. */
+int nqs_log_psi(nqs_ctx* ctx, const int8_t* s, int64_t n, void* out);
+
+/* Vector-Jacobian product of ln psi (paper, appendix on Jacobians and their
+ * products): grad_out[k] = sum_n g[n] O_k(s_n), O_k = d ln psi / d p_k.
+ * g: device [n], grad_out: device [P]; both float64 for NQS_FP64 and float32
+ * otherwise.  Backs the backward pass of the autograd function. */
+int nqs_log_psi_vjp(nqs_ctx* ctx, const int8_t* s, int64_t n, const void* g, void* grad_out);
+
+/* Jacobian O[n][P] = d ln psi(s_n) / d p (paper, log-derivative equation),
+ * O_a = s, O_b = tanh theta, O_W[j][i] = tanh(theta_j) s_i; with center != 0
+ * the column means over the n rows are subtracted and the result is scaled
+ * by 1/sqrt(n) (the stored form of the dense Jacobian QGT).  O_out: device,
+ * float64 for NQS_FP64 and float32 otherwise, row-major. */
+int nqs_jacobian(nqs_ctx* ctx, const int8_t* s, int64_t n, void* O_out, int center);
+
+/* Energy statistics and gradient on the current sample batch (paper,
+ * force-vector equation and real-parameter gradient): local energies,
+ * mean/variance/error, and grad = 2 Re Cov[O, E] = (2/N_s) O^T (E - mean).
+ * E: host, or NULL.  grad: device float64 [P], or NULL.  Synchronises when E
+ * is given.  Errors: NQS_ENUMERIC if the mean is not finite. */
+int nqs_expect_and_grad(nqs_ctx* ctx, nqs_stats* E, double* grad);
+
+/* Stochastic reconfiguration (paper, SR preconditioner and QGT solve):
+ * solve (Re G + diag_shift I) delta = f with f the gradient of the last
+ * nqs_expect_and_grad and G = (1/N_s) dO^T dO the QGT estimator on the same
+ * batch, by conjugate gradients from delta = 0 with FP64 inner products,
+ * stopping when ||r|| <= tol ||f|| or after maxiter iterations (<= 0 means
+ * min(P, 10000)); then update p <- p - lr * delta.  kind picks the on-the-fly
+ * product G v = (1/N_s) O^T (O v - mean(O v)) (no Jacobian stored) or the
+ * dense matrix built once on MFMA.  delta_out: device float64 [P] or NULL.
+ * info: host or NULL.  Errors: NQS_ENOTCONV (the update is still applied),
+ * NQS_ENUMERIC, NQS_ESTATE (no gradient yet). */
+int nqs_sr_update(nqs_ctx* ctx, nqs_qgt kind, double diag_shift, double lr, double tol,
+                  int maxiter, double* delta_out, nqs_sr_info* info);
+
+/* One VMC step: nqs_sample -> nqs_expect_and_grad -> nqs_sr_update (paper,
+ * ground-state search with the SR preconditioner).  rep: host, required. */
+int nqs_vmc_step(nqs_ctx* ctx, const nqs_step_cfg* cfg, nqs_step_report* rep);
+
+/* One VMC step for each of n contexts (each on its own stream), issued in
+ * lock-step so that the contexts' kernels overlap on the device.  Each
+ * context's result is identical to an nqs_vmc_step on it alone.  cfgs and
+ * reps: host arrays of n.  Returns the first non-OK status; every report's
+ * `status` holds its own. */
+int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs,
+                   nqs_step_report* reps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NQS_H */

@@ -1,0 +1,964 @@
+// C ABI of libnqs (declared in include/nqs.h): context state, workspace
+// layout and the host-side orchestration of the kernels.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nqs.h"
+#include "kernels.h"
+
+using namespace nqs;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Buffers {
+    double *Pm, *grad, *x, *r, *p, *Ap, *tmpv, *gacc;
+    int32_t* bonds;
+    int8_t* sub;
+    Tables tab;
+    int8_t* chains;
+    void* tch;
+    int8_t* samples;
+    void* tsm;
+    void* tx;
+    double *eloc, *vvec, *wbuf, *stats, *dpart;
+    uint32_t* acc_count;
+    CgScalars* sc;
+    void* part;
+    // dense QGT
+    void* O;
+    void* G;
+    double *colsum, *fp, *xp, *rp, *pp, *App;
+    int* tiles;
+};
+
+}  // namespace
+
+struct nqs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // Hamiltonian
+    int ham_kind = -1;
+    int N = 0;
+    std::vector<int32_t> bonds;
+    std::vector<int8_t> sub;
+    bool has_sub = false;
+    double J = 0.0, h = 0.0;
+    // model
+    bool has_model = false;
+    int M = 0, vb = 1, hb = 1, prec = 0;
+    Dims d{};
+    size_t P = 0;
+    // sampler
+    bool has_sampler = false;
+    int rule = 0, C = 0, S = 0, K = 0, sz0 = 0;
+    uint64_t seed = 0;
+    uint64_t prop = 0;
+    int qgt = NQS_QGT_ONTHEFLY;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    Buffers b{};
+    long Ns = 0, Bx = 0;
+    int ksplit = 1, ndpart = 1, Pld = 0, ntiles = 0;
+    // state
+    bool params_set = false, chains_dirty = true, have_samples = false, have_grad = false;
+    double acceptance = 0.0;
+    CgScalars* h_sc = nullptr;  // pinned
+    double* h_stats = nullptr;  // pinned [4]
+    uint32_t* h_acc = nullptr;  // pinned [C]
+    size_t h_acc_n = 0;
+};
+
+namespace {
+
+int fail(nqs_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, NQS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int last_launch(nqs_ctx* c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, NQS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return NQS_OK;
+}
+
+size_t esize(int prec) { return prec == 0 ? 8 : 4; }
+
+// Walk the workspace; with base == nullptr only the size is computed.
+size_t layout(nqs_ctx* c, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + ALIGN - 1) / ALIGN * ALIGN;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const Dims& d = c->d;
+    const size_t es = esize(c->prec);
+    const size_t PV = (size_t)d.Ma * d.Na;
+    const size_t PVX = PV > c->P ? PV : c->P;
+    Buffers& b = c->b;
+    b.Pm = (double*)take(8 * PV);
+    b.grad = (double*)take(8 * PV);
+    b.x = (double*)take(8 * PV);
+    b.r = (double*)take(8 * PV);
+    b.p = (double*)take(8 * PV);
+    b.Ap = (double*)take(8 * PV);
+    b.tmpv = (double*)take(8 * PVX);
+    b.gacc = (double*)take(8 * PV);
+    b.bonds = (int32_t*)take(8 * c->bonds.size() / 2 + 8);
+    b.sub = (int8_t*)take((size_t)c->N + 16);
+    b.tab.Tt = take(es * (size_t)d.N * d.Mw);
+    b.tab.Tj = take(es * (size_t)d.Mw * d.Nw);
+    b.tab.Ks = take(es * 2 * (size_t)d.N);
+    b.tab.Wa = take(es * (size_t)d.Na * d.Mw);
+    if (c->prec == 2) {
+        b.tab.Whi = (uint16_t*)take(2 * (size_t)d.Kb * d.Mw);
+        b.tab.Wlo = (uint16_t*)take(2 * (size_t)d.Kb * d.Mw);
+    } else {
+        b.tab.Whi = b.tab.Wlo = nullptr;
+    }
+    b.chains = (int8_t*)take((size_t)c->C * d.N);
+    b.tch = take(es * (size_t)c->C * d.Mw);
+    b.samples = (int8_t*)take((size_t)c->Ns * d.N);
+    b.tsm = take(es * (size_t)c->Ns * d.Mw);
+    b.tx = take(es * (size_t)c->Bx * d.Mw);
+    b.eloc = (double*)take(8 * (size_t)c->Bx);
+    b.vvec = (double*)take(8 * (size_t)c->Bx);
+    b.wbuf = (double*)take(8 * (size_t)c->Bx);
+    b.stats = (double*)take(8 * 8);
+    b.dpart = (double*)take(8 * (size_t)c->ndpart);
+    b.acc_count = (uint32_t*)take(4 * (size_t)c->C);
+    b.sc = (CgScalars*)take(sizeof(CgScalars));
+    b.part = take(es * (size_t)c->ksplit * PV);
+    if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
+        b.O = take(es * (size_t)c->Ns * c->Pld);
+        b.G = take(es * (size_t)c->P * c->Pld);
+        b.colsum = (double*)take(8 * (size_t)c->Pld);
+        b.fp = (double*)take(8 * (size_t)c->Pld);
+        b.xp = (double*)take(8 * (size_t)c->Pld);
+        b.rp = (double*)take(8 * (size_t)c->Pld);
+        b.pp = (double*)take(8 * (size_t)c->Pld);
+        b.App = (double*)take(8 * (size_t)c->Pld);
+        b.tiles = (int*)take(8 * (size_t)c->ntiles);
+    } else {
+        b.O = b.G = nullptr;
+        b.colsum = b.fp = b.xp = b.rp = b.pp = b.App = nullptr;
+        b.tiles = nullptr;
+    }
+    return (off + ALIGN - 1) / ALIGN * ALIGN;
+}
+
+bool configured(const nqs_ctx* c) { return c->ham_kind >= 0 && c->has_model && c->has_sampler; }
+
+void derive(nqs_ctx* c) {
+    Dims& d = c->d;
+    d.N = c->N;
+    d.M = c->M;
+    d.Na = round_up(c->N + 1, 16);
+    d.Ma = round_up(c->M + 1, 16);
+    const int m64 = round_up(c->M, 64);
+    d.Mw = d.Ma > m64 ? d.Ma : m64;
+    d.Nw = round_up(c->N, 64);
+    d.Kb = round_up(d.Na, 32);
+    d.QM = (c->M + 63) / 64;
+    d.vb = c->vb;
+    d.hb = c->hb;
+    c->P = (size_t)(c->vb ? c->N : 0) + (c->hb ? c->M : 0) + (size_t)c->M * c->N;
+    if (c->has_sampler) {
+        c->Ns = (long)c->C * c->S;
+        c->Bx = c->Ns > 1024 ? c->Ns : 1024;
+        c->ksplit = outer_ksplit(c->Bx);
+        c->Pld = round_up((int)c->P, 128);
+        c->ntiles = gram_tiles((int)c->P);
+        long nd = (long)d.Ma * d.Na / 256 + 2;
+        const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->P / 4 + 2;
+        if (nd2 > nd) nd = nd2;
+        if (nd3 > nd) nd = nd3;
+        c->ndpart = (int)nd;
+    }
+}
+
+void invalidate_binding(nqs_ctx* c) {
+    c->bound = false;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->have_samples = c->have_grad = false;
+}
+
+HamDev ham_dev(const nqs_ctx* c) {
+    HamDev H;
+    H.kind = c->ham_kind;
+    H.n_bonds = (int)(c->bonds.size() / 2);
+    H.bonds = c->b.bonds;
+    H.sub = c->has_sub ? c->b.sub : nullptr;
+    H.J = c->J;
+    H.h = c->h;
+    return H;
+}
+
+int need_bound(nqs_ctx* c) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound) return fail(c, NQS_ESTATE, "no workspace bound");
+    if (!c->params_set) return fail(c, NQS_ESTATE, "parameters not set");
+    return NQS_OK;
+}
+
+int set_device(nqs_ctx* c) {
+    HIPCHK(c, hipSetDevice(c->device));
+    return NQS_OK;
+}
+
+// tanh(theta) of the chains' current configurations
+void refresh_chains(nqs_ctx* c) {
+    if (!c->chains_dirty) return;
+    launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr, 0);
+    c->chains_dirty = false;
+}
+
+int check_bonds(nqs_ctx* c, int n_sites, int n_bonds, const int32_t* bonds) {
+    if (n_sites < 2 || n_bonds < 1 || !bonds) return fail(c, NQS_EINVAL, "bad lattice size");
+    for (int k = 0; k < n_bonds; ++k) {
+        const int a = bonds[2 * k], b2 = bonds[2 * k + 1];
+        if (a < 0 || a >= n_sites || b2 < 0 || b2 >= n_sites || a == b2)
+            return fail(c, NQS_EINVAL, "bond " + std::to_string(k) + " has a bad site index");
+    }
+    return NQS_OK;
+}
+
+int set_ham(nqs_ctx* c, int kind, int n_sites, int n_bonds, const int32_t* bonds, double J,
+            double h, const int8_t* sub) {
+    int st = check_bonds(c, n_sites, n_bonds, bonds);
+    if (st) return st;
+    if (!std::isfinite(J) || !std::isfinite(h)) return fail(c, NQS_EINVAL, "non-finite coupling");
+    if (c->has_model && n_sites != c->N) {
+        c->has_model = false;
+        c->has_sampler = false;
+        c->params_set = false;
+    }
+    c->ham_kind = kind;
+    c->N = n_sites;
+    c->bonds.assign(bonds, bonds + 2 * (size_t)n_bonds);
+    c->J = J;
+    c->h = h;
+    c->has_sub = sub != nullptr;
+    c->sub.assign((size_t)n_sites, 0);
+    if (sub)
+        for (int i = 0; i < n_sites; ++i) c->sub[i] = sub[i] ? 1 : 0;
+    if (c->bound) {
+        // same sizes: refresh the device copy in place
+        if (c->has_model && layout(c, nullptr) <= c->ws_bytes) {
+            layout(c, c->ws);
+            HIPCHK(c, hipMemcpyAsync(c->b.bonds, c->bonds.data(), 4 * c->bonds.size(),
+                                     hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->b.sub, c->sub.data(), c->sub.size(), hipMemcpyHostToDevice,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            invalidate_binding(c);
+        }
+    }
+    return NQS_OK;
+}
+
+int sync_scalars(nqs_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->b.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NQS_OK;
+}
+
+int cg_check_interval() {
+    static int v = [] {
+        const char* e = std::getenv("NQS_CG_CHECK");
+        int x = e ? std::atoi(e) : 0;
+        return x > 0 ? x : 10;
+    }();
+    return v;
+}
+
+// ---- staged pieces of the hot path (asynchronous unless noted) -------------
+
+void issue_sample(nqs_ctx* c, int n_discard, uint8_t* accept_log) {
+    refresh_chains(c);
+    SampleArgs a{};
+    a.C = c->C;
+    a.K = c->K;
+    a.seed = c->seed;
+    a.s = c->b.chains;
+    a.tch = c->b.tch;
+    a.n_bonds = (int)(c->bonds.size() / 2);
+    a.bonds = c->b.bonds;
+    for (int q = 0; q < n_discard; ++q) {
+        a.prop_base = c->prop;
+        a.record = 0;
+        launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
+        c->prop += (uint64_t)c->K;
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr, 0);
+    }
+    launch_zero(c->stream, c->b.acc_count, 4 * (size_t)c->C);
+    a.acc_count = c->b.acc_count;
+    a.acc_log = accept_log;
+    a.log_stride = (long)c->S * c->K;
+    const size_t es = esize(c->prec);
+    for (int q = 0; q < c->S; ++q) {
+        a.prop_base = c->prop;
+        a.record = 1;
+        a.rec = c->b.samples + (size_t)q * c->d.N;
+        a.rec_stride = (long)c->S * c->d.N;
+        a.log_offset = (long)q * c->K;
+        launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
+        c->prop += (uint64_t)c->K;
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch,
+                     (char*)c->b.tsm + es * (size_t)q * c->d.Mw, (long)c->S * c->d.Mw);
+    }
+    c->have_samples = true;
+    c->have_grad = false;
+}
+
+void issue_energy_grad(nqs_ctx* c) {
+    const long n = c->Ns;
+    launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), c->b.samples, c->b.tsm, n,
+                c->b.eloc);
+    launch_stats(c->stream, c->b.eloc, n, c->b.stats);
+    launch_center(c->stream, c->b.eloc, c->b.stats, 2.0 / (double)n, n, c->b.vvec);
+    launch_outer(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, n, c->b.vvec, 1, c->b.part,
+                 c->ksplit, c->b.sc);
+    launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, c->ksplit, nullptr, 0.0, c->b.grad,
+                        c->b.dpart, c->b.sc, 1);
+    c->have_grad = true;
+}
+
+int read_stats(nqs_ctx* c, nqs_stats* E) {
+    HIPCHK(c, hipMemcpyAsync(c->h_stats, c->b.stats, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (E) {
+        E->mean = c->h_stats[0];
+        E->variance = c->h_stats[1];
+        E->error = c->h_stats[2];
+        E->acceptance = c->acceptance;
+    }
+    if (!std::isfinite(c->h_stats[0])) return fail(c, NQS_ENUMERIC, "non-finite energy");
+    return NQS_OK;
+}
+
+int read_acceptance(nqs_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->h_acc, c->b.acc_count, 4 * (size_t)c->C, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double acc = 0.0;
+    for (int k = 0; k < c->C; ++k) acc += c->h_acc[k];
+    c->acceptance = acc / ((double)c->C * c->S * c->K);
+    return NQS_OK;
+}
+
+// dense Jacobian form: build G once for this batch and set up CG in packed space
+void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
+    const int P = (int)c->P;
+    launch_jacobian(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O, P, c->Pld);
+    launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum);
+    launch_gram(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.G, c->b.tiles, c->ntiles);
+    launch_pack(c->stream, c->d, c->b.grad, c->b.fp, P);
+    launch_cg_init(c->stream, P, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
+                   maxiter);
+}
+
+void issue_cg_init(nqs_ctx* c, double tol, int maxiter) {
+    launch_cg_init(c->stream, c->d.Ma * c->d.Na, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.dpart,
+                   c->b.sc, tol, maxiter);
+}
+
+void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
+    const Dims& d = c->d;
+    for (int it = 0; it < iters; ++it) {
+        if (kind == NQS_QGT_ONTHEFLY) {
+            launch_w(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.p, c->b.wbuf,
+                     c->b.dpart, c->b.sc);
+            launch_outer(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.wbuf, 0,
+                         c->b.part, c->ksplit, c->b.sc);
+            launch_reduce_outer(c->stream, d, c->prec, c->b.part, c->ksplit, c->b.p, shift,
+                                c->b.Ap, c->b.dpart, c->b.sc, 0);
+            launch_cg_update(c->stream, d.Ma * d.Na, c->b.x, c->b.r, c->b.p, c->b.Ap, c->b.dpart,
+                             c->b.sc);
+        } else {
+            launch_dense_matvec(c->stream, c->prec, c->b.G, (int)c->P, c->Pld, c->b.pp, shift,
+                                c->b.App, c->b.dpart, c->b.sc);
+            launch_cg_update(c->stream, (int)c->P, c->b.xp, c->b.rp, c->b.pp, c->b.App, c->b.dpart,
+                             c->b.sc);
+        }
+    }
+}
+
+// delta (internal layout) is in b.x after this
+void issue_finish_solve(nqs_ctx* c, int kind) {
+    if (kind == NQS_QGT_JACOBIAN_DENSE) launch_unpack(c->stream, c->d, c->b.xp, c->b.x, (int)c->P);
+}
+
+void issue_update(nqs_ctx* c, double lr) {
+    launch_axpy_update(c->stream, c->d.Ma * c->d.Na, c->b.Pm, c->b.x, lr, c->b.sc);
+    launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
+    c->chains_dirty = true;
+    c->have_grad = false;
+    c->have_samples = false;  // the held batch's activations belong to the old parameters
+}
+
+int sr_status(nqs_ctx* c, nqs_sr_info* info) {
+    const CgScalars& s = *c->h_sc;
+    if (info) {
+        info->iterations = s.iters;
+        info->converged = (s.rr <= s.tol2) ? 1 : 0;
+        info->rel_residual = s.rr0 > 0 ? std::sqrt(s.rr / s.rr0) : 0.0;
+    }
+    if (s.bad) return fail(c, NQS_ENUMERIC, "non-finite value in the SR solve or update");
+    if (!(s.rr <= s.tol2)) return fail(c, NQS_ENOTCONV, "CG reached maxiter before tolerance");
+    return NQS_OK;
+}
+
+int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
+    const int every = cg_check_interval();
+    int launched = 0;
+    while (launched < maxiter) {
+        const int k = (maxiter - launched) < every ? (maxiter - launched) : every;
+        issue_cg_iters(c, kind, shift, k);
+        launched += k;
+        int st = sync_scalars(c);
+        if (st) return st;
+        if (c->h_sc->done) break;
+    }
+    return NQS_OK;
+}
+
+int default_maxiter(const nqs_ctx* c, int maxiter) {
+    if (maxiter > 0) return maxiter;
+    return c->P < 10000 ? (int)c->P : 10000;
+}
+
+__global__ void k_f32_to_f64(const float* a, double* b, long n) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) b[e] = (double)a[e];
+}
+__global__ void k_f64_to_f32(const double* a, float* b, long n) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) b[e] = (float)a[e];
+}
+__global__ void k_check_finite(const double* a, long n, int* flag) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n && !isfinite(a[e])) *flag = 1;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
+    if (!out) return NQS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return NQS_EINVAL;
+    nqs_ctx* c = new nqs_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_sc, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return NQS_EDEVICE;
+    }
+    *out = c;
+    return NQS_OK;
+}
+
+void nqs_destroy(nqs_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->h_sc) hipHostFree(c->h_sc);
+    if (c->h_stats) hipHostFree(c->h_stats);
+    if (c->h_acc) hipHostFree(c->h_acc);
+    delete c;
+}
+
+const char* nqs_last_error(const nqs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int nqs_set_stream(nqs_ctx* c, void* hip_stream) {
+    if (!c) return NQS_EINVAL;
+    if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)hip_stream;
+    return NQS_OK;
+}
+
+int nqs_set_tfim(nqs_ctx* c, int n_sites, int n_bonds, const int32_t* bonds, double J, double h) {
+    if (!c) return NQS_EINVAL;
+    return set_ham(c, 0, n_sites, n_bonds, bonds, J, h, nullptr);
+}
+
+int nqs_set_heisenberg(nqs_ctx* c, int n_sites, int n_bonds, const int32_t* bonds, double J,
+                       const int8_t* sublattice) {
+    if (!c) return NQS_EINVAL;
+    return set_ham(c, 1, n_sites, n_bonds, bonds, J, 0.0, sublattice);
+}
+
+int nqs_set_rbm(nqs_ctx* c, int n_hidden, int visible_bias, int hidden_bias, nqs_precision prec) {
+    if (!c) return NQS_EINVAL;
+    if (c->ham_kind < 0) return fail(c, NQS_ESTATE, "set a Hamiltonian first");
+    if (n_hidden < 1 || n_hidden > 2048) return fail(c, NQS_EINVAL, "n_hidden must be in [1, 2048]");
+    if (prec < NQS_FP64 || prec > NQS_BF16) return fail(c, NQS_EINVAL, "bad precision");
+    if (c->N > 4096) return fail(c, NQS_EINVAL, "at most 4096 sites");
+    c->M = n_hidden;
+    c->vb = visible_bias ? 1 : 0;
+    c->hb = hidden_bias ? 1 : 0;
+    c->prec = (int)prec;
+    c->has_model = true;
+    c->params_set = false;
+    derive(c);
+    invalidate_binding(c);
+    return NQS_OK;
+}
+
+size_t nqs_num_params(const nqs_ctx* c) { return (c && c->has_model) ? c->P : 0; }
+
+int nqs_set_sampler(nqs_ctx* c, nqs_rule rule, int n_chains, int samples_per_chain,
+                    int sweep_size, uint64_t seed, int total_sz_zero) {
+    if (!c) return NQS_EINVAL;
+    if (!c->has_model) return fail(c, NQS_ESTATE, "set the RBM first");
+    if (rule != NQS_RULE_LOCAL && rule != NQS_RULE_EXCHANGE) return fail(c, NQS_EINVAL, "bad rule");
+    if (n_chains < 1 || samples_per_chain < 1 || sweep_size < 1)
+        return fail(c, NQS_EINVAL, "chains, samples and sweep size must be positive");
+    if ((long)n_chains * samples_per_chain > (1L << 26)) return fail(c, NQS_EINVAL, "too many samples");
+    if (total_sz_zero && (c->N % 2)) return fail(c, NQS_EINVAL, "total_sz_zero needs even n_sites");
+    c->rule = (int)rule;
+    c->C = n_chains;
+    c->S = samples_per_chain;
+    c->K = sweep_size;
+    c->seed = seed;
+    c->sz0 = total_sz_zero ? 1 : 0;
+    c->has_sampler = true;
+    derive(c);
+    invalidate_binding(c);
+    if (c->h_acc) hipHostFree(c->h_acc);
+    c->h_acc = nullptr;
+    if (hipHostMalloc((void**)&c->h_acc, 4 * (size_t)n_chains, hipHostMallocDefault) != hipSuccess)
+        return fail(c, NQS_EDEVICE, "pinned host buffer");
+    return NQS_OK;
+}
+
+int nqs_set_qgt(nqs_ctx* c, nqs_qgt kind) {
+    if (!c) return NQS_EINVAL;
+    if (kind != NQS_QGT_ONTHEFLY && kind != NQS_QGT_JACOBIAN_DENSE)
+        return fail(c, NQS_EINVAL, "bad QGT kind");
+    if (c->qgt != (int)kind) {
+        c->qgt = (int)kind;
+        invalidate_binding(c);
+    }
+    return NQS_OK;
+}
+
+size_t nqs_workspace_bytes(const nqs_ctx* c) {
+    if (!c || !configured(c)) return 0;
+    nqs_ctx tmp = *c;
+    tmp.h_sc = nullptr;
+    tmp.h_stats = nullptr;
+    tmp.h_acc = nullptr;
+    const size_t n = layout(&tmp, nullptr);
+    return n;
+}
+
+int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return NQS_EINVAL;
+    if (!configured(c)) return fail(c, NQS_ESTATE, "Hamiltonian, RBM and sampler must be set");
+    const size_t need = layout(c, nullptr);
+    if (!dev_ptr || bytes < need)
+        return fail(c, NQS_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
+    if ((uintptr_t)dev_ptr % ALIGN) return fail(c, NQS_EINVAL, "workspace must be 256-byte aligned");
+    int st = set_device(c);
+    if (st) return st;
+    c->ws = (char*)dev_ptr;
+    c->ws_bytes = bytes;
+    layout(c, c->ws);
+    launch_zero(c->stream, c->ws, need);
+    HIPCHK(c, hipMemcpyAsync(c->b.bonds, c->bonds.data(), 4 * c->bonds.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->b.sub, c->sub.data(), c->sub.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
+        std::vector<int> t(2 * (size_t)c->ntiles);
+        fill_gram_tiles((int)c->P, t.data());
+        HIPCHK(c, hipMemcpyAsync(c->b.tiles, t.data(), 4 * t.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    launch_init_chains(c->stream, c->N, c->C, c->seed, c->sz0, c->b.chains);
+    c->prop = 0;
+    c->bound = true;
+    c->params_set = false;
+    c->chains_dirty = true;
+    c->have_samples = c->have_grad = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return last_launch(c);
+}
+
+int nqs_set_params(nqs_ctx* c, const double* p, int on_device) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound) return fail(c, NQS_ESTATE, "no workspace bound");
+    if (!p) return fail(c, NQS_EINVAL, "null parameters");
+    int st = set_device(c);
+    if (st) return st;
+    std::vector<double> h(c->P);
+    if (on_device) {
+        HIPCHK(c, hipMemcpyAsync(h.data(), p, 8 * c->P, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::memcpy(h.data(), p, 8 * c->P);
+    }
+    for (size_t k = 0; k < c->P; ++k)
+        if (!std::isfinite(h[k])) return fail(c, NQS_ENUMERIC, "non-finite parameter");
+    HIPCHK(c, hipMemcpyAsync(c->b.tmpv, h.data(), 8 * c->P, hipMemcpyHostToDevice, c->stream));
+    launch_unpack(c->stream, c->d, c->b.tmpv, c->b.Pm, (int)c->P);
+    launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->params_set = true;
+    c->chains_dirty = true;
+    c->have_grad = false;
+    if (c->have_samples)  // activations of the held batch follow the new parameters
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.samples, (int)c->Ns, c->b.tsm,
+                     nullptr, 0);
+    return last_launch(c);
+}
+
+int nqs_get_params(nqs_ctx* c, double* p, int on_device) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!p) return fail(c, NQS_EINVAL, "null output");
+    launch_pack(c->stream, c->d, c->b.Pm, c->b.tmpv, (int)c->P);
+    HIPCHK(c, hipMemcpyAsync(p, c->b.tmpv, 8 * c->P,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return last_launch(c);
+}
+
+int nqs_reset_chains(nqs_ctx* c) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound) return fail(c, NQS_ESTATE, "no workspace bound");
+    launch_init_chains(c->stream, c->N, c->C, c->seed, c->sz0, c->b.chains);
+    c->prop = 0;
+    c->chains_dirty = true;
+    return last_launch(c);
+}
+
+int nqs_get_chains(nqs_ctx* c, int8_t* out, int on_device) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound || !out) return fail(c, NQS_ESTATE, "no workspace bound or null output");
+    HIPCHK(c, hipMemcpyAsync(out, c->b.chains, (size_t)c->C * c->N,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NQS_OK;
+}
+
+int nqs_set_chains(nqs_ctx* c, const int8_t* in, int on_device) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound || !in) return fail(c, NQS_ESTATE, "no workspace bound or null input");
+    HIPCHK(c, hipMemcpyAsync(c->b.chains, in, (size_t)c->C * c->N,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->chains_dirty = true;
+    return NQS_OK;
+}
+
+uint64_t nqs_proposal_count(const nqs_ctx* c) { return c ? c->prop : 0; }
+
+int nqs_get_state(nqs_ctx* c, void* blob, size_t* bytes) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!bytes) return fail(c, NQS_EINVAL, "null size");
+    const size_t need = 32 + 8 * c->P + (size_t)c->C * c->N;
+    if (!blob) {
+        *bytes = need;
+        return NQS_OK;
+    }
+    if (*bytes < need) return fail(c, NQS_EINVAL, "blob too small");
+    char* o = (char*)blob;
+    const uint64_t hdr[4] = {0x4E51535354415445ull, (uint64_t)c->P,
+                             ((uint64_t)c->C << 32) | (uint32_t)c->N, c->prop};
+    std::memcpy(o, hdr, 32);
+    st = nqs_get_params(c, (double*)(o + 32), 0);
+    if (st) return st;
+    st = nqs_get_chains(c, (int8_t*)(o + 32 + 8 * c->P), 0);
+    if (st) return st;
+    *bytes = need;
+    return NQS_OK;
+}
+
+int nqs_set_state(nqs_ctx* c, const void* blob, size_t bytes) {
+    if (!c) return NQS_EINVAL;
+    if (!c->bound) return fail(c, NQS_ESTATE, "no workspace bound");
+    const size_t need = 32 + 8 * c->P + (size_t)c->C * c->N;
+    if (!blob || bytes < need) return fail(c, NQS_EINVAL, "blob too small");
+    uint64_t hdr[4];
+    std::memcpy(hdr, blob, 32);
+    if (hdr[0] != 0x4E51535354415445ull || hdr[1] != c->P ||
+        hdr[2] != (((uint64_t)c->C << 32) | (uint32_t)c->N))
+        return fail(c, NQS_EINVAL, "blob does not match this configuration");
+    const char* in = (const char*)blob;
+    int st = nqs_set_params(c, (const double*)(in + 32), 0);
+    if (st) return st;
+    st = nqs_set_chains(c, (const int8_t*)(in + 32 + 8 * c->P), 0);
+    if (st) return st;
+    c->prop = hdr[3];
+    c->have_samples = c->have_grad = false;
+    return NQS_OK;
+}
+
+int nqs_sample(nqs_ctx* c, int n_discard_segments, int8_t* samples_out, uint8_t* accept_log,
+               double* acceptance) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n_discard_segments < 0) return fail(c, NQS_EINVAL, "negative discard count");
+    st = set_device(c);
+    if (st) return st;
+    issue_sample(c, n_discard_segments, accept_log);
+    if (samples_out)
+        HIPCHK(c, hipMemcpyAsync(samples_out, c->b.samples, (size_t)c->Ns * c->N,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    st = last_launch(c);
+    if (st) return st;
+    if (acceptance) {
+        st = read_acceptance(c);
+        if (st) return st;
+        *acceptance = c->acceptance;
+    }
+    return NQS_OK;
+}
+
+int nqs_load_samples(nqs_ctx* c, const int8_t* samples, int64_t n_samples) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!samples || n_samples != c->Ns)
+        return fail(c, NQS_EINVAL, "n_samples must equal n_chains * samples_per_chain");
+    HIPCHK(c, hipMemcpyAsync(c->b.samples, samples, (size_t)c->Ns * c->N, hipMemcpyDeviceToDevice,
+                             c->stream));
+    launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.samples, (int)c->Ns, c->b.tsm, nullptr, 0);
+    c->have_samples = true;
+    c->have_grad = false;
+    return last_launch(c);
+}
+
+int nqs_local_energy(nqs_ctx* c, const int8_t* s, int64_t n, double* eloc_out) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!s || !eloc_out))) return fail(c, NQS_EINVAL, "bad batch");
+    for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+        const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+        const int8_t* sk = s + (size_t)k0 * c->N;
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, sk, (int)m, c->b.tx, nullptr, 0);
+        launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), sk, c->b.tx, m, eloc_out + k0);
+    }
+    return last_launch(c);
+}
+
+int nqs_log_psi(nqs_ctx* c, const int8_t* s, int64_t n, void* out) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!s || !out))) return fail(c, NQS_EINVAL, "bad batch");
+    launch_log_psi(c->stream, c->d, c->prec, c->b.Pm, c->b.tab, s, n, out);
+    return last_launch(c);
+}
+
+int nqs_log_psi_vjp(nqs_ctx* c, const int8_t* s, int64_t n, const void* g, void* grad_out) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!s || !g)) || !grad_out) return fail(c, NQS_EINVAL, "bad batch");
+    const int PV = c->d.Ma * c->d.Na;
+    launch_zero(c->stream, c->b.gacc, 8 * (size_t)PV);
+    for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+        const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+        const int8_t* sk = s + (size_t)k0 * c->N;
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, sk, (int)m, c->b.tx, nullptr, 0);
+        if (c->prec == 0)
+            HIPCHK(c, hipMemcpyAsync(c->b.vvec, (const double*)g + k0, 8 * (size_t)m,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        else
+            k_f32_to_f64<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>((const float*)g + k0,
+                                                                             c->b.vvec, m);
+        launch_outer(c->stream, c->d, c->prec, sk, c->b.tx, m, c->b.vvec, 1, c->b.part, c->ksplit,
+                     c->b.sc);
+        launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, c->ksplit, nullptr, 0.0, c->b.Ap,
+                            c->b.dpart, c->b.sc, 1);
+        launch_axpy_update(c->stream, PV, c->b.gacc, c->b.Ap, -1.0, c->b.sc);
+    }
+    if (c->prec == 0) {
+        launch_pack(c->stream, c->d, c->b.gacc, (double*)grad_out, (int)c->P);
+    } else {
+        launch_pack(c->stream, c->d, c->b.gacc, c->b.tmpv, (int)c->P);
+        k_f64_to_f32<<<(unsigned)((c->P + 255) / 256), 256, 0, c->stream>>>(c->b.tmpv,
+                                                                           (float*)grad_out,
+                                                                           (long)c->P);
+    }
+    return last_launch(c);
+}
+
+int nqs_jacobian(nqs_ctx* c, const int8_t* s, int64_t n, void* O_out, int center) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n < 1 || !s || !O_out) return fail(c, NQS_EINVAL, "bad batch");
+    const size_t es = esize(c->prec);
+    for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+        const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+        const int8_t* sk = s + (size_t)k0 * c->N;
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, sk, (int)m, c->b.tx, nullptr, 0);
+        launch_jacobian(c->stream, c->d, c->prec, sk, c->b.tx, m,
+                        (char*)O_out + es * (size_t)k0 * c->P, (int)c->P, (long)c->P);
+    }
+    if (center) {
+        if (n > 65535) return fail(c, NQS_EINVAL, "centring supports at most 65535 rows");
+        launch_center_cols(c->stream, c->prec, O_out, n, (long)c->P, (int)c->P, c->b.tmpv);
+    }
+    return last_launch(c);
+}
+
+int nqs_expect_and_grad(nqs_ctx* c, nqs_stats* E, double* grad) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!c->have_samples) return fail(c, NQS_ESTATE, "no samples: call nqs_sample first");
+    st = set_device(c);
+    if (st) return st;
+    issue_energy_grad(c);
+    if (grad) launch_pack(c->stream, c->d, c->b.grad, grad, (int)c->P);
+    st = last_launch(c);
+    if (st) return st;
+    if (E) return read_stats(c, E);
+    return NQS_OK;
+}
+
+int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol, int maxiter,
+                  double* delta_out, nqs_sr_info* info) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!c->have_grad) return fail(c, NQS_ESTATE, "no gradient: call nqs_expect_and_grad first");
+    if (kind == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
+        return fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace (nqs_set_qgt)");
+    if (!(diag_shift >= 0) || !std::isfinite(lr) || !(tol >= 0))
+        return fail(c, NQS_EINVAL, "bad solver settings");
+    st = set_device(c);
+    if (st) return st;
+    const int mi = default_maxiter(c, maxiter);
+    if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi);
+    else issue_cg_init(c, tol, mi);
+    st = run_cg(c, kind, diag_shift, mi);
+    if (st) return st;
+    issue_finish_solve(c, kind);
+    if (delta_out) launch_pack(c->stream, c->d, c->b.x, delta_out, (int)c->P);
+    issue_update(c, lr);
+    st = last_launch(c);
+    if (st) return st;
+    st = sync_scalars(c);
+    if (st) return st;
+    return sr_status(c, info);
+}
+
+int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
+    if (!c) return NQS_EINVAL;
+    if (!cfg || !rep) return fail(c, NQS_EINVAL, "null settings or report");
+    std::memset(rep, 0, sizeof(*rep));
+    int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
+    if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
+    if (!st) st = nqs_sr_update(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol,
+                                cfg->cg_maxiter, nullptr, &rep->sr);
+    if (st == NQS_OK || st == NQS_ENOTCONV) {
+        int s2 = read_acceptance(c);
+        if (!s2) s2 = read_stats(c, &rep->energy);
+        if (s2) st = s2;
+    }
+    rep->status = st;
+    return st;
+}
+
+int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_step_report* reps) {
+    if (!ctxs || n < 0 || (n > 0 && (!cfgs || !reps))) return NQS_EINVAL;
+    std::vector<int> st(n, NQS_OK), mi(n, 0), launched(n, 0), active(n, 1);
+    for (int k = 0; k < n; ++k) {
+        std::memset(&reps[k], 0, sizeof(nqs_step_report));
+        nqs_ctx* c = ctxs[k];
+        st[k] = need_bound(c);
+        if (!st[k] && cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
+            st[k] = fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace");
+        if (!st[k]) st[k] = set_device(c);
+    }
+    // sampling, energies and gradients for every context, then CG init
+    for (int k = 0; k < n; ++k) {
+        if (st[k]) continue;
+        nqs_ctx* c = ctxs[k];
+        issue_sample(c, 0, nullptr);
+        issue_energy_grad(c);
+        mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
+        if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfgs[k].cg_tol, mi[k]);
+        else issue_cg_init(c, cfgs[k].cg_tol, mi[k]);
+        st[k] = last_launch(c);
+    }
+    // lock-step CG: a block of iterations on every unconverged context, then
+    // one check per context
+    const int every = cg_check_interval();
+    bool any = true;
+    while (any) {
+        any = false;
+        for (int k = 0; k < n; ++k) {
+            if (st[k] || !active[k]) continue;
+            nqs_ctx* c = ctxs[k];
+            const int b2 = (mi[k] - launched[k]) < every ? (mi[k] - launched[k]) : every;
+            issue_cg_iters(c, cfgs[k].qgt, cfgs[k].diag_shift, b2);
+            launched[k] += b2;
+            if (hipMemcpyAsync(c->h_sc, c->b.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
+                               c->stream) != hipSuccess)
+                st[k] = fail(c, NQS_EDEVICE, "scalar readback");
+        }
+        for (int k = 0; k < n; ++k) {
+            if (st[k] || !active[k]) continue;
+            nqs_ctx* c = ctxs[k];
+            if (hipStreamSynchronize(c->stream) != hipSuccess) {
+                st[k] = fail(c, NQS_EDEVICE, "stream synchronise");
+                continue;
+            }
+            if (c->h_sc->done || launched[k] >= mi[k]) active[k] = 0;
+            else any = true;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        if (st[k]) continue;
+        nqs_ctx* c = ctxs[k];
+        issue_finish_solve(c, cfgs[k].qgt);
+        issue_update(c, cfgs[k].lr);
+        st[k] = last_launch(c);
+    }
+    int first = NQS_OK;
+    for (int k = 0; k < n; ++k) {
+        nqs_ctx* c = ctxs[k];
+        if (!st[k]) st[k] = sync_scalars(c);
+        if (!st[k]) st[k] = sr_status(c, &reps[k].sr);
+        if (st[k] == NQS_OK || st[k] == NQS_ENOTCONV) {
+            int s2 = read_acceptance(c);
+            if (!s2) s2 = read_stats(c, &reps[k].energy);
+            if (s2) st[k] = s2;
+        }
+        reps[k].status = st[k];
+        if (st[k] && !first) first = st[k];
+    }
+    return first;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Host-side launchers of the libnqs kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace nqs {
+
+// Derived per-parameter tables in the compute precision R (double for FP64,
+// float otherwise):
+//   Tt [N][Mw]  tanh(2 W_ji) at [i][j]  (site-major; sampler rows)
+//   Tj [Mw][Nw] tanh(2 W_ji) at [j][i]  (hidden-major; local energies)
+//   Ks [N][2]   site factor K_i(+1), K_i(-1) (FP64) or their logs (FP32)
+//   Wa [Na][Mw] W~^T: W_ji at [i][j], b_j at [N][j] (theta contraction)
+//   Whi, Wlo [Mw][Kb] BF16 two-term split of W~ (hidden-major; BF16 form only)
+struct Tables {
+    void* Tt;
+    void* Tj;
+    void* Ks;
+    void* Wa;
+    uint16_t* Whi;
+    uint16_t* Wlo;
+};
+
+// Scalars and counters the CG kernels keep on the device (float64 slots).
+struct CgScalars {
+    double rr;        // r . r
+    double rr0;       // f . f
+    double pAp;       // p . A p
+    double alpha;
+    double beta;
+    double tol2;      // tol^2 * f.f
+    double wmean;     // mean of w in the current product
+    double pad0;
+    int32_t iters;    // iterations done
+    int32_t done;     // converged or stopped
+    int32_t maxiter;
+    int32_t bad;      // non-finite scalar seen
+    uint32_t counter[8];  // last-block counters
+};
+
+// tables.hip
+void launch_unpack(hipStream_t st, const Dims& d, const double* p, double* Pm, int P);
+void launch_pack(hipStream_t st, const Dims& d, const double* Pm, double* p, int P);
+void launch_mask(hipStream_t st, const Dims& d, double* V);
+void launch_tables(hipStream_t st, const Dims& d, int prec, const double* Pm, const Tables& t);
+void launch_init_chains(hipStream_t st, int N, int C, uint64_t seed, int sz0, int8_t* s);
+void launch_zero(hipStream_t st, void* p, size_t bytes);
+
+// theta.hip: t~ = tanh(S~ W~^T) for `rows` configurations (row stride N),
+// written to dst1 (row stride Mw) and, if dst2 != null, to dst2 with row
+// stride dst2_stride elements.
+void launch_theta(hipStream_t st, const Dims& d, int prec, const Tables& t, const int8_t* s,
+                  int rows, void* dst1, void* dst2, long dst2_stride);
+// ln psi(s) (out: float64 for prec 0, float32 otherwise)
+void launch_log_psi(hipStream_t st, const Dims& d, int prec, const double* Pm, const Tables& t,
+                    const int8_t* s, long n, void* out);
+
+// sampler.hip
+struct SampleArgs {
+    int C;                 // chains
+    int K;                 // proposals in this launch
+    int record;            // write the final configuration to rec (row stride rec_stride)
+    uint64_t seed;
+    uint64_t prop_base;    // global proposal index of the first proposal
+    int8_t* s;             // [C][N] chain configurations (in/out)
+    const void* tch;       // [C][Mw] tanh(theta) at the start of the launch
+    int8_t* rec;           // recorded configuration destination
+    long rec_stride;       // bytes between chains in rec
+    uint8_t* acc_log;      // [C][log_stride] accept flags or null
+    long log_stride;
+    long log_offset;
+    uint32_t* acc_count;   // [C] accepted counts (accumulated) or null
+    int n_bonds;
+    const int32_t* bonds;  // exchange rule
+};
+void launch_sample(hipStream_t st, const Dims& d, int prec, int rule, const Tables& t,
+                   const SampleArgs& a);
+
+// eloc.hip
+struct HamDev {
+    int kind;              // 0 TFIM, 1 Heisenberg
+    int n_bonds;
+    const int32_t* bonds;  // [n_bonds][2]
+    const int8_t* sub;     // [N] or null
+    double J, h;
+};
+void launch_eloc(hipStream_t st, const Dims& d, int prec, const Tables& t, const HamDev& H,
+                 const int8_t* s, const void* tact, long n, double* out);
+
+// sr.hip
+void launch_stats(hipStream_t st, const double* E, long n, double* out3);
+void launch_center(hipStream_t st, const double* E, const double* stats, double scale, long n,
+                   double* v);
+void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
+              const double* V, double* w, double* wpart, CgScalars* sc);
+int outer_ksplit(long n);
+void launch_outer(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
+                  long n, const double* v, int v_mode, void* part, int ksplit,
+                  const CgScalars* sc);
+void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
+                         const double* p, double shift, double* out, double* dpart,
+                         CgScalars* sc, int mode);
+void launch_cg_init(hipStream_t st, int total, const double* f, double* x, double* r, double* p,
+                    double* dpart, CgScalars* sc, double tol, int maxiter);
+void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
+                      const double* Ap, double* dpart, CgScalars* sc);
+void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
+                        CgScalars* sc);
+
+// dense.hip
+void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
+                     long n, void* O, int P, long ld);
+void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs);
+int gram_tiles(int P);
+void fill_gram_tiles(int P, int* host_tiles);
+void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
+                 const int* tiles, int ntiles);
+void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
+                         double shift, double* out, double* dpart, CgScalars* sc);
+
+}  // namespace nqs

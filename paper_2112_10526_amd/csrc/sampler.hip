@@ -1,0 +1,172 @@
+// Metropolis-Hastings sampling with a persistent per-chain wave (paper,
+// Monte Carlo samplers section; local and exchange rules).
+//
+// One wave64 owns one chain.  Lane l keeps tanh(theta_j) for hidden units
+// j = l + 64 q (q < QM) in registers for the whole launch, and the chain's
+// configuration sits in LDS.  Random draws are made 64 at a time: lane l
+// evaluates the Philox block of proposal p0 + l, and proposal p0 + q reads
+// lane q's site/bond and uniform with v_readlane.
+//
+// Single flip of site i (local rule):
+//   psi(s')/psi(s) = K_i(s_i) prod_j f_j,  f_j = 1 - s_i t_j T_ij,
+//   T_ij = tanh(2 W_ji),  K_i(s) = exp(-2 a_i s) prod_j cosh(2 W_ji),
+// from cosh(theta - x)/cosh(theta) = cosh x (1 - tanh(theta) tanh x) with
+// x = 2 s_i W_ji; after acceptance t_j <- (t_j - s_i T_ij) / f_j (tanh
+// subtraction formula; f_j is the denominator already computed).
+// Exchange of an antiparallel pair (a, b) (s_b = -s_a):
+//   psi(s'')/psi(s) = K_a(s_a) K_b(s_b) prod_j g_j,
+//   g_j = 1 - T_ja T_jb - s_a t_j (T_ja - T_jb),
+//   t_j <- (t_j (1 - T_ja T_jb) - s_a (T_ja - T_jb)) / g_j.
+// FP64: the product is formed directly and u < r^2 is tested.  FP32: each
+// lane's partial product goes through ln, the wave sums the logs, and
+// ln u < 2 ln r is tested.
+#include "kernels.h"
+
+namespace nqs {
+
+template <typename R, int QMAX, int RULE>
+__global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt,
+                                                const R* __restrict__ Ks, SampleArgs a) {
+    extern __shared__ int8_t lds_s[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 4 + wave;
+    if (c >= a.C) return;  // uniform per wave
+    const int N = d.N, Mw = d.Mw, QM = d.QM;
+    int8_t* s = lds_s + wave * round_up(N, 16);
+    int8_t* sg = a.s + (size_t)c * N;
+    for (int i = lane; i < N; i += 64) s[i] = sg[i];
+    __builtin_amdgcn_wave_barrier();
+
+    const R* tc = (const R*)a.tch + (size_t)c * Mw;
+    R t[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) t[q] = q < QM ? tc[lane + 64 * q] : (R)0;
+
+    uint32_t n_acc = 0;
+    for (int p0 = 0; p0 < a.K; p0 += 64) {
+        const uint64_t pidx = a.prop_base + (uint64_t)(p0 + lane);
+        const uint4 x = philox10(make_uint4((uint32_t)pidx, (uint32_t)(pidx >> 32), (uint32_t)c,
+                                            TAG_METROPOLIS), a.seed);
+        int ia_l, ib_l = 0;
+        if (RULE == 0) {
+            ia_l = mulshift(x.x, N);
+        } else {
+            const int k = mulshift(x.x, a.n_bonds);
+            ia_l = a.bonds[2 * k];
+            ib_l = a.bonds[2 * k + 1];
+        }
+        const double u_l = unit53(x.y, x.z);
+        // FP32 path compares logarithms; u = 0 gives -inf and always accepts
+        const float lu_l = sizeof(R) == 8 ? 0.0f : logf((float)u_l);
+        const int np = min(64, a.K - p0);
+        for (int q = 0; q < np; ++q) {
+            const int ia = __builtin_amdgcn_readlane(ia_l, q);
+            const int sa = s[ia];
+            bool accept;
+            if (RULE == 0) {
+                const R* Trow = Tt + (size_t)ia * Mw;
+                R f[QMAX], Tv[QMAX];
+                R prod = (R)1;
+#pragma unroll
+                for (int qq = 0; qq < QMAX; ++qq) {
+                    if (qq < QM) {
+                        Tv[qq] = Trow[lane + 64 * qq];
+                        f[qq] = (R)1 - (R)sa * t[qq] * Tv[qq];
+                        prod *= f[qq];
+                    }
+                }
+                const R kf = Ks[2 * ia + (sa < 0)];
+                if constexpr (sizeof(R) == 8) {
+                    const double r = wave_prod(prod) * kf;
+                    accept = readlane(u_l, q) < r * r;
+                } else {
+                    const float lr = wave_sum(__logf(prod)) + kf;
+                    accept = readlane(lu_l, q) < 2.0f * lr;
+                }
+                if (accept) {
+#pragma unroll
+                    for (int qq = 0; qq < QMAX; ++qq)
+                        if (qq < QM) t[qq] = (t[qq] - (R)sa * Tv[qq]) / f[qq];
+                    s[ia] = (int8_t)-sa;  // every lane stores the same value
+                }
+            } else {
+                const int ib = __builtin_amdgcn_readlane(ib_l, q);
+                const int sb = s[ib];
+                if (sa == sb) {
+                    accept = true;  // identity move, ratio 1
+                } else {
+                    const R* Ta_row = Tt + (size_t)ia * Mw;
+                    const R* Tb_row = Tt + (size_t)ib * Mw;
+                    R g[QMAX], TT[QMAX], Td[QMAX];
+                    R prod = (R)1;
+#pragma unroll
+                    for (int qq = 0; qq < QMAX; ++qq) {
+                        if (qq < QM) {
+                            const R ta = Ta_row[lane + 64 * qq], tb = Tb_row[lane + 64 * qq];
+                            TT[qq] = (R)1 - ta * tb;
+                            Td[qq] = (R)sa * (ta - tb);
+                            g[qq] = TT[qq] - t[qq] * Td[qq];
+                            prod *= g[qq];
+                        }
+                    }
+                    const R ka = Ks[2 * ia + (sa < 0)], kb = Ks[2 * ib + (sb < 0)];
+                    if constexpr (sizeof(R) == 8) {
+                        const double r = wave_prod(prod) * ka * kb;
+                        accept = readlane(u_l, q) < r * r;
+                    } else {
+                        const float lr = wave_sum(__logf(prod)) + ka + kb;
+                        accept = readlane(lu_l, q) < 2.0f * lr;
+                    }
+                    if (accept) {
+#pragma unroll
+                        for (int qq = 0; qq < QMAX; ++qq)
+                            if (qq < QM) t[qq] = (t[qq] * TT[qq] - Td[qq]) / g[qq];
+                        s[ia] = (int8_t)sb;
+                        s[ib] = (int8_t)sa;
+                    }
+                }
+            }
+            n_acc += accept ? 1u : 0u;
+            if (a.acc_log && lane == 0)
+                a.acc_log[(size_t)c * a.log_stride + a.log_offset + p0 + q] = accept ? 1 : 0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < N; i += 64) {
+        sg[i] = s[i];
+        if (a.record) a.rec[(size_t)c * a.rec_stride + i] = s[i];
+    }
+    if (a.acc_count && lane == 0) a.acc_count[c] += n_acc;
+}
+
+template <typename R, int QMAX>
+static void launch_q(hipStream_t st, const Dims& d, int rule, const Tables& t,
+                     const SampleArgs& a) {
+    const dim3 grid((a.C + 3) / 4);
+    const size_t lds = 4 * (size_t)round_up(d.N, 16);
+    if (rule == 0)
+        k_sample<R, QMAX, 0><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+    else
+        k_sample<R, QMAX, 1><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+}
+
+template <typename R>
+static void launch_r(hipStream_t st, const Dims& d, int rule, const Tables& t,
+                     const SampleArgs& a) {
+    if (d.QM <= 1) launch_q<R, 1>(st, d, rule, t, a);
+    else if (d.QM <= 2) launch_q<R, 2>(st, d, rule, t, a);
+    else if (d.QM <= 4) launch_q<R, 4>(st, d, rule, t, a);
+    else if (d.QM <= 8) launch_q<R, 8>(st, d, rule, t, a);
+    else if (d.QM <= 16) launch_q<R, 16>(st, d, rule, t, a);
+    else launch_q<R, 32>(st, d, rule, t, a);
+}
+
+// Caller guarantees d.QM <= 32 (M <= 2048).
+void launch_sample(hipStream_t st, const Dims& d, int prec, int rule, const Tables& t,
+                   const SampleArgs& a) {
+    if (a.C <= 0 || a.K <= 0) return;
+    if (prec == 0) launch_r<double>(st, d, rule, t, a);
+    else launch_r<float>(st, d, rule, t, a);
+}
+
+}  // namespace nqs

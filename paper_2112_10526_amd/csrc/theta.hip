@@ -1,0 +1,181 @@
+// Hidden pre-activations theta = W s + b on MFMA, with tanh in the epilogue,
+// and ln psi(s).
+//
+// The contraction Theta[r][j] = sum_i s~[r][i] W~^T[i][j] (s~ augmented with a
+// 1 at i = N so that row N of W~^T adds b) runs on CDNA4 matrix cores:
+//   FP64 path: v_mfma_f64_16x16x4f64,
+//   FP32 path: v_mfma_f32_16x16x4f32,
+//   BF16 form: v_mfma_f32_16x16x32_bf16 twice (W = W_hi + W_lo, both BF16,
+//              spins exact), FP32 accumulation.
+// Operand lane layouts (16x16 tiles, 64 lanes): A[row = lane % 16][k = lane / 16]
+// (BF16: k = 8 * (lane / 16) + e), B[k][col = lane % 16]; accumulator slot i
+// of lane l holds D[acc_row(l / 16, i)][l % 16] (see common.h).
+// One workgroup = 4 waves = 64 rows x 64 hidden columns; each wave owns 16 rows.
+#include "kernels.h"
+
+namespace nqs {
+
+template <typename R>
+__device__ __forceinline__ R act(R th, int col, int M) {
+    return col < M ? (R)tanh(th) : (col == M ? (R)1 : (R)0);
+}
+
+template <typename R>
+__device__ __forceinline__ R spin_aug(const int8_t* __restrict__ s, int N, int r, int rows, int k) {
+    if (r >= rows || k > N) return (R)0;
+    return k == N ? (R)1 : (R)s[(size_t)r * N + k];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_theta(Dims d, const int8_t* __restrict__ s, int rows,
+                                               const R* __restrict__ Wa, R* __restrict__ dst1,
+                                               R* __restrict__ dst2, long dst2_stride) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * 64 + wave * 16;
+    const int col0 = blockIdx.y * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    typedef typename std::conditional<sizeof(R) == 8, v4d, v4f>::type acc_t;
+    acc_t acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < d.Na; k0 += 4) {
+        const int k = k0 + lk;
+        const R a = spin_aug<R>(s, d.N, row0 + lr, rows, k);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = col0 + ct * 16 + lr;
+            const R b = col < d.Mw ? Wa[(size_t)k * d.Mw + col] : (R)0;
+            if constexpr (sizeof(R) == 8)
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
+            else
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = col0 + ct * 16 + lr;
+        if (col >= d.Mw) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = row0 + acc_row<R>(lk, i);
+            if (row >= rows) continue;
+            const R t = act<R>(acc[ct][i], col, d.M);
+            dst1[(size_t)row * d.Mw + col] = t;
+            if (dst2) dst2[(size_t)row * dst2_stride + col] = t;
+        }
+    }
+}
+
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+// BF16 form: spins are exact in BF16 (+1 = 0x3F80, -1 = 0xBF80).
+__device__ __forceinline__ v8bf spins_bf16(const int8_t* __restrict__ s, int N, int r, int rows,
+                                           int k0) {
+    v8s v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        short bits = 0;
+        if (r < rows && k <= N) {
+            const int sv = k == N ? 1 : (int)s[(size_t)r * N + k];
+            bits = sv > 0 ? (short)0x3F80 : (short)0xBF80;
+        }
+        v[e] = bits;
+    }
+    return __builtin_bit_cast(v8bf, v);
+}
+
+__global__ __launch_bounds__(256) void k_theta_bf16(Dims d, const int8_t* __restrict__ s, int rows,
+                                                    const uint16_t* __restrict__ Whi,
+                                                    const uint16_t* __restrict__ Wlo,
+                                                    float* __restrict__ dst1, float* __restrict__ dst2,
+                                                    long dst2_stride) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * 64 + wave * 16;
+    const int col0 = blockIdx.y * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4f acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = v4f{0, 0, 0, 0};
+    for (int k0 = 0; k0 < d.Kb; k0 += 32) {
+        const int kk = k0 + 8 * lk;
+        const v8bf a = spins_bf16(s, d.N, row0 + lr, rows, kk);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = col0 + ct * 16 + lr;
+            v8s bh = {0, 0, 0, 0, 0, 0, 0, 0}, bl = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (col < d.Mw) {
+                bh = *(const v8s*)(Whi + (size_t)col * d.Kb + kk);
+                bl = *(const v8s*)(Wlo + (size_t)col * d.Kb + kk);
+            }
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh),
+                                                              acc[ct], 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl),
+                                                              acc[ct], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = col0 + ct * 16 + lr;
+        if (col >= d.Mw) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = row0 + acc_row<float>(lk, i);
+            if (row >= rows) continue;
+            const float t = act<float>(acc[ct][i], col, d.M);
+            dst1[(size_t)row * d.Mw + col] = t;
+            if (dst2) dst2[(size_t)row * dst2_stride + col] = t;
+        }
+    }
+}
+
+// ln psi(s) = sum_i a_i s_i + sum_j ln cosh theta_j; one wave per configuration.
+template <typename R>
+__global__ __launch_bounds__(256) void k_log_psi(Dims d, const double* __restrict__ Pm,
+                                                 const R* __restrict__ Wa,
+                                                 const int8_t* __restrict__ s, long n,
+                                                 R* __restrict__ out) {
+    const long r = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    const int8_t* sr = s + r * d.N;
+    R acc = 0;
+    for (int j = lane; j < d.M; j += 64) {
+        R th = Wa[(size_t)d.N * d.Mw + j];
+        for (int i = 0; i < d.N; ++i) th += (R)sr[i] * Wa[(size_t)i * d.Mw + j];
+        const R ath = th < 0 ? -th : th;
+        // ln cosh x = |x| + ln(1 + e^{-2|x|}) - ln 2, finite for any x
+        acc += ath + (R)log1p(exp(-2 * ath)) - (R)0.69314718055994530942;
+    }
+    if (d.vb)
+        for (int i = lane; i < d.N; i += 64) acc += (R)(Pm[(size_t)d.M * d.Na + i] * sr[i]);
+    acc = wave_sum(acc);
+    if (lane == 0) out[r] = acc;
+}
+
+void launch_theta(hipStream_t st, const Dims& d, int prec, const Tables& t, const int8_t* s,
+                  int rows, void* dst1, void* dst2, long dst2_stride) {
+    if (rows <= 0) return;
+    dim3 grid((rows + 63) / 64, (d.Mw + 63) / 64);
+    if (prec == 0)
+        k_theta<double><<<grid, 256, 0, st>>>(d, s, rows, (const double*)t.Wa, (double*)dst1,
+                                              (double*)dst2, dst2_stride);
+    else if (prec == 1)
+        k_theta<float><<<grid, 256, 0, st>>>(d, s, rows, (const float*)t.Wa, (float*)dst1,
+                                             (float*)dst2, dst2_stride);
+    else
+        k_theta_bf16<<<grid, 256, 0, st>>>(d, s, rows, t.Whi, t.Wlo, (float*)dst1, (float*)dst2,
+                                           dst2_stride);
+}
+
+void launch_log_psi(hipStream_t st, const Dims& d, int prec, const double* Pm, const Tables& t,
+                    const int8_t* s, long n, void* out) {
+    if (n <= 0) return;
+    const int nb = (int)((n + 3) / 4);
+    if (prec == 0)
+        k_log_psi<double><<<nb, 256, 0, st>>>(d, Pm, (const double*)t.Wa, s, n, (double*)out);
+    else
+        k_log_psi<float><<<nb, 256, 0, st>>>(d, Pm, (const float*)t.Wa, s, n, (float*)out);
+}
+
+}  // namespace nqs

@@ -1,0 +1,271 @@
+"""Python face of libnqs: one ``VMCState`` per C context.
+
+PyTorch supplies device memory (the workspace and every input/output tensor)
+and the HIP stream; the method itself runs in libnqs's kernels.  There is no
+fallback: without a GPU or without ``libnqs.so`` every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NqsError, NqsSrInfo, NqsStats, NqsStepCfg, NqsStepReport
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class SrInfo:
+    iterations: int
+    converged: bool
+    rel_residual: float
+
+
+@dataclasses.dataclass
+class StepReport:
+    energy: dict
+    sr: SrInfo
+    status: int
+
+
+def _stats_dict(s: NqsStats) -> dict:
+    return dict(mean=s.mean, variance=s.variance, error=s.error, acceptance=s.acceptance)
+
+
+class VMCState:
+    """A real RBM variational state with a Metropolis sampler on one GPU."""
+
+    def __init__(self, *, model: str, n_sites: int, bonds, J: float, h: float = 0.0,
+                 sublattice=None, n_hidden: int, visible_bias: bool = True,
+                 hidden_bias: bool = True, precision: str = "fp64", rule: str = "local",
+                 n_chains: int, samples_per_chain: int, sweep_size: int, seed: int,
+                 total_sz_zero: bool = False, qgt: str = "onthefly", device: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None, params=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libnqs needs a HIP device; none is visible")
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.precision = precision
+        self.n_sites, self.n_hidden = n_sites, n_hidden
+        self.n_chains, self.samples_per_chain, self.sweep_size = n_chains, samples_per_chain, sweep_size
+        self.rdtype = torch.float64 if precision == "fp64" else torch.float32
+        h_ctx = ctypes.c_void_p()
+        st = self.lib.nqs_create(ctypes.byref(h_ctx), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st:
+            raise NqsError(st, "nqs_create failed")
+        self.ctx = h_ctx
+        b = np.ascontiguousarray(bonds, dtype=np.int32)
+        self._bonds = b
+        if model == "tfim":
+            self._check(self.lib.nqs_set_tfim(self.ctx, n_sites, b.shape[0],
+                                              b.ctypes.data_as(ctypes.c_void_p), J, h))
+        elif model == "heisenberg":
+            sub = None if sublattice is None else np.ascontiguousarray(sublattice, dtype=np.int8)
+            self._check(self.lib.nqs_set_heisenberg(
+                self.ctx, n_sites, b.shape[0], b.ctypes.data_as(ctypes.c_void_p), J,
+                None if sub is None else sub.ctypes.data_as(ctypes.c_void_p)))
+        else:
+            raise ValueError(f"unknown model {model!r}")
+        self._check(self.lib.nqs_set_rbm(self.ctx, n_hidden, int(visible_bias), int(hidden_bias),
+                                         _lib.PRECISIONS[precision]))
+        self._check(self.lib.nqs_set_sampler(self.ctx, _lib.RULES[rule], n_chains,
+                                             samples_per_chain, sweep_size, seed,
+                                             int(total_sz_zero)))
+        self._check(self.lib.nqs_set_qgt(self.ctx, _lib.QGTS[qgt]))
+        self.n_params = int(self.lib.nqs_num_params(self.ctx))
+        self.workspace_bytes = int(self.lib.nqs_workspace_bytes(self.ctx))
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.nqs_bind_workspace(self.ctx, ctypes.c_void_p(base + off),
+                                                self.workspace_bytes))
+        if params is not None:
+            self.set_params(params)
+
+    @classmethod
+    def from_workload(cls, w, precision: Optional[str] = None, qgt: str = "onthefly",
+                      device: int = 0, stream=None, params=None, n_chains: Optional[int] = None):
+        """Build the state of a ``synth.Workload`` (initial parameters included)."""
+        return cls(model=w.model, n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
+                   sublattice=w.sublattice(), n_hidden=w.n_hidden,
+                   precision=precision or w.precision, rule=w.rule,
+                   n_chains=n_chains or w.n_chains, samples_per_chain=w.samples_per_chain,
+                   sweep_size=w.sweep_size, seed=w.chain_seed, total_sz_zero=w.total_sz_zero,
+                   qgt=qgt, device=device, stream=stream,
+                   params=w.params() if params is None else params)
+
+    # ------------------------------------------------------------------
+    def _check(self, st: int):
+        if st != _lib.NQS_OK:
+            msg = self.lib.nqs_last_error(self.ctx).decode()
+            raise NqsError(st, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.nqs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_samples(self) -> int:
+        return self.n_chains * self.samples_per_chain
+
+    def _dev(self, t: torch.Tensor, dtype) -> torch.Tensor:
+        return t.to(device=self.device, dtype=dtype).contiguous()
+
+    # ------------------------------------------------------------------
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64)) if not torch.is_tensor(p) else p
+        if torch.is_tensor(p):
+            p = self._dev(p, torch.float64)
+            self._check(self.lib.nqs_set_params(self.ctx, _ptr(p), 1))
+        else:
+            if p.size != self.n_params:
+                raise ValueError(f"expected {self.n_params} parameters")
+            self._check(self.lib.nqs_set_params(self.ctx, p.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params)
+        self._check(self.lib.nqs_get_params(self.ctx, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def get_chains(self) -> np.ndarray:
+        out = np.zeros((self.n_chains, self.n_sites), dtype=np.int8)
+        self._check(self.lib.nqs_get_chains(self.ctx, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def set_chains(self, s):
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        self._check(self.lib.nqs_set_chains(self.ctx, s.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def reset_chains(self):
+        self._check(self.lib.nqs_reset_chains(self.ctx))
+
+    @property
+    def proposal_count(self) -> int:
+        return int(self.lib.nqs_proposal_count(self.ctx))
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.nqs_get_state(self.ctx, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.lib.nqs_get_state(self.ctx, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes):
+        self._check(self.lib.nqs_set_state(self.ctx, blob, len(blob)))
+
+    # ------------------------------------------------------------------
+    def sample(self, n_discard: int = 0, return_samples: bool = True, log_accepts: bool = False):
+        """Advance the chains; returns (samples [C, S, N] int8, accept log, acceptance)."""
+        smp = None
+        if return_samples:
+            smp = torch.empty((self.n_chains, self.samples_per_chain, self.n_sites),
+                              dtype=torch.int8, device=self.device)
+        acc = None
+        if log_accepts:
+            acc = torch.empty((self.n_chains, self.samples_per_chain * self.sweep_size),
+                              dtype=torch.uint8, device=self.device)
+        a = ctypes.c_double(0.0)
+        self._check(self.lib.nqs_sample(self.ctx, n_discard, _ptr(smp), _ptr(acc), ctypes.byref(a)))
+        return smp, acc, a.value
+
+    def thermalize(self, n_segments: int):
+        a = ctypes.c_double(0.0)
+        self._check(self.lib.nqs_sample(self.ctx, n_segments, None, None, ctypes.byref(a)))
+
+    def load_samples(self, s: torch.Tensor):
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        self._check(self.lib.nqs_load_samples(self.ctx, _ptr(s), s.shape[0]))
+        self._held = s
+
+    def local_energy(self, s: torch.Tensor) -> torch.Tensor:
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        out = torch.empty(s.shape[0], dtype=torch.float64, device=self.device)
+        self._check(self.lib.nqs_local_energy(self.ctx, _ptr(s), s.shape[0], _ptr(out)))
+        return out
+
+    def log_psi(self, s: torch.Tensor) -> torch.Tensor:
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        out = torch.empty(s.shape[0], dtype=self.rdtype, device=self.device)
+        self._check(self.lib.nqs_log_psi(self.ctx, _ptr(s), s.shape[0], _ptr(out)))
+        return out
+
+    def log_psi_vjp(self, s: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        g = self._dev(g.reshape(-1), self.rdtype)
+        out = torch.empty(self.n_params, dtype=self.rdtype, device=self.device)
+        self._check(self.lib.nqs_log_psi_vjp(self.ctx, _ptr(s), s.shape[0], _ptr(g), _ptr(out)))
+        return out
+
+    def jacobian(self, s: torch.Tensor, center: bool = False) -> torch.Tensor:
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        out = torch.empty((s.shape[0], self.n_params), dtype=self.rdtype, device=self.device)
+        self._check(self.lib.nqs_jacobian(self.ctx, _ptr(s), s.shape[0], _ptr(out), int(center)))
+        return out
+
+    def expect_and_grad(self, want_grad: bool = True):
+        st = NqsStats()
+        g = torch.empty(self.n_params, dtype=torch.float64, device=self.device) if want_grad else None
+        self._check(self.lib.nqs_expect_and_grad(self.ctx, ctypes.byref(st), _ptr(g)))
+        return _stats_dict(st), g
+
+    def sr_update(self, qgt: str = "onthefly", diag_shift: float = 0.01, lr: float = 0.01,
+                  tol: float = 1e-6, maxiter: int = 0, want_delta: bool = True,
+                  allow_notconv: bool = False):
+        info = NqsSrInfo()
+        d = torch.empty(self.n_params, dtype=torch.float64, device=self.device) if want_delta else None
+        st = self.lib.nqs_sr_update(self.ctx, _lib.QGTS[qgt], diag_shift, lr, tol, maxiter, _ptr(d),
+                                    ctypes.byref(info))
+        if not (st == _lib.NQS_OK or (allow_notconv and st == _lib.NQS_ENOTCONV)):
+            self._check(st)
+        return d, SrInfo(info.iterations, bool(info.converged), info.rel_residual)
+
+    def vmc_step(self, qgt: str = "onthefly", diag_shift: float = 0.01, lr: float = 0.01,
+                 tol: float = 1e-6, maxiter: int = 0) -> StepReport:
+        cfg = NqsStepCfg(_lib.QGTS[qgt], diag_shift, lr, tol, maxiter)
+        rep = NqsStepReport()
+        st = self.lib.nqs_vmc_step(self.ctx, ctypes.byref(cfg), ctypes.byref(rep))
+        if st not in (_lib.NQS_OK, _lib.NQS_ENOTCONV):
+            self._check(st)
+        return StepReport(_stats_dict(rep.energy),
+                          SrInfo(rep.sr.iterations, bool(rep.sr.converged), rep.sr.rel_residual),
+                          rep.status)
+
+
+def batch_step(states: Sequence[VMCState], cfgs: Sequence[dict]) -> list:
+    """One SR step for every state, issued in lock-step across their streams."""
+    n = len(states)
+    if n == 0:
+        return []
+    lib = states[0].lib
+    ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in states])
+    c_cfgs = (NqsStepCfg * n)()
+    for k, c in enumerate(cfgs):
+        c_cfgs[k] = NqsStepCfg(_lib.QGTS[c.get("qgt", "onthefly")], c.get("diag_shift", 0.01),
+                               c.get("lr", 0.01), c.get("tol", 1e-6), c.get("maxiter", 0))
+    reps = (NqsStepReport * n)()
+    lib.nqs_batch_step(ctxs, n, c_cfgs, reps)
+    out = []
+    for k in range(n):
+        r = reps[k]
+        if r.status not in (_lib.NQS_OK, _lib.NQS_ENOTCONV):
+            msg = lib.nqs_last_error(states[k].ctx).decode()
+            raise NqsError(r.status, f"context {k}: {msg}")
+        out.append(StepReport(_stats_dict(r.energy),
+                              SrInfo(r.sr.iterations, bool(r.sr.converged), r.sr.rel_residual),
+                              r.status))
+    return out

@@ -1,0 +1,61 @@
+"""CPU checks of the boundary: the C-ABI library builds for gfx950, loads, and
+exports every entry point that include/nqs.h declares; the Python layer has
+no CPU fallback."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nqs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nqs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("nqs_create", "nqs_set_tfim", "nqs_set_heisenberg", "nqs_set_rbm",
+                 "nqs_set_sampler", "nqs_sample", "nqs_local_energy", "nqs_expect_and_grad",
+                 "nqs_sr_update", "nqs_vmc_step", "nqs_batch_step", "nqs_jacobian",
+                 "nqs_log_psi_vjp"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2112_10526_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2112_10526_amd import build
+        build.build()
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(_lib.EXPORTS) == declared_functions()
+    lib = _lib.load()
+    assert lib.nqs_last_error(None) == b"null context"
+    assert lib.nqs_num_params(None) == 0
+    assert lib.nqs_workspace_bytes(None) == 0
+
+
+def test_create_fails_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2112_10526_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.nqs_create(ctypes.byref(h), 0, None) != 0
+
+
+def test_python_layer_has_no_cpu_fallback():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import synth
+    from paper_2112_10526_amd.nqs import VMCState
+    with pytest.raises(RuntimeError):
+        VMCState.from_workload(synth.WORKLOADS["tfim1d_n10"])
