@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the RBM-VMC hot path on the 10x10 transverse-field Ising model.
+
+Workload (synthetic, seeded): 2D TFIM on a periodic 10 x 10 lattice, J = 1,
+h = 3.044; real RBM with alpha = 2 (200 hidden units, 20,300 parameters),
+initial parameters N(0, 0.01^2) from seed 1; Metropolis-local sampling with
+4096 chains x 4 samples per SR step (16,384 samples), 100 proposals between
+recorded samples; SR with the on-the-fly QGT product, CG tolerance 1e-6,
+diagonal shift 0.01, learning rate 0.01.  The chains are thermalised for
+100 x 100 proposals before timing (not timed).
+
+One timed "step" = one full SR step: sampling, local energies, statistics,
+force, CG solve and parameter update.  `value` is the BF16 form's end-to-end
+local energies per second (samples x SR steps / s); the FP64 path is timed the
+same way and reported beside it.  The dominant kernel of the timed region is
+timed with HIP events on the stream it runs on, for the roofline figure.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "local energies/s + SR steps/s, 10×10 TFIM, BF16 vs FP64; p99 step latency"
+PEAK = {  # MI355X dense peaks
+    "mfma_fp64": 78.6e12, "mfma_fp32": 157.3e12, "mfma_bf16": 2.5e15,
+    "valu_fp64": 78.6e12, "valu_fp32": 157.3e12, "hbm": 8.0e12,
+}
+
+
+def kernel_work(cls: str, w, precision: str):
+    """Algorithmic work of one launch of a kernel class: (bound, flops or bytes, unit, peak)."""
+    N, M, Ns, C, K = w.n_sites, w.n_hidden, w.n_samples, w.n_chains, w.sweep_size
+    P = N + M + N * M
+    mf = "mfma_fp64" if precision == "fp64" else "mfma_fp32"
+    vf = "valu_fp64" if precision == "fp64" else "valu_fp32"
+    if cls in ("outer", "qgt_w"):
+        # one product of the Jacobian J [Ns x P] with a vector: 2 Ns P flops
+        return "mfma", 2.0 * Ns * P, "TFLOP/s", PEAK[mf]
+    if cls == "sample":
+        # every proposal: M factors (FMA + MUL) of the amplitude ratio
+        return "alu", 4.0 * C * K * M, "TFLOP/s", PEAK[vf]
+    if cls == "eloc":
+        # every sample: N single-flip ratios of M factors (MUL, FMA, MUL)
+        return "alu", 6.0 * Ns * N * M / 2.0, "TFLOP/s", PEAK[vf]
+    if cls == "theta":
+        return "mfma", 2.0 * C * (N + 1) * M, "TFLOP/s", PEAK[mf]
+    return "hbm", float("nan"), "GB/s", PEAK["hbm"]
+
+
+def make(w, precision):
+    from paper_2112_10526_amd.nqs import VMCState
+    st = VMCState.from_workload(w, precision=precision)
+    st.thermalize(w.thermalize_segments)
+    return st
+
+
+def run_precision(w, precision, steps, warmup, torch):
+    st = make(w, precision)
+    # warm-up steps, profiled in full to find the dominant kernel class
+    st.profile_enable(None)
+    for _ in range(warmup):
+        st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    prof = st.profile_read()
+    dominant = max(prof, key=lambda k: prof[k]["ms"])
+    # timed region: only the dominant class carries events
+    st.profile_enable([dominant])
+    lat, iters, acc, energies = [], [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        rep = st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        lat.append(time.perf_counter() - a)
+        iters.append(rep.sr.iterations)
+        acc.append(rep.energy["acceptance"])
+        energies.append(rep.energy["mean"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tp = st.profile_read()[dominant]
+    # stage rate: sampling + local energies, from a separately profiled step
+    st.profile_enable(["sample", "theta", "eloc"])
+    st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    sp = st.profile_read()
+    stage_ms = sp["sample"]["ms"] + sp["theta"]["ms"] + sp["eloc"]["ms"]
+    elapsed = t1 - t0
+    lat_ms = np.array(lat) * 1e3
+    out = dict(
+        precision=precision,
+        value=w.n_samples * steps / elapsed,
+        ms_per_step=elapsed / steps * 1e3,
+        sr_steps_per_s=steps / elapsed,
+        p50_ms=float(np.percentile(lat_ms, 50)),
+        p99_ms=float(np.percentile(lat_ms, 99)),
+        cg_iters_mean=float(np.mean(iters)),
+        acceptance_mean=float(np.mean(acc)),
+        energy_first=energies[0], energy_last=energies[-1],
+        stage_local_energies_per_s=w.n_samples / (stage_ms * 1e-3) if stage_ms > 0 else None,
+        warmup_profile_ms={k: round(v["ms"] / max(warmup, 1), 4) for k, v in prof.items()
+                           if v["launches"]},
+        dominant=dict(kernel_class=dominant, launches=tp["launches"], total_ms=tp["ms"]),
+    )
+    st.close()
+    return out
+
+
+def cpu_baseline(w, n_chains=256, steps=2):
+    """The oracle (plain FP64 CPU code) on a bounded sample of the workload:
+    the first `n_chains` chains, one full SR step each time."""
+    from oracle import core
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
+    ch = core.init_chains(w.n_sites, n_chains, w.chain_seed)
+    th = core.sample(rbm, ch, 1, 10 * w.sweep_size, w.chain_seed, 0, mode="cached")
+    ch, prop = th.chains, 10 * w.sweep_size
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rbm, ch, rep = core.vmc_step(rbm, ham, ch, w.samples_per_chain, w.sweep_size,
+                                     w.chain_seed, prop, "local", w.diag_shift, w.lr, w.cg_tol)
+        times.append(time.perf_counter() - t0)
+        prop += w.samples_per_chain * w.sweep_size
+    n = n_chains * w.samples_per_chain
+    return dict(value=n / float(np.median(times)), unit="local energies/s",
+                cores=core.num_threads(), kind="oracle",
+                sample=(f"{n_chains} of 4096 chains x {w.samples_per_chain} samples "
+                        f"({n} local energies) of the same 10x10 workload, full SR step "
+                        f"(sampling, local energies, Jacobian, force, CG), median of {steps}"),
+                seconds_per_step=float(np.median(times)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--compare", default="fp64", help="second precision to time ('' = none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
+              "no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = synth.WORKLOADS["tfim2d_l10"]
+    main_run = run_precision(w, args.precision, args.steps, args.warmup, torch)
+    print(f"[bench] {args.precision}: {main_run['value']:.4g} local energies/s", file=sys.stderr,
+          flush=True)
+    cmp_run = None
+    if args.compare and args.compare != args.precision:
+        cmp_run = run_precision(w, args.compare, args.steps, args.warmup, torch)
+        print(f"[bench] {args.compare}: {cmp_run['value']:.4g} local energies/s", file=sys.stderr,
+              flush=True)
+    dom = main_run["dominant"]
+    bound, work, unit, peak = kernel_work(dom["kernel_class"], w, args.precision)
+    avg_s = dom["total_ms"] * 1e-3 / max(dom["launches"], 1)
+    achieved = work / avg_s if avg_s > 0 else float("nan")
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    roofline = dict(bound=bound, kernel=dom["kernel_class"], achieved=achieved / scale,
+                    peak=peak / scale, unit=unit, frac=achieved / peak,
+                    avg_launch_us=avg_s * 1e6, work_per_launch=work, traffic=None)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    line = dict(
+        metric=METRIC, value=main_run["value"], unit="local energies/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=main_run["ms_per_step"],
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=args.precision,
+        data="synthetic",
+        config=dict(workload="tfim2d_l10: 2D TFIM 10x10 periodic J=1 h=3.044, real RBM alpha=2 "
+                             "(200 hidden), 4096 chains x 4 samples, 100 proposals per sample, "
+                             "SR on-the-fly QGT + CG tol 1e-6 shift 0.01 lr 0.01",
+                    n_samples=w.n_samples, n_params=w.n_params, parallelism="1 GPU"),
+        sr_steps_per_s=main_run["sr_steps_per_s"], p50_ms=main_run["p50_ms"],
+        p99_ms=main_run["p99_ms"],
+        stage_local_energies_per_s=main_run["stage_local_energies_per_s"],
+        cg_iters_mean=main_run["cg_iters_mean"], acceptance=main_run["acceptance_mean"],
+        roofline=roofline, cpu_baseline=cpu,
+        compare=cmp_run, detail=main_run,
+    )
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -228,6 +228,10 @@ int nqs_set_state(nqs_ctx* ctx, const void* blob, size_t bytes);
 int nqs_sample(nqs_ctx* ctx, int n_discard_segments, int8_t* samples_out,
                uint8_t* accept_log, double* acceptance);
 
+/* Advance every chain by n_segments * sweep_size proposals without recording
+ * samples (thermalisation; the same draws nqs_sample would have made). */
+int nqs_thermalize(nqs_ctx* ctx, int n_segments);
+
 /* Replace the context's current sample batch by n_samples configurations
  * (device int8 [n_samples][n_sites]; n_samples must equal n_chains *
  * samples_per_chain), so that estimators and the SR solve can be run on an
@@ -289,6 +293,41 @@ int nqs_vmc_step(nqs_ctx* ctx, const nqs_step_cfg* cfg, nqs_step_report* rep);
  * `status` holds its own. */
 int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs,
                    nqs_step_report* reps);
+
+/* ------------------------------------------------------------------------- */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Kernel classes timed by the event profiler. */
+enum {
+    NQS_PROF_SAMPLE = 0,    /* Metropolis sampler */
+    NQS_PROF_THETA = 1,     /* theta contraction + tanh */
+    NQS_PROF_ELOC = 2,      /* local energies */
+    NQS_PROF_STATS = 3,     /* energy statistics and centring */
+    NQS_PROF_QGT_W = 4,     /* w = J v (contraction 1) */
+    NQS_PROF_OUTER = 5,     /* J^T z (contraction 2, force and QGT product) */
+    NQS_PROF_REDUCE = 6,    /* chunk reduction + diagonal shift + p.Ap */
+    NQS_PROF_CGVEC = 7,     /* CG vector updates and dot products */
+    NQS_PROF_JACOBIAN = 8,  /* dense Jacobian build and centring */
+    NQS_PROF_GRAM = 9,      /* dense QGT Gram matrix */
+    NQS_PROF_DENSE_MV = 10, /* dense QGT product */
+    NQS_PROF_UPDATE = 11,   /* parameter update and table rebuild */
+    NQS_PROF_CLASSES = 12
+};
+
+/* Time every launch of the kernel classes selected by `class_mask` (bit k =
+ * class k) with HIP events on the context's stream; 0 switches timing off.
+ * Enabling clears earlier totals.  Up to 65536 launches are timed; later
+ * launches are counted but not timed. */
+int nqs_profile_enable(nqs_ctx* ctx, uint32_t class_mask);
+
+/* Totals since nqs_profile_enable: ms[k] summed kernel time and launches[k]
+ * launch count for k < n (n <= NQS_PROF_CLASSES); host arrays.  Synchronises
+ * the stream. */
+int nqs_profile_read(nqs_ctx* ctx, double* ms, int64_t* launches, int n);
+
+/* Name of kernel class k, or NULL. */
+const char* nqs_profile_class_name(int k);
 
 #ifdef __cplusplus
 }

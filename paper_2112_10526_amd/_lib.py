@@ -21,10 +21,13 @@ EXPORTS = [
     "nqs_set_heisenberg", "nqs_set_rbm", "nqs_num_params", "nqs_set_sampler", "nqs_set_qgt",
     "nqs_workspace_bytes", "nqs_bind_workspace", "nqs_set_params", "nqs_get_params",
     "nqs_reset_chains", "nqs_get_chains", "nqs_set_chains", "nqs_proposal_count",
-    "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_load_samples", "nqs_local_energy",
+    "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_thermalize", "nqs_load_samples", "nqs_local_energy",
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
-    "nqs_vmc_step", "nqs_batch_step",
+    "nqs_vmc_step", "nqs_batch_step", "nqs_profile_enable", "nqs_profile_read",
+    "nqs_profile_class_name",
 ]
+PROF_CLASSES = ["sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
+                "jacobian", "gram", "dense_matvec", "update"]
 
 
 class NqsStats(ctypes.Structure):
@@ -82,6 +85,7 @@ def load(path: str = LIB_PATH):
         "nqs_get_state": (I, [V, V, ctypes.POINTER(SZ)]),
         "nqs_set_state": (I, [V, V, SZ]),
         "nqs_sample": (I, [V, I, V, V, ctypes.POINTER(D)]),
+        "nqs_thermalize": (I, [V, I]),
         "nqs_load_samples": (I, [V, V, I64]),
         "nqs_local_energy": (I, [V, V, I64, V]),
         "nqs_log_psi": (I, [V, V, I64, V]),
@@ -92,6 +96,9 @@ def load(path: str = LIB_PATH):
         "nqs_vmc_step": (I, [V, ctypes.POINTER(NqsStepCfg), ctypes.POINTER(NqsStepReport)]),
         "nqs_batch_step": (I, [ctypes.POINTER(V), I, ctypes.POINTER(NqsStepCfg),
                                ctypes.POINTER(NqsStepReport)]),
+        "nqs_profile_enable": (I, [V, ctypes.c_uint32]),
+        "nqs_profile_read": (I, [V, V, V, I]),
+        "nqs_profile_class_name": (ctypes.c_char_p, [I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -17,7 +17,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Buffers {
-    double *Pm, *grad, *x, *r, *p, *Ap, *tmpv, *gacc;
+    double *Pm, *grad, *x, *r, *p, *p2, *Ap, *tmpv, *gacc;
     int32_t* bonds;
     int8_t* sub;
     Tables tab;
@@ -67,7 +67,9 @@ struct nqs_ctx {
     bool bound = false;
     Buffers b{};
     long Ns = 0, Bx = 0;
-    int ksplit = 1, ndpart = 1, Pld = 0, ntiles = 0;
+    int ksplit = 1, chunk = 256, ndpart = 1, Pld = 0, ntiles = 0;
+    size_t lds_limit = 65536;
+    long cg_iter = 0;
     // state
     bool params_set = false, chains_dirty = true, have_samples = false, have_grad = false;
     double acceptance = 0.0;
@@ -75,6 +77,12 @@ struct nqs_ctx {
     double* h_stats = nullptr;  // pinned [4]
     uint32_t* h_acc = nullptr;  // pinned [C]
     size_t h_acc_n = 0;
+    // event profiler
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    std::vector<int> ev_class;
+    size_t ev_used = 0;
+    int64_t prof_count[NQS_PROF_CLASSES] = {};
 };
 
 namespace {
@@ -83,6 +91,26 @@ int fail(nqs_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
     return code;
 }
+
+// Brackets the launches issued in its scope with a pair of HIP events when
+// the kernel class is being profiled.
+struct ProfScope {
+    nqs_ctx* c;
+    long slot = -1;
+    ProfScope(nqs_ctx* ctx, int k) : c(ctx) {
+        if (!((c->prof_mask >> k) & 1u)) return;
+        c->prof_count[k] += 1;
+        if (c->ev_used + 2 > c->ev.size()) return;
+        slot = (long)c->ev_used;
+        c->ev_used += 2;
+        c->ev_class[slot / 2] = k;
+        hipEventRecord(c->ev[slot], c->stream);
+    }
+    ~ProfScope() {
+        if (slot >= 0) hipEventRecord(c->ev[slot + 1], c->stream);
+    }
+};
+#define PROF(k) ProfScope prof_scope_(c, k)
 
 #define HIPCHK(ctx, call)                                                                  \
     do {                                                                                   \
@@ -118,6 +146,7 @@ size_t layout(nqs_ctx* c, char* base) {
     b.x = (double*)take(8 * PV);
     b.r = (double*)take(8 * PV);
     b.p = (double*)take(8 * PV);
+    b.p2 = (double*)take(8 * PV);
     b.Ap = (double*)take(8 * PV);
     b.tmpv = (double*)take(8 * PVX);
     b.gacc = (double*)take(8 * PV);
@@ -183,7 +212,8 @@ void derive(nqs_ctx* c) {
     if (c->has_sampler) {
         c->Ns = (long)c->C * c->S;
         c->Bx = c->Ns > 1024 ? c->Ns : 1024;
-        c->ksplit = outer_ksplit(c->Bx);
+        c->chunk = outer_chunk(d, c->prec, c->lds_limit);
+        c->ksplit = outer_ksplit(c->Bx, c->chunk);
         c->Pld = round_up((int)c->P, 128);
         c->ntiles = gram_tiles((int)c->P);
         long nd = (long)d.Ma * d.Na / 256 + 2;
@@ -227,7 +257,10 @@ int set_device(nqs_ctx* c) {
 // tanh(theta) of the chains' current configurations
 void refresh_chains(nqs_ctx* c) {
     if (!c->chains_dirty) return;
-    launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr, 0);
+    {
+        PROF(NQS_PROF_THETA);
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr, 0);
+    }
     c->chains_dirty = false;
 }
 
@@ -308,7 +341,10 @@ void issue_sample(nqs_ctx* c, int n_discard, uint8_t* accept_log) {
         a.record = 0;
         launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
         c->prop += (uint64_t)c->K;
+        {
+        PROF(NQS_PROF_THETA);
         launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr, 0);
+    }
     }
     launch_zero(c->stream, c->b.acc_count, 4 * (size_t)c->C);
     a.acc_count = c->b.acc_count;
@@ -321,10 +357,16 @@ void issue_sample(nqs_ctx* c, int n_discard, uint8_t* accept_log) {
         a.rec = c->b.samples + (size_t)q * c->d.N;
         a.rec_stride = (long)c->S * c->d.N;
         a.log_offset = (long)q * c->K;
-        launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
+        {
+            PROF(NQS_PROF_SAMPLE);
+            launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
+        }
         c->prop += (uint64_t)c->K;
-        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch,
-                     (char*)c->b.tsm + es * (size_t)q * c->d.Mw, (long)c->S * c->d.Mw);
+        {
+            PROF(NQS_PROF_THETA);
+            launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch,
+                         (char*)c->b.tsm + es * (size_t)q * c->d.Mw, (long)c->S * c->d.Mw);
+        }
     }
     c->have_samples = true;
     c->have_grad = false;
@@ -332,14 +374,26 @@ void issue_sample(nqs_ctx* c, int n_discard, uint8_t* accept_log) {
 
 void issue_energy_grad(nqs_ctx* c) {
     const long n = c->Ns;
-    launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), c->b.samples, c->b.tsm, n,
-                c->b.eloc);
-    launch_stats(c->stream, c->b.eloc, n, c->b.stats);
-    launch_center(c->stream, c->b.eloc, c->b.stats, 2.0 / (double)n, n, c->b.vvec);
-    launch_outer(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, n, c->b.vvec, 1, c->b.part,
-                 c->ksplit, c->b.sc);
-    launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, c->ksplit, nullptr, 0.0, c->b.grad,
-                        c->b.dpart, c->b.sc, 1);
+    {
+        PROF(NQS_PROF_ELOC);
+        launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), c->b.samples, c->b.tsm, n,
+                    c->b.eloc);
+    }
+    {
+        PROF(NQS_PROF_STATS);
+        launch_stats(c->stream, c->b.eloc, n, c->b.stats);
+        launch_center(c->stream, c->b.eloc, c->b.stats, 2.0 / (double)n, n, c->b.vvec);
+    }
+    {
+        PROF(NQS_PROF_OUTER);
+        launch_outer(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, n, c->b.vvec, 1, c->b.part,
+                     c->chunk, c->b.sc);
+    }
+    {
+        PROF(NQS_PROF_REDUCE);
+        launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, outer_ksplit(n, c->chunk),
+                            nullptr, 0.0, c->b.grad, c->b.dpart, c->b.sc, 1);
+    }
     c->have_grad = true;
 }
 
@@ -370,36 +424,68 @@ int read_acceptance(nqs_ctx* c) {
 // dense Jacobian form: build G once for this batch and set up CG in packed space
 void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
     const int P = (int)c->P;
-    launch_jacobian(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O, P, c->Pld);
-    launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum);
-    launch_gram(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.G, c->b.tiles, c->ntiles);
+    {
+        PROF(NQS_PROF_JACOBIAN);
+        launch_jacobian(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O, P,
+                        c->Pld);
+        launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum);
+    }
+    {
+        PROF(NQS_PROF_GRAM);
+        launch_gram(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.G, c->b.tiles, c->ntiles);
+    }
     launch_pack(c->stream, c->d, c->b.grad, c->b.fp, P);
     launch_cg_init(c->stream, P, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
                    maxiter);
 }
 
 void issue_cg_init(nqs_ctx* c, double tol, int maxiter) {
+    c->cg_iter = 0;
     launch_cg_init(c->stream, c->d.Ma * c->d.Na, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.dpart,
                    c->b.sc, tol, maxiter);
 }
 
+// CG iterations; the on-the-fly form alternates the direction between two
+// buffers (contraction 1 reads p_old and writes p_new = r + beta p_old).
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
     const Dims& d = c->d;
     for (int it = 0; it < iters; ++it) {
         if (kind == NQS_QGT_ONTHEFLY) {
-            launch_w(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.p, c->b.wbuf,
-                     c->b.dpart, c->b.sc);
-            launch_outer(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.wbuf, 0,
-                         c->b.part, c->ksplit, c->b.sc);
-            launch_reduce_outer(c->stream, d, c->prec, c->b.part, c->ksplit, c->b.p, shift,
-                                c->b.Ap, c->b.dpart, c->b.sc, 0);
-            launch_cg_update(c->stream, d.Ma * d.Na, c->b.x, c->b.r, c->b.p, c->b.Ap, c->b.dpart,
-                             c->b.sc);
+            double* p_old = (c->cg_iter & 1) ? c->b.p2 : c->b.p;
+            double* p_new = (c->cg_iter & 1) ? c->b.p : c->b.p2;
+            c->cg_iter += 1;
+            {
+                PROF(NQS_PROF_QGT_W);
+                launch_w(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.r, p_old,
+                         p_new, c->b.wbuf, c->b.dpart, c->b.sc, c->lds_limit);
+            }
+            {
+                PROF(NQS_PROF_OUTER);
+                launch_outer(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.wbuf, 0,
+                             c->b.part, c->chunk, c->b.sc);
+            }
+            {
+                PROF(NQS_PROF_REDUCE);
+                launch_reduce_outer(c->stream, d, c->prec, c->b.part,
+                                    outer_ksplit(c->Ns, c->chunk), p_new, shift, c->b.Ap,
+                                    c->b.dpart, c->b.sc, 0);
+            }
+            {
+                PROF(NQS_PROF_CGVEC);
+                launch_cg_update(c->stream, d.Ma * d.Na, c->b.x, c->b.r, p_new, c->b.Ap,
+                                 c->b.dpart, c->b.sc, 0);
+            }
         } else {
-            launch_dense_matvec(c->stream, c->prec, c->b.G, (int)c->P, c->Pld, c->b.pp, shift,
-                                c->b.App, c->b.dpart, c->b.sc);
-            launch_cg_update(c->stream, (int)c->P, c->b.xp, c->b.rp, c->b.pp, c->b.App, c->b.dpart,
-                             c->b.sc);
+            {
+                PROF(NQS_PROF_DENSE_MV);
+                launch_dense_matvec(c->stream, c->prec, c->b.G, (int)c->P, c->Pld, c->b.pp, shift,
+                                    c->b.App, c->b.dpart, c->b.sc);
+            }
+            {
+                PROF(NQS_PROF_CGVEC);
+                launch_cg_update(c->stream, (int)c->P, c->b.xp, c->b.rp, c->b.pp, c->b.App,
+                                 c->b.dpart, c->b.sc, 1);
+            }
         }
     }
 }
@@ -410,8 +496,11 @@ void issue_finish_solve(nqs_ctx* c, int kind) {
 }
 
 void issue_update(nqs_ctx* c, double lr) {
-    launch_axpy_update(c->stream, c->d.Ma * c->d.Na, c->b.Pm, c->b.x, lr, c->b.sc);
-    launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
+    {
+        PROF(NQS_PROF_UPDATE);
+        launch_axpy_update(c->stream, c->d.Ma * c->d.Na, c->b.Pm, c->b.x, lr, c->b.sc);
+        launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
+    }
     c->chains_dirty = true;
     c->have_grad = false;
     c->have_samples = false;  // the held batch's activations belong to the old parameters
@@ -476,6 +565,10 @@ int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
     nqs_ctx* c = new nqs_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        lds > 0)
+        c->lds_limit = (size_t)lds;
     if (hipSetDevice(device) != hipSuccess ||
         hipHostMalloc((void**)&c->h_sc, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -492,6 +585,7 @@ void nqs_destroy(nqs_ctx* c) {
     if (c->h_sc) hipHostFree(c->h_sc);
     if (c->h_stats) hipHostFree(c->h_stats);
     if (c->h_acc) hipHostFree(c->h_acc);
+    for (auto& e : c->ev) hipEventDestroy(e);
     delete c;
 }
 
@@ -746,6 +840,37 @@ int nqs_sample(nqs_ctx* c, int n_discard_segments, int8_t* samples_out, uint8_t*
     return NQS_OK;
 }
 
+int nqs_thermalize(nqs_ctx* c, int n_segments) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n_segments < 0) return fail(c, NQS_EINVAL, "negative segment count");
+    st = set_device(c);
+    if (st) return st;
+    refresh_chains(c);
+    SampleArgs a{};
+    a.C = c->C;
+    a.K = c->K;
+    a.seed = c->seed;
+    a.s = c->b.chains;
+    a.tch = c->b.tch;
+    a.n_bonds = (int)(c->bonds.size() / 2);
+    a.bonds = c->b.bonds;
+    for (int q = 0; q < n_segments; ++q) {
+        a.prop_base = c->prop;
+        {
+            PROF(NQS_PROF_SAMPLE);
+            launch_sample(c->stream, c->d, c->prec, c->rule, c->b.tab, a);
+        }
+        c->prop += (uint64_t)c->K;
+        {
+            PROF(NQS_PROF_THETA);
+            launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.chains, c->C, c->b.tch, nullptr,
+                         0);
+        }
+    }
+    return last_launch(c);
+}
+
 int nqs_load_samples(nqs_ctx* c, const int8_t* samples, int64_t n_samples) {
     int st = need_bound(c);
     if (st) return st;
@@ -796,10 +921,10 @@ int nqs_log_psi_vjp(nqs_ctx* c, const int8_t* s, int64_t n, const void* g, void*
         else
             k_f32_to_f64<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>((const float*)g + k0,
                                                                              c->b.vvec, m);
-        launch_outer(c->stream, c->d, c->prec, sk, c->b.tx, m, c->b.vvec, 1, c->b.part, c->ksplit,
+        launch_outer(c->stream, c->d, c->prec, sk, c->b.tx, m, c->b.vvec, 1, c->b.part, c->chunk,
                      c->b.sc);
-        launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, c->ksplit, nullptr, 0.0, c->b.Ap,
-                            c->b.dpart, c->b.sc, 1);
+        launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, outer_ksplit(m, c->chunk),
+                            nullptr, 0.0, c->b.Ap, c->b.dpart, c->b.sc, 1);
         launch_axpy_update(c->stream, PV, c->b.gacc, c->b.Ap, -1.0, c->b.sc);
     }
     if (c->prec == 0) {
@@ -959,6 +1084,47 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         if (st[k] && !first) first = st[k];
     }
     return first;
+}
+
+int nqs_profile_enable(nqs_ctx* c, uint32_t class_mask) {
+    if (!c) return NQS_EINVAL;
+    int st = set_device(c);
+    if (st) return st;
+    if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (class_mask && c->ev.empty()) {
+        const size_t pairs = 4096;
+        c->ev.resize(2 * pairs);
+        c->ev_class.assign(pairs, 0);
+        for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    c->prof_mask = class_mask;
+    c->ev_used = 0;
+    for (auto& k : c->prof_count) k = 0;
+    return NQS_OK;
+}
+
+int nqs_profile_read(nqs_ctx* c, double* ms, int64_t* launches, int n) {
+    if (!c) return NQS_EINVAL;
+    if (n < 0 || n > NQS_PROF_CLASSES) return fail(c, NQS_EINVAL, "bad class count");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> tot(NQS_PROF_CLASSES, 0.0);
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]));
+        tot[c->ev_class[i / 2]] += t;
+    }
+    for (int k = 0; k < n; ++k) {
+        if (ms) ms[k] = tot[k];
+        if (launches) launches[k] = c->prof_count[k];
+    }
+    return NQS_OK;
+}
+
+const char* nqs_profile_class_name(int k) {
+    static const char* names[NQS_PROF_CLASSES] = {
+        "sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
+        "jacobian", "gram", "dense_matvec", "update"};
+    return (k >= 0 && k < NQS_PROF_CLASSES) ? names[k] : nullptr;
 }
 
 }  // extern "C"

@@ -95,10 +95,13 @@ void launch_stats(hipStream_t st, const double* E, long n, double* out3);
 void launch_center(hipStream_t st, const double* E, const double* stats, double scale, long n,
                    double* v);
 void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
-              const double* V, double* w, double* wpart, CgScalars* sc);
-int outer_ksplit(long n);
+              const double* r, const double* p_old, double* p_new, double* w, double* wpart,
+              CgScalars* sc, size_t lds_limit);
+int outer_chunk(const Dims& d, int prec, size_t lds_limit);
+int outer_ksplit(long n, int chunk);
+// part: [outer_ksplit(n, chunk)][Ma][Na]
 void launch_outer(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
-                  long n, const double* v, int v_mode, void* part, int ksplit,
+                  long n, const double* v, int v_mode, void* part, int chunk,
                   const CgScalars* sc);
 void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                          const double* p, double shift, double* out, double* dpart,
@@ -106,7 +109,7 @@ void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* pa
 void launch_cg_init(hipStream_t st, int total, const double* f, double* x, double* r, double* p,
                     double* dpart, CgScalars* sc, double tol, int maxiter);
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, CgScalars* sc);
+                      const double* Ap, double* dpart, CgScalars* sc, int update_p);
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc);
 

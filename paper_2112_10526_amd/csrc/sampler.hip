@@ -59,18 +59,41 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
         // FP32 path compares logarithms; u = 0 gives -inf and always accepts
         const float lu_l = sizeof(R) == 8 ? 0.0f : logf((float)u_l);
         const int np = min(64, a.K - p0);
+        // table rows of the next proposal are loaded one proposal ahead
+        R Ta[QMAX], Tb[QMAX];
+        {
+            const int ia0 = __builtin_amdgcn_readlane(ia_l, 0);
+            const int ib0 = __builtin_amdgcn_readlane(ib_l, 0);
+#pragma unroll
+            for (int qq = 0; qq < QMAX; ++qq) {
+                Ta[qq] = qq < QM ? Tt[(size_t)ia0 * Mw + lane + 64 * qq] : (R)0;
+                Tb[qq] = (RULE == 1 && qq < QM) ? Tt[(size_t)ib0 * Mw + lane + 64 * qq] : (R)0;
+            }
+        }
         for (int q = 0; q < np; ++q) {
             const int ia = __builtin_amdgcn_readlane(ia_l, q);
             const int sa = s[ia];
+            R Tv[QMAX], Tw[QMAX];
+#pragma unroll
+            for (int qq = 0; qq < QMAX; ++qq) { Tv[qq] = Ta[qq]; Tw[qq] = Tb[qq]; }
+            if (q + 1 < np) {
+                const int ian = __builtin_amdgcn_readlane(ia_l, q + 1);
+                const int ibn = __builtin_amdgcn_readlane(ib_l, q + 1);
+#pragma unroll
+                for (int qq = 0; qq < QMAX; ++qq) {
+                    if (qq < QM) {
+                        Ta[qq] = Tt[(size_t)ian * Mw + lane + 64 * qq];
+                        if (RULE == 1) Tb[qq] = Tt[(size_t)ibn * Mw + lane + 64 * qq];
+                    }
+                }
+            }
             bool accept;
             if (RULE == 0) {
-                const R* Trow = Tt + (size_t)ia * Mw;
-                R f[QMAX], Tv[QMAX];
+                R f[QMAX];
                 R prod = (R)1;
 #pragma unroll
                 for (int qq = 0; qq < QMAX; ++qq) {
                     if (qq < QM) {
-                        Tv[qq] = Trow[lane + 64 * qq];
                         f[qq] = (R)1 - (R)sa * t[qq] * Tv[qq];
                         prod *= f[qq];
                     }
@@ -95,14 +118,12 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
                 if (sa == sb) {
                     accept = true;  // identity move, ratio 1
                 } else {
-                    const R* Ta_row = Tt + (size_t)ia * Mw;
-                    const R* Tb_row = Tt + (size_t)ib * Mw;
                     R g[QMAX], TT[QMAX], Td[QMAX];
                     R prod = (R)1;
 #pragma unroll
                     for (int qq = 0; qq < QMAX; ++qq) {
                         if (qq < QM) {
-                            const R ta = Ta_row[lane + 64 * qq], tb = Tb_row[lane + 64 * qq];
+                            const R ta = Tv[qq], tb = Tw[qq];
                             TT[qq] = (R)1 - ta * tb;
                             Td[qq] = (R)sa * (ta - tb);
                             g[qq] = TT[qq] - t[qq] * Td[qq];

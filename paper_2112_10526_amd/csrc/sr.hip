@@ -86,42 +86,112 @@ __global__ void k_center(const double* __restrict__ E, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// contraction 1: w_k = t~_k . (V s~_k), V = current CG direction [Ma][Na]
-// One block = 4 waves = 64 samples; every wave: 16 samples x all Ma rows of V,
-// 8 column tiles of 16 hidden units at a time.
+// contraction 1 with the CG direction update folded in:
+//   p_new = r + beta p_old   (beta = 0 on the first iteration)
+//   w_k   = t~_k . (P s~_k),  P = p_new as the [Ma][Na] matrix
+// One block = 4 waves = 64 samples; the block's spins are staged in LDS once,
+// P is staged 64 hidden rows at a time (converted to the MFMA type), and
+// every wave multiplies its 16 samples against the staged rows.  Block 0 also
+// writes p_new for the other kernels of the iteration.
 // ---------------------------------------------------------------------------
+// Stage rows [k0, k0 + rows) of the augmented spins (s, 1, 0 ...) into
+// LDS [rows][Na]; rows at or beyond kend are zero.  Source rows are
+// contiguous, so the copy is a flat byte stream read 16 bytes per lane.
+__device__ __forceinline__ void stage_spins(int8_t* __restrict__ Ss, const int8_t* __restrict__ s,
+                                            int N, int Na, long k0, int rows, long kend) {
+    const int tid = threadIdx.x;
+    const long nrow = max(0L, min((long)rows, kend - k0));
+    const long total = nrow * N;
+    const int8_t* src = s + k0 * N;
+    for (long base = 0; base < total; base += 256 * 16) {
+        int8_t b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const long e = base + u * 256 + tid;
+            b[u] = e < total ? src[e] : (int8_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const long e = base + u * 256 + tid;
+            if (e < total) {
+                const int rl = (int)(e / N), i = (int)(e - (long)rl * N);
+                Ss[rl * Na + i] = b[u];
+            }
+        }
+    }
+    // augmented columns and rows past the end
+    for (int e = tid; e < rows * (Na - N); e += 256) {
+        const int rl = e / (Na - N), i = N + (e - rl * (Na - N));
+        Ss[rl * Na + i] = (rl < nrow && i == N) ? (int8_t)1 : (int8_t)0;
+    }
+    for (long e = nrow * Na + tid; e < (long)rows * Na; e += 256) Ss[e] = 0;
+}
+
 template <typename R>
-__device__ __forceinline__ R spin_aug(const int8_t* __restrict__ s, int N, long k, long n, int i) {
-    if (k >= n || i > N) return (R)0;
-    return i == N ? (R)1 : (R)s[k * N + i];
+__device__ __forceinline__ int8_t spin_aug8(const int8_t* __restrict__ s, int N, long k, long n,
+                                            int i) {
+    if (k >= n || i > N) return 0;
+    return i == N ? (int8_t)1 : s[k * N + i];
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_qgt_w(Dims d, const int8_t* __restrict__ s,
                                                const R* __restrict__ tact, long n,
-                                               const double* __restrict__ V,
-                                               double* __restrict__ w, double* __restrict__ wpart,
-                                               CgScalars* sc) {
+                                               const double* __restrict__ r,
+                                               const double* __restrict__ p_old,
+                                               double* __restrict__ p_new, double* __restrict__ w,
+                                               double* __restrict__ wpart, CgScalars* sc,
+                                               int jrows) {
     if (sc->done) return;
+    extern __shared__ __align__(16) char lds_raw[];
     __shared__ double sh[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Na = d.Na, NaP = d.Na + 1;
+    R* Vs = (R*)lds_raw;                      // [jrows][NaP]
+    int8_t* Ss = (int8_t*)(Vs + jrows * NaP); // [64][Na]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const long row0 = (long)blockIdx.x * 64 + wave * 16;
+    const long rowb = (long)blockIdx.x * 64;
+    const double beta = sc->beta;
+    stage_spins(Ss, s, d.N, Na, rowb, 64, n);
     typedef typename std::conditional<sizeof(R) == 8, v4d, v4f>::type acc_t;
     R wacc[4] = {0, 0, 0, 0};
-    const int nct = d.Ma / 16;
-    for (int ct0 = 0; ct0 < nct; ct0 += 8) {
-        acc_t acc[8];
+    const int8_t* Sw = Ss + (wave * 16 + lr) * Na;
+    for (int jc = 0; jc < d.Ma; jc += jrows) {
+        __syncthreads();
+        const int rows = min(jrows, d.Ma - jc);
+        {
+            // rows jc.. of P are contiguous: batched loads, then LDS stores
+            const int total = rows * Na;
+            const size_t g0 = (size_t)jc * Na;
+            for (int base = 0; base < total; base += 256 * 8) {
+                double v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < d.Na; k0 += 4) {
-            const int i = k0 + lk;
-            const R a = spin_aug<R>(s, d.N, row0 + lr, n, i);
+                for (int u = 0; u < 8; ++u) {
+                    const int e = base + u * 256 + tid;
+                    v[u] = e < total ? r[g0 + e] + beta * p_old[g0 + e] : 0.0;
+                }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (ct0 + c < nct) {
-                    const int j = (ct0 + c) * 16 + lr;
-                    const R b = (R)V[(size_t)j * d.Na + i];
+                for (int u = 0; u < 8; ++u) {
+                    const int e = base + u * 256 + tid;
+                    if (e < total) {
+                        const int jl = e / Na, i = e - jl * Na;
+                        Vs[jl * NaP + i] = (R)v[u];
+                        if (blockIdx.x == 0) p_new[g0 + e] = v[u];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const int nct = rows / 16;
+        acc_t acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = acc_t{0, 0, 0, 0};
+        for (int k0 = 0; k0 < Na; k0 += 4) {
+            const R a = (R)Sw[k0 + lk];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c < nct) {
+                    const R b = Vs[(c * 16 + lr) * NaP + k0 + lk];
                     if constexpr (sizeof(R) == 8)
                         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
                     else
@@ -130,12 +200,12 @@ __global__ __launch_bounds__(256) void k_qgt_w(Dims d, const int8_t* __restrict_
             }
         }
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (ct0 + c < nct) {
-                const int j = (ct0 + c) * 16 + lr;
+        for (int c = 0; c < 4; ++c) {
+            if (c < nct) {
+                const int j = jc + c * 16 + lr;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const long k = row0 + acc_row<R>(lk, q);
+                    const long k = rowb + wave * 16 + acc_row<R>(lk, q);
                     const R t = k < n ? tact[k * d.Mw + j] : (R)0;
                     wacc[q] += t * acc[c][q];
                 }
@@ -146,17 +216,18 @@ __global__ __launch_bounds__(256) void k_qgt_w(Dims d, const int8_t* __restrict_
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const double v = row16_sum((double)wacc[q]);
-        const long k = row0 + acc_row<R>(lk, q);
-        if (lr == 0 && k < n) w[k] = v;
-        if (lr == 0 && k < n) wsum += v;
+        const long k = rowb + wave * 16 + acc_row<R>(lk, q);
+        if (lr == 0 && k < n) {
+            w[k] = v;
+            wsum += v;
+        }
     }
-    // block partial of sum_k w_k (lanes 0, 16, 32, 48 carry the row sums);
-    // the last block turns the partials into mean(w)
+    // block partial of sum_k w_k; the last block turns the partials into mean(w)
     wsum = block_sum<256>(wsum, sh);
-    if (threadIdx.x == 0) wpart[blockIdx.x] = wsum;
+    if (tid == 0) wpart[blockIdx.x] = wsum;
     if (arrive_last(&sc->counter[4])) {
         const double tot = final_sum(wpart, gridDim.x, sh);
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             sc->wmean = tot / (double)n;
             sc->counter[4] = 0;
         }
@@ -166,44 +237,72 @@ __global__ __launch_bounds__(256) void k_qgt_w(Dims d, const int8_t* __restrict_
 // ---------------------------------------------------------------------------
 // contraction 2: part[kc][j][i] = sum_{k in chunk kc} t~_kj z_k s~_ki
 // z_k = (w_k - mean w) / n (v_mode 0, QGT product) or z_k = v_k (v_mode 1).
-// grid = (ceil(Ma / 64), ksplit); each wave owns one 16-row tile of hidden
-// units and walks the Na site columns 8 tiles at a time.
+// grid = (ceil(Ma / (16 JG)), ksplit).  The block stages t~ z for its chunk
+// of samples and JG hidden tiles, and the chunk's spins, in LDS; wave w owns
+// hidden tile w % JG and every (4/JG)-th site tile starting at w / JG.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int JG>
 __global__ __launch_bounds__(256) void k_outer(Dims d, const int8_t* __restrict__ s,
                                                const R* __restrict__ tact, long n,
                                                const double* __restrict__ v, int v_mode,
-                                               R* __restrict__ part, long chunk,
+                                               R* __restrict__ part, int chunk,
                                                const CgScalars* __restrict__ sc) {
     if (v_mode == 0 && sc->done) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    extern __shared__ __align__(16) char lds_raw[];
+    constexpr int JW = 16 * JG;  // hidden rows staged
+    constexpr int IG = 4 / JG;   // site-tile groups
+    const int Na = d.Na;
+    const int KC = (chunk + 3) / 4 * 4;
+    R* Ts = (R*)lds_raw;                     // [KC][JW]
+    int8_t* Ss = (int8_t*)(Ts + KC * JW);    // [KC][Na]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int jt = blockIdx.x * 4 + wave;  // hidden-unit tile
-    if (jt * 16 >= d.Ma) return;
     double shift = 0.0, scale = 1.0;
     if (v_mode == 0) {
         shift = sc->wmean;
         scale = 1.0 / (double)n;
     }
     const long kbeg = (long)blockIdx.y * chunk;
-    const long kend = min(n, kbeg + chunk);
-    const int j = jt * 16 + lr;
+    const int kn = (int)max(0L, min((long)chunk, n - kbeg));
+    const int j0 = blockIdx.x * JW;
+    R* zs = (R*)(Ss + KC * Na + 16 - ((KC * Na) & 15));  // [KC] scaled z, 16-byte aligned
+    for (int kl = tid; kl < KC; kl += 256)
+        zs[kl] = kl < kn ? (R)((v[kbeg + kl] - shift) * scale) : (R)0;
+    stage_spins(Ss, s, d.N, Na, kbeg, KC, kbeg + kn);
+    __syncthreads();
+    for (int base = 0; base < KC * JW; base += 256 * 8) {
+        R t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + u * 256 + tid;
+            const int kl = e / JW, j = j0 + (e - kl * JW);
+            t[u] = (kl < kn && j < d.Ma) ? tact[(kbeg + kl) * d.Mw + j] : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + u * 256 + tid;
+            if (e < KC * JW) Ts[e] = t[u] * zs[e / JW];
+        }
+    }
+    __syncthreads();
+    const int jt = blockIdx.x * JG + wave % JG;
+    if (jt * 16 >= d.Ma) return;
+    const int nct = Na / 16;
     typedef typename std::conditional<sizeof(R) == 8, v4d, v4f>::type acc_t;
-    const int nct = d.Na / 16;
-    R* out = part + (size_t)blockIdx.y * d.Ma * d.Na;
-    for (int ct0 = 0; ct0 < nct; ct0 += 8) {
+    R* out = part + (size_t)blockIdx.y * d.Ma * Na;
+    const R* Tw = Ts + (wave % JG) * 16 + lr;
+    for (int ct0 = wave / JG; ct0 < nct; ct0 += IG * 8) {
         acc_t acc[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[c] = acc_t{0, 0, 0, 0};
-        for (long k0 = kbeg; k0 < kend; k0 += 4) {
-            const long k = k0 + lk;
-            R a = (R)0;
-            if (k < kend) a = tact[k * d.Mw + j] * (R)((v[k] - shift) * scale);
+        for (int k0 = 0; k0 < KC; k0 += 4) {
+            const R a = Tw[(k0 + lk) * JW];
+            const int8_t* Sk = Ss + (k0 + lk) * Na + lr;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                if (ct0 + c < nct) {
-                    const int i = (ct0 + c) * 16 + lr;
-                    const R b = k < kend ? spin_aug<R>(s, d.N, k, n, i) : (R)0;
+                const int ct = ct0 + c * IG;
+                if (ct < nct) {
+                    const R b = (R)Sk[ct * 16];
                     if constexpr (sizeof(R) == 8)
                         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
                     else
@@ -213,12 +312,13 @@ __global__ __launch_bounds__(256) void k_outer(Dims d, const int8_t* __restrict_
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            if (ct0 + c < nct) {
-                const int i = (ct0 + c) * 16 + lr;
+            const int ct = ct0 + c * IG;
+            if (ct < nct) {
+                const int i = ct * 16 + lr;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jj = jt * 16 + acc_row<R>(lk, q);
-                    out[(size_t)jj * d.Na + i] = acc[c][q];
+                    out[(size_t)jj * Na + i] = acc[c][q];
                 }
             }
         }
@@ -243,7 +343,15 @@ __global__ __launch_bounds__(256) void k_reduce_outer(Dims d, const R* __restric
         const bool keep = (j < d.M && i < d.N) || (d.hb && j < d.M && i == d.N) ||
                           (d.vb && j == d.M && i < d.N);
         if (keep) {
-            for (int kc = 0; kc < ksplit; ++kc) val += (double)part[(size_t)kc * total + e];
+            int kc = 0;
+            for (; kc + 8 <= ksplit; kc += 8) {
+                R x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = part[(size_t)(kc + u) * total + e];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) val += (double)x[u];
+            }
+            for (; kc < ksplit; ++kc) val += (double)part[(size_t)kc * total + e];
             if (p) val += shift * p[e];
         }
         out[e] = val;
@@ -325,6 +433,7 @@ __global__ __launch_bounds__(256) void k_cg_init(int total, const double* __rest
         if (threadIdx.x == 0) {
             sc->rr = s;
             sc->rr0 = s;
+            sc->beta = 0.0;
             sc->tol2 = tol * tol * s;
             sc->iters = 0;
             sc->maxiter = maxiter;
@@ -357,33 +466,68 @@ void launch_center(hipStream_t st, const double* E, const double* stats, double 
                    double* v) {
     k_center<<<nblk(n, 256), 256, 0, st>>>(E, stats, scale, n, v);
 }
-void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
-              const double* V, double* w, double* wpart, CgScalars* sc) {
-    const int nb = nblk(n, 64);
-    if (prec == 0)
-        k_qgt_w<double><<<nb, 256, 0, st>>>(d, s, (const double*)tact, n, V, w, wpart, sc);
-    else
-        k_qgt_w<float><<<nb, 256, 0, st>>>(d, s, (const float*)tact, n, V, w, wpart, sc);
+// rows of P staged per pass by contraction 1, within the LDS limit
+static int w_jrows(const Dims& d, int prec, size_t lds_limit) {
+    const size_t es = prec == 0 ? 8 : 4;
+    for (int jr = 64; jr >= 16; jr /= 2)
+        if (es * jr * (size_t)(d.Na + 1) + 64 * (size_t)d.Na <= lds_limit) return jr;
+    return 16;
 }
-int outer_ksplit(long n) {
-    // about 256 samples per chunk, at most 64 chunks
-    long ks = (n + 255) / 256;
-    if (ks > 64) ks = 64;
-    if (ks < 1) ks = 1;
-    return (int)ks;
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
+              const double* r, const double* p_old, double* p_new, double* w, double* wpart,
+              CgScalars* sc, size_t lds_limit) {
+    const int nb = nblk(n, 64);
+    const size_t es = prec == 0 ? 8 : 4;
+    const int jr = w_jrows(d, prec, lds_limit);
+    const size_t lds = es * jr * (size_t)(d.Na + 1) + 64 * (size_t)d.Na;
+    if (prec == 0) {
+        allow_lds(k_qgt_w<double>, lds);
+        k_qgt_w<double><<<nb, 256, lds, st>>>(d, s, (const double*)tact, n, r, p_old, p_new, w,
+                                              wpart, sc, jr);
+    } else {
+        allow_lds(k_qgt_w<float>, lds);
+        k_qgt_w<float><<<nb, 256, lds, st>>>(d, s, (const float*)tact, n, r, p_old, p_new, w,
+                                             wpart, sc, jr);
+    }
+}
+size_t outer_lds_bytes(const Dims& d, int prec, int chunk) {
+    const int KC = (chunk + 3) / 4 * 4;
+    const int JW = prec == 0 ? 32 : 64;
+    const size_t es = prec == 0 ? 8 : 4;
+    return (size_t)KC * JW * es + (size_t)KC * d.Na + 16 + (size_t)KC * es;
+}
+// Samples per chunk of contraction 2: up to 256, within the LDS limit.
+int outer_chunk(const Dims& d, int prec, size_t lds_limit) {
+    int c = 256;
+    while (c > 16 && outer_lds_bytes(d, prec, c) > lds_limit) c -= 16;
+    return c;
+}
+int outer_ksplit(long n, int chunk) {
+    long ks = (n + chunk - 1) / chunk;
+    return ks < 1 ? 1 : (int)ks;
 }
 void launch_outer(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
-                  long n, const double* v, int v_mode, void* part, int ksplit,
+                  long n, const double* v, int v_mode, void* part, int chunk,
                   const CgScalars* sc) {
-    long chunk = (n + ksplit - 1) / ksplit;
-    chunk = (chunk + 3) / 4 * 4;
-    const dim3 grid(nblk(d.Ma, 64), ksplit);
-    if (prec == 0)
-        k_outer<double><<<grid, 256, 0, st>>>(d, s, (const double*)tact, n, v, v_mode,
-                                              (double*)part, chunk, sc);
-    else
-        k_outer<float><<<grid, 256, 0, st>>>(d, s, (const float*)tact, n, v, v_mode,
-                                             (float*)part, chunk, sc);
+    const int ksplit = outer_ksplit(n, chunk);
+    const size_t lds = outer_lds_bytes(d, prec, chunk);
+    if (prec == 0) {
+        const dim3 grid(nblk(d.Ma, 32), ksplit);
+        allow_lds(k_outer<double, 2>, lds);
+        k_outer<double, 2><<<grid, 256, lds, st>>>(d, s, (const double*)tact, n, v, v_mode,
+                                                   (double*)part, chunk, sc);
+    } else {
+        const dim3 grid(nblk(d.Ma, 64), ksplit);
+        allow_lds(k_outer<float, 4>, lds);
+        k_outer<float, 4><<<grid, 256, lds, st>>>(d, s, (const float*)tact, n, v, v_mode,
+                                                  (float*)part, chunk, sc);
+    }
 }
 void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                          const double* p, double shift, double* out, double* dpart,
@@ -401,9 +545,9 @@ void launch_cg_init(hipStream_t st, int total, const double* f, double* x, doubl
     k_cg_init<<<nblk(total, 256), 256, 0, st>>>(total, f, x, r, p, dpart, sc, tol, maxiter);
 }
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, CgScalars* sc) {
+                      const double* Ap, double* dpart, CgScalars* sc, int update_p) {
     k_cg_update<<<nblk(total, 256), 256, 0, st>>>(total, x, r, p, Ap, dpart, sc);
-    k_cg_p<<<nblk(total, 256), 256, 0, st>>>(total, r, p, sc);
+    if (update_p) k_cg_p<<<nblk(total, 256), 256, 0, st>>>(total, r, p, sc);
 }
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc) {

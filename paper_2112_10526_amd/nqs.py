@@ -47,7 +47,7 @@ class VMCState:
                  hidden_bias: bool = True, precision: str = "fp64", rule: str = "local",
                  n_chains: int, samples_per_chain: int, sweep_size: int, seed: int,
                  total_sz_zero: bool = False, qgt: str = "onthefly", device: int = 0,
-                 stream: Optional[torch.cuda.Stream] = None, params=None):
+                 stream: Optional[torch.cuda.Stream] = None, params=None, allocate: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("libnqs needs a HIP device; none is visible")
         self.lib = _lib.load()
@@ -82,17 +82,30 @@ class VMCState:
         self._check(self.lib.nqs_set_qgt(self.ctx, _lib.QGTS[qgt]))
         self.n_params = int(self.lib.nqs_num_params(self.ctx))
         self.workspace_bytes = int(self.lib.nqs_workspace_bytes(self.ctx))
-        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.workspace = None
+        self._pending_params = params
+        if allocate:
+            self.bind()
+
+    def bind(self):
+        """Allocate the workspace (the context's whole HBM footprint) and bind it."""
+        if self.workspace is not None:
+            return
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                         device=self.device)
         base = self.workspace.data_ptr()
         off = (-base) % 256
         self._check(self.lib.nqs_bind_workspace(self.ctx, ctypes.c_void_p(base + off),
                                                 self.workspace_bytes))
-        if params is not None:
-            self.set_params(params)
+        if self._pending_params is not None:
+            self.set_params(self._pending_params)
+            self._pending_params = None
 
     @classmethod
     def from_workload(cls, w, precision: Optional[str] = None, qgt: str = "onthefly",
-                      device: int = 0, stream=None, params=None, n_chains: Optional[int] = None):
+                      device: int = 0, stream=None, params=None, n_chains: Optional[int] = None,
+                      allocate: bool = True):
         """Build the state of a ``synth.Workload`` (initial parameters included)."""
         return cls(model=w.model, n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
                    sublattice=w.sublattice(), n_hidden=w.n_hidden,
@@ -100,7 +113,7 @@ class VMCState:
                    n_chains=n_chains or w.n_chains, samples_per_chain=w.samples_per_chain,
                    sweep_size=w.sweep_size, seed=w.chain_seed, total_sz_zero=w.total_sz_zero,
                    qgt=qgt, device=device, stream=stream,
-                   params=w.params() if params is None else params)
+                   params=w.params() if params is None else params, allocate=allocate)
 
     # ------------------------------------------------------------------
     def _check(self, st: int):
@@ -109,9 +122,11 @@ class VMCState:
             raise NqsError(st, msg)
 
     def close(self):
+        """Destroy the context and release its workspace."""
         if getattr(self, "ctx", None):
             self.lib.nqs_destroy(self.ctx)
             self.ctx = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -184,8 +199,8 @@ class VMCState:
         return smp, acc, a.value
 
     def thermalize(self, n_segments: int):
-        a = ctypes.c_double(0.0)
-        self._check(self.lib.nqs_sample(self.ctx, n_segments, None, None, ctypes.byref(a)))
+        """Advance the chains by n_segments * sweep_size unrecorded proposals."""
+        self._check(self.lib.nqs_thermalize(self.ctx, n_segments))
 
     def load_samples(self, s: torch.Tensor):
         s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
@@ -244,6 +259,27 @@ class VMCState:
         return StepReport(_stats_dict(rep.energy),
                           SrInfo(rep.sr.iterations, bool(rep.sr.converged), rep.sr.rel_residual),
                           rep.status)
+
+
+def _profile_enable(self, classes=None):
+    """Time kernel classes with HIP events (None = all)."""
+    mask = 0
+    for k, name in enumerate(_lib.PROF_CLASSES):
+        if classes is None or name in classes:
+            mask |= 1 << k
+    self._check(self.lib.nqs_profile_enable(self.ctx, mask))
+
+
+def _profile_read(self) -> dict:
+    n = len(_lib.PROF_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    self._check(self.lib.nqs_profile_read(self.ctx, ms, cnt, n))
+    return {name: dict(ms=ms[k], launches=cnt[k]) for k, name in enumerate(_lib.PROF_CLASSES)}
+
+
+VMCState.profile_enable = _profile_enable
+VMCState.profile_read = _profile_read
 
 
 def batch_step(states: Sequence[VMCState], cfgs: Sequence[dict]) -> list:

@@ -1,0 +1,182 @@
+"""GPU tests of the three additional forms and of the headline workload at full
+size: differentiation (autograd function over the hand-written vJp kernel,
+dense Jacobian QGT at the N=64 chain size), serving (each run's result is the
+same alone and in the mix), and the 10x10 TFIM step in the benchmark's launch
+configuration checked against the oracle on sampled chains and by properties."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible HIP device")
+    return torch
+
+
+def _state(w, **kw):
+    from paper_2112_10526_amd.nqs import VMCState
+    print(f"[case] {w.name} {kw}", flush=True)
+    return VMCState.from_workload(w, **kw)
+
+
+# ----------------------------------------------------------------------------
+# differentiation form
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+def test_autograd_log_psi_matches_oracle(precision, tol):
+    torch = _torch()
+    from paper_2112_10526_amd.autograd import log_psi
+    w = synth.WORKLOADS["heis1d_n64"].replace(sigma=0.05)
+    st = _state(w, precision=precision, n_chains=64)
+    s = torch.from_numpy(synth.sz0_configs(2048, w.n_sites, 9)).cuda()
+    p = torch.tensor(w.params(), device="cuda", requires_grad=True)
+    wts = torch.from_numpy(np.random.default_rng(1).normal(size=2048)).cuda()
+    y = log_psi(p, s, st)
+    (y.double() * wts).sum().backward()
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ref = core.jacobian(rbm, s.cpu().numpy()).T @ wts.cpu().numpy()
+    g = p.grad.cpu().numpy()
+    assert np.abs(g - ref).max() <= tol * np.abs(ref).max()
+    yo = core.log_psi(rbm, s.cpu().numpy())
+    assert np.abs(y.detach().double().cpu().numpy() - yo).max() <= (1e-12 if precision == "fp64" else 2e-5) * np.abs(yo).max()
+
+
+def test_autograd_finite_differences_fp64():
+    torch = _torch()
+    from paper_2112_10526_amd.autograd import log_psi
+    w = synth.WORKLOADS["heis1d_n64"].replace(sigma=0.1, L=16, alpha=2)
+    st = _state(w, precision="fp64", n_chains=16)
+    s = torch.from_numpy(synth.sz0_configs(64, w.n_sites, 2)).cuda()
+    p0 = torch.tensor(w.params(), device="cuda")
+    p = p0.clone().requires_grad_(True)
+    log_psi(p, s, st).sum().backward()
+    g = p.grad.cpu().numpy()
+    rng = np.random.default_rng(3)
+    h = 1e-5
+    for k in rng.choice(p0.numel(), 12, replace=False):
+        e = torch.zeros_like(p0)
+        e[k] = h
+        fp = log_psi(p0 + e, s, st).sum().item()
+        fm = log_psi(p0 - e, s, st).sum().item()
+        assert abs((fp - fm) / (2 * h) - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
+
+
+def test_dense_qgt_full_size_fp32():
+    """N = 64 chain, alpha = 8 (33,344 parameters), 16,384 samples: dense
+    Jacobian (2.2 GB) + MFMA Gram (4.4 GB) + CG against the on-the-fly solve."""
+    torch = _torch()
+    w = synth.WORKLOADS["heis1d_n64"]
+    s = torch.from_numpy(synth.sz0_configs(w.n_samples, w.n_sites, 12))
+    out = {}
+    for qgt in ("onthefly", "jacobian_dense"):
+        st = _state(w, precision="fp32", qgt=qgt)
+        st.load_samples(s)
+        st.expect_and_grad()
+        d, info = st.sr_update(qgt=qgt, diag_shift=0.01, lr=0.0, tol=1e-6, maxiter=3000)
+        assert info.converged, (qgt, info)
+        out[qgt] = d.cpu().numpy()
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+    a, b = out["onthefly"], out["jacobian_dense"]
+    assert np.abs(a - b).max() <= 2e-3 * np.abs(a).max()
+
+
+# ----------------------------------------------------------------------------
+# serving form
+# ----------------------------------------------------------------------------
+def _serve(reqs, budget, slots=16, precision="bf16"):
+    from paper_2112_10526_amd.serving import Server
+    srv = Server(budget, max_slots=slots, n_streams=4, precision=precision,
+                 thermalize_segments=5, keep_params=True)
+    return srv.serve(reqs, realtime=False)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp64"])
+def test_serving_result_same_alone_and_in_mix(precision):
+    _torch()
+    from paper_2112_10526_amd.serving import Request
+    reqs = [Request(0, 0.0, 4, 0.8, 1, 1024, 4, 11, 21), Request(1, 0.0, 6, 3.0, 2, 2048, 3, 12, 22),
+            Request(2, 0.0, 5, 1.7, 4, 1024, 5, 13, 23), Request(3, 0.0, 7, 2.5, 1, 4096, 2, 14, 24)]
+    alone = {}
+    for r in reqs:
+        out = _serve([r], 1 << 34, precision=precision)
+        alone[r.id] = out["results"][r.id]
+    mix = _serve(reqs, 1 << 34, precision=precision)["results"]
+    tight = _serve(reqs, max(x.footprint for x in alone.values()) + 1, precision=precision)
+    for r in reqs:
+        a = alone[r.id]
+        for other in (mix[r.id], tight["results"][r.id]):
+            assert other.energies == a.energies, r.id
+            np.testing.assert_array_equal(other.params, a.params)
+    assert tight["peak_hbm_bytes"] <= max(x.footprint for x in alone.values()) + 1
+
+
+def test_serving_poisson_stream_smoke():
+    _torch()
+    from paper_2112_10526_amd.serving import requests_from_stream
+    reqs = requests_from_stream(8, seed=5, rate=200.0, n_steps=3, L_range=(4, 8),
+                                samples=(1024, 2048))
+    out = _serve(reqs, 2 << 30)
+    assert out["sr_steps"] == 24
+    assert out["p99_step_ms"] >= out["p50_step_ms"] > 0
+    for r in out["results"].values():
+        assert np.all(np.isfinite(r.energies)) and len(r.energies) == 3
+
+
+# ----------------------------------------------------------------------------
+# headline workload, full size, benchmark launch configuration
+# ----------------------------------------------------------------------------
+def test_tfim2d_full_size_step_fp64():
+    torch = _torch()
+    w = synth.WORKLOADS["tfim2d_l10"]
+    st = _state(w, precision="fp64")
+    ch0 = st.get_chains()
+    smp, acc, a = st.sample(log_accepts=True)
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
+    # sampled chains, bit-exact (chain ids 0..31 and 4064..4095)
+    for c0 in (0, 4064):
+        ref = core.sample(rbm, ch0[c0:c0 + 32], w.samples_per_chain, w.sweep_size, w.chain_seed,
+                          0, chain_offset=c0, mode="cached", log_accepts=True)
+        assert ref.margins.min() > 1e-12
+        np.testing.assert_array_equal(acc[c0:c0 + 32].cpu().numpy(), ref.accepts)
+        np.testing.assert_array_equal(smp[c0:c0 + 32].cpu().numpy(), ref.samples)
+    flat = smp.reshape(-1, w.n_sites).cpu().numpy()
+    # energies and gradient of the whole batch
+    stats, g = st.expect_and_grad()
+    E = core.local_energy(rbm, ham, flat)
+    assert abs(stats["mean"] - E.mean()) <= 1e-10 * abs(E.mean())
+    idx = np.random.default_rng(0).choice(flat.shape[0], 256, replace=False)
+    e_gpu = st.local_energy(torch.from_numpy(flat[idx])).cpu().numpy()
+    assert np.abs(e_gpu - E[idx]).max() <= 1e-10 * np.abs(E[idx]).max()
+    # the SR direction solves the oracle's system to the CG tolerance
+    d, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=1e-6)
+    assert info.converged
+    O = core.jacobian(rbm, flat)
+    f = core.force(O, E)
+    assert np.abs(g.cpu().numpy() - f).max() <= 1e-10 * np.abs(f).max()
+    dd = d.cpu().numpy()
+    res = core.qgt_matvec(O, dd, 0.01) - f
+    assert np.linalg.norm(res) <= 2e-6 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_tfim2d_full_size_reduced_precision_energy(precision):
+    """The BF16/FP32 forms on the identical full batch: energies within 1e-4."""
+    torch = _torch()
+    w = synth.WORKLOADS["tfim2d_l10"].replace(sigma=0.05)
+    s = synth.random_configs(w.n_samples, w.n_sites, 99)
+    st = _state(w, precision=precision)
+    e = st.local_energy(torch.from_numpy(s)).cpu().numpy()
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
+    idx = np.random.default_rng(1).choice(w.n_samples, 512, replace=False)
+    ref = core.local_energy(rbm, ham, s[idx])
+    assert (np.abs(e[idx] - ref) / np.abs(ref)).max() <= 1e-4

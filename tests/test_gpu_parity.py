@@ -263,6 +263,8 @@ def test_cg_maxiter_reports_notconv():
         st.sr_update(tol=1e-12, maxiter=1)
     assert e.value.status == 5
     # allowed explicitly: the step is still applied and reported
+    st.load_samples(torch.from_numpy(_batch(w, 41)))
+    st.expect_and_grad()
     _, info = st.sr_update(tol=1e-12, maxiter=1, allow_notconv=True)
     assert info.iterations == 1 and not info.converged
 
