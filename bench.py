@@ -57,6 +57,129 @@ def kernel_work(cls: str, w, precision: str):
     return "hbm", float("nan"), "GB/s", PEAK["hbm"]
 
 
+# kernel class -> (source file of its kernel, symbol prefix in profiles)
+KERNELS = {
+    "qgt_w": ("qgt.hip", "k_w3"), "outer": ("qgt.hip", "k_outer3"),
+    "reduce": ("qgt.hip", "k_reduce2"), "cgvec": ("qgt.hip", "k_update2"),
+    "sample": ("sampler.hip", "k_sample"), "eloc": ("eloc.hip", "k_eloc"),
+    "theta": ("theta.hip", "k_theta"),
+}
+CSRC = os.path.join(ROOT, "paper_2112_10526_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest(cls: str) -> str:
+    """Digest of the sources a kernel class is built from (its file + shared headers)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "kernels.h", KERNELS.get(cls, ("qgt.hip",))[0]):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(cls: str, precision: str) -> str:
+    return os.path.join(PROFILES, f"traffic_{KERNELS.get(cls, (None, cls))[1]}_tfim2d_l10_{precision}.md")
+
+
+def read_traffic(cls: str, precision: str):
+    """HBM bytes per launch from the committed counter summary, or None when it is
+    missing or was taken on other kernel sources."""
+    path = traffic_file(cls, precision)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("source_digest") != source_digest(cls):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _per_dispatch(rows, counter, match):
+    """Mean over dispatches of kernels whose name contains `match` of the counter (summed
+    over its instances within one dispatch)."""
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if not per:
+        names = sorted({r.get("Kernel_Name", "")[:80] for r in rows})
+        raise SystemExit(f"no {counter} rows for a kernel matching {match!r}; kernels: {names}")
+    return float(np.mean(list(per.values()))), len(per)
+
+
+def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
+    """Write the traffic summary of one kernel class from two counter runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch), each scaled by the same counter on a plain copy of
+    copy_mib MiB (torch's elementwise multiply by 1: one read, one write)."""
+    sym = KERNELS[cls][1]
+    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    copy_bytes = copy_mib * 2.0 ** 20
+    cf, _ = _per_dispatch(fr, "FETCH_SIZE", "MulFunctor")
+    cw, _ = _per_dispatch(wr, "WRITE_SIZE", "MulFunctor")
+    kf, nf = _per_dispatch(fr, "FETCH_SIZE", sym)
+    kw, nw = _per_dispatch(wr, "WRITE_SIZE", sym)
+    f_scale, w_scale = copy_bytes / cf, copy_bytes / cw
+    fetch_b, write_b = kf * f_scale, kw * w_scale
+    lines = [
+        f"# HBM traffic of `{sym}` (10x10 TFIM workload, {precision})", "",
+        "Two rocprofv3 counter runs of the same command, one counter each:", "",
+        f"    {cmds[0]}", f"    {cmds[1]}", "",
+        f"Counters are KiB per dispatch; each is scaled by what it reads for a plain copy of "
+        f"{copy_mib} MiB (torch elementwise multiply by 1, one read and one write) run in the "
+        f"same process.", "",
+        f"- kernel_class: {cls}",
+        f"- source_digest: `{source_digest(cls)}`",
+        f"- copy_fetch_kib: {cf:.1f}", f"- copy_write_kib: {cw:.1f}",
+        f"- fetch_scale: {f_scale:.4f}", f"- write_scale: {w_scale:.4f}",
+        f"- dispatches: {nf} (fetch run), {nw} (write run)",
+        f"- fetch_kib_per_launch: {kf:.1f}", f"- write_kib_per_launch: {kw:.1f}",
+        f"- fetch_bytes_per_launch: {fetch_b:.0f}", f"- write_bytes_per_launch: {write_b:.0f}",
+        f"- hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
+    ]
+    path = traffic_file(cls, precision)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+
+
+def summarize_stats(stats_csv, cmd, title):
+    """Markdown table of a rocprofv3 kernel_stats.csv."""
+    import csv
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    out = [f"# {title}", "", "Command:", "", f"    {cmd}", "",
+           "| kernel | calls | avg us | min us | max us | total ms | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    print("\n".join(out))
+
+
 def make(w, precision):
     from paper_2112_10526_amd.nqs import VMCState
     st = VMCState.from_workload(w, precision=precision)
@@ -146,7 +269,21 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp64", help="second precision to time ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
+                    help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-traffic", nargs=6,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CLASS", "COPY_MIB", "FETCH_CMD", "WRITE_CMD"),
+                    help="write profiles/traffic_*.md from two counter runs and exit")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
+    if args.summarize_traffic:
+        fd, wd, cls, mib, c1, c2 = args.summarize_traffic
+        summarize_traffic(fd, wd, cls, args.precision, int(mib), (c1, c2))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
               "no multi-GPU path", file=sys.stderr)
@@ -156,6 +293,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     w = synth.WORKLOADS["tfim2d_l10"]
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * 2 ** 20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # one read + one write of the buffer
+        torch.cuda.synchronize()
+        del src, dst
     main_run = run_precision(w, args.precision, args.steps, args.warmup, torch)
     print(f"[bench] {args.precision}: {main_run['value']:.4g} local energies/s", file=sys.stderr,
           flush=True)
@@ -171,7 +316,8 @@ def main():
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     roofline = dict(bound=bound, kernel=dom["kernel_class"], achieved=achieved / scale,
                     peak=peak / scale, unit=unit, frac=achieved / peak,
-                    avg_launch_us=avg_s * 1e6, work_per_launch=work, traffic=None)
+                    avg_launch_us=avg_s * 1e6, work_per_launch=work,
+                    traffic=read_traffic(dom["kernel_class"], args.precision))
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = dict(
         metric=METRIC, value=main_run["value"], unit="local energies/s", n_gpus=1,

@@ -312,7 +312,8 @@ enum {
     NQS_PROF_GRAM = 9,      /* dense QGT Gram matrix */
     NQS_PROF_DENSE_MV = 10, /* dense QGT product */
     NQS_PROF_UPDATE = 11,   /* parameter update and table rebuild */
-    NQS_PROF_CLASSES = 12
+    NQS_PROF_PREPARE = 12,  /* per-step layout of the batch for the contractions */
+    NQS_PROF_CLASSES = 13
 };
 
 /* Time every launch of the kernel classes selected by `class_mask` (bit k =

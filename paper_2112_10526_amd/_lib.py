@@ -27,7 +27,7 @@ EXPORTS = [
     "nqs_profile_class_name",
 ]
 PROF_CLASSES = ["sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
-                "jacobian", "gram", "dense_matvec", "update"]
+                "jacobian", "gram", "dense_matvec", "update", "prepare"]
 
 
 class NqsStats(ctypes.Structure):

@@ -27,6 +27,9 @@ struct Buffers {
     void* tsm;
     void* tx;
     double *eloc, *vvec, *wbuf, *stats, *dpart;
+    QgtBatch q;
+    double *rrp, *pap;
+    void* Pop;
     uint32_t* acc_count;
     CgScalars* sc;
     void* part;
@@ -70,6 +73,8 @@ struct nqs_ctx {
     int ksplit = 1, chunk = 256, ndpart = 1, Pld = 0, ntiles = 0;
     size_t lds_limit = 65536;
     long cg_iter = 0;
+    double cg_tol = 1e-6;
+    int cg_maxiter = 0;
     // state
     bool params_set = false, chains_dirty = true, have_samples = false, have_grad = false;
     double acceptance = 0.0;
@@ -174,7 +179,19 @@ size_t layout(nqs_ctx* c, char* base) {
     b.dpart = (double*)take(8 * (size_t)c->ndpart);
     b.acc_count = (uint32_t*)take(4 * (size_t)c->C);
     b.sc = (CgScalars*)take(sizeof(CgScalars));
-    b.part = take(es * (size_t)c->ksplit * PV);
+    {
+        const long Nsp = qgt_padded_samples(c->Ns);
+        b.q.Nsp = Nsp;
+        b.q.Sp = (int8_t*)take((size_t)Nsp * d.Kb);
+        b.q.St = (int8_t*)take((size_t)Nsp * d.Kb);
+        b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
+        b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp));
+        b.rrp = (double*)take(16 * (size_t)qgt_nbu(d));
+        b.pap = (double*)take(8 * (size_t)qgt_nbu(d));
+        b.Pop = take(qgt_pop_bytes(d, c->prec));
+        const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
+        b.part = take(es * ks * PV);
+    }
     if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
         b.O = take(es * (size_t)c->Ns * c->Pld);
         b.G = take(es * (size_t)c->P * c->Pld);
@@ -201,8 +218,11 @@ void derive(nqs_ctx* c) {
     d.M = c->M;
     d.Na = round_up(c->N + 1, 16);
     d.Ma = round_up(c->M + 1, 16);
-    const int m64 = round_up(c->M, 64);
-    d.Mw = d.Ma > m64 ? d.Ma : m64;
+    // the sampler keeps 64 * QMAX activations per chain (QMAX = QM rounded up
+    // to a power of two); rows are padded that far with zero table entries
+    int qmax = 1;
+    while (qmax < (c->M + 63) / 64) qmax *= 2;
+    d.Mw = d.Ma > 64 * qmax ? d.Ma : 64 * qmax;
     d.Nw = round_up(c->N, 64);
     d.Kb = round_up(d.Na, 32);
     d.QM = (c->M + 63) / 64;
@@ -377,7 +397,7 @@ void issue_energy_grad(nqs_ctx* c) {
     {
         PROF(NQS_PROF_ELOC);
         launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), c->b.samples, c->b.tsm, n,
-                    c->b.eloc);
+                    c->b.eloc, c->lds_limit);
     }
     {
         PROF(NQS_PROF_STATS);
@@ -385,14 +405,17 @@ void issue_energy_grad(nqs_ctx* c) {
         launch_center(c->stream, c->b.eloc, c->b.stats, 2.0 / (double)n, n, c->b.vvec);
     }
     {
+        PROF(NQS_PROF_PREPARE);
+        launch_qgt_prepare(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, n, c->b.q);
+    }
+    {
         PROF(NQS_PROF_OUTER);
-        launch_outer(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, n, c->b.vvec, 1, c->b.part,
-                     c->chunk, c->b.sc);
+        launch_qgt_outer(c->stream, c->d, c->prec, c->b.q, n, c->b.vvec, 1, c->b.part, c->b.sc);
     }
     {
         PROF(NQS_PROF_REDUCE);
-        launch_reduce_outer(c->stream, c->d, c->prec, c->b.part, outer_ksplit(n, c->chunk),
-                            nullptr, 0.0, c->b.grad, c->b.dpart, c->b.sc, 1);
+        launch_qgt_reduce(c->stream, c->d, c->prec, c->b.part, qgt_ksplit(c->b.q), nullptr, 0.0,
+                          c->b.grad, nullptr, c->b.sc, 0);
     }
     c->have_grad = true;
 }
@@ -441,39 +464,49 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
 
 void issue_cg_init(nqs_ctx* c, double tol, int maxiter) {
     c->cg_iter = 0;
-    launch_cg_init(c->stream, c->d.Ma * c->d.Na, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.dpart,
-                   c->b.sc, tol, maxiter);
+    c->cg_tol = tol;
+    c->cg_maxiter = maxiter;
+    launch_qgt_init(c->stream, c->d, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.rrp, c->b.sc);
 }
 
-// CG iterations; the on-the-fly form alternates the direction between two
-// buffers (contraction 1 reads p_old and writes p_new = r + beta p_old).
+// CG iterations.  On-the-fly form: iteration it first tests convergence on
+// the residual left by iteration it - 1, then forms p_new = r + beta p_old
+// (the direction alternates between two buffers) and applies the QGT.
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
     const Dims& d = c->d;
+    const int nbu = qgt_nbu(d);
     for (int it = 0; it < iters; ++it) {
         if (kind == NQS_QGT_ONTHEFLY) {
-            double* p_old = (c->cg_iter & 1) ? c->b.p2 : c->b.p;
-            double* p_new = (c->cg_iter & 1) ? c->b.p : c->b.p2;
+            const long k = c->cg_iter;
+            double* p_old = (k & 1) ? c->b.p2 : c->b.p;
+            double* p_new = (k & 1) ? c->b.p : c->b.p2;
+            double* rr_cur = c->b.rrp + (k & 1) * nbu;
+            double* rr_oth = c->b.rrp + ((k + 1) & 1) * nbu;
             c->cg_iter += 1;
             {
+                PROF(NQS_PROF_CGVEC);
+                launch_qgt_pnew(c->stream, d, c->prec, c->b.r, p_old, p_new, c->b.Pop, rr_cur,
+                                rr_oth, (int)k, c->cg_tol, c->cg_maxiter, c->b.sc);
+            }
+            {
                 PROF(NQS_PROF_QGT_W);
-                launch_w(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.r, p_old,
-                         p_new, c->b.wbuf, c->b.dpart, c->b.sc, c->lds_limit);
+                launch_qgt_w(c->stream, d, c->prec, c->b.q, c->b.tsm, c->Ns, c->b.Pop, c->b.wbuf,
+                             c->b.sc);
             }
             {
                 PROF(NQS_PROF_OUTER);
-                launch_outer(c->stream, d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.wbuf, 0,
-                             c->b.part, c->chunk, c->b.sc);
+                launch_qgt_outer(c->stream, d, c->prec, c->b.q, c->Ns, c->b.wbuf, 0, c->b.part,
+                                 c->b.sc);
             }
             {
                 PROF(NQS_PROF_REDUCE);
-                launch_reduce_outer(c->stream, d, c->prec, c->b.part,
-                                    outer_ksplit(c->Ns, c->chunk), p_new, shift, c->b.Ap,
-                                    c->b.dpart, c->b.sc, 0);
+                launch_qgt_reduce(c->stream, d, c->prec, c->b.part, qgt_ksplit(c->b.q), p_new,
+                                  shift, c->b.Ap, c->b.pap, c->b.sc, 1);
             }
             {
                 PROF(NQS_PROF_CGVEC);
-                launch_cg_update(c->stream, d.Ma * d.Na, c->b.x, c->b.r, p_new, c->b.Ap,
-                                 c->b.dpart, c->b.sc, 0);
+                launch_qgt_update(c->stream, d, c->b.x, c->b.r, p_new, c->b.Ap, c->b.pap, rr_cur,
+                                  rr_oth, c->b.sc);
             }
         } else {
             {
@@ -520,9 +553,11 @@ int sr_status(nqs_ctx* c, nqs_sr_info* info) {
 
 int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
     const int every = cg_check_interval();
+    // the on-the-fly form tests convergence at the start of an iteration
+    const int limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
     int launched = 0;
-    while (launched < maxiter) {
-        const int k = (maxiter - launched) < every ? (maxiter - launched) : every;
+    while (launched < limit) {
+        const int k = (limit - launched) < every ? (limit - launched) : every;
         issue_cg_iters(c, kind, shift, k);
         launched += k;
         int st = sync_scalars(c);
@@ -892,7 +927,8 @@ int nqs_local_energy(nqs_ctx* c, const int8_t* s, int64_t n, double* eloc_out) {
         const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
         const int8_t* sk = s + (size_t)k0 * c->N;
         launch_theta(c->stream, c->d, c->prec, c->b.tab, sk, (int)m, c->b.tx, nullptr, 0);
-        launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), sk, c->b.tx, m, eloc_out + k0);
+        launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), sk, c->b.tx, m, eloc_out + k0,
+                    c->lds_limit);
     }
     return last_launch(c);
 }
@@ -1016,7 +1052,7 @@ int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
 
 int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_step_report* reps) {
     if (!ctxs || n < 0 || (n > 0 && (!cfgs || !reps))) return NQS_EINVAL;
-    std::vector<int> st(n, NQS_OK), mi(n, 0), launched(n, 0), active(n, 1);
+    std::vector<int> st(n, NQS_OK), mi(n, 0), lim(n, 0), launched(n, 0), active(n, 1);
     for (int k = 0; k < n; ++k) {
         std::memset(&reps[k], 0, sizeof(nqs_step_report));
         nqs_ctx* c = ctxs[k];
@@ -1032,6 +1068,7 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         issue_sample(c, 0, nullptr);
         issue_energy_grad(c);
         mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
+        lim[k] = cfgs[k].qgt == NQS_QGT_ONTHEFLY ? mi[k] + 1 : mi[k];
         if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfgs[k].cg_tol, mi[k]);
         else issue_cg_init(c, cfgs[k].cg_tol, mi[k]);
         st[k] = last_launch(c);
@@ -1045,7 +1082,7 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         for (int k = 0; k < n; ++k) {
             if (st[k] || !active[k]) continue;
             nqs_ctx* c = ctxs[k];
-            const int b2 = (mi[k] - launched[k]) < every ? (mi[k] - launched[k]) : every;
+            const int b2 = (lim[k] - launched[k]) < every ? (lim[k] - launched[k]) : every;
             issue_cg_iters(c, cfgs[k].qgt, cfgs[k].diag_shift, b2);
             launched[k] += b2;
             if (hipMemcpyAsync(c->h_sc, c->b.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
@@ -1059,7 +1096,7 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
                 st[k] = fail(c, NQS_EDEVICE, "stream synchronise");
                 continue;
             }
-            if (c->h_sc->done || launched[k] >= mi[k]) active[k] = 0;
+            if (c->h_sc->done || launched[k] >= lim[k]) active[k] = 0;
             else any = true;
         }
     }
@@ -1123,7 +1160,7 @@ int nqs_profile_read(nqs_ctx* c, double* ms, int64_t* launches, int n) {
 const char* nqs_profile_class_name(int k) {
     static const char* names[NQS_PROF_CLASSES] = {
         "sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
-        "jacobian", "gram", "dense_matvec", "update"};
+        "jacobian", "gram", "dense_matvec", "update", "prepare"};
     return (k >= 0 && k < NQS_PROF_CLASSES) ? names[k] : nullptr;
 }
 

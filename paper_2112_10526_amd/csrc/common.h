@@ -24,8 +24,9 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 // O_W = t s, O_b = t, O_a = s (paper, log-derivative equation), so the QGT
 // products and the force become two dense contractions over samples.
 // Hidden-unit rows of activations and tables have Mw >= M + 1 entries, a
-// multiple of 16 and covering 64 * ceil(M / 64) (one wave64 spans the hidden
-// units of one chain in the sampler).
+// multiple of 16 and covering 64 * QMAX with QMAX = ceil(M / 64) rounded up to
+// a power of two (one wave64 spans the hidden units of one chain in the
+// sampler, QMAX per lane); entries past M are zero in the tables.
 // ---------------------------------------------------------------------------
 struct Dims {
     int N;        // sites

@@ -88,7 +88,7 @@ struct HamDev {
     double J, h;
 };
 void launch_eloc(hipStream_t st, const Dims& d, int prec, const Tables& t, const HamDev& H,
-                 const int8_t* s, const void* tact, long n, double* out);
+                 const int8_t* s, const void* tact, long n, double* out, size_t lds_limit);
 
 // sr.hip
 void launch_stats(hipStream_t st, const double* E, long n, double* out3);
@@ -112,6 +112,38 @@ void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p
                       const double* Ap, double* dpart, CgScalars* sc, int update_p);
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc);
+
+// qgt.hip: force and on-the-fly QGT products of one SR step, and CG
+struct QgtBatch {
+    int8_t* Sp;      // [Nsp][Kb] augmented spins, sample-major
+    int8_t* St;      // [Kb][Nsp] augmented spins, site-major
+    void* Th;        // [Ma][Nsp] t~ hidden-major (FP64) or two BF16 planes
+    long Nsp;        // samples padded to a multiple of 256
+    double* wpart;   // [qgt_nbw(n)] block partials of sum w
+};
+long qgt_padded_samples(long n);
+size_t qgt_th_bytes(const Dims& d, int prec, long Nsp);
+int qgt_nbw(long n);
+int qgt_nbu(const Dims& d);
+int qgt_ksplit(const QgtBatch& q);
+void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
+                        const void* tact, long n, const QgtBatch& q);
+size_t qgt_pop_bytes(const Dims& d, int prec);
+void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
+                     const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
+                     const double* rrp_prev, int it, double tol, int maxiter, CgScalars* sc);
+void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
+                  long n, const void* Pop, double* w, const CgScalars* sc);
+void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
+                      const double* v, int v_mode, void* part, const CgScalars* sc);
+void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
+                       const double* p, double shift, double* out, double* pap,
+                       const CgScalars* sc, int cg);
+void launch_qgt_update(hipStream_t st, const Dims& d, double* x, double* r, const double* p,
+                       const double* Ap, const double* pap, const double* rrp_cur,
+                       double* rrp_next, CgScalars* sc);
+void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
+                     double* p, double* rrp0, CgScalars* sc);
 
 // dense.hip
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,

@@ -24,6 +24,16 @@
 
 namespace nqs {
 
+// 1/x: hardware reciprocal refined by two Newton steps (FP64), or the FP32
+// hardware reciprocal.  The factors are in (0, 2), away from zero.
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return y;
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename R, int QMAX, int RULE>
 __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt,
                                                 const R* __restrict__ Ks, SampleArgs a) {
@@ -31,7 +41,7 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = blockIdx.x * 4 + wave;
     if (c >= a.C) return;  // uniform per wave
-    const int N = d.N, Mw = d.Mw, QM = d.QM;
+    const int N = d.N, Mw = d.Mw;
     int8_t* s = lds_s + wave * round_up(N, 16);
     int8_t* sg = a.s + (size_t)c * N;
     for (int i = lane; i < N; i += 64) s[i] = sg[i];
@@ -40,7 +50,7 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
     const R* tc = (const R*)a.tch + (size_t)c * Mw;
     R t[QMAX];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) t[q] = q < QM ? tc[lane + 64 * q] : (R)0;
+    for (int q = 0; q < QMAX; ++q) t[q] = tc[lane + 64 * q];
 
     uint32_t n_acc = 0;
     for (int p0 = 0; p0 < a.K; p0 += 64) {
@@ -59,16 +69,22 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
         // FP32 path compares logarithms; u = 0 gives -inf and always accepts
         const float lu_l = sizeof(R) == 8 ? 0.0f : logf((float)u_l);
         const int np = min(64, a.K - p0);
-        // table rows of the next proposal are loaded one proposal ahead
+        // table rows and site factors of the next proposal are loaded one
+        // proposal ahead
         R Ta[QMAX], Tb[QMAX];
+        R ka_n[2], kb_n[2];
         {
             const int ia0 = __builtin_amdgcn_readlane(ia_l, 0);
             const int ib0 = __builtin_amdgcn_readlane(ib_l, 0);
 #pragma unroll
             for (int qq = 0; qq < QMAX; ++qq) {
-                Ta[qq] = qq < QM ? Tt[(size_t)ia0 * Mw + lane + 64 * qq] : (R)0;
-                Tb[qq] = (RULE == 1 && qq < QM) ? Tt[(size_t)ib0 * Mw + lane + 64 * qq] : (R)0;
+                Ta[qq] = Tt[(size_t)ia0 * Mw + lane + 64 * qq];
+                Tb[qq] = RULE == 1 ? Tt[(size_t)ib0 * Mw + lane + 64 * qq] : (R)0;
             }
+            ka_n[0] = Ks[2 * ia0];
+            ka_n[1] = Ks[2 * ia0 + 1];
+            kb_n[0] = RULE == 1 ? Ks[2 * ib0] : (R)0;
+            kb_n[1] = RULE == 1 ? Ks[2 * ib0 + 1] : (R)0;
         }
         for (int q = 0; q < np; ++q) {
             const int ia = __builtin_amdgcn_readlane(ia_l, q);
@@ -76,15 +92,21 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
             R Tv[QMAX], Tw[QMAX];
 #pragma unroll
             for (int qq = 0; qq < QMAX; ++qq) { Tv[qq] = Ta[qq]; Tw[qq] = Tb[qq]; }
+            const R ka_c[2] = {ka_n[0], ka_n[1]};
+            const R kb_c[2] = {kb_n[0], kb_n[1]};
             if (q + 1 < np) {
                 const int ian = __builtin_amdgcn_readlane(ia_l, q + 1);
                 const int ibn = __builtin_amdgcn_readlane(ib_l, q + 1);
 #pragma unroll
                 for (int qq = 0; qq < QMAX; ++qq) {
-                    if (qq < QM) {
-                        Ta[qq] = Tt[(size_t)ian * Mw + lane + 64 * qq];
-                        if (RULE == 1) Tb[qq] = Tt[(size_t)ibn * Mw + lane + 64 * qq];
-                    }
+                    Ta[qq] = Tt[(size_t)ian * Mw + lane + 64 * qq];
+                    if (RULE == 1) Tb[qq] = Tt[(size_t)ibn * Mw + lane + 64 * qq];
+                }
+                ka_n[0] = Ks[2 * ian];
+                ka_n[1] = Ks[2 * ian + 1];
+                if (RULE == 1) {
+                    kb_n[0] = Ks[2 * ibn];
+                    kb_n[1] = Ks[2 * ibn + 1];
                 }
             }
             bool accept;
@@ -93,12 +115,10 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
                 R prod = (R)1;
 #pragma unroll
                 for (int qq = 0; qq < QMAX; ++qq) {
-                    if (qq < QM) {
-                        f[qq] = (R)1 - (R)sa * t[qq] * Tv[qq];
-                        prod *= f[qq];
-                    }
+                    f[qq] = (R)1 - (R)sa * t[qq] * Tv[qq];
+                    prod *= f[qq];
                 }
-                const R kf = Ks[2 * ia + (sa < 0)];
+                const R kf = sa < 0 ? ka_c[1] : ka_c[0];
                 if constexpr (sizeof(R) == 8) {
                     const double r = wave_prod(prod) * kf;
                     accept = readlane(u_l, q) < r * r;
@@ -108,8 +128,7 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
                 }
                 if (accept) {
 #pragma unroll
-                    for (int qq = 0; qq < QMAX; ++qq)
-                        if (qq < QM) t[qq] = (t[qq] - (R)sa * Tv[qq]) / f[qq];
+                    for (int qq = 0; qq < QMAX; ++qq) t[qq] = (t[qq] - (R)sa * Tv[qq]) * recip(f[qq]);
                     s[ia] = (int8_t)-sa;  // every lane stores the same value
                 }
             } else {
@@ -122,15 +141,13 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
                     R prod = (R)1;
 #pragma unroll
                     for (int qq = 0; qq < QMAX; ++qq) {
-                        if (qq < QM) {
-                            const R ta = Tv[qq], tb = Tw[qq];
-                            TT[qq] = (R)1 - ta * tb;
-                            Td[qq] = (R)sa * (ta - tb);
-                            g[qq] = TT[qq] - t[qq] * Td[qq];
-                            prod *= g[qq];
-                        }
+                        const R ta = Tv[qq], tb = Tw[qq];
+                        TT[qq] = (R)1 - ta * tb;
+                        Td[qq] = (R)sa * (ta - tb);
+                        g[qq] = TT[qq] - t[qq] * Td[qq];
+                        prod *= g[qq];
                     }
-                    const R ka = Ks[2 * ia + (sa < 0)], kb = Ks[2 * ib + (sb < 0)];
+                    const R ka = sa < 0 ? ka_c[1] : ka_c[0], kb = sb < 0 ? kb_c[1] : kb_c[0];
                     if constexpr (sizeof(R) == 8) {
                         const double r = wave_prod(prod) * ka * kb;
                         accept = readlane(u_l, q) < r * r;
@@ -141,7 +158,7 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
                     if (accept) {
 #pragma unroll
                         for (int qq = 0; qq < QMAX; ++qq)
-                            if (qq < QM) t[qq] = (t[qq] * TT[qq] - Td[qq]) / g[qq];
+                            t[qq] = (t[qq] * TT[qq] - Td[qq]) * recip(g[qq]);
                         s[ia] = (int8_t)sb;
                         s[ib] = (int8_t)sa;
                     }
