@@ -38,14 +38,23 @@ PEAK = {  # MI355X dense peaks
 
 
 def kernel_work(cls: str, w, precision: str):
-    """Algorithmic work of one launch of a kernel class: (bound, flops or bytes, unit, peak)."""
+    """Algorithmic work of one launch of a kernel class: (bound, flops or bytes, unit, peak).
+
+    The two QGT contractions each apply J [Ns x P] (or its transpose) once:
+    2 Ns P flops, over the factors of J, which are read once per launch:
+    per sample N spin bytes, M activations (8 B FP64; 4 B in the BF16/FP32
+    forms, FP32 or a BF16 hi/lo pair) and one 8-byte weight (w or z).  FP64
+    runs on the FP64 matrix cores (78.6 TFLOP/s; 23 flop/B, above the 9.8 of
+    the HBM ridge: MFMA-bound); the BF16 form (44 flop/B against a ridge of
+    312) is HBM-bound.
+    """
     N, M, Ns, C, K = w.n_sites, w.n_hidden, w.n_samples, w.n_chains, w.sweep_size
     P = N + M + N * M
-    mf = "mfma_fp64" if precision == "fp64" else "mfma_fp32"
     vf = "valu_fp64" if precision == "fp64" else "valu_fp32"
     if cls in ("outer", "qgt_w"):
-        # one product of the Jacobian J [Ns x P] with a vector: 2 Ns P flops
-        return "mfma", 2.0 * Ns * P, "TFLOP/s", PEAK[mf]
+        if precision == "fp64":
+            return "mfma", 2.0 * Ns * P, "TFLOP/s", PEAK["mfma_fp64"]
+        return "hbm", float(Ns * (N + 4 * M + 8) + 4 * P), "GB/s", PEAK["hbm"]
     if cls == "sample":
         # every proposal: M factors (FMA + MUL) of the amplitude ratio
         return "alu", 4.0 * C * K * M, "TFLOP/s", PEAK[vf]
@@ -53,7 +62,8 @@ def kernel_work(cls: str, w, precision: str):
         # every sample: N single-flip ratios of M factors (MUL, FMA, MUL)
         return "alu", 6.0 * Ns * N * M / 2.0, "TFLOP/s", PEAK[vf]
     if cls == "theta":
-        return "mfma", 2.0 * C * (N + 1) * M, "TFLOP/s", PEAK[mf]
+        return "mfma", 2.0 * C * (N + 1) * M, "TFLOP/s", \
+            PEAK["mfma_fp64" if precision == "fp64" else "mfma_bf16"]
     return "hbm", float("nan"), "GB/s", PEAK["hbm"]
 
 

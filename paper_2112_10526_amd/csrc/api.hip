@@ -79,6 +79,8 @@ struct nqs_ctx {
     bool params_set = false, chains_dirty = true, have_samples = false, have_grad = false;
     double acceptance = 0.0;
     CgScalars* h_sc = nullptr;  // pinned
+    int32_t* h_flag = nullptr;  // pinned [2]: CG stop flag after a batch of iterations
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
     double* h_stats = nullptr;  // pinned [4]
     uint32_t* h_acc = nullptr;  // pinned [C]
     size_t h_acc_n = 0;
@@ -170,7 +172,7 @@ size_t layout(nqs_ctx* c, char* base) {
     b.chains = (int8_t*)take((size_t)c->C * d.N);
     b.tch = take(es * (size_t)c->C * d.Mw);
     b.samples = (int8_t*)take((size_t)c->Ns * d.N);
-    b.tsm = take(es * (size_t)c->Ns * d.Mw);
+    b.tsm = take(es * (size_t)qgt_act_rows(c->Ns) * d.Mw);
     b.tx = take(es * (size_t)c->Bx * d.Mw);
     b.eloc = (double*)take(8 * (size_t)c->Bx);
     b.vvec = (double*)take(8 * (size_t)c->Bx);
@@ -182,12 +184,12 @@ size_t layout(nqs_ctx* c, char* base) {
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
-        b.q.Sp = (int8_t*)take((size_t)Nsp * d.Kb);
+        b.q.Sp = take((size_t)Nsp * d.Kq * (c->prec == 0 ? 1 : 2));
         b.q.St = (int8_t*)take((size_t)Nsp * d.Kb);
         b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
-        b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp));
+        b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp, c->prec));
         b.rrp = (double*)take(16 * (size_t)qgt_nbu(d));
-        b.pap = (double*)take(8 * (size_t)qgt_nbu(d));
+        b.pap = (double*)take(8 * (size_t)qgt_nbr(d));
         b.Pop = take(qgt_pop_bytes(d, c->prec));
         const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
         b.part = take(es * ks * PV);
@@ -225,6 +227,7 @@ void derive(nqs_ctx* c) {
     d.Mw = d.Ma > 64 * qmax ? d.Ma : 64 * qmax;
     d.Nw = round_up(c->N, 64);
     d.Kb = round_up(d.Na, 32);
+    d.Kq = round_up(d.Na, 128);
     d.QM = (c->M + 63) / 64;
     d.vb = c->vb;
     d.hb = c->hb;
@@ -551,18 +554,38 @@ int sr_status(nqs_ctx* c, nqs_sr_info* info) {
     return NQS_OK;
 }
 
+// Issues CG iterations in batches and reads the stop flag of each batch while
+// the next batch is already queued, so the device never waits for the host.
+// Iterations issued after the stop return at once (every CG kernel tests the
+// flag first).
 int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
     const int every = cg_check_interval();
     // the on-the-fly form tests convergence at the start of an iteration
     const int limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
-    int launched = 0;
-    while (launched < limit) {
+    int launched = 0, issued = 0, checked = 0;
+    auto issue_batch = [&]() -> int {
         const int k = (limit - launched) < every ? (limit - launched) : every;
         issue_cg_iters(c, kind, shift, k);
         launched += k;
-        int st = sync_scalars(c);
-        if (st) return st;
-        if (c->h_sc->done) break;
+        const int slot = issued & 1;
+        HIPCHK(c, hipMemcpyAsync(&c->h_flag[slot], &c->b.sc->done, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->flag_ev[slot], c->stream));
+        ++issued;
+        return NQS_OK;
+    };
+    if (limit <= 0) return NQS_OK;
+    int st = issue_batch();
+    if (st) return st;
+    while (checked < issued) {
+        if (launched < limit && issued - checked < 2) {
+            st = issue_batch();
+            if (st) return st;
+        }
+        HIPCHK(c, hipEventSynchronize(c->flag_ev[checked & 1]));
+        const bool stop = c->h_flag[checked & 1] != 0;
+        ++checked;
+        if (stop) break;
     }
     return NQS_OK;
 }
@@ -606,8 +629,11 @@ int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
         c->lds_limit = (size_t)lds;
     if (hipSetDevice(device) != hipSuccess ||
         hipHostMalloc((void**)&c->h_sc, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete c;
+        hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->flag_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->flag_ev[1], hipEventDisableTiming) != hipSuccess) {
+        nqs_destroy(c);
         return NQS_EDEVICE;
     }
     *out = c;
@@ -619,6 +645,9 @@ void nqs_destroy(nqs_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->h_sc) hipHostFree(c->h_sc);
     if (c->h_stats) hipHostFree(c->h_stats);
+    if (c->h_flag) hipHostFree(c->h_flag);
+    for (auto& e : c->flag_ev)
+        if (e) hipEventDestroy(e);
     if (c->h_acc) hipHostFree(c->h_acc);
     for (auto& e : c->ev) hipEventDestroy(e);
     delete c;

@@ -36,6 +36,7 @@ struct Dims {
     int Mw;       // activation / table row width
     int Nw;       // round_up(N, 64): width of the hidden-major table rows
     int Kb;       // round_up(Na, 32): K extent of the BF16 theta operand
+    int Kq;       // round_up(Na, 128): site extent of the CG operands (whole k-groups)
     int QM;       // ceil(M / 64): hidden units per lane in the sampler
     int vb, hb;   // visible / hidden bias present
 };

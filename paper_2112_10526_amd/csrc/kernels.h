@@ -115,16 +115,19 @@ void launch_axpy_update(hipStream_t st, int total, double* x, const double* delt
 
 // qgt.hip: force and on-the-fly QGT products of one SR step, and CG
 struct QgtBatch {
-    int8_t* Sp;      // [Nsp][Kb] augmented spins, sample-major
+    void* Sp;        // [Nsp][Kq] augmented spins, sample-major: int8 (FP64) or BF16
     int8_t* St;      // [Kb][Nsp] augmented spins, site-major
     void* Th;        // [Ma][Nsp] t~ hidden-major (FP64) or two BF16 planes
     long Nsp;        // samples padded to a multiple of 256
-    double* wpart;   // [qgt_nbw(n)] block partials of sum w
+    double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w
 };
 long qgt_padded_samples(long n);
 size_t qgt_th_bytes(const Dims& d, int prec, long Nsp);
-int qgt_nbw(long n);
+int qgt_nbw(long n, int prec);
+// activation rows to allocate for n samples (whole contraction-1 blocks)
+long qgt_act_rows(long n);
 int qgt_nbu(const Dims& d);
+int qgt_nbr(const Dims& d);
 int qgt_ksplit(const QgtBatch& q);
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q);

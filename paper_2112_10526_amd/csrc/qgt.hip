@@ -11,7 +11,8 @@
 //
 // Once per SR step the batch is laid out for the matrix cores with the
 // contracted (sample or site) index contiguous:
-//   Sp  int8 [Nsp][Kb]  augmented spins, sample-major   (contraction 1, A)
+//   Sp  [Nsp][Kq]       augmented spins, sample-major   (contraction 1, A):
+//                       int8 (FP64 path) or BF16 (BF16 forms)
 //   St  int8 [Kb][Nsp]  augmented spins, site-major     (contraction 2, B)
 //   Th  [Ma][Nsp]       t~ hidden-major: FP64, or two BF16 planes hi/lo
 // FP64 path: v_mfma_f64_16x16x4f64.  FP32/BF16 forms: v_mfma_f32_16x16x32_bf16
@@ -24,6 +25,8 @@
 // consumer recomputes the same sum), and block 0 publishes the CG scalars for
 // the host.
 #include "kernels.h"
+
+#include <type_traits>
 
 namespace nqs {
 
@@ -38,11 +41,24 @@ __device__ __forceinline__ double bsum256(double v, double* sh) {
     return r;
 }
 
-// fixed-order sum of nb partials, identical in every block
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb, double* sh) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) a += part[b];
-    return bsum256(a, sh);
+// Fixed-order sums of partial arrays in 256-thread blocks (the same order in
+// every block).  The first 4 x 256 entries are loaded by pload4 (clamped,
+// unconditional) so a kernel can issue them together with its other loads;
+// psum adds the rest and reduces over the block.
+__device__ __forceinline__ void pload4(const double* a, int na, double (&x)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = u * 256 + (int)threadIdx.x;
+        x[u] = na > 0 ? a[min(i, na - 1)] : 0.0;
+    }
+}
+__device__ __forceinline__ double psum(const double* a, int na, const double (&x)[4], double* sh) {
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u * 256 + (int)threadIdx.x < na) t += x[u];
+    for (int i = 1024 + (int)threadIdx.x; i < na; i += 256) t += a[i];
+    return bsum256(t, sh);
 }
 
 __device__ __forceinline__ uint16_t bf16_rn(float f) { return f32_to_bf16_bits(f); }
@@ -56,8 +72,11 @@ __device__ __forceinline__ void split2(float x, uint16_t& hi, uint16_t& lo) {
 // ---------------------------------------------------------------------------
 // per-step layout kernels
 // ---------------------------------------------------------------------------
+// Sp holds int8 spins (FP64 path) or their BF16 bit patterns (BF16 forms,
+// sp_bf16 = 1: the contraction-1 A operand without conversion).
 __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s, int N, long n,
-                                                    int Kb, long Nsp, int8_t* __restrict__ Sp,
+                                                    int Kb, int Kq, long Nsp, int sp_bf16,
+                                                    void* __restrict__ Sp,
                                                     int8_t* __restrict__ St) {
     __shared__ int8_t tile[64][68];
     const long k0 = (long)blockIdx.x * 64;
@@ -69,7 +88,12 @@ __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s
         int8_t v = 0;
         if (k < n) v = i < N ? s[k * N + i] : (i == N ? (int8_t)1 : (int8_t)0);
         tile[kl][il] = v;
-        if (i < Kb) Sp[k * Kb + i] = v;
+        if (i < Kq) {
+            if (sp_bf16)
+                ((uint16_t*)Sp)[k * Kq + i] = v > 0 ? 0x3F80 : (v < 0 ? 0xBF80 : 0);
+            else
+                ((int8_t*)Sp)[k * Kq + i] = v;
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
@@ -114,20 +138,31 @@ __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long
 //   rr_it <= tol^2 rr_0, it >= maxiter or non-finite; else beta = rr_it /
 //   rr_{it-1} (0 at it = 0) and p_new = r + beta p_old.
 // p_new is written in FP64 [Ma][Na] and in the operand layout of
-// contraction 1: FP64 path k-major [Kb][Ma]; BF16 forms two planes [Ma][Kb].
-// One thread per (j, i < Kb).
+// contraction 1: FP64 path k-major [Kq][Ma]; BF16 forms two planes [Ma][Kq].
+// One thread per (j, i < Kq).
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void k_pnew(Dims d, const double* __restrict__ r,
-                                              const double* __restrict__ p_old,
-                                              double* __restrict__ p_new, void* __restrict__ Pop,
-                                              const double* __restrict__ rrp_cur,
-                                              const double* __restrict__ rrp_prev, int nbu, int it,
+__global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
+                                              const double* p_old,
+                                              double* p_new, void* Pop,
+                                              const double* rrp_cur,
+                                              const double* rrp_prev, int nbu, int it,
                                               double tol, int maxiter, CgScalars* sc) {
-    if (sc->done) return;
     __shared__ double sh[4];
-    const double rr = sum_partials(rrp_cur, nbu, sh);
-    const double rrprev = it > 0 ? sum_partials(rrp_prev, nbu, sh) : rr;
+    // the element loads do not depend on the scalars: issue them first
+    // (clamped, unconditional loads: no branch between them)
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int j = e / d.Kq, i = e - j * d.Kq;
+    const bool own = e < d.Ma * d.Kq && i < d.Na;
+    const size_t g = (size_t)min(j, d.Ma - 1) * d.Na + min(i, d.Na - 1);
+    const double re = r[g], pe = p_old[g];
+    double xa[4], xb[4];
+    pload4(rrp_cur, nbu, xa);
+    pload4(rrp_prev, it > 0 ? nbu : 0, xb);
+    asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
+    if (sc->done) return;
+    const double rr = psum(rrp_cur, nbu, xa, sh);
+    const double rrprev = it > 0 ? psum(rrp_prev, nbu, xb, sh) : rr;
     const double rr0 = it == 0 ? rr : sc->rr0;
     const double tol2 = tol * tol * rr0;
     const bool stop = !(rr > tol2) || it >= maxiter || !isfinite(rr);
@@ -146,13 +181,10 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* __restrict__
         }
     }
     if (stop) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= d.Ma * d.Kb) return;
-    const int j = e / d.Kb, i = e - j * d.Kb;
+    if (e >= d.Ma * d.Kq) return;
     double v = 0.0;
-    if (i < d.Na) {
-        const size_t g = (size_t)j * d.Na + i;
-        v = r[g] + beta * p_old[g];
+    if (own) {
+        v = re + beta * pe;
         p_new[g] = v;
     }
     if constexpr (MODE == 0) {
@@ -161,96 +193,298 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* __restrict__
         uint16_t hi, lo;
         split2((float)v, hi, lo);
         ((uint16_t*)Pop)[e] = hi;
-        ((uint16_t*)Pop)[(size_t)d.Ma * d.Kb + e] = lo;
+        ((uint16_t*)Pop)[(size_t)d.Ma * d.Kq + e] = lo;
     }
 }
 
+// block sum over nw waves, identical order in every block
+__device__ __forceinline__ double bsum_waves(double v, double* sh, int nw) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int q = 0; q < nw; ++q) r += sh[q];
+    __syncthreads();
+    return r;
+}
+
+// Waves per block and tiles per wave for `tiles` tiles over at most maxw waves.
+static inline void wave_split(int tiles, int maxw, int& waves, int& per_wave) {
+    per_wave = (tiles + maxw - 1) / maxw;
+    waves = (tiles + per_wave - 1) / per_wave;
+}
+
 // ---------------------------------------------------------------------------
-// contraction 1: w_k = t~_k . (P s~_k) for 16 samples per block; the four
-// waves split the hidden tiles (wave w: tiles w, w + 4, ...) and their row
-// sums meet in LDS.  Operands come straight from L2: spins from Sp, P in the
-// layout written by k_pnew.
+// contraction 1: w_k = t~_k . (P s~_k) for the 16 RT samples of a block.
+// Wave w computes hidden tiles w, w + nw, ... (16 x 16 blocks of S P^T for
+// each of the RT sample tiles, so each P fragment serves RT tiles) and
+// weights them with tanh(theta).  Sites run in whole groups (128 BF16 / 32
+// FP64) over the zero-padded extent Kq, so a group's loads are unconditional
+// and issued together.  Rows past n have zero spins (k_prep_spins), so their
+// products vanish; their activation rows (the activation buffer holds whole
+// blocks of rows) are read but only ever multiply those zeros.
 // ---------------------------------------------------------------------------
+template <int MODE> struct WRows { static constexpr int RT = MODE == 0 ? 2 : 4; };  // k_w5 / k_w6
+constexpr int W_ROWS_MAX = 64;  // samples per contraction-1 block, largest form
+
+// FP64 blocks have at most 8 waves (the FP64 fragments need the registers)
 template <int MODE>
-__global__ __launch_bounds__(256) void k_w3(Dims d, const int8_t* __restrict__ Sp,
-                                            const void* __restrict__ tact_v, long n,
-                                            const void* __restrict__ Pop,
-                                            double* __restrict__ w, double* __restrict__ wpart,
-                                            const CgScalars* __restrict__ sc) {
+__global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int8_t* __restrict__ Sp,
+                                             const void* __restrict__ tact_v, long n,
+                                             const void* __restrict__ Pop,
+                                             double* __restrict__ w, double* __restrict__ wpart,
+                                             const CgScalars* __restrict__ sc) {
+    constexpr int RT = WRows<MODE>::RT;
     if (sc->done) return;
-    __shared__ double wsh[4][16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ double wsh[16][16 * RT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const long r0 = (long)blockIdx.x * 16;
-    const int Kb = d.Kb, Ma = d.Ma, nct = d.Ma / 16;
-    const int8_t* Srow = Sp + (r0 + lr) * Kb;
-    double rs[4] = {0, 0, 0, 0};
+    const long r0 = (long)blockIdx.x * (16 * RT);
+    const int Kq = d.Kq, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
+    const int8_t* Sbase = Sp + (r0 + lr) * Kq;  // sample tile rt: + 16 rt Kq
+    double rs[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rs[rt][q] = 0.0;
     if constexpr (MODE == 0) {
         const double* Pt = (const double*)Pop;
         const double* tact = (const double*)tact_v;
-        for (int ct = wave; ct < nct; ct += 4) {
-            v4d acc = v4d{0, 0, 0, 0};
-            const double* Pc = Pt + ct * 16 + lr;
-            for (int k0 = 0; k0 < d.Na; k0 += 4) {
-                const double a = (double)Srow[k0 + lk];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Pc[(size_t)(k0 + lk) * Ma], acc, 0, 0, 0);
-            }
+        for (int ct = wave; ct < nct; ct += nw) {
             const int j = ct * 16 + lr;
+            double tv[RT][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const long k = r0 + acc_row<double>(lk, q);
-                rs[q] += (k < n ? tact[k * d.Mw + j] : 0.0) * acc[q];
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<double>(lk, q)) * Mw + j];
+            v4d acc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4d{0, 0, 0, 0};
+            const double* Pc = Pt + (size_t)(4 * lk) * Ma + j;
+            for (int g = 0; g < Kq; g += 32) {
+                double b[2][4];
+                uint32_t sb[RT][2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) b[u][e] = Pc[(size_t)(g + 16 * u + e) * Ma];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
+                __builtin_amdgcn_sched_barrier(0);  // keep the group's loads together
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt) {
+                            const double a = (double)(int8_t)(sb[rt][u] >> (8 * e));
+                            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u][e], acc[rt], 0, 0, 0);
+                        }
             }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rs[rt][q] += tv[rt][q] * acc[rt][q];
         }
     } else {
         const uint16_t* Ph = (const uint16_t*)Pop;
-        const uint16_t* Pl = Ph + (size_t)Ma * Kb;
+        const uint16_t* Pl = Ph + (size_t)Ma * Kq;
         const float* tact = (const float*)tact_v;
-        float rsf[4] = {0, 0, 0, 0};
-        for (int ct = wave; ct < nct; ct += 4) {
-            v4f acc = v4f{0, 0, 0, 0};
-            const size_t prow = (size_t)(ct * 16 + lr) * Kb + 8 * lk;
-            for (int k0 = 0; k0 < Kb; k0 += 32) {
-                const uint64_t sb = *(const uint64_t*)(Srow + k0 + 8 * lk);
-                v8s av;
+        float rsf[RT][4];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int8_t sv = (int8_t)(sb >> (8 * e));
-                    av[e] = sv > 0 ? (short)0x3F80 : (sv < 0 ? (short)0xBF80 : (short)0);
-                }
-                const v8bf a = __builtin_bit_cast(v8bf, av);
-                const v8s bh = *(const v8s*)(Ph + prow + k0);
-                const v8s bl = *(const v8s*)(Pl + prow + k0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl), acc, 0, 0, 0);
-            }
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
+        for (int ct = wave; ct < nct; ct += nw) {
             const int j = ct * 16 + lr;
+            float tv[RT][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const long k = r0 + acc_row<float>(lk, q);
-                rsf[q] += (k < n ? tact[k * d.Mw + j] : 0.0f) * acc[q];
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<float>(lk, q)) * Mw + j];
+            v4f acc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
+            const size_t prow = (size_t)j * Kq + 8 * lk;
+            for (int g = 0; g < Kq; g += 128) {
+                v8s bh[4], bl[4];
+                uint64_t sb[RT][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bh[u] = *(const v8s*)(Ph + prow + g + 32 * u);
+                    bl[u] = *(const v8s*)(Pl + prow + g + 32 * u);
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        sb[rt][u] = *(const uint64_t*)(Sbase + (size_t)16 * rt * Kq + g + 32 * u + 8 * lk);
+                __builtin_amdgcn_sched_barrier(0);  // keep the group's loads together
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        v8s av;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int8_t sv = (int8_t)(sb[rt][u] >> (8 * e));
+                            av[e] = sv > 0 ? (short)0x3F80 : (sv < 0 ? (short)0xBF80 : (short)0);
+                        }
+                        const v8bf a = __builtin_bit_cast(v8bf, av);
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh[u]), acc[rt], 0, 0, 0);
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl[u]), acc[rt], 0, 0, 0);
+                    }
             }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rs[q] = (double)rsf[q];
-    }
-    // row sums over the 16 columns of each tile, then over the four waves
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const double v = row16_sum(rs[q]);
-        if (lr == 0) wsh[wave][MODE == 0 ? acc_row<double>(lk, q) : acc_row<float>(lk, q)] = v;
+            for (int q = 0; q < 4; ++q) rs[rt][q] = (double)rsf[rt][q];
     }
+    // sums over the 16 columns of the wave's tiles, then over the waves in order
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = row16_sum(rs[rt][q]);
+            const int row = MODE == 0 ? acc_row<double>(lk, q) : acc_row<float>(lk, q);
+            if (lr == 0) wsh[wave][16 * rt + row] = v;
+        }
     __syncthreads();
-    if (tid < 16) {
+    if (tid < 16 * RT) {
         const long k = r0 + tid;
-        const double v = (wsh[0][tid] + wsh[1][tid]) + (wsh[2][tid] + wsh[3][tid]);
+        double v = 0.0;
+        for (int q = 0; q < nw; ++q) v += wsh[q][tid];
         if (k < n) w[k] = v;
         wsh[0][tid] = k < n ? v : 0.0;
     }
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
-        for (int q = 0; q < 16; ++q) t += wsh[0][q];
+        for (int q = 0; q < 16 * RT; ++q) t += wsh[0][q];
+        wpart[blockIdx.x] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// contraction 1, BF16 form, 64 samples per block: the block's spins (64 rows
+// of Kq BF16 values) are staged in LDS once and shared by all waves; wave w
+// keeps the P fragments of its hidden tile in registers and applies them to
+// the four sample tiles.  All first-tile global loads are issued together.
+// ---------------------------------------------------------------------------
+constexpr int W6_ROWS = 64;
+
+static inline size_t w6_lds(const Dims& d) { return (size_t)W6_ROWS * (2 * d.Kq + 16); }
+
+__global__ __launch_bounds__(1024) void k_w6(Dims d, const uint16_t* __restrict__ Sp,
+                                             const float* __restrict__ tact, long n,
+                                             const uint16_t* __restrict__ Ph,
+                                             double* __restrict__ w, double* __restrict__ wpart,
+                                             const CgScalars* __restrict__ sc) {
+    constexpr int RT = W6_ROWS / 16;
+    if (sc->done) return;
+    extern __shared__ __align__(16) char lds_w6[];
+    __shared__ double wsh[16][W6_ROWS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int nth = blockDim.x;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long r0 = (long)blockIdx.x * W6_ROWS;
+    const int Kq = d.Kq, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
+    const int SS = 2 * Kq + 16;  // LDS row stride of the staged spins (bytes)
+    const uint16_t* Pl = Ph + (size_t)Ma * Kq;
+    // ---- issue: spins of the block (16-byte units), the first tile's
+    // activations and first P group (every wave has at least one tile)
+    const int UR = Kq / 8;  // 16-byte units per row
+    const int US = W6_ROWS * UR;
+    const char* Sb = (const char*)(Sp + r0 * Kq);
+    const float* tb = tact + r0 * Mw;             // 32-bit offsets from block bases
+    const int toff = acc_row<float>(lk, 0) * Mw;  // rows 4 lk + q of each sample tile
+    const uint4 rs0 = *(const uint4*)(Sb + min(tid, US - 1) * 16);
+    const uint4 rs1 = *(const uint4*)(Sb + min(nth + tid, US - 1) * 16);
+    float tv[RT][4];
+    v8s bh[4], bl[4];
+    auto load_tile = [&](int ct, int g) {
+        const int j = ct * 16 + lr;
+        if (g == 0) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
+        }
+        const int prow = j * Kq + 8 * lk + g;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bh[u] = *(const v8s*)(Ph + prow + 32 * u);
+            bl[u] = *(const v8s*)(Pl + prow + 32 * u);
+        }
+    };
+    load_tile(wave, 0);
+    __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
+    {
+        const int e0 = tid, e1 = nth + tid;
+        if (e0 < US) *(uint4*)(lds_w6 + (e0 / UR) * SS + 16 * (e0 % UR)) = rs0;
+        if (e1 < US) *(uint4*)(lds_w6 + (e1 / UR) * SS + 16 * (e1 % UR)) = rs1;
+        for (int e = 2 * nth + tid; e < US; e += nth)  // wide rows only
+            *(uint4*)(lds_w6 + (e / UR) * SS + 16 * (e % UR)) = *(const uint4*)(Sb + e * 16);
+    }
+    __syncthreads();
+    float rsf[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
+    for (int ct = wave; ct < nct; ct += nw) {
+        v4f acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
+        for (int g = 0; g < Kq; g += 128) {
+            if (ct != wave || g != 0) load_tile(ct, g);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const v8bf a = __builtin_bit_cast(
+                        v8bf, *(const v8s*)(lds_w6 + (16 * rt + lr) * SS + 2 * (g + 32 * u + 8 * lk)));
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh[u]), acc[rt], 0, 0, 0);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl[u]), acc[rt], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);  // one k-step of spins live at a time
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
+    }
+    // sums over the 16 columns of the wave's tiles, then over the waves in order
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = row16_sum((double)rsf[rt][q]);
+            if (lr == 0) wsh[wave][16 * rt + acc_row<float>(lk, q)] = v;
+        }
+    __syncthreads();
+    if (tid < W6_ROWS) {
+        const long k = r0 + tid;
+        double v = 0.0;
+        for (int q = 0; q < nw; ++q) v += wsh[q][tid];
+        if (k < n) w[k] = v;
+        wsh[0][tid] = k < n ? v : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < W6_ROWS; ++q) t += wsh[0][q];
         wpart[blockIdx.x] = t;
     }
 }
@@ -258,107 +492,178 @@ __global__ __launch_bounds__(256) void k_w3(Dims d, const int8_t* __restrict__ S
 // ---------------------------------------------------------------------------
 // contraction 2: part[kc][j][i] = sum_{k in chunk kc} t~_kj z_k s~_ki
 // v_mode 0: z_k = (w_k - mean w) / n with mean w from the contraction-1
-// partials; v_mode 1: z_k = v_k.  grid = (Ma / 16, Nsp / 256): one hidden
-// tile and one chunk of 256 samples per block; the tile's t~ rows and the
-// chunk's z are staged in LDS and the four waves split the site tiles.
+// partials; v_mode 1: z_k = v_k.  One block per (hidden tile jt, chunk kc of
+// 256 samples); the tile's t~ rows and the chunk's z are staged in LDS and
+// wave w computes site tiles w, w + nw, ..., holding its spins in registers.
+// All global loads of a block are issued before any of them is consumed
+// (clamped indices, so they are unconditional).
+// Block order: the hardware deals consecutive blocks to the 8 XCDs in turn;
+// the blocks of one chunk are placed on one XCD, so that chunk's spins are
+// brought into a single L2.
 // ---------------------------------------------------------------------------
+constexpr int OKC = 256;         // samples per chunk
+constexpr int OKD = OKC + 1;     // FP64 LDS row stride of t~ (doubles)
+constexpr int OKP = OKC + 8;     // BF16 LDS row stride of t~ (halves)
+constexpr int NXCD = 8;
+
+// 16-byte unit e of the t~ tile: global source (elements) and LDS destination (bytes)
 template <int MODE>
-__global__ __launch_bounds__(256) void k_outer3(Dims d, const int8_t* __restrict__ St,
-                                                const void* __restrict__ Th, long Nsp, long n,
-                                                const double* __restrict__ v, int v_mode,
-                                                const double* __restrict__ wpart, int nbw,
-                                                void* __restrict__ part_v,
-                                                const CgScalars* __restrict__ sc) {
+__device__ __forceinline__ void a_unit(int e, long Nsp, long plane, size_t& src, int& dst) {
+    if constexpr (MODE == 0) {  // 16 rows x 128 units (2 doubles each)
+        const int row = e >> 7, c = e & 127;
+        src = (size_t)row * Nsp + 2 * c;
+        dst = (row * OKD + 2 * c) * 8;
+    } else {  // 2 planes x 16 rows x 32 units (8 halves each)
+        const int pl = e >> 9, row = (e >> 5) & 15, c = e & 31;
+        src = (size_t)pl * plane + (size_t)row * Nsp + 8 * c;
+        dst = ((pl * 16 + row) * OKP + 8 * c) * 2;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restrict__ St,
+                                                 const void* __restrict__ Th, long Nsp, long n,
+                                                 const double* __restrict__ v, int v_mode,
+                                                 const double* __restrict__ wpart, int nbw,
+                                                 void* __restrict__ part_v, int ksplit,
+                                                 const CgScalars* __restrict__ sc) {
     if (v_mode == 0 && sc->done) return;
-    constexpr int KC = 256;
-    __shared__ double sh[4];
-    constexpr int KD = KC + 1;  // FP64 row stride: the 16 rows fall in distinct banks
-    __shared__ __align__(16) char lds[MODE == 0 ? 16 * KD * 8 + KC * 8 : 2 * 16 * (KC + 8) * 2 + 2 * KC * 2];
+    constexpr int UA = MODE == 0 ? 16 * OKC * 8 / 16 : 2 * 16 * OKC * 2 / 16;
+    constexpr int BA = MODE == 0 ? 8 : 4;   // t~ units per thread issued up front
+    constexpr int BW = 2;                   // mean-w partials per thread issued up front
+    constexpr int KS = MODE == 0 ? OKC / 16 : OKC / 32;  // k-steps per chunk
+    using SW = typename std::conditional<MODE == 0, uint32_t, uint64_t>::type;
+    __shared__ __align__(16) char lds6[MODE == 0 ? 16 * OKD * 8 + OKC * 8
+                                                  : 2 * 16 * OKP * 2 + 2 * OKC * 2];
+    __shared__ double sh[16];
+    // block -> (jt, kc), chunks grouped by XCD
+    const int nj = d.Ma / 16;
+    const int L = blockIdx.x, x = L % NXCD, m = L / NXCD;
+    const int jt = m % nj, kc = x + NXCD * (m / nj);
+    if (kc >= ksplit) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nth = blockDim.x, nw = nth >> 6;
     const int lr = lane & 15, lk = lane >> 4;
+    const long kbeg = (long)kc * OKC;
+    const int nit = d.Na / 16;
+    const long plane = (long)d.Ma * Nsp;
+    const char* Ab = (const char*)Th;
+    const size_t abase = (size_t)jt * 16 * Nsp + kbeg;
+    // ---- issue: mean-w partials, t~ tile, z source, this wave's first spins
+    double wp[BW];
+#pragma unroll
+    for (int u = 0; u < BW; ++u) {
+        const int b = u * nth + tid;
+        wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
+    }
+    uint4 ra[BA];
+#pragma unroll
+    for (int u = 0; u < BA; ++u) {
+        const int e = min(u * nth + tid, UA - 1);
+        size_t src;
+        int dst;
+        a_unit<MODE>(e, Nsp, plane, src, dst);
+        ra[u] = *(const uint4*)(Ab + (abase + src) * (MODE == 0 ? 8 : 2));
+    }
+    const double vz = v[min(kbeg + (tid & (OKC - 1)), n - 1)];
+    SW sb[KS];
+    {
+        const int8_t* Sr = St + (size_t)(wave * 16 + lr) * Nsp + kbeg;
+#pragma unroll
+        for (int u = 0; u < KS; ++u)
+            sb[u] = *(const SW*)(Sr + (MODE == 0 ? 16 * u + 4 * lk : 32 * u + 8 * lk));
+    }
+    __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
+    // ---- consume
     double shift = 0.0, scale = 1.0;
     if (v_mode == 0) {
-        shift = sum_partials(wpart, nbw, sh) / (double)n;
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < BW; ++u) a += wp[u];
+        for (int b = BW * nth + tid; b < nbw; b += nth) a += wpart[b];
+        shift = bsum_waves(a, sh, nw) / (double)n;
         scale = 1.0 / (double)n;
     }
-    const int jt = blockIdx.x;
-    const long kbeg = (long)blockIdx.y * KC;
-    const int nit = d.Na / 16;
-    if constexpr (MODE == 0) {
-        double* As = (double*)lds;           // [16][KD]
-        double* zs = As + 16 * KD;           // [KC]
-        const double* T = (const double*)Th;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = u * 256 + tid;
-            const int rl = e / KC, kl = e - rl * KC;
-            As[rl * KD + kl] = T[(size_t)(jt * 16 + rl) * Nsp + kbeg + kl];
+    for (int u = 0; u < BA; ++u) {
+        const int e = u * nth + tid;
+        if (e < UA) {
+            size_t src;
+            int dst;
+            a_unit<MODE>(e, Nsp, plane, src, dst);
+            uint2* q = (uint2*)(lds6 + dst);
+            q[0] = make_uint2(ra[u].x, ra[u].y);
+            q[1] = make_uint2(ra[u].z, ra[u].w);
         }
-        {
-            const long k = kbeg + tid;
-            zs[tid] = k < n ? (v[k] - shift) * scale : 0.0;
+    }
+    for (int e = BA * nth + tid; e < UA; e += nth) {  // small blocks only
+        size_t src;
+        int dst;
+        a_unit<MODE>(e, Nsp, plane, src, dst);
+        const uint4 q4 = *(const uint4*)(Ab + (abase + src) * (MODE == 0 ? 8 : 2));
+        uint2* q = (uint2*)(lds6 + dst);
+        q[0] = make_uint2(q4.x, q4.y);
+        q[1] = make_uint2(q4.z, q4.w);
+    }
+    for (int t = tid; t < OKC; t += nth) {
+        const long k = kbeg + t;
+        const double vk = t == (tid & (OKC - 1)) ? vz : v[min(k, n - 1)];
+        const double z = k < n ? (vk - shift) * scale : 0.0;
+        if constexpr (MODE == 0) {
+            ((double*)(lds6 + 16 * OKD * 8))[t] = z;
+        } else {
+            uint16_t h, l;
+            split2((float)z, h, l);
+            uint16_t* zh = (uint16_t*)(lds6 + 2 * 16 * OKP * 2);
+            zh[t] = h;
+            zh[OKC + t] = l;
         }
-        __syncthreads();
-        for (int it = wave; it < nit; it += 4) {
-            v4d acc = v4d{0, 0, 0, 0};
+    }
+    __syncthreads();
+    for (int it = wave; it < nit; it += nw) {
+        if (it != wave) {
             const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
-#pragma unroll 2
-            for (int k0 = 0; k0 < KC; k0 += 16) {
-                const uint32_t sb = *(const uint32_t*)(Sr + k0 + 4 * lk);
+#pragma unroll
+            for (int u = 0; u < KS; ++u)
+                sb[u] = *(const SW*)(Sr + (MODE == 0 ? 16 * u + 4 * lk : 32 * u + 8 * lk));
+        }
+        if constexpr (MODE == 0) {
+            const double* As = (const double*)lds6;
+            const double* zs = As + 16 * OKD;
+            v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int kl = k0 + 4 * lk + e;
-                    const int sv = (int8_t)(sb >> (8 * e));
+                    const int kl = 16 * u + 4 * lk + e;
+                    const int sv = (int8_t)(sb[u] >> (8 * e));
                     const double z = zs[kl];
                     const double b = sv > 0 ? z : (sv < 0 ? -z : 0.0);
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * KD + kl], b, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * OKD + kl], b, acc, 0, 0, 0);
                 }
+                __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
             }
-            double* out = (double*)part_v + (size_t)blockIdx.y * d.Ma * d.Na;
+            double* out = (double*)part_v + (size_t)kc * d.Ma * d.Na;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 out[(size_t)(jt * 16 + acc_row<double>(lk, q)) * d.Na + it * 16 + lr] = acc[q];
-        }
-    } else {
-        constexpr int KP = KC + 8;
-        uint16_t* Ah = (uint16_t*)lds;       // [16][KP]
-        uint16_t* Al = Ah + 16 * KP;
-        uint16_t* zh = Al + 16 * KP;         // [KC]
-        uint16_t* zl = zh + KC;
-        const uint16_t* Thi = (const uint16_t*)Th;
-        const uint16_t* Tlo = Thi + (size_t)d.Ma * Nsp;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = u * 256 + tid;
-            const int rl = e / KC, kl = e - rl * KC;
-            const size_t g = (size_t)(jt * 16 + rl) * Nsp + kbeg + kl;
-            Ah[rl * KP + kl] = Thi[g];
-            Al[rl * KP + kl] = Tlo[g];
-        }
-        {
-            const long k = kbeg + tid;
-            const float z = k < n ? (float)((v[k] - shift) * scale) : 0.0f;
-            uint16_t h, l;
-            split2(z, h, l);
-            zh[tid] = h;
-            zl[tid] = l;
-        }
-        __syncthreads();
-        for (int it = wave; it < nit; it += 4) {
+        } else {
+            const uint16_t* Ah = (const uint16_t*)lds6;
+            const uint16_t* Al = Ah + 16 * OKP;
+            const uint16_t* zh = Al + 16 * OKP;
+            const uint16_t* zl = zh + OKC;
             v4f acc = v4f{0, 0, 0, 0};
-            const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
-#pragma unroll 2
-            for (int k0 = 0; k0 < KC; k0 += 32) {
-                const int kk = k0 + 8 * lk;
-                const v8bf ah = __builtin_bit_cast(v8bf, *(const v8s*)(Ah + lr * KP + kk));
-                const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(Al + lr * KP + kk));
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
+                const int kk = 32 * u + 8 * lk;
+                const v8bf ah = __builtin_bit_cast(v8bf, *(const v8s*)(Ah + lr * OKP + kk));
+                const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(Al + lr * OKP + kk));
                 const v8s zhv = *(const v8s*)(zh + kk);
                 const v8s zlv = *(const v8s*)(zl + kk);
-                const uint64_t sb = *(const uint64_t*)(Sr + kk);
                 v8s bh, bl;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int8_t sv = (int8_t)(sb >> (8 * e));
+                    const int8_t sv = (int8_t)(sb[u] >> (8 * e));
                     const short sgn = sv < 0 ? (short)0x8000 : (short)0;
                     bh[e] = sv ? (short)(zhv[e] ^ sgn) : (short)0;
                     bl[e] = sv ? (short)(zlv[e] ^ sgn) : (short)0;
@@ -368,8 +673,9 @@ __global__ __launch_bounds__(256) void k_outer3(Dims d, const int8_t* __restrict
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b1, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b2, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b1, acc, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
             }
-            float* out = (float*)part_v + (size_t)blockIdx.y * d.Ma * d.Na;
+            float* out = (float*)part_v + (size_t)kc * d.Ma * d.Na;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 out[(size_t)(jt * 16 + acc_row<float>(lk, q)) * d.Na + it * 16 + lr] = acc[q];
@@ -378,36 +684,47 @@ __global__ __launch_bounds__(256) void k_outer3(Dims d, const int8_t* __restrict
 }
 
 // out[e] = sum_kc part[kc][e] + shift p[e] (parameter entries only); with p,
-// also the block partials of p . out.
+// also the block partials of p . out.  A block covers 64 entries; wave w sums
+// the chunk slabs [w ks/4, (w + 1) ks/4) and the four sums meet in LDS.
 template <typename R>
-__global__ __launch_bounds__(256) void k_reduce2(Dims d, const R* __restrict__ part, int ksplit,
+__global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ part, int ksplit,
                                                  const double* __restrict__ p, double shift,
                                                  double* __restrict__ out,
                                                  double* __restrict__ pap,
                                                  const CgScalars* __restrict__ sc, int cg) {
     if (cg && sc->done) return;
+    __shared__ double ws[4][64];
     __shared__ double sh[4];
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int total = d.Ma * d.Na;
-    double val = 0.0, dot = 0.0;
-    if (e < total) {
+    const int e = blockIdx.x * 64 + lane;
+    const int ec = e < total ? e : total - 1;
+    const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
+    double val = 0.0;
+    int kc = kb;
+    for (; kc + 16 <= ke; kc += 16) {
+        R x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = part[(size_t)(kc + u) * total + ec];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) val += (double)x[u];
+    }
+    for (; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
+    ws[wave][lane] = val;
+    __syncthreads();
+    double dot = 0.0;
+    if (wave == 0 && e < total) {
         const int j = e / d.Na, i = e - j * d.Na;
         const bool keep = (j < d.M && i < d.N) || (d.hb && j < d.M && i == d.N) ||
                           (d.vb && j == d.M && i < d.N);
+        double o = 0.0;
         if (keep) {
-            int kc = 0;
-            for (; kc + 16 <= ksplit; kc += 16) {
-                R x[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = part[(size_t)(kc + u) * total + e];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) val += (double)x[u];
-            }
-            for (; kc < ksplit; ++kc) val += (double)part[(size_t)kc * total + e];
-            if (p) val += shift * p[e];
+            o = (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]);
+            if (p) o += shift * p[e];
         }
-        out[e] = val;
-        if (p) dot = val * p[e];
+        out[e] = o;
+        if (p) dot = o * p[e];
     }
     if (!cg) return;
     dot = bsum256(dot, sh);
@@ -415,18 +732,28 @@ __global__ __launch_bounds__(256) void k_reduce2(Dims d, const R* __restrict__ p
 }
 
 // alpha = rr / p.Ap; x += alpha p; r -= alpha Ap; block partials of r.r.
-__global__ __launch_bounds__(256) void k_update2(int total, double* __restrict__ x,
-                                                 double* __restrict__ r,
-                                                 const double* __restrict__ p,
-                                                 const double* __restrict__ Ap,
-                                                 const double* __restrict__ pap, int nbr,
-                                                 const double* __restrict__ rrp_cur,
-                                                 double* __restrict__ rrp_next, int nbu,
+__global__ __launch_bounds__(256) void k_update2(int total, double* x,
+                                                 double* r,
+                                                 const double* p,
+                                                 const double* Ap,
+                                                 const double* pap, int nbr,
+                                                 const double* rrp_cur,
+                                                 double* rrp_next, int nbu,
                                                  CgScalars* sc) {
-    if (sc->done) return;
     __shared__ double sh[4];
-    const double pAp = sum_partials(pap, nbr, sh);
-    const double rr = sum_partials(rrp_cur, nbu, sh);
+    // the element loads do not depend on the scalars: issue them first
+    // (clamped, unconditional loads: no branch between them)
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const bool own = e < total;
+    const int ec = own ? e : total - 1;
+    const double xe = x[ec], re0 = r[ec], pe = p[ec], ape = Ap[ec];
+    double xa[4], xb[4];
+    pload4(pap, nbr, xa);
+    pload4(rrp_cur, nbu, xb);
+    asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
+    if (sc->done) return;
+    const double pAp = psum(pap, nbr, xa, sh);
+    const double rr = psum(rrp_cur, nbu, xb, sh);
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -439,11 +766,10 @@ __global__ __launch_bounds__(256) void k_update2(int total, double* __restrict__
         sc->alpha = alpha;
         sc->pAp = pAp;
     }
-    const int e = blockIdx.x * 256 + threadIdx.x;
     double q = 0.0;
-    if (e < total) {
-        x[e] += alpha * p[e];
-        const double re = r[e] - alpha * Ap[e];
+    if (own) {
+        x[e] = xe + alpha * pe;
+        const double re = re0 - alpha * ape;
         r[e] = re;
         q = re * re;
     }
@@ -488,8 +814,8 @@ size_t qgt_th_bytes(const Dims& d, int prec, long Nsp) {
 
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q) {
-    const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Kb, 64));
-    k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, q.Nsp, q.Sp, q.St);
+    const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Kq, 64));
+    k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, prec != 0, q.Sp, q.St);
     const dim3 gt((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Ma, 64));
     if (prec == 0)
         k_prep_t<double, 0><<<gt, 256, 0, st>>>((const double*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
@@ -497,16 +823,20 @@ void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s
         k_prep_t<float, 1><<<gt, 256, 0, st>>>((const float*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
 }
 
-int qgt_nbw(long n) { return nb_of(n, 16); }
+int qgt_nbw(long n, int prec) {
+    return nb_of(n, 16 * (prec == 0 ? WRows<0>::RT : WRows<1>::RT));
+}
+long qgt_act_rows(long n) { return (n + W_ROWS_MAX - 1) / W_ROWS_MAX * W_ROWS_MAX; }
 int qgt_nbu(const Dims& d) { return nb_of((long)d.Ma * d.Na, 256); }
+int qgt_nbr(const Dims& d) { return nb_of((long)d.Ma * d.Na, 64); }
 size_t qgt_pop_bytes(const Dims& d, int prec) {
-    return prec == 0 ? (size_t)d.Kb * d.Ma * 8 : (size_t)2 * d.Ma * d.Kb * 2;
+    return prec == 0 ? (size_t)d.Kq * d.Ma * 8 : (size_t)2 * d.Ma * d.Kq * 2;
 }
 
 void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
                      const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
                      const double* rrp_prev, int it, double tol, int maxiter, CgScalars* sc) {
-    const int nb = nb_of((long)d.Ma * d.Kb, 256), nbu = qgt_nbu(d);
+    const int nb = nb_of((long)d.Ma * d.Kq, 256), nbu = qgt_nbu(d);
     if (prec == 0)
         k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbu, it, tol,
                                       maxiter, sc);
@@ -517,36 +847,52 @@ void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
 
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
                   long n, const void* Pop, double* w, const CgScalars* sc) {
-    const int nb = qgt_nbw(n);
-    if (prec == 0)
-        k_w3<0><<<nb, 256, 0, st>>>(d, q.Sp, tact, n, Pop, w, q.wpart, sc);
-    else
-        k_w3<1><<<nb, 256, 0, st>>>(d, q.Sp, tact, n, Pop, w, q.wpart, sc);
+    int waves, per;
+    wave_split(d.Ma / 16, prec == 0 ? 8 : 16, waves, per);
+    const int nb = qgt_nbw(n, prec);
+    if (prec == 0) {
+        k_w5<0><<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, tact, n, Pop, w, q.wpart, sc);
+    } else {
+        const size_t lds = w6_lds(d);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_w6, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+        k_w6<<<nb, 64 * waves, lds, st>>>(d, (const uint16_t*)q.Sp, (const float*)tact, n,
+                                          (const uint16_t*)Pop, w, q.wpart, sc);
+    }
 }
 
-int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / 256); }
+int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / OKC); }
+
+// waves of a contraction-2 block
+static int outer_waves(const Dims& d) {
+    int waves, per;
+    wave_split(d.Na / 16, 16, waves, per);
+    return waves;
+}
 
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
                       const double* v, int v_mode, void* part, const CgScalars* sc) {
-    const dim3 grid((unsigned)(d.Ma / 16), (unsigned)qgt_ksplit(q));
-    const int nbw = qgt_nbw(n);
+    const int ks = qgt_ksplit(q), nj = d.Ma / 16;
+    const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
+    const int nw = outer_waves(d), nbw = qgt_nbw(n, prec);
     if (prec == 0)
-        k_outer3<0><<<grid, 256, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw, part,
-                                         sc);
+        k_outer6<0><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
+                                            part, ks, sc);
     else
-        k_outer3<1><<<grid, 256, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw, part,
-                                         sc);
+        k_outer6<1><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
+                                            part, ks, sc);
 }
 
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                        const double* p, double shift, double* out, double* pap,
                        const CgScalars* sc, int cg) {
-    const int nb = qgt_nbu(d);
+    const int nb = qgt_nbr(d);
     if (prec == 0)
-        k_reduce2<double><<<nb, 256, 0, st>>>(d, (const double*)part, ksplit, p, shift, out, pap,
+        k_reduce3<double><<<nb, 256, 0, st>>>(d, (const double*)part, ksplit, p, shift, out, pap,
                                               sc, cg);
     else
-        k_reduce2<float><<<nb, 256, 0, st>>>(d, (const float*)part, ksplit, p, shift, out, pap,
+        k_reduce3<float><<<nb, 256, 0, st>>>(d, (const float*)part, ksplit, p, shift, out, pap,
                                              sc, cg);
 }
 
@@ -554,7 +900,8 @@ void launch_qgt_update(hipStream_t st, const Dims& d, double* x, double* r, cons
                        const double* Ap, const double* pap, const double* rrp_cur,
                        double* rrp_next, CgScalars* sc) {
     const int nb = qgt_nbu(d);
-    k_update2<<<nb, 256, 0, st>>>(d.Ma * d.Na, x, r, p, Ap, pap, nb, rrp_cur, rrp_next, nb, sc);
+    k_update2<<<nb, 256, 0, st>>>(d.Ma * d.Na, x, r, p, Ap, pap, qgt_nbr(d), rrp_cur, rrp_next, nb,
+                                  sc);
 }
 
 void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,

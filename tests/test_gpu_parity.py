@@ -239,6 +239,37 @@ def test_sr_direction_parity_fp64(wname, chains):
     np.testing.assert_allclose(st.get_params(), params, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_sr_direction_many_sites(precision):
+    """16x16 Heisenberg (N = 256, M = 256, 66,048 parameters; several site and hidden
+    tile groups per block) on a ragged batch of 333 samples: the CG direction
+    satisfies the oracle's SR system.  Bound: the CG tolerance plus the operand
+    rounding of the form (FP64: 1e-15; BF16 split pairs and FP32 sums: 3e-5)
+    times |G| |d| with |G| <= shift + |O_c|_F^2 / n."""
+    torch = _torch()
+    w = HEIS2D.replace(sigma=0.05, alpha=1, n_chains=111, samples_per_chain=3)
+    params = w.params()
+    st, w = make_state(w, precision=precision, params=params)
+    s = synth.sz0_configs(333, w.n_sites, 43)
+    st.load_samples(torch.from_numpy(s))
+    st.expect_and_grad()
+    tol = 1e-6
+    delta, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=tol, maxiter=4000)
+    assert info.converged, info
+    rbm, ham = oracle_model(w, params)
+    O = core.jacobian(rbm, s)
+    E = core.local_energy(rbm, ham, s)
+    f = core.force(O, E)
+    d = delta.cpu().numpy()
+    res = np.linalg.norm(core.qgt_matvec(O, d, 0.01) - f)
+    Oc = O - O.mean(axis=0)
+    gnorm = 0.01 + (Oc * Oc).sum() / O.shape[0]
+    eps = 1e-15 if precision == "fp64" else 3e-5
+    bound = 2 * tol * np.linalg.norm(f) + eps * gnorm * np.linalg.norm(d)
+    print(f"residual {res:.3e} bound {bound:.3e} iterations {info.iterations}")
+    assert res <= bound
+
+
 def test_sr_update_applies_step():
     torch = _torch()
     w = TFIM1D.replace(sigma=0.05)
