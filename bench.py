@@ -68,11 +68,11 @@ def kernel_work(cls: str, w, precision: str):
 
 
 # kernel class -> (source file of its kernel, symbol prefix in profiles)
-KERNELS = {
-    "qgt_w": ("qgt.hip", "k_w3"), "outer": ("qgt.hip", "k_outer3"),
-    "reduce": ("qgt.hip", "k_reduce2"), "cgvec": ("qgt.hip", "k_update2"),
-    "sample": ("sampler.hip", "k_sample"), "eloc": ("eloc.hip", "k_eloc"),
-    "theta": ("theta.hip", "k_theta"),
+KERNELS = {  # (BF16 form, the benchmark's main run)
+    "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer6<1>"),
+    "reduce": ("qgt.hip", "k_reduce3<float>"), "cg_vec": ("qgt.hip", "k_update2"),
+    "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
+    "theta": ("theta.hip", "k_theta_bf16"),
 }
 CSRC = os.path.join(ROOT, "paper_2112_10526_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
@@ -89,7 +89,8 @@ def source_digest(cls: str) -> str:
 
 
 def traffic_file(cls: str, precision: str) -> str:
-    return os.path.join(PROFILES, f"traffic_{KERNELS.get(cls, (None, cls))[1]}_tfim2d_l10_{precision}.md")
+    sym = KERNELS.get(cls, (None, cls))[1].split("<")[0]
+    return os.path.join(PROFILES, f"traffic_{sym}_tfim2d_l10_{precision}.md")
 
 
 def read_traffic(cls: str, precision: str):

@@ -184,8 +184,9 @@ size_t layout(nqs_ctx* c, char* base) {
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
-        b.q.Sp = take((size_t)Nsp * d.Kq * (c->prec == 0 ? 1 : 2));
-        b.q.St = (int8_t*)take((size_t)Nsp * d.Kb);
+        // FP64: int8 spins; BF16 forms: one bit per spin
+        b.q.Sp = take((size_t)Nsp * d.Kq / (c->prec == 0 ? 1 : 8));
+        b.q.St = (int8_t*)take((size_t)Nsp * d.Kb / (c->prec == 0 ? 1 : 8));
         b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
         b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp, c->prec));
         b.rrp = (double*)take(16 * (size_t)qgt_nbu(d));

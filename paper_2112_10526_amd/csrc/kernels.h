@@ -115,8 +115,8 @@ void launch_axpy_update(hipStream_t st, int total, double* x, const double* delt
 
 // qgt.hip: force and on-the-fly QGT products of one SR step, and CG
 struct QgtBatch {
-    void* Sp;        // [Nsp][Kq] augmented spins, sample-major: int8 (FP64) or BF16
-    int8_t* St;      // [Kb][Nsp] augmented spins, site-major
+    void* Sp;        // augmented spins, sample-major: int8 [Nsp][Kq] (FP64) or bits [Nsp][Kq/8]
+    int8_t* St;      // augmented spins, site-major: int8 [Kb][Nsp] (FP64) or bits [Kb][Nsp/8]
     void* Th;        // [Ma][Nsp] t~ hidden-major (FP64) or two BF16 planes
     long Nsp;        // samples padded to a multiple of 256
     double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w

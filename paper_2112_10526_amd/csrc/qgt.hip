@@ -11,9 +11,9 @@
 //
 // Once per SR step the batch is laid out for the matrix cores with the
 // contracted (sample or site) index contiguous:
-//   Sp  [Nsp][Kq]       augmented spins, sample-major   (contraction 1, A):
-//                       int8 (FP64 path) or BF16 (BF16 forms)
-//   St  int8 [Kb][Nsp]  augmented spins, site-major     (contraction 2, B)
+//   Sp  augmented spins, sample-major (contraction 1, A)
+//   St  augmented spins, site-major   (contraction 2, B)
+//       (int8 on the FP64 path; one bit per spin in the BF16 forms)
 //   Th  [Ma][Nsp]       t~ hidden-major: FP64, or two BF16 planes hi/lo
 // FP64 path: v_mfma_f64_16x16x4f64.  FP32/BF16 forms: v_mfma_f32_16x16x32_bf16
 // with every FP32 operand split into two BF16 terms (x = hi + lo) and the
@@ -72,11 +72,14 @@ __device__ __forceinline__ void split2(float x, uint16_t& hi, uint16_t& lo) {
 // ---------------------------------------------------------------------------
 // per-step layout kernels
 // ---------------------------------------------------------------------------
-// Sp holds int8 spins (FP64 path) or their BF16 bit patterns (BF16 forms,
-// sp_bf16 = 1: the contraction-1 A operand without conversion).
+// FP64 path: int8 spins, Sp [Nsp][Kq] and St [Kb][Nsp].
+// BF16 forms: one bit per spin (1 = up, also for the constant column i = N;
+// 0 for padding rows and columns, whose products are zero or discarded):
+// Sp [Nsp][Kq / 8] bytes, bit e of byte b = site 8 b + e;
+// St [Kb][Nsp / 8] bytes, bit e of byte c = sample 8 c + e.
 __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s, int N, long n,
-                                                    int Kb, int Kq, long Nsp, int sp_bf16,
-                                                    void* __restrict__ Sp,
+                                                    int Kb, int Kq, long Nsp, int bits,
+                                                    int8_t* __restrict__ Sp,
                                                     int8_t* __restrict__ St) {
     __shared__ int8_t tile[64][68];
     const long k0 = (long)blockIdx.x * 64;
@@ -88,19 +91,45 @@ __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s
         int8_t v = 0;
         if (k < n) v = i < N ? s[k * N + i] : (i == N ? (int8_t)1 : (int8_t)0);
         tile[kl][il] = v;
-        if (i < Kq) {
-            if (sp_bf16)
-                ((uint16_t*)Sp)[k * Kq + i] = v > 0 ? 0x3F80 : (v < 0 ? 0xBF80 : 0);
-            else
-                ((int8_t*)Sp)[k * Kq + i] = v;
-        }
+        if (!bits && i < Kq) Sp[k * Kq + i] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int il = e >> 6, kl = e & 63;
-        const int i = i0 + il;
-        if (i < Kb) St[(long)i * Nsp + k0 + kl] = tile[kl][il];
+    if (!bits) {
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int il = e >> 6, kl = e & 63;
+            const int i = i0 + il;
+            if (i < Kb) St[(long)i * Nsp + k0 + kl] = tile[kl][il];
+        }
+        return;
     }
+    for (int e = threadIdx.x; e < 64 * 8; e += 256) {
+        // sample-major byte: sample k0 + (e >> 3), sites i0 + 8 (e & 7) + 0..7
+        {
+            const int kl = e >> 3, b = e & 7;
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v |= (uint32_t)(tile[kl][8 * b + q] > 0) << q;
+            const int i = i0 + 8 * b;
+            if (i < Kq) Sp[(k0 + kl) * (Kq / 8) + i / 8] = (int8_t)v;
+        }
+        // site-major byte: site i0 + (e >> 3), samples k0 + 8 (e & 7) + 0..7
+        {
+            const int il = e >> 3, c = e & 7;
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v |= (uint32_t)(tile[8 * c + q][il] > 0) << q;
+            const int i = i0 + il;
+            if (i < Kb) St[(long)i * (Nsp / 8) + (k0 + 8 * c) / 8] = (int8_t)v;
+        }
+    }
+}
+
+// 8 spins (bits of byte b) as BF16 +-1, packed as 8 halves
+__device__ __forceinline__ v8s bits_to_bf16(uint32_t b) {
+    v8s r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (short)(0xBF80 ^ (((b >> e) & 1u) << 15));
+    return r;
 }
 
 template <typename R, int MODE>
@@ -376,88 +405,68 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 }
 
 // ---------------------------------------------------------------------------
-// contraction 1, BF16 form, 64 samples per block: the block's spins (64 rows
-// of Kq BF16 values) are staged in LDS once and shared by all waves; wave w
+// contraction 1, BF16 form, 64 samples per block (four sample tiles): wave w
 // keeps the P fragments of its hidden tile in registers and applies them to
-// the four sample tiles.  All first-tile global loads are issued together.
+// the four tiles, whose spins (one bit each) it reads directly.  All of a
+// wave's global loads are issued together.
 // ---------------------------------------------------------------------------
 constexpr int W6_ROWS = 64;
 
-static inline size_t w6_lds(const Dims& d) { return (size_t)W6_ROWS * (2 * d.Kq + 16); }
-
-__global__ __launch_bounds__(1024) void k_w6(Dims d, const uint16_t* __restrict__ Sp,
+__global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__ Sp,
                                              const float* __restrict__ tact, long n,
                                              const uint16_t* __restrict__ Ph,
                                              double* __restrict__ w, double* __restrict__ wpart,
                                              const CgScalars* __restrict__ sc) {
     constexpr int RT = W6_ROWS / 16;
     if (sc->done) return;
-    extern __shared__ __align__(16) char lds_w6[];
     __shared__ double wsh[16][W6_ROWS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int nth = blockDim.x;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * W6_ROWS;
-    const int Kq = d.Kq, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
-    const int SS = 2 * Kq + 16;  // LDS row stride of the staged spins (bytes)
+    const int Kq = d.Kq, KB = d.Kq / 8, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
     const uint16_t* Pl = Ph + (size_t)Ma * Kq;
-    // ---- issue: spins of the block (16-byte units), the first tile's
-    // activations and first P group (every wave has at least one tile)
-    const int UR = Kq / 8;  // 16-byte units per row
-    const int US = W6_ROWS * UR;
-    const char* Sb = (const char*)(Sp + r0 * Kq);
-    const float* tb = tact + r0 * Mw;             // 32-bit offsets from block bases
+    // 32-bit offsets from block-uniform bases
+    const uint8_t* sb0 = Sp + r0 * KB + lr * KB;  // sample tile rt: + 16 rt KB
+    const float* tb = tact + r0 * Mw;
     const int toff = acc_row<float>(lk, 0) * Mw;  // rows 4 lk + q of each sample tile
-    const uint4 rs0 = *(const uint4*)(Sb + min(tid, US - 1) * 16);
-    const uint4 rs1 = *(const uint4*)(Sb + min(nth + tid, US - 1) * 16);
-    float tv[RT][4];
-    v8s bh[4], bl[4];
-    auto load_tile = [&](int ct, int g) {
-        const int j = ct * 16 + lr;
-        if (g == 0) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
-        }
-        const int prow = j * Kq + 8 * lk + g;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            bh[u] = *(const v8s*)(Ph + prow + 32 * u);
-            bl[u] = *(const v8s*)(Pl + prow + 32 * u);
-        }
-    };
-    load_tile(wave, 0);
-    __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
-    {
-        const int e0 = tid, e1 = nth + tid;
-        if (e0 < US) *(uint4*)(lds_w6 + (e0 / UR) * SS + 16 * (e0 % UR)) = rs0;
-        if (e1 < US) *(uint4*)(lds_w6 + (e1 / UR) * SS + 16 * (e1 % UR)) = rs1;
-        for (int e = 2 * nth + tid; e < US; e += nth)  // wide rows only
-            *(uint4*)(lds_w6 + (e / UR) * SS + 16 * (e % UR)) = *(const uint4*)(Sb + e * 16);
-    }
-    __syncthreads();
     float rsf[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
     for (int ct = wave; ct < nct; ct += nw) {
+        const int j = ct * 16 + lr;
+        float tv[RT][4];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
         v4f acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
+        const int prow = j * Kq + 8 * lk;
         for (int g = 0; g < Kq; g += 128) {
-            if (ct != wave || g != 0) load_tile(ct, g);
+            v8s bh[4], bl[4];
+            uint4 sbits[RT];  // 128 sites of each of the lane's sample rows
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bh[u] = *(const v8s*)(Ph + prow + g + 32 * u);
+                bl[u] = *(const v8s*)(Pl + prow + g + 32 * u);
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) sbits[rt] = *(const uint4*)(sb0 + 16 * rt * KB + g / 8);
+            __builtin_amdgcn_sched_barrier(0);  // the group's loads together
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    const v8bf a = __builtin_bit_cast(
-                        v8bf, *(const v8s*)(lds_w6 + (16 * rt + lr) * SS + 2 * (g + 32 * u + 8 * lk)));
+                    // sites g + 32 u + 8 lk + e: byte 4 u + lk of the group
+                    const uint32_t word = u == 0 ? sbits[rt].x : u == 1 ? sbits[rt].y
+                                        : u == 2 ? sbits[rt].z : sbits[rt].w;
+                    const v8bf a = __builtin_bit_cast(v8bf, bits_to_bf16(word >> (8 * lk)));
                     acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh[u]), acc[rt], 0, 0, 0);
                     acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl[u]), acc[rt], 0, 0, 0);
                 }
-                __builtin_amdgcn_sched_barrier(0);  // one k-step of spins live at a time
             }
         }
 #pragma unroll
@@ -532,7 +541,8 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
     constexpr int BA = MODE == 0 ? 8 : 4;   // t~ units per thread issued up front
     constexpr int BW = 2;                   // mean-w partials per thread issued up front
     constexpr int KS = MODE == 0 ? OKC / 16 : OKC / 32;  // k-steps per chunk
-    using SW = typename std::conditional<MODE == 0, uint32_t, uint64_t>::type;
+    // spins of the lane's site row over the chunk: FP64 path int8 (4 per
+    // k-step), BF16 forms one bit each (byte 4 u + lk of k-step u)
     __shared__ __align__(16) char lds6[MODE == 0 ? 16 * OKD * 8 + OKC * 8
                                                   : 2 * 16 * OKP * 2 + 2 * OKC * 2];
     __shared__ double sh[16];
@@ -566,13 +576,20 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         ra[u] = *(const uint4*)(Ab + (abase + src) * (MODE == 0 ? 8 : 2));
     }
     const double vz = v[min(kbeg + (tid & (OKC - 1)), n - 1)];
-    SW sb[KS];
-    {
-        const int8_t* Sr = St + (size_t)(wave * 16 + lr) * Nsp + kbeg;
+    uint32_t sb[KS];
+    auto load_spins = [&](int it) {
+        if constexpr (MODE == 0) {
+            const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
 #pragma unroll
-        for (int u = 0; u < KS; ++u)
-            sb[u] = *(const SW*)(Sr + (MODE == 0 ? 16 * u + 4 * lk : 32 * u + 8 * lk));
-    }
+            for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
+        } else {
+            const int8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 8) + kbeg / 8;
+            const uint4 x0 = *(const uint4*)Sr, x1 = *(const uint4*)(Sr + 16);
+            sb[0] = x0.x; sb[1] = x0.y; sb[2] = x0.z; sb[3] = x0.w;
+            sb[4] = x1.x; sb[5] = x1.y; sb[6] = x1.z; sb[7] = x1.w;
+        }
+    };
+    load_spins(wave);
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
     // ---- consume
     double shift = 0.0, scale = 1.0;
@@ -621,12 +638,7 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
     }
     __syncthreads();
     for (int it = wave; it < nit; it += nw) {
-        if (it != wave) {
-            const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
-#pragma unroll
-            for (int u = 0; u < KS; ++u)
-                sb[u] = *(const SW*)(Sr + (MODE == 0 ? 16 * u + 4 * lk : 32 * u + 8 * lk));
-        }
+        if (it != wave) load_spins(it);
         if constexpr (MODE == 0) {
             const double* As = (const double*)lds6;
             const double* zs = As + 16 * OKD;
@@ -660,13 +672,13 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
                 const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(Al + lr * OKP + kk));
                 const v8s zhv = *(const v8s*)(zh + kk);
                 const v8s zlv = *(const v8s*)(zl + kk);
+                const uint32_t bits = sb[u] >> (8 * lk);
                 v8s bh, bl;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int8_t sv = (int8_t)(sb[u] >> (8 * e));
-                    const short sgn = sv < 0 ? (short)0x8000 : (short)0;
-                    bh[e] = sv ? (short)(zhv[e] ^ sgn) : (short)0;
-                    bl[e] = sv ? (short)(zlv[e] ^ sgn) : (short)0;
+                for (int e = 0; e < 8; ++e) {  // spin down: flip the sign of z
+                    const short sgn = (short)((~(bits >> e) & 1u) << 15);
+                    bh[e] = (short)(zhv[e] ^ sgn);
+                    bl[e] = (short)(zlv[e] ^ sgn);
                 }
                 const v8bf b1 = __builtin_bit_cast(v8bf, bh);
                 const v8bf b2 = __builtin_bit_cast(v8bf, bl);
@@ -815,7 +827,7 @@ size_t qgt_th_bytes(const Dims& d, int prec, long Nsp) {
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q) {
     const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Kq, 64));
-    k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, prec != 0, q.Sp, q.St);
+    k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, prec != 0, (int8_t*)q.Sp, q.St);
     const dim3 gt((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Ma, 64));
     if (prec == 0)
         k_prep_t<double, 0><<<gt, 256, 0, st>>>((const double*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
@@ -853,12 +865,8 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
     if (prec == 0) {
         k_w5<0><<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, tact, n, Pop, w, q.wpart, sc);
     } else {
-        const size_t lds = w6_lds(d);
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void*)k_w6, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
-        k_w6<<<nb, 64 * waves, lds, st>>>(d, (const uint16_t*)q.Sp, (const float*)tact, n,
-                                          (const uint16_t*)Pop, w, q.wpart, sc);
+        k_w6<<<nb, 64 * waves, 0, st>>>(d, (const uint8_t*)q.Sp, (const float*)tact, n,
+                                        (const uint16_t*)Pop, w, q.wpart, sc);
     }
 }
 
