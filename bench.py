@@ -70,7 +70,7 @@ def kernel_work(cls: str, w, precision: str):
 # kernel class -> (source file of its kernel, symbol prefix in profiles)
 KERNELS = {  # (BF16 form, the benchmark's main run)
     "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer6<1>"),
-    "reduce": ("qgt.hip", "k_reduce3<float>"), "cg_vec": ("qgt.hip", "k_update2"),
+    "reduce": ("qgt.hip", "k_update3<float>"), "cg_vec": ("qgt.hip", "k_pnew<1>"),
     "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
     "theta": ("theta.hip", "k_theta_bf16"),
 }

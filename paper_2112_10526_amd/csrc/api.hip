@@ -28,7 +28,7 @@ struct Buffers {
     void* tx;
     double *eloc, *vvec, *wbuf, *stats, *dpart;
     QgtBatch q;
-    double *rrp, *pap;
+    double *rrp, *pap, *ppart;
     void* Pop;
     uint32_t* acc_count;
     CgScalars* sc;
@@ -189,8 +189,9 @@ size_t layout(nqs_ctx* c, char* base) {
         b.q.St = (int8_t*)take((size_t)Nsp * d.Kb / (c->prec == 0 ? 1 : 8));
         b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
         b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp, c->prec));
-        b.rrp = (double*)take(16 * (size_t)qgt_nbu(d));
-        b.pap = (double*)take(8 * (size_t)qgt_nbr(d));
+        b.rrp = (double*)take(16 * (size_t)qgt_nbr(d));
+        b.pap = (double*)take(8 * (size_t)qgt_nbo(d, b.q));   // p.G p partials
+        b.ppart = (double*)take(8 * (size_t)qgt_nbp(d));      // p.p partials
         b.Pop = take(qgt_pop_bytes(d, c->prec));
         const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
         b.part = take(es * ks * PV);
@@ -414,7 +415,8 @@ void issue_energy_grad(nqs_ctx* c) {
     }
     {
         PROF(NQS_PROF_OUTER);
-        launch_qgt_outer(c->stream, c->d, c->prec, c->b.q, n, c->b.vvec, 1, c->b.part, c->b.sc);
+        launch_qgt_outer(c->stream, c->d, c->prec, c->b.q, n, c->b.vvec, 1, c->b.part, c->b.pap,
+                         c->b.sc);
     }
     {
         PROF(NQS_PROF_REDUCE);
@@ -478,19 +480,19 @@ void issue_cg_init(nqs_ctx* c, double tol, int maxiter) {
 // (the direction alternates between two buffers) and applies the QGT.
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
     const Dims& d = c->d;
-    const int nbu = qgt_nbu(d);
+    const int nbv = qgt_nbr(d);
     for (int it = 0; it < iters; ++it) {
         if (kind == NQS_QGT_ONTHEFLY) {
             const long k = c->cg_iter;
             double* p_old = (k & 1) ? c->b.p2 : c->b.p;
             double* p_new = (k & 1) ? c->b.p : c->b.p2;
-            double* rr_cur = c->b.rrp + (k & 1) * nbu;
-            double* rr_oth = c->b.rrp + ((k + 1) & 1) * nbu;
+            double* rr_cur = c->b.rrp + (k & 1) * nbv;
+            double* rr_oth = c->b.rrp + ((k + 1) & 1) * nbv;
             c->cg_iter += 1;
             {
                 PROF(NQS_PROF_CGVEC);
                 launch_qgt_pnew(c->stream, d, c->prec, c->b.r, p_old, p_new, c->b.Pop, rr_cur,
-                                rr_oth, (int)k, c->cg_tol, c->cg_maxiter, c->b.sc);
+                                rr_oth, (int)k, c->cg_tol, c->cg_maxiter, c->b.ppart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_QGT_W);
@@ -500,17 +502,12 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             {
                 PROF(NQS_PROF_OUTER);
                 launch_qgt_outer(c->stream, d, c->prec, c->b.q, c->Ns, c->b.wbuf, 0, c->b.part,
-                                 c->b.sc);
+                                 c->b.pap, c->b.sc);
             }
             {
                 PROF(NQS_PROF_REDUCE);
-                launch_qgt_reduce(c->stream, d, c->prec, c->b.part, qgt_ksplit(c->b.q), p_new,
-                                  shift, c->b.Ap, c->b.pap, c->b.sc, 1);
-            }
-            {
-                PROF(NQS_PROF_CGVEC);
-                launch_qgt_update(c->stream, d, c->b.x, c->b.r, p_new, c->b.Ap, c->b.pap, rr_cur,
-                                  rr_oth, c->b.sc);
+                launch_qgt_update3(c->stream, d, c->prec, c->b.q, c->b.part, shift, c->b.x,
+                                   c->b.r, p_new, c->b.pap, c->b.ppart, rr_cur, rr_oth, c->b.sc);
             }
         } else {
             {

@@ -127,24 +127,29 @@ int qgt_nbw(long n, int prec);
 // activation rows to allocate for n samples (whole contraction-1 blocks)
 long qgt_act_rows(long n);
 int qgt_nbu(const Dims& d);
-int qgt_nbr(const Dims& d);
+int qgt_nbr(const Dims& d);   // CG vector blocks (64 entries): r.r partials
+int qgt_nbp(const Dims& d);   // direction blocks: p.p partials
 int qgt_ksplit(const QgtBatch& q);
+int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per chunk)
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q);
 size_t qgt_pop_bytes(const Dims& d, int prec);
 void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
                      const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, int it, double tol, int maxiter, CgScalars* sc);
+                     const double* rrp_prev, int it, double tol, int maxiter, double* ppart,
+                     CgScalars* sc);
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
                   long n, const void* Pop, double* w, const CgScalars* sc);
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
-                      const double* v, int v_mode, void* part, const CgScalars* sc);
+                      const double* v, int v_mode, void* part, double* papart,
+                      const CgScalars* sc);
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                        const double* p, double shift, double* out, double* pap,
                        const CgScalars* sc, int cg);
-void launch_qgt_update(hipStream_t st, const Dims& d, double* x, double* r, const double* p,
-                       const double* Ap, const double* pap, const double* rrp_cur,
-                       double* rrp_next, CgScalars* sc);
+void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
+                        const void* part, double shift, double* x, double* r, const double* p,
+                        const double* papart, const double* ppart, const double* rrp_cur,
+                        double* rrp_next, CgScalars* sc);
 void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
                      double* p, double* rrp0, CgScalars* sc);
 

@@ -167,8 +167,8 @@ __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long
 //   rr_it <= tol^2 rr_0, it >= maxiter or non-finite; else beta = rr_it /
 //   rr_{it-1} (0 at it = 0) and p_new = r + beta p_old.
 // p_new is written in FP64 [Ma][Na] and in the operand layout of
-// contraction 1: FP64 path k-major [Kq][Ma]; BF16 forms two planes [Ma][Kq].
-// One thread per (j, i < Kq).
+// contraction 1: FP64 path k-major [Kq][Ma]; BF16 forms two planes [Ma][Kq];
+// with block partials of p . p.  One thread per (j, i < Kq).
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
@@ -176,7 +176,8 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
                                               double* p_new, void* Pop,
                                               const double* rrp_cur,
                                               const double* rrp_prev, int nbu, int it,
-                                              double tol, int maxiter, CgScalars* sc) {
+                                              double tol, int maxiter, double* ppart,
+                                              CgScalars* sc) {
     __shared__ double sh[4];
     // the element loads do not depend on the scalars: issue them first
     // (clamped, unconditional loads: no branch between them)
@@ -210,20 +211,24 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
         }
     }
     if (stop) return;
-    if (e >= d.Ma * d.Kq) return;
     double v = 0.0;
     if (own) {
         v = re + beta * pe;
         p_new[g] = v;
     }
-    if constexpr (MODE == 0) {
-        ((double*)Pop)[(size_t)i * d.Ma + j] = v;
-    } else {
-        uint16_t hi, lo;
-        split2((float)v, hi, lo);
-        ((uint16_t*)Pop)[e] = hi;
-        ((uint16_t*)Pop)[(size_t)d.Ma * d.Kq + e] = lo;
+    if (e < d.Ma * d.Kq) {
+        if constexpr (MODE == 0) {
+            ((double*)Pop)[(size_t)i * d.Ma + j] = v;
+        } else {
+            uint16_t hi, lo;
+            split2((float)v, hi, lo);
+            ((uint16_t*)Pop)[e] = hi;
+            ((uint16_t*)Pop)[(size_t)d.Ma * d.Kq + e] = lo;
+        }
     }
+    // block partials of p . p (for the diagonal-shift part of p . (G + shift) p)
+    const double pp = bsum256(v * v, sh);
+    if (threadIdx.x == 0) ppart[blockIdx.x] = pp;
 }
 
 // block sum over nw waves, identical order in every block
@@ -501,7 +506,9 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
 // ---------------------------------------------------------------------------
 // contraction 2: part[kc][j][i] = sum_{k in chunk kc} t~_kj z_k s~_ki
 // v_mode 0: z_k = (w_k - mean w) / n with mean w from the contraction-1
-// partials; v_mode 1: z_k = v_k.  One block per (hidden tile jt, chunk kc of
+// partials, and the blocks of hidden tile 0 write their chunk's partial of
+// p . G p without the shift; v_mode 1: z_k = v_k.
+// One block per (hidden tile jt, chunk kc of
 // 256 samples); the tile's t~ rows and the chunk's z are staged in LDS and
 // wave w computes site tiles w, w + nw, ..., holding its spins in registers.
 // All global loads of a block are issued before any of them is consumed
@@ -535,6 +542,7 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
                                                  const double* __restrict__ v, int v_mode,
                                                  const double* __restrict__ wpart, int nbw,
                                                  void* __restrict__ part_v, int ksplit,
+                                                 double* __restrict__ papart,
                                                  const CgScalars* __restrict__ sc) {
     if (v_mode == 0 && sc->done) return;
     constexpr int UA = MODE == 0 ? 16 * OKC * 8 / 16 : 2 * 16 * OKC * 2 / 16;
@@ -550,7 +558,7 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
     const int nj = d.Ma / 16;
     const int L = blockIdx.x, x = L % NXCD, m = L / NXCD;
     const int jt = m % nj, kc = x + NXCD * (m / nj);
-    if (kc >= ksplit) return;
+    if (kc >= ksplit) return;  // no chunk for this block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nth = blockDim.x, nw = nth >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -622,10 +630,12 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         q[0] = make_uint2(q4.x, q4.y);
         q[1] = make_uint2(q4.z, q4.w);
     }
+    double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
     for (int t = tid; t < OKC; t += nth) {
         const long k = kbeg + t;
         const double vk = t == (tid & (OKC - 1)) ? vz : v[min(k, n - 1)];
         const double z = k < n ? (vk - shift) * scale : 0.0;
+        zw += z * (vk - shift);
         if constexpr (MODE == 0) {
             ((double*)(lds6 + 16 * OKD * 8))[t] = z;
         } else {
@@ -635,6 +645,12 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
             zh[t] = h;
             zh[OKC + t] = l;
         }
+    }
+    // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
+    // chunk, from the blocks of hidden tile 0
+    if (v_mode == 0 && jt == 0) {
+        const double t = bsum_waves(zw, sh, nw);
+        if (tid == 0) papart[kc] = t;
     }
     __syncthreads();
     for (int it = wave; it < nit; it += nw) {
@@ -743,29 +759,45 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
     if (threadIdx.x == 0) pap[blockIdx.x] = dot;
 }
 
-// alpha = rr / p.Ap; x += alpha p; r -= alpha Ap; block partials of r.r.
-__global__ __launch_bounds__(256) void k_update2(int total, double* x,
-                                                 double* r,
-                                                 const double* p,
-                                                 const double* Ap,
-                                                 const double* pap, int nbr,
-                                                 const double* rrp_cur,
-                                                 double* rrp_next, int nbu,
+// CG update, 64 entries per block (wave w sums chunk slabs [w ks/4, (w+1) ks/4)):
+//   Ap = sum_kc part[kc] + shift p (parameter entries only),
+//   p.Ap = sum of the per-chunk partials of p.G p + shift * sum of the p.p partials,
+//   alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; block partials of r.r.
+template <typename R>
+__global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int ksplit, double shift,
+                                                 double* x, double* r, const double* p,
+                                                 const double* papart, int npa,
+                                                 const double* ppart, int npp,
+                                                 const double* rrp_cur, double* rrp_next, int nbv,
                                                  CgScalars* sc) {
+    __shared__ double ws[4][64];
     __shared__ double sh[4];
-    // the element loads do not depend on the scalars: issue them first
-    // (clamped, unconditional loads: no branch between them)
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    const bool own = e < total;
-    const int ec = own ? e : total - 1;
-    const double xe = x[ec], re0 = r[ec], pe = p[ec], ape = Ap[ec];
-    double xa[4], xb[4];
-    pload4(pap, nbr, xa);
-    pload4(rrp_cur, nbu, xb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int total = d.Ma * d.Na;
+    const int e = blockIdx.x * 64 + lane;
+    const int ec = e < total ? e : total - 1;
+    // every load that does not depend on the scalars, issued up front
+    const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
+    R xs[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
+    const double xe = x[ec], re0 = r[ec], pe = p[ec];
+    double xa[4], xb[4], xc[4];
+    pload4(papart, npa, xa);
+    pload4(ppart, npp, xb);
+    pload4(rrp_cur, nbv, xc);
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
     if (sc->done) return;
-    const double pAp = psum(pap, nbr, xa, sh);
-    const double rr = psum(rrp_cur, nbu, xb, sh);
+    double val = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        if (kb + u < ke) val += (double)xs[u];
+    for (int kc = kb + 16; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
+    ws[wave][lane] = val;
+    const double pJz = psum(papart, npa, xa, sh);
+    const double pp = psum(ppart, npp, xb, sh);
+    const double rr = psum(rrp_cur, nbv, xc, sh);  // (its barriers also publish ws)
+    const double pAp = pJz + shift * pp;
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -779,23 +811,27 @@ __global__ __launch_bounds__(256) void k_update2(int total, double* x,
         sc->pAp = pAp;
     }
     double q = 0.0;
-    if (own) {
+    if (wave == 0 && e < total) {
+        const int j = e / d.Na, i = e - j * d.Na;
+        const bool keep = (j < d.M && i < d.N) || (d.hb && j < d.M && i == d.N) ||
+                          (d.vb && j == d.M && i < d.N);
+        const double ap = keep ? (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]) + shift * pe
+                               : 0.0;
         x[e] = xe + alpha * pe;
-        const double re = re0 - alpha * ape;
-        r[e] = re;
-        q = re * re;
+        const double rn = re0 - alpha * ap;
+        r[e] = rn;
+        q = rn * rn;
     }
     q = bsum256(q, sh);
     if (threadIdx.x == 0) rrp_next[blockIdx.x] = q;
 }
 
-// x = 0, r = p = f, partials of f.f; clears the CG flags.
-__global__ __launch_bounds__(256) void k_init2(int total, const double* __restrict__ f,
-                                               double* __restrict__ x, double* __restrict__ r,
-                                               double* __restrict__ p, double* __restrict__ rrp0,
-                                               CgScalars* sc) {
-    __shared__ double sh[4];
-    const int e = blockIdx.x * 256 + threadIdx.x;
+// x = 0, r = p = f, partials of f.f (64 entries per block); clears the CG flags.
+__global__ __launch_bounds__(64) void k_init2(int total, const double* __restrict__ f,
+                                              double* __restrict__ x, double* __restrict__ r,
+                                              double* __restrict__ p, double* __restrict__ rrp0,
+                                              CgScalars* sc) {
+    const int e = blockIdx.x * 64 + threadIdx.x;
     double q = 0.0;
     if (e < total) {
         const double fe = f[e];
@@ -804,7 +840,7 @@ __global__ __launch_bounds__(256) void k_init2(int total, const double* __restri
         p[e] = fe;
         q = fe * fe;
     }
-    q = bsum256(q, sh);
+    q = wave_sum(q);
     if (threadIdx.x == 0) rrp0[blockIdx.x] = q;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->done = 0;
@@ -847,14 +883,15 @@ size_t qgt_pop_bytes(const Dims& d, int prec) {
 
 void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
                      const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, int it, double tol, int maxiter, CgScalars* sc) {
-    const int nb = nb_of((long)d.Ma * d.Kq, 256), nbu = qgt_nbu(d);
+                     const double* rrp_prev, int it, double tol, int maxiter, double* ppart,
+                     CgScalars* sc) {
+    const int nb = qgt_nbp(d), nbv = qgt_nbr(d);
     if (prec == 0)
-        k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbu, it, tol,
-                                      maxiter, sc);
+        k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, it, tol,
+                                      maxiter, ppart, sc);
     else
-        k_pnew<1><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbu, it, tol,
-                                      maxiter, sc);
+        k_pnew<1><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, it, tol,
+                                      maxiter, ppart, sc);
 }
 
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
@@ -880,16 +917,17 @@ static int outer_waves(const Dims& d) {
 }
 
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
-                      const double* v, int v_mode, void* part, const CgScalars* sc) {
+                      const double* v, int v_mode, void* part, double* papart,
+                      const CgScalars* sc) {
     const int ks = qgt_ksplit(q), nj = d.Ma / 16;
     const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
     const int nw = outer_waves(d), nbw = qgt_nbw(n, prec);
     if (prec == 0)
         k_outer6<0><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
-                                            part, ks, sc);
+                                            part, ks, papart, sc);
     else
         k_outer6<1><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
-                                            part, ks, sc);
+                                            part, ks, papart, sc);
 }
 
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
@@ -904,18 +942,27 @@ void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part
                                              sc, cg);
 }
 
-void launch_qgt_update(hipStream_t st, const Dims& d, double* x, double* r, const double* p,
-                       const double* Ap, const double* pap, const double* rrp_cur,
-                       double* rrp_next, CgScalars* sc) {
-    const int nb = qgt_nbu(d);
-    k_update2<<<nb, 256, 0, st>>>(d.Ma * d.Na, x, r, p, Ap, pap, qgt_nbr(d), rrp_cur, rrp_next, nb,
-                                  sc);
-}
-
 void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
                      double* p, double* rrp0, CgScalars* sc) {
-    const int nb = qgt_nbu(d);
-    k_init2<<<nb, 256, 0, st>>>(d.Ma * d.Na, f, x, r, p, rrp0, sc);
+    // 64 entries per block: the r.r partials match those of k_update3
+    const int nb = qgt_nbr(d);
+    k_init2<<<nb, 64, 0, st>>>(d.Ma * d.Na, f, x, r, p, rrp0, sc);
+}
+
+int qgt_nbp(const Dims& d) { return nb_of((long)d.Ma * d.Kq, 256); }
+int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
+
+void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
+                        const void* part, double shift, double* x, double* r, const double* p,
+                        const double* papart, const double* ppart, const double* rrp_cur,
+                        double* rrp_next, CgScalars* sc) {
+    const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q), npp = qgt_nbp(d);
+    if (prec == 0)
+        k_update3<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, shift, x, r, p, papart,
+                                              npa, ppart, npp, rrp_cur, rrp_next, nb, sc);
+    else
+        k_update3<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, shift, x, r, p, papart,
+                                             npa, ppart, npp, rrp_cur, rrp_next, nb, sc);
 }
 
 }  // namespace nqs
