@@ -306,8 +306,8 @@ enum {
     NQS_PROF_STATS = 3,     /* energy statistics and centring */
     NQS_PROF_QGT_W = 4,     /* w = J v (contraction 1) */
     NQS_PROF_OUTER = 5,     /* J^T z (contraction 2, force and QGT product) */
-    NQS_PROF_REDUCE = 6,    /* chunk reduction + diagonal shift + p.Ap */
-    NQS_PROF_CGVEC = 7,     /* CG vector updates and dot products */
+    NQS_PROF_REDUCE = 6,    /* chunk reduction + diagonal shift + CG update of x and r */
+    NQS_PROF_CGVEC = 7,     /* CG direction and dot products */
     NQS_PROF_JACOBIAN = 8,  /* dense Jacobian build and centring */
     NQS_PROF_GRAM = 9,      /* dense QGT Gram matrix */
     NQS_PROF_DENSE_MV = 10, /* dense QGT product */
@@ -318,14 +318,22 @@ enum {
 
 /* Time every launch of the kernel classes selected by `class_mask` (bit k =
  * class k) with HIP events on the context's stream; 0 switches timing off.
- * Enabling clears earlier totals.  Up to 65536 launches are timed; later
- * launches are counted but not timed. */
+ * Enabling clears earlier totals.  Up to 16384 launches are timed; later ones
+ * are neither timed nor counted.  While a CG kernel class is timed, CG
+ * iterations are launched one kernel at a time (no graph replay). */
 int nqs_profile_enable(nqs_ctx* ctx, uint32_t class_mask);
 
 /* Totals since nqs_profile_enable: ms[k] summed kernel time and launches[k]
- * launch count for k < n (n <= NQS_PROF_CLASSES); host arrays.  Synchronises
- * the stream. */
+ * timed launches for k < n (n <= NQS_PROF_CLASSES); host arrays.
+ * Synchronises the stream. */
 int nqs_profile_read(nqs_ctx* ctx, double* ms, int64_t* launches, int n);
+
+/* On-the-fly CG (section "Solving linear systems"): with enable != 0 (the
+ * default) a full batch of iterations is captured once as a HIP graph and
+ * replayed, which removes most of the per-kernel launch cost; with 0 every
+ * kernel is launched on the stream.  The results are identical either way.
+ * Drops a captured graph; synchronises the stream. */
+int nqs_set_cg_graphs(nqs_ctx* ctx, int enable);
 
 /* Name of kernel class k, or NULL. */
 const char* nqs_profile_class_name(int k);

@@ -24,7 +24,7 @@ EXPORTS = [
     "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_thermalize", "nqs_load_samples", "nqs_local_energy",
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
     "nqs_vmc_step", "nqs_batch_step", "nqs_profile_enable", "nqs_profile_read",
-    "nqs_profile_class_name",
+    "nqs_profile_class_name", "nqs_set_cg_graphs",
 ]
 PROF_CLASSES = ["sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
                 "jacobian", "gram", "dense_matvec", "update", "prepare"]
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         "nqs_profile_enable": (I, [V, ctypes.c_uint32]),
         "nqs_profile_read": (I, [V, V, V, I]),
         "nqs_profile_class_name": (ctypes.c_char_p, [I]),
+        "nqs_set_cg_graphs": (I, [V, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -90,6 +90,10 @@ struct nqs_ctx {
     std::vector<int> ev_class;
     size_t ev_used = 0;
     int64_t prof_count[NQS_PROF_CLASSES] = {};
+    // a full batch of on-the-fly CG iterations captured as a HIP graph
+    bool graphs = true;
+    hipGraphExec_t cg_graph = nullptr;
+    hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -106,11 +110,11 @@ struct ProfScope {
     long slot = -1;
     ProfScope(nqs_ctx* ctx, int k) : c(ctx) {
         if (!((c->prof_mask >> k) & 1u)) return;
-        c->prof_count[k] += 1;
-        if (c->ev_used + 2 > c->ev.size()) return;
+        if (c->ev_used + 2 > c->ev.size()) return;  // pool full: neither timed nor counted
         slot = (long)c->ev_used;
         c->ev_used += 2;
         c->ev_class[slot / 2] = k;
+        c->prof_count[k] += 1;
         hipEventRecord(c->ev[slot], c->stream);
     }
     ~ProfScope() {
@@ -468,11 +472,12 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
                    maxiter);
 }
 
-void issue_cg_init(nqs_ctx* c, double tol, int maxiter) {
+void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
     c->cg_iter = 0;
     c->cg_tol = tol;
     c->cg_maxiter = maxiter;
-    launch_qgt_init(c->stream, c->d, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.rrp, c->b.sc);
+    launch_qgt_init(c->stream, c->d, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.rrp, tol, maxiter,
+                    shift, c->b.sc);
 }
 
 // CG iterations.  On-the-fly form: iteration it first tests convergence on
@@ -492,7 +497,7 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             {
                 PROF(NQS_PROF_CGVEC);
                 launch_qgt_pnew(c->stream, d, c->prec, c->b.r, p_old, p_new, c->b.Pop, rr_cur,
-                                rr_oth, (int)k, c->cg_tol, c->cg_maxiter, c->b.ppart, c->b.sc);
+                                rr_oth, c->b.ppart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_QGT_W);
@@ -506,8 +511,8 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             }
             {
                 PROF(NQS_PROF_REDUCE);
-                launch_qgt_update3(c->stream, d, c->prec, c->b.q, c->b.part, shift, c->b.x,
-                                   c->b.r, p_new, c->b.pap, c->b.ppart, rr_cur, rr_oth, c->b.sc);
+                launch_qgt_update3(c->stream, d, c->prec, c->b.q, c->b.part, c->b.x, c->b.r,
+                                   p_new, c->b.pap, c->b.ppart, rr_cur, rr_oth, c->b.sc);
             }
         } else {
             {
@@ -552,20 +557,69 @@ int sr_status(nqs_ctx* c, nqs_sr_info* info) {
     return NQS_OK;
 }
 
+void drop_graphs(nqs_ctx* c) {
+    if (c->cg_graph) hipGraphExecDestroy(c->cg_graph);
+    c->cg_graph = nullptr;
+}
+
+// Records one batch of `every` on-the-fly iterations (starting at an even
+// iteration, so the alternating buffers line up) as a graph.
+int capture_batch(nqs_ctx* c, double shift, int every) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t run = c->stream;
+    const long it0 = c->cg_iter;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        issue_cg_iters(c, NQS_QGT_ONTHEFLY, shift, every);
+        e = hipStreamEndCapture(c->cap_stream, &graph);
+    }
+    c->stream = run;
+    c->cg_iter = it0;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->cg_graph, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->cg_graph = nullptr;
+        return fail(c, NQS_EDEVICE, std::string("CG graph capture: ") + hipGetErrorString(e));
+    }
+    return NQS_OK;
+}
+
+// kernel classes of the on-the-fly CG iterations
+constexpr uint32_t CG_CLASSES = (1u << NQS_PROF_QGT_W) | (1u << NQS_PROF_OUTER) |
+                                (1u << NQS_PROF_REDUCE) | (1u << NQS_PROF_CGVEC);
+
 // Issues CG iterations in batches and reads the stop flag of each batch while
 // the next batch is already queued, so the device never waits for the host.
 // Iterations issued after the stop return at once (every CG kernel tests the
-// flag first).
+// flag first).  Full on-the-fly batches are replayed from one captured graph
+// (the iteration kernels take their scalars from the device) unless CG kernel
+// classes are being timed, which needs one event pair per launch and batches
+// of one iteration.
 int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
-    const int every = cg_check_interval();
+    // while CG kernels are timed, the stop flag is read after every iteration
+    // so that almost no launch after the stop is timed
+    const int every = (c->prof_mask & CG_CLASSES) ? 1 : cg_check_interval();
     // the on-the-fly form tests convergence at the start of an iteration
     const int limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
+    const bool use_graphs = c->graphs && kind == NQS_QGT_ONTHEFLY && every % 2 == 0 &&
+                            !(c->prof_mask & CG_CLASSES);
     int launched = 0, issued = 0, checked = 0;
     auto issue_batch = [&]() -> int {
         const int k = (limit - launched) < every ? (limit - launched) : every;
-        issue_cg_iters(c, kind, shift, k);
-        launched += k;
         const int slot = issued & 1;
+        if (use_graphs && k == every && c->cg_iter % 2 == 0) {
+            if (!c->cg_graph) {
+                const int st = capture_batch(c, shift, every);
+                if (st) return st;
+            }
+            HIPCHK(c, hipGraphLaunch(c->cg_graph, c->stream));
+            c->cg_iter += every;
+        } else {
+            issue_cg_iters(c, kind, shift, k);
+        }
+        launched += k;
         HIPCHK(c, hipMemcpyAsync(&c->h_flag[slot], &c->b.sc->done, sizeof(int32_t),
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipEventRecord(c->flag_ev[slot], c->stream));
@@ -580,8 +634,9 @@ int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
             st = issue_batch();
             if (st) return st;
         }
-        HIPCHK(c, hipEventSynchronize(c->flag_ev[checked & 1]));
-        const bool stop = c->h_flag[checked & 1] != 0;
+        const int slot = checked & 1;
+        HIPCHK(c, hipEventSynchronize(c->flag_ev[slot]));
+        const bool stop = c->h_flag[slot] != 0;
         ++checked;
         if (stop) break;
     }
@@ -648,6 +703,8 @@ void nqs_destroy(nqs_ctx* c) {
         if (e) hipEventDestroy(e);
     if (c->h_acc) hipHostFree(c->h_acc);
     for (auto& e : c->ev) hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -745,6 +802,7 @@ int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
     if ((uintptr_t)dev_ptr % ALIGN) return fail(c, NQS_EINVAL, "workspace must be 256-byte aligned");
     int st = set_device(c);
     if (st) return st;
+    drop_graphs(c);  // captured against the previous buffers
     c->ws = (char*)dev_ptr;
     c->ws_bytes = bytes;
     layout(c, c->ws);
@@ -1047,7 +1105,7 @@ int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double
     if (st) return st;
     const int mi = default_maxiter(c, maxiter);
     if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi);
-    else issue_cg_init(c, tol, mi);
+    else issue_cg_init(c, tol, mi, diag_shift);
     st = run_cg(c, kind, diag_shift, mi);
     if (st) return st;
     issue_finish_solve(c, kind);
@@ -1097,7 +1155,7 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
         lim[k] = cfgs[k].qgt == NQS_QGT_ONTHEFLY ? mi[k] + 1 : mi[k];
         if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfgs[k].cg_tol, mi[k]);
-        else issue_cg_init(c, cfgs[k].cg_tol, mi[k]);
+        else issue_cg_init(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
         st[k] = last_launch(c);
     }
     // lock-step CG: a block of iterations on every unconverged context, then
@@ -1156,10 +1214,10 @@ int nqs_profile_enable(nqs_ctx* c, uint32_t class_mask) {
     if (st) return st;
     if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
     if (class_mask && c->ev.empty()) {
-        const size_t pairs = 4096;
+        const size_t pairs = 16384;
         c->ev.resize(2 * pairs);
         c->ev_class.assign(pairs, 0);
-        for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+        for (auto& e : c->ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     c->prof_mask = class_mask;
     c->ev_used = 0;
@@ -1181,6 +1239,16 @@ int nqs_profile_read(nqs_ctx* c, double* ms, int64_t* launches, int n) {
         if (ms) ms[k] = tot[k];
         if (launches) launches[k] = c->prof_count[k];
     }
+    return NQS_OK;
+}
+
+int nqs_set_cg_graphs(nqs_ctx* c, int enable) {
+    if (!c) return NQS_EINVAL;
+    int st = set_device(c);
+    if (st) return st;
+    if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->graphs = enable != 0;
     return NQS_OK;
 }
 

@@ -39,6 +39,12 @@ struct CgScalars {
     int32_t maxiter;
     int32_t bad;      // non-finite scalar seen
     uint32_t counter[8];  // last-block counters
+    // on-the-fly CG: set by the init kernel, so that the iteration kernels take
+    // no per-iteration arguments (a batch of iterations can be replayed as is)
+    double tol;       // relative residual tolerance
+    double shift;     // diagonal shift
+    int32_t it;       // index of the next iteration (advanced by the update kernel)
+    int32_t pad1;
 };
 
 // tables.hip
@@ -136,8 +142,7 @@ void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s
 size_t qgt_pop_bytes(const Dims& d, int prec);
 void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
                      const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, int it, double tol, int maxiter, double* ppart,
-                     CgScalars* sc);
+                     const double* rrp_prev, double* ppart, CgScalars* sc);
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
                   long n, const void* Pop, double* w, const CgScalars* sc);
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
@@ -147,11 +152,12 @@ void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part
                        const double* p, double shift, double* out, double* pap,
                        const CgScalars* sc, int cg);
 void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
-                        const void* part, double shift, double* x, double* r, const double* p,
+                        const void* part, double* x, double* r, const double* p,
                         const double* papart, const double* ppart, const double* rrp_cur,
                         double* rrp_next, CgScalars* sc);
 void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
-                     double* p, double* rrp0, CgScalars* sc);
+                     double* p, double* rrp0, double tol, int maxiter, double shift,
+                     CgScalars* sc);
 
 // dense.hip
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,

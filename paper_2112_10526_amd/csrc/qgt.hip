@@ -52,6 +52,33 @@ __device__ __forceinline__ void pload4(const double* a, int na, double (&x)[4]) 
         x[u] = na > 0 ? a[min(i, na - 1)] : 0.0;
     }
 }
+// three sums of psum's kind with one barrier
+__device__ __forceinline__ void psum3(const double* a, int na, const double (&xa)[4],
+                                      const double* b, int nb, const double (&xb)[4],
+                                      const double* c, int nc, const double (&xc)[4],
+                                      double (&out)[3]) {
+    __shared__ double s3[3][4];
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = u * 256 + (int)threadIdx.x;
+        if (i < na) t[0] += xa[u];
+        if (i < nb) t[1] += xb[u];
+        if (i < nc) t[2] += xc[u];
+    }
+    for (int i = 1024 + (int)threadIdx.x; i < na; i += 256) t[0] += a[i];
+    for (int i = 1024 + (int)threadIdx.x; i < nb; i += 256) t[1] += b[i];
+    for (int i = 1024 + (int)threadIdx.x; i < nc; i += 256) t[2] += c[i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double v = wave_sum(t[q]);
+        if ((threadIdx.x & 63) == 0) s3[q][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[q] = (s3[q][0] + s3[q][1]) + (s3[q][2] + s3[q][3]);
+}
+
 __device__ __forceinline__ double psum(const double* a, int na, const double (&x)[4], double* sh) {
     double t = 0.0;
 #pragma unroll
@@ -175,8 +202,7 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
                                               const double* p_old,
                                               double* p_new, void* Pop,
                                               const double* rrp_cur,
-                                              const double* rrp_prev, int nbu, int it,
-                                              double tol, int maxiter, double* ppart,
+                                              const double* rrp_prev, int nbu, double* ppart,
                                               CgScalars* sc) {
     __shared__ double sh[4];
     // the element loads do not depend on the scalars: issue them first
@@ -188,9 +214,11 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
     const double re = r[g], pe = p_old[g];
     double xa[4], xb[4];
     pload4(rrp_cur, nbu, xa);
-    pload4(rrp_prev, it > 0 ? nbu : 0, xb);
+    pload4(rrp_prev, nbu, xb);
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
     if (sc->done) return;
+    const int it = sc->it, maxiter = sc->maxiter;
+    const double tol = sc->tol;
     const double rr = psum(rrp_cur, nbu, xa, sh);
     const double rrprev = it > 0 ? psum(rrp_prev, nbu, xb, sh) : rr;
     const double rr0 = it == 0 ? rr : sc->rr0;
@@ -231,13 +259,15 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
     if (threadIdx.x == 0) ppart[blockIdx.x] = pp;
 }
 
-// block sum over nw waves, identical order in every block
+// block sum over nw <= 16 waves, identical order in every block (sh: 16 slots)
 __device__ __forceinline__ double bsum_waves(double v, double* sh, int nw) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0.0;
-    for (int q = 0; q < nw; ++q) r += sh[q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (q < nw) r += sh[q];
     __syncthreads();
     return r;
 }
@@ -394,18 +424,17 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
             if (lr == 0) wsh[wave][16 * rt + row] = v;
         }
     __syncthreads();
-    if (tid < 16 * RT) {
-        const long k = r0 + tid;
+    if (wave == 0) {  // one lane per sample, then over the block's samples
         double v = 0.0;
-        for (int q = 0; q < nw; ++q) v += wsh[q][tid];
-        if (k < n) w[k] = v;
-        wsh[0][tid] = k < n ? v : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int q = 0; q < 16 * RT; ++q) t += wsh[0][q];
-        wpart[blockIdx.x] = t;
+        const long k = r0 + lane;
+        if (lane < 16 * RT) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (q < nw) v += wsh[q][lane];
+            if (k < n) w[k] = v;
+        }
+        const double t = wave_sum(lane < 16 * RT && k < n ? v : 0.0);
+        if (lane == 0) wpart[blockIdx.x] = t;
     }
 }
 
@@ -479,7 +508,8 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
 #pragma unroll
             for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
     }
-    // sums over the 16 columns of the wave's tiles, then over the waves in order
+    // sums over the 16 columns of the wave's tiles, then over the waves in
+    // order (wave 0, one lane per sample), then over the block's samples
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -488,18 +518,15 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
             if (lr == 0) wsh[wave][16 * rt + acc_row<float>(lk, q)] = v;
         }
     __syncthreads();
-    if (tid < W6_ROWS) {
-        const long k = r0 + tid;
+    if (wave == 0) {
         double v = 0.0;
-        for (int q = 0; q < nw; ++q) v += wsh[q][tid];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q < nw) v += wsh[q][lane];
+        const long k = r0 + lane;
         if (k < n) w[k] = v;
-        wsh[0][tid] = k < n ? v : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int q = 0; q < W6_ROWS; ++q) t += wsh[0][q];
-        wpart[blockIdx.x] = t;
+        const double t = wave_sum(k < n ? v : 0.0);
+        if (lane == 0) wpart[blockIdx.x] = t;
     }
 }
 
@@ -759,12 +786,14 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
     if (threadIdx.x == 0) pap[blockIdx.x] = dot;
 }
 
-// CG update, 64 entries per block (wave w sums chunk slabs [w ks/4, (w+1) ks/4)):
+// CG update, 64 entries per block (wave w sums chunk slabs [w ks/4, (w+1) ks/4));
+// the diagonal shift comes from the device scalars and block 0 advances the
+// iteration index:
 //   Ap = sum_kc part[kc] + shift p (parameter entries only),
 //   p.Ap = sum of the per-chunk partials of p.G p + shift * sum of the p.p partials,
 //   alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; block partials of r.r.
 template <typename R>
-__global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int ksplit, double shift,
+__global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int ksplit,
                                                  double* x, double* r, const double* p,
                                                  const double* papart, int npa,
                                                  const double* ppart, int npp,
@@ -788,15 +817,16 @@ __global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int kspl
     pload4(rrp_cur, nbv, xc);
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
     if (sc->done) return;
+    const double shift = sc->shift;
     double val = 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u)
         if (kb + u < ke) val += (double)xs[u];
     for (int kc = kb + 16; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
     ws[wave][lane] = val;
-    const double pJz = psum(papart, npa, xa, sh);
-    const double pp = psum(ppart, npp, xb, sh);
-    const double rr = psum(rrp_cur, nbv, xc, sh);  // (its barriers also publish ws)
+    double t3[3];
+    psum3(papart, npa, xa, ppart, npp, xb, rrp_cur, nbv, xc, t3);  // (its barrier publishes ws)
+    const double pJz = t3[0], pp = t3[1], rr = t3[2];
     const double pAp = pJz + shift * pp;
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
@@ -809,6 +839,7 @@ __global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int kspl
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->alpha = alpha;
         sc->pAp = pAp;
+        sc->it += 1;  // read by the next direction kernel
     }
     double q = 0.0;
     if (wave == 0 && e < total) {
@@ -830,6 +861,7 @@ __global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int kspl
 __global__ __launch_bounds__(64) void k_init2(int total, const double* __restrict__ f,
                                               double* __restrict__ x, double* __restrict__ r,
                                               double* __restrict__ p, double* __restrict__ rrp0,
+                                              double tol, int maxiter, double shift,
                                               CgScalars* sc) {
     const int e = blockIdx.x * 64 + threadIdx.x;
     double q = 0.0;
@@ -846,6 +878,10 @@ __global__ __launch_bounds__(64) void k_init2(int total, const double* __restric
         sc->done = 0;
         sc->bad = 0;
         sc->iters = 0;
+        sc->it = 0;
+        sc->tol = tol;
+        sc->maxiter = maxiter;
+        sc->shift = shift;
     }
 }
 
@@ -883,15 +919,12 @@ size_t qgt_pop_bytes(const Dims& d, int prec) {
 
 void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
                      const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, int it, double tol, int maxiter, double* ppart,
-                     CgScalars* sc) {
+                     const double* rrp_prev, double* ppart, CgScalars* sc) {
     const int nb = qgt_nbp(d), nbv = qgt_nbr(d);
     if (prec == 0)
-        k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, it, tol,
-                                      maxiter, ppart, sc);
+        k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, ppart, sc);
     else
-        k_pnew<1><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, it, tol,
-                                      maxiter, ppart, sc);
+        k_pnew<1><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, ppart, sc);
 }
 
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
@@ -943,26 +976,27 @@ void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part
 }
 
 void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
-                     double* p, double* rrp0, CgScalars* sc) {
+                     double* p, double* rrp0, double tol, int maxiter, double shift,
+                     CgScalars* sc) {
     // 64 entries per block: the r.r partials match those of k_update3
     const int nb = qgt_nbr(d);
-    k_init2<<<nb, 64, 0, st>>>(d.Ma * d.Na, f, x, r, p, rrp0, sc);
+    k_init2<<<nb, 64, 0, st>>>(d.Ma * d.Na, f, x, r, p, rrp0, tol, maxiter, shift, sc);
 }
 
 int qgt_nbp(const Dims& d) { return nb_of((long)d.Ma * d.Kq, 256); }
 int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
 
 void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
-                        const void* part, double shift, double* x, double* r, const double* p,
+                        const void* part, double* x, double* r, const double* p,
                         const double* papart, const double* ppart, const double* rrp_cur,
                         double* rrp_next, CgScalars* sc) {
     const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q), npp = qgt_nbp(d);
     if (prec == 0)
-        k_update3<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, shift, x, r, p, papart,
-                                              npa, ppart, npp, rrp_cur, rrp_next, nb, sc);
+        k_update3<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p, papart, npa,
+                                              ppart, npp, rrp_cur, rrp_next, nb, sc);
     else
-        k_update3<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, shift, x, r, p, papart,
-                                             npa, ppart, npp, rrp_cur, rrp_next, nb, sc);
+        k_update3<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p, papart, npa,
+                                             ppart, npp, rrp_cur, rrp_next, nb, sc);
 }
 
 }  // namespace nqs

@@ -278,8 +278,15 @@ def _profile_read(self) -> dict:
     return {name: dict(ms=ms[k], launches=cnt[k]) for k, name in enumerate(_lib.PROF_CLASSES)}
 
 
+def _set_cg_graphs(self, enable: bool = True) -> None:
+    """Replay full batches of on-the-fly CG iterations from captured HIP graphs
+    (default) or launch every kernel on the stream."""
+    self._check(self.lib.nqs_set_cg_graphs(self.ctx, 1 if enable else 0))
+
+
 VMCState.profile_enable = _profile_enable
 VMCState.profile_read = _profile_read
+VMCState.set_cg_graphs = _set_cg_graphs
 
 
 def batch_step(states: Sequence[VMCState], cfgs: Sequence[dict]) -> list:

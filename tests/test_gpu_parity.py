@@ -270,6 +270,32 @@ def test_sr_direction_many_sites(precision):
     assert res <= bound
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_cg_graph_replay_matches_stream_launches(precision):
+    """Graph-replayed CG batches give bit-identical solves to stream launches,
+    on several solves in a row with other work between them (the graphs are
+    captured once and replayed)."""
+    torch = _torch()
+    w = TFIM2D.replace(sigma=0.05, n_chains=256)
+    params = w.params()
+    out = {}
+    for graphs in (True, False):
+        st, w2 = make_state(w, precision=precision, params=params)
+        st.set_cg_graphs(graphs)
+        res = []
+        for seed in (51, 52, 53):
+            st.load_samples(torch.from_numpy(_batch(w2, seed)))
+            st.local_energy(torch.from_numpy(_batch(w2, seed + 10)[:64]))
+            st.expect_and_grad()
+            d, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=1e-8, maxiter=2000)
+            assert info.converged and info.iterations > 20, info
+            res.append((d.cpu().numpy().copy(), info.iterations))
+        out[graphs] = res
+    for (a, ia), (b, ib) in zip(out[True], out[False]):
+        assert ia == ib
+        np.testing.assert_array_equal(a, b)
+
+
 def test_sr_update_applies_step():
     torch = _torch()
     w = TFIM1D.replace(sigma=0.05)
