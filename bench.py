@@ -130,7 +130,9 @@ def _counter_rows(d):
 
 def _per_dispatch(rows, counter, match):
     """Mean over dispatches of kernels whose name contains `match` of the counter (summed
-    over its instances within one dispatch)."""
+    over its instances within one dispatch).  Dispatches below a tenth of the largest one
+    are left out: they are the CG launches queued after a solve had stopped, which
+    return at once."""
     per = {}
     for r in rows:
         if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
@@ -140,7 +142,9 @@ def _per_dispatch(rows, counter, match):
     if not per:
         names = sorted({r.get("Kernel_Name", "")[:80] for r in rows})
         raise SystemExit(f"no {counter} rows for a kernel matching {match!r}; kernels: {names}")
-    return float(np.mean(list(per.values()))), len(per)
+    vals = np.array(list(per.values()))
+    vals = vals[vals >= 0.1 * vals.max()]
+    return float(vals.mean()), len(vals)
 
 
 def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
@@ -167,7 +171,7 @@ def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
         f"- source_digest: `{source_digest(cls)}`",
         f"- copy_fetch_kib: {cf:.1f}", f"- copy_write_kib: {cw:.1f}",
         f"- fetch_scale: {f_scale:.4f}", f"- write_scale: {w_scale:.4f}",
-        f"- dispatches: {nf} (fetch run), {nw} (write run)",
+        f"- dispatches counted: {nf} (fetch run), {nw} (write run)",
         f"- fetch_kib_per_launch: {kf:.1f}", f"- write_kib_per_launch: {kw:.1f}",
         f"- fetch_bytes_per_launch: {fetch_b:.0f}", f"- write_bytes_per_launch: {write_b:.0f}",
         f"- hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
@@ -176,6 +180,36 @@ def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(path)
+
+
+def summarize_waves(counter_dir, cmd):
+    """Markdown table of the wave-state counters (SQ_*) of the BF16 hot-path kernels."""
+    import collections
+    rows = _counter_rows(counter_dir)
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["# Wave-state counters of the hot-path kernels (10x10 TFIM workload, BF16 form)", "",
+           "Command:", "", "    " + cmd, "",
+           "Median over the dispatches of one kernel (dispatches that return at once after a "
+           "CG solve has stopped are left out); WAVE_CYCLES, WAIT_* and ACTIVE_* are summed "
+           "over waves.", "",
+           "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for name in ["nqs::k_w6", "nqs::k_outer6<1>", "nqs::k_update3<float>", "nqs::k_pnew<1>",
+                 "nqs::k_sample<float, 4, 0>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
+        if name not in agg:
+            continue
+        d = agg[name]
+        wc = np.array(d["SQ_WAVE_CYCLES"])
+        keep = wc >= 0.1 * wc.max()
+        med = {k: float(np.median(np.array(v)[keep])) for k, v in d.items() if len(v) == len(wc)}
+        w = med["SQ_WAVE_CYCLES"]
+        out.append(f"| `{name}` | {med['SQ_WAVES']:.0f} | {w / med['SQ_WAVES']:.0f} | "
+                   f"{100 * med['SQ_WAIT_ANY'] / w:.0f} | {100 * med['SQ_WAIT_INST_ANY'] / w:.0f} | "
+                   f"{100 * med['SQ_ACTIVE_INST_ANY'] / w:.0f} |")
+    print("\n".join(out))
 
 
 def summarize_stats(stats_csv, cmd, title):
@@ -300,12 +334,17 @@ def main():
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
                     help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-waves", nargs=2, metavar=("COUNTER_DIR", "CMD"),
+                    help="print a markdown table of SQ wave-state counters and exit")
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_DIR", "WRITE_DIR", "CLASS", "COPY_MIB", "FETCH_CMD", "WRITE_CMD"),
                     help="write profiles/traffic_*.md from two counter runs and exit")
     args = ap.parse_args()
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
+        return
+    if args.summarize_waves:
+        summarize_waves(*args.summarize_waves)
         return
     if args.summarize_traffic:
         fd, wd, cls, mib, c1, c2 = args.summarize_traffic
