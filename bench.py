@@ -73,7 +73,7 @@ def kernel_work(cls: str, w, precision: str):
 # kernel class -> (source file of its kernel, symbol prefix in profiles)
 KERNELS = {  # (BF16 form, the benchmark's main run)
     "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer6<1>"),
-    "reduce": ("qgt.hip", "k_update3<float>"), "cg_vec": ("qgt.hip", "k_pnew<1>"),
+    "reduce": ("qgt.hip", "k_update4<float>"),
     "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
     "theta": ("theta.hip", "k_theta_bf16"),
 }
@@ -197,7 +197,7 @@ def summarize_waves(counter_dir, cmd):
            "over waves.", "",
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
-    for name in ["nqs::k_w6", "nqs::k_outer6<1>", "nqs::k_update3<float>", "nqs::k_pnew<1>",
+    for name in ["nqs::k_w6", "nqs::k_outer6<1>", "nqs::k_update4<float>",
                  "nqs::k_sample<float, 4, 0>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
         if name not in agg:
             continue

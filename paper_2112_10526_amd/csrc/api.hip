@@ -28,7 +28,7 @@ struct Buffers {
     void* tx;
     double *eloc, *vvec, *wbuf, *stats, *dpart;
     QgtBatch q;
-    double *rrp, *pap, *ppart;
+    double *rrp, *pap;
     void* Pop;
     uint32_t* acc_count;
     CgScalars* sc;
@@ -193,10 +193,10 @@ size_t layout(nqs_ctx* c, char* base) {
         b.q.St = (int8_t*)take((size_t)Nsp * d.Kb / (c->prec == 0 ? 1 : 8));
         b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
         b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp, c->prec));
-        b.rrp = (double*)take(16 * (size_t)qgt_nbr(d));
+        // CG head partials (r.r, r.p, p.p), one set per iteration parity
+        b.rrp = (double*)take(8 * 2 * 3 * (size_t)qgt_nbr(d));
         b.pap = (double*)take(8 * (size_t)qgt_nbo(d, b.q));   // p.G p partials
-        b.ppart = (double*)take(8 * (size_t)qgt_nbp(d));      // p.p partials
-        b.Pop = take(qgt_pop_bytes(d, c->prec));
+        b.Pop = take(qgt_pop_bytes(d, c->prec));               // r, contraction-1 layout
         const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
         b.part = take(es * ks * PV);
     }
@@ -476,13 +476,15 @@ void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
     c->cg_iter = 0;
     c->cg_tol = tol;
     c->cg_maxiter = maxiter;
-    launch_qgt_init(c->stream, c->d, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.rrp, tol, maxiter,
-                    shift, c->b.sc);
+    launch_qgt_init(c->stream, c->d, c->prec, c->b.grad, c->b.x, c->b.r, c->b.p, c->b.p2,
+                    c->b.Pop, c->b.rrp, c->b.wbuf, c->Ns, tol, maxiter, shift, c->b.sc);
 }
 
-// CG iterations.  On-the-fly form: iteration it first tests convergence on
-// the residual left by iteration it - 1, then forms p_new = r + beta p_old
-// (the direction alternates between two buffers) and applies the QGT.
+// CG iterations.  On-the-fly form, three kernels per iteration: the head
+// (convergence test on the residual left by iteration it - 1, beta) with
+// w = J r + beta w; the chunk partials of J^T z; the update, which forms
+// p_new = r + beta p_old (the direction alternates between two buffers, the
+// head partials too) and updates x and r.
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
     const Dims& d = c->d;
     const int nbv = qgt_nbr(d);
@@ -491,18 +493,13 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             const long k = c->cg_iter;
             double* p_old = (k & 1) ? c->b.p2 : c->b.p;
             double* p_new = (k & 1) ? c->b.p : c->b.p2;
-            double* rr_cur = c->b.rrp + (k & 1) * nbv;
-            double* rr_oth = c->b.rrp + ((k + 1) & 1) * nbv;
+            double* aux_cur = c->b.rrp + (k & 1) * 3 * nbv;
+            double* aux_next = c->b.rrp + ((k + 1) & 1) * 3 * nbv;
             c->cg_iter += 1;
-            {
-                PROF(NQS_PROF_CGVEC);
-                launch_qgt_pnew(c->stream, d, c->prec, c->b.r, p_old, p_new, c->b.Pop, rr_cur,
-                                rr_oth, c->b.ppart, c->b.sc);
-            }
             {
                 PROF(NQS_PROF_QGT_W);
                 launch_qgt_w(c->stream, d, c->prec, c->b.q, c->b.tsm, c->Ns, c->b.Pop, c->b.wbuf,
-                             c->b.sc);
+                             aux_cur, c->b.sc);
             }
             {
                 PROF(NQS_PROF_OUTER);
@@ -511,8 +508,8 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             }
             {
                 PROF(NQS_PROF_REDUCE);
-                launch_qgt_update3(c->stream, d, c->prec, c->b.q, c->b.part, c->b.x, c->b.r,
-                                   p_new, c->b.pap, c->b.ppart, rr_cur, rr_oth, c->b.sc);
+                launch_qgt_update(c->stream, d, c->prec, c->b.q, c->b.part, c->b.x, c->b.r, p_old,
+                                  p_new, c->b.Pop, c->b.pap, aux_next, c->b.sc);
             }
         } else {
             {

@@ -43,6 +43,8 @@ struct CgScalars {
     // no per-iteration arguments (a batch of iterations can be replayed as is)
     double tol;       // relative residual tolerance
     double shift;     // diagonal shift
+    double pp;        // p . p of the current direction
+    double rr_prev;   // r . r of the previous iteration
     int32_t it;       // index of the next iteration (advanced by the update kernel)
     int32_t pad1;
 };
@@ -133,31 +135,32 @@ int qgt_nbw(long n, int prec);
 // activation rows to allocate for n samples (whole contraction-1 blocks)
 long qgt_act_rows(long n);
 int qgt_nbu(const Dims& d);
-int qgt_nbr(const Dims& d);   // CG vector blocks (64 entries): r.r partials
-int qgt_nbp(const Dims& d);   // direction blocks: p.p partials
+int qgt_nbr(const Dims& d);   // CG vector blocks (64 entries): head partials per array
 int qgt_ksplit(const QgtBatch& q);
 int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per chunk)
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q);
+// bytes of a vector in the contraction-1 operand layout
 size_t qgt_pop_bytes(const Dims& d, int prec);
-void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
-                     const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, double* ppart, CgScalars* sc);
+// CG iteration, kernel 1: head (stop test, beta, p.p) + w = J r + beta w (in place)
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
-                  long n, const void* Pop, double* w, const CgScalars* sc);
+                  long n, const void* Rop, double* w, const double* aux, CgScalars* sc);
+// kernel 2 (and the force with v_mode 1): chunk partials of J^T z
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
                       const double* v, int v_mode, void* part, double* papart,
                       const CgScalars* sc);
+// force: sum of the chunk partials
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                        const double* p, double shift, double* out, double* pap,
                        const CgScalars* sc, int cg);
-void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
-                        const void* part, double* x, double* r, const double* p,
-                        const double* papart, const double* ppart, const double* rrp_cur,
-                        double* rrp_next, CgScalars* sc);
-void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
-                     double* p, double* rrp0, double tol, int maxiter, double shift,
-                     CgScalars* sc);
+// kernel 3: direction, product, x and r, head partials for the next iteration
+void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
+                       const void* part, double* x, double* r, const double* p_old,
+                       double* p_new, void* Rop, const double* papart, double* aux_next,
+                       CgScalars* sc);
+void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, double* x,
+                     double* r, double* p, double* p2, void* Rop, double* aux0, double* w, long n,
+                     double tol, int maxiter, double shift, CgScalars* sc);
 
 // dense.hip
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,

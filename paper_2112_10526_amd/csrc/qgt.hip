@@ -189,46 +189,75 @@ __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long
 }
 
 // ---------------------------------------------------------------------------
-// CG direction (start of iteration it):
-//   rr_it = r.r from the partials of the previous update; stop if
-//   rr_it <= tol^2 rr_0, it >= maxiter or non-finite; else beta = rr_it /
-//   rr_{it-1} (0 at it = 0) and p_new = r + beta p_old.
-// p_new is written in FP64 [Ma][Na] and in the operand layout of
-// contraction 1: FP64 path k-major [Kq][Ma]; BF16 forms two planes [Ma][Kq];
-// with block partials of p . p.  One thread per (j, i < Kq).
+// CG iteration it runs in three kernels: contraction 1 (with the CG "head"),
+// contraction 2, and the update.  Standard CG steps, arranged so that no
+// kernel forms the direction for the matrix cores:
+//   w_it = J p_it = J r_it + beta_it w_{it-1}            (contraction 1 of r)
+//   p_it.p_it = r.r + 2 beta r.p_{it-1} + beta^2 p_{it-1}.p_{it-1}
+// with the three dot products left as block partials by the previous update.
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
-                                              const double* p_old,
-                                              double* p_new, void* Pop,
-                                              const double* rrp_cur,
-                                              const double* rrp_prev, int nbu, double* ppart,
-                                              CgScalars* sc) {
-    __shared__ double sh[4];
-    // the element loads do not depend on the scalars: issue them first
-    // (clamped, unconditional loads: no branch between them)
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    const int j = e / d.Kq, i = e - j * d.Kq;
-    const bool own = e < d.Ma * d.Kq && i < d.Na;
-    const size_t g = (size_t)min(j, d.Ma - 1) * d.Na + min(i, d.Na - 1);
-    const double re = r[g], pe = p_old[g];
-    double xa[4], xb[4];
-    pload4(rrp_cur, nbu, xa);
-    pload4(rrp_prev, nbu, xb);
-    asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
-    if (sc->done) return;
-    const int it = sc->it, maxiter = sc->maxiter;
-    const double tol = sc->tol;
-    const double rr = psum(rrp_cur, nbu, xa, sh);
-    const double rrprev = it > 0 ? psum(rrp_prev, nbu, xb, sh) : rr;
+
+// Loads the first partial of this thread (index threadIdx.x), clamped and
+// unconditional, so that it can be issued early.
+__device__ __forceinline__ double pload1(const double* a, int na) {
+    return na > 0 ? a[min((int)threadIdx.x, na - 1)] : 0.0;
+}
+
+// Fixed-order block sums of three partial arrays of length na (nw waves,
+// one barrier); x* hold what pload1 loaded, the rest is read here.
+__device__ __forceinline__ void psum3n(const double* a, const double* b, const double* c, int na,
+                                       int nth, int nw, double xa, double xb, double xc,
+                                       double (&out)[3]) {
+    __shared__ double s3[3][16];
+    double t[3] = {0.0, 0.0, 0.0};
+    if ((int)threadIdx.x < na) {
+        t[0] = xa;
+        t[1] = xb;
+        t[2] = xc;
+    }
+    for (int i = nth + (int)threadIdx.x; i < na; i += nth) {
+        t[0] += a[i];
+        t[1] += b[i];
+        t[2] += c[i];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double v = wave_sum(t[q]);
+        if ((threadIdx.x & 63) == 0) s3[q][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w)
+            if (w < nw) r += s3[q][w];
+        out[q] = r;
+    }
+}
+
+// CG head of iteration it: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the
+// partials (aux: three arrays of nbv), the stop rule (r.r <= tol^2 r0.r0,
+// it >= maxiter, or non-finite), beta_it = r.r / r_{it-1}.r_{it-1} (0 at it =
+// 0) and p_it.p_it.  Block 0 publishes them.  Returns false when the solve
+// stops here (the same in every block).
+__device__ __forceinline__ bool cg_head(const double* aux, int nbv, int nth, int nw, double xa,
+                                        double xb, double xc, CgScalars* sc, double& beta) {
+    double t[3];
+    psum3n(aux, aux + nbv, aux + 2 * nbv, nbv, nth, nw, xa, xb, xc, t);
+    const double rr = t[0], rp = t[1], ppo = t[2];
+    const int it = sc->it;
     const double rr0 = it == 0 ? rr : sc->rr0;
+    const double tol = sc->tol;
     const double tol2 = tol * tol * rr0;
-    const bool stop = !(rr > tol2) || it >= maxiter || !isfinite(rr);
-    const double beta = it == 0 ? 0.0 : rr / rrprev;
+    const bool stop = !(rr > tol2) || it >= sc->maxiter || !isfinite(rr);
+    beta = it == 0 ? 0.0 : rr / sc->rr_prev;
+    const double pp = rr + 2.0 * beta * rp + beta * beta * ppo;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rr = rr;
         sc->iters = it;
         sc->beta = beta;
+        sc->pp = pp;
         if (it == 0) {
             sc->rr0 = rr0;
             sc->tol2 = tol2;
@@ -238,25 +267,7 @@ __global__ __launch_bounds__(256) void k_pnew(Dims d, const double* r,
             if (!isfinite(rr)) sc->bad = 1;
         }
     }
-    if (stop) return;
-    double v = 0.0;
-    if (own) {
-        v = re + beta * pe;
-        p_new[g] = v;
-    }
-    if (e < d.Ma * d.Kq) {
-        if constexpr (MODE == 0) {
-            ((double*)Pop)[(size_t)i * d.Ma + j] = v;
-        } else {
-            uint16_t hi, lo;
-            split2((float)v, hi, lo);
-            ((uint16_t*)Pop)[e] = hi;
-            ((uint16_t*)Pop)[(size_t)d.Ma * d.Kq + e] = lo;
-        }
-    }
-    // block partials of p . p (for the diagonal-shift part of p . (G + shift) p)
-    const double pp = bsum256(v * v, sh);
-    if (threadIdx.x == 0) ppart[blockIdx.x] = pp;
+    return !stop;
 }
 
 // block sum over nw <= 16 waves, identical order in every block (sh: 16 slots)
@@ -297,13 +308,17 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
                                              const void* __restrict__ tact_v, long n,
                                              const void* __restrict__ Pop,
                                              double* __restrict__ w, double* __restrict__ wpart,
-                                             const CgScalars* __restrict__ sc) {
+                                             const double* __restrict__ aux, int nbv,
+                                             CgScalars* sc) {
     constexpr int RT = WRows<MODE>::RT;
     if (sc->done) return;
     __shared__ double wsh[16][16 * RT];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * (16 * RT);
+    // CG head inputs and the previous w, issued before the contraction
+    const double xa = pload1(aux, nbv), xb = pload1(aux + nbv, nbv), xc = pload1(aux + 2 * nbv, nbv);
+    const double wold = w[min(r0 + (lane & (16 * RT - 1)), n - 1)];
     const int Kq = d.Kq, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
     const int8_t* Sbase = Sp + (r0 + lr) * Kq;  // sample tile rt: + 16 rt Kq
     double rs[RT][4];
@@ -414,6 +429,8 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 #pragma unroll
             for (int q = 0; q < 4; ++q) rs[rt][q] = (double)rsf[rt][q];
     }
+    double beta;
+    if (!cg_head(aux, nbv, blockDim.x, nw, xa, xb, xc, sc, beta)) return;
     // sums over the 16 columns of the wave's tiles, then over the waves in order
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -431,6 +448,7 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 #pragma unroll
             for (int q = 0; q < 16; ++q)
                 if (q < nw) v += wsh[q][lane];
+            v += beta * wold;  // J p = J r + beta J p_old
             if (k < n) w[k] = v;
         }
         const double t = wave_sum(lane < 16 * RT && k < n ? v : 0.0);
@@ -440,9 +458,10 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 
 // ---------------------------------------------------------------------------
 // contraction 1, BF16 form, 64 samples per block (four sample tiles): wave w
-// keeps the P fragments of its hidden tile in registers and applies them to
-// the four tiles, whose spins (one bit each) it reads directly.  All of a
-// wave's global loads are issued together.
+// keeps the fragments of its hidden tile of the contracted vector (the CG
+// residual, two BF16 planes) in registers and applies them to the four tiles,
+// whose spins (one bit each) it reads directly.  All of a wave's global loads
+// are issued together.
 // ---------------------------------------------------------------------------
 constexpr int W6_ROWS = 64;
 
@@ -450,10 +469,13 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
                                              const float* __restrict__ tact, long n,
                                              const uint16_t* __restrict__ Ph,
                                              double* __restrict__ w, double* __restrict__ wpart,
-                                             const CgScalars* __restrict__ sc) {
+                                             const double* __restrict__ aux, int nbv,
+                                             CgScalars* sc) {
     constexpr int RT = W6_ROWS / 16;
     if (sc->done) return;
     __shared__ double wsh[16][W6_ROWS];
+    __shared__ double wold_s[W6_ROWS];   // previous w of the block's samples
+    __shared__ double head_s[3][1024];   // this thread's CG head partials
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * W6_ROWS;
@@ -468,7 +490,11 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
-    for (int ct = wave; ct < nct; ct += nw) {
+    double beta = 0.0;
+    // one hidden tile; in the wave's first tile (head) the CG head partials
+    // and the previous w are fetched behind the first group's loads and
+    // parked in LDS, so that no register holds them during the MFMAs
+    auto tile = [&](int ct, auto head) {
         const int j = ct * 16 + lr;
         float tv[RT][4];
 #pragma unroll
@@ -489,6 +515,18 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) sbits[rt] = *(const uint4*)(sb0 + 16 * rt * KB + g / 8);
+            if constexpr (decltype(head)::value) {
+                if (g == 0) {
+                    __builtin_amdgcn_sched_barrier(0);  // behind the contraction's loads
+                    const double xa = pload1(aux, nbv), xb = pload1(aux + nbv, nbv),
+                                 xc = pload1(aux + 2 * nbv, nbv);
+                    const double wo = w[min(r0 + lane, n - 1)];
+                    head_s[0][tid] = xa;
+                    head_s[1][tid] = xb;
+                    head_s[2][tid] = xc;
+                    if (wave == 0) wold_s[lane] = wo;
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);  // the group's loads together
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -507,7 +545,13 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
-    }
+    };
+    tile(wave, std::true_type{});  // every wave has a first tile
+    for (int ct = wave + nw; ct < nct; ct += nw) tile(ct, std::false_type{});
+    // CG head (each thread reads back the partials it parked)
+    if (!cg_head(aux, nbv, blockDim.x, nw, head_s[0][tid], head_s[1][tid], head_s[2][tid], sc,
+                 beta))
+        return;
     // sums over the 16 columns of the wave's tiles, then over the waves in
     // order (wave 0, one lane per sample), then over the block's samples
 #pragma unroll
@@ -523,6 +567,7 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             if (q < nw) v += wsh[q][lane];
+        v += beta * wold_s[lane];  // J p = J r + beta J p_old
         const long k = r0 + lane;
         if (k < n) w[k] = v;
         const double t = wave_sum(k < n ? v : 0.0);
@@ -786,21 +831,22 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
     if (threadIdx.x == 0) pap[blockIdx.x] = dot;
 }
 
-// CG update, 64 entries per block (wave w sums chunk slabs [w ks/4, (w+1) ks/4));
-// the diagonal shift comes from the device scalars and block 0 advances the
-// iteration index:
-//   Ap = sum_kc part[kc] + shift p (parameter entries only),
-//   p.Ap = sum of the per-chunk partials of p.G p + shift * sum of the p.p partials,
-//   alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; block partials of r.r.
+// CG update of iteration it, 64 entries per block (wave w sums chunk slabs
+// [w ks/4, (w+1) ks/4)), with r.r, beta and p.p from the head:
+//   p_it = r + beta p_{it-1};  Ap = sum_kc part[kc] + shift p_it (parameter
+//   entries only);  p.Ap = sum of the per-chunk partials of p.G p + shift p.p;
+//   alpha = r.r / p.Ap;  x += alpha p_it;  r -= alpha Ap;
+// writes p_it, r (also in the contraction-1 operand layout) and the block
+// partials of r.r, r.p_it, p_it.p_it for the next head.  Block 0 advances the
+// iteration index.
 template <typename R>
-__global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int ksplit,
-                                                 double* x, double* r, const double* p,
-                                                 const double* papart, int npa,
-                                                 const double* ppart, int npp,
-                                                 const double* rrp_cur, double* rrp_next, int nbv,
-                                                 CgScalars* sc) {
+__global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int ksplit, double* x,
+                                                 double* r, const double* p_old, double* p_new,
+                                                 void* Rop, const double* papart, int npa,
+                                                 double* aux_next, int nbv, CgScalars* sc) {
     __shared__ double ws[4][64];
     __shared__ double sh[4];
+    __shared__ double s3[3][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int total = d.Ma * d.Na;
     const int e = blockIdx.x * 64 + lane;
@@ -810,24 +856,20 @@ __global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int kspl
     R xs[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
-    const double xe = x[ec], re0 = r[ec], pe = p[ec];
-    double xa[4], xb[4], xc[4];
+    const double xe = x[ec], re0 = r[ec], po = p_old[ec];
+    double xa[4];
     pload4(papart, npa, xa);
-    pload4(ppart, npp, xb);
-    pload4(rrp_cur, nbv, xc);
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
     if (sc->done) return;
-    const double shift = sc->shift;
+    const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
     double val = 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u)
         if (kb + u < ke) val += (double)xs[u];
     for (int kc = kb + 16; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
     ws[wave][lane] = val;
-    double t3[3];
-    psum3(papart, npa, xa, ppart, npp, xb, rrp_cur, nbv, xc, t3);  // (its barrier publishes ws)
-    const double pJz = t3[0], pp = t3[1], rr = t3[2];
-    const double pAp = pJz + shift * pp;
+    const double pGp = psum(papart, npa, xa, sh);  // (its barriers also publish ws)
+    const double pAp = pGp + shift * pp;
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -839,41 +881,81 @@ __global__ __launch_bounds__(256) void k_update3(Dims d, const R* part, int kspl
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->alpha = alpha;
         sc->pAp = pAp;
-        sc->it += 1;  // read by the next direction kernel
+        sc->rr_prev = rr;
+        sc->it += 1;  // read by the next head
     }
-    double q = 0.0;
+    double q[3] = {0.0, 0.0, 0.0};
     if (wave == 0 && e < total) {
         const int j = e / d.Na, i = e - j * d.Na;
         const bool keep = (j < d.M && i < d.N) || (d.hb && j < d.M && i == d.N) ||
                           (d.vb && j == d.M && i < d.N);
-        const double ap = keep ? (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]) + shift * pe
+        const double pn = re0 + beta * po;
+        const double ap = keep ? (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]) + shift * pn
                                : 0.0;
-        x[e] = xe + alpha * pe;
         const double rn = re0 - alpha * ap;
+        x[e] = xe + alpha * pn;
         r[e] = rn;
-        q = rn * rn;
+        p_new[e] = pn;
+        if constexpr (sizeof(R) == 8) {
+            ((double*)Rop)[(size_t)i * d.Ma + j] = rn;
+        } else {
+            uint16_t hi, lo;
+            split2((float)rn, hi, lo);
+            ((uint16_t*)Rop)[(size_t)j * d.Kq + i] = hi;
+            ((uint16_t*)Rop)[(size_t)d.Ma * d.Kq + (size_t)j * d.Kq + i] = lo;
+        }
+        q[0] = rn * rn;
+        q[1] = rn * pn;
+        q[2] = pn * pn;
     }
-    q = bsum256(q, sh);
-    if (threadIdx.x == 0) rrp_next[blockIdx.x] = q;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(q[k]);
+        if (lane == 0) s3[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        aux_next[(size_t)k * nbv + blockIdx.x] = (s3[k][0] + s3[k][1]) + (s3[k][2] + s3[k][3]);
+    }
 }
 
-// x = 0, r = p = f, partials of f.f (64 entries per block); clears the CG flags.
-__global__ __launch_bounds__(64) void k_init2(int total, const double* __restrict__ f,
+// CG start (x0 = 0): r = f, both direction buffers 0, r in the contraction-1
+// operand layout (its padding is cleared beforehand), head partials
+// (f.f, 0, 0), 64 entries per block; scalars for the iteration kernels.
+template <typename R>
+__global__ __launch_bounds__(64) void k_init3(Dims d, const double* __restrict__ f,
                                               double* __restrict__ x, double* __restrict__ r,
-                                              double* __restrict__ p, double* __restrict__ rrp0,
-                                              double tol, int maxiter, double shift,
+                                              double* __restrict__ p, double* __restrict__ p2,
+                                              void* __restrict__ Rop, double* __restrict__ aux0,
+                                              int nbv, double tol, int maxiter, double shift,
                                               CgScalars* sc) {
+    const int total = d.Ma * d.Na;
     const int e = blockIdx.x * 64 + threadIdx.x;
     double q = 0.0;
     if (e < total) {
         const double fe = f[e];
+        const int j = e / d.Na, i = e - j * d.Na;
         x[e] = 0.0;
         r[e] = fe;
-        p[e] = fe;
+        p[e] = 0.0;
+        p2[e] = 0.0;
+        if constexpr (sizeof(R) == 8) {
+            ((double*)Rop)[(size_t)i * d.Ma + j] = fe;
+        } else {
+            uint16_t hi, lo;
+            split2((float)fe, hi, lo);
+            ((uint16_t*)Rop)[(size_t)j * d.Kq + i] = hi;
+            ((uint16_t*)Rop)[(size_t)d.Ma * d.Kq + (size_t)j * d.Kq + i] = lo;
+        }
         q = fe * fe;
     }
     q = wave_sum(q);
-    if (threadIdx.x == 0) rrp0[blockIdx.x] = q;
+    if (threadIdx.x == 0) {
+        aux0[blockIdx.x] = q;
+        aux0[nbv + blockIdx.x] = 0.0;
+        aux0[2 * (size_t)nbv + blockIdx.x] = 0.0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->done = 0;
         sc->bad = 0;
@@ -882,6 +964,7 @@ __global__ __launch_bounds__(64) void k_init2(int total, const double* __restric
         sc->tol = tol;
         sc->maxiter = maxiter;
         sc->shift = shift;
+        sc->rr_prev = 0.0;
     }
 }
 
@@ -917,26 +1000,17 @@ size_t qgt_pop_bytes(const Dims& d, int prec) {
     return prec == 0 ? (size_t)d.Kq * d.Ma * 8 : (size_t)2 * d.Ma * d.Kq * 2;
 }
 
-void launch_qgt_pnew(hipStream_t st, const Dims& d, int prec, const double* r,
-                     const double* p_old, double* p_new, void* Pop, const double* rrp_cur,
-                     const double* rrp_prev, double* ppart, CgScalars* sc) {
-    const int nb = qgt_nbp(d), nbv = qgt_nbr(d);
-    if (prec == 0)
-        k_pnew<0><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, ppart, sc);
-    else
-        k_pnew<1><<<nb, 256, 0, st>>>(d, r, p_old, p_new, Pop, rrp_cur, rrp_prev, nbv, ppart, sc);
-}
-
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
-                  long n, const void* Pop, double* w, const CgScalars* sc) {
+                  long n, const void* Rop, double* w, const double* aux, CgScalars* sc) {
     int waves, per;
     wave_split(d.Ma / 16, prec == 0 ? 8 : 16, waves, per);
-    const int nb = qgt_nbw(n, prec);
+    const int nb = qgt_nbw(n, prec), nbv = qgt_nbr(d);
     if (prec == 0) {
-        k_w5<0><<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, tact, n, Pop, w, q.wpart, sc);
+        k_w5<0><<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, tact, n, Rop, w, q.wpart, aux,
+                                           nbv, sc);
     } else {
         k_w6<<<nb, 64 * waves, 0, st>>>(d, (const uint8_t*)q.Sp, (const float*)tact, n,
-                                        (const uint16_t*)Pop, w, q.wpart, sc);
+                                        (const uint16_t*)Rop, w, q.wpart, aux, nbv, sc);
     }
 }
 
@@ -975,28 +1049,33 @@ void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part
                                              sc, cg);
 }
 
-void launch_qgt_init(hipStream_t st, const Dims& d, const double* f, double* x, double* r,
-                     double* p, double* rrp0, double tol, int maxiter, double shift,
-                     CgScalars* sc) {
-    // 64 entries per block: the r.r partials match those of k_update3
+void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, double* x,
+                     double* r, double* p, double* p2, void* Rop, double* aux0, double* w, long n,
+                     double tol, int maxiter, double shift, CgScalars* sc) {
+    launch_zero(st, Rop, qgt_pop_bytes(d, prec));
+    launch_zero(st, w, 8 * (size_t)n);
     const int nb = qgt_nbr(d);
-    k_init2<<<nb, 64, 0, st>>>(d.Ma * d.Na, f, x, r, p, rrp0, tol, maxiter, shift, sc);
+    if (prec == 0)
+        k_init3<double><<<nb, 64, 0, st>>>(d, f, x, r, p, p2, Rop, aux0, nb, tol, maxiter, shift,
+                                           sc);
+    else
+        k_init3<float><<<nb, 64, 0, st>>>(d, f, x, r, p, p2, Rop, aux0, nb, tol, maxiter, shift,
+                                          sc);
 }
 
-int qgt_nbp(const Dims& d) { return nb_of((long)d.Ma * d.Kq, 256); }
 int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
 
-void launch_qgt_update3(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
-                        const void* part, double* x, double* r, const double* p,
-                        const double* papart, const double* ppart, const double* rrp_cur,
-                        double* rrp_next, CgScalars* sc) {
-    const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q), npp = qgt_nbp(d);
+void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
+                       const void* part, double* x, double* r, const double* p_old,
+                       double* p_new, void* Rop, const double* papart, double* aux_next,
+                       CgScalars* sc) {
+    const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q);
     if (prec == 0)
-        k_update3<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p, papart, npa,
-                                              ppart, npp, rrp_cur, rrp_next, nb, sc);
+        k_update4<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop,
+                                              papart, npa, aux_next, nb, sc);
     else
-        k_update3<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p, papart, npa,
-                                             ppart, npp, rrp_cur, rrp_next, nb, sc);
+        k_update4<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new, Rop,
+                                             papart, npa, aux_next, nb, sc);
 }
 
 }  // namespace nqs
