@@ -188,6 +188,7 @@ size_t layout(nqs_ctx* c, char* base) {
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
+        b.q.kc = qgt_chunk(c->prec);
         // FP64: int8 spins; BF16 forms: one bit per spin
         b.q.Sp = take((size_t)Nsp * d.Kq / (c->prec == 0 ? 1 : 8));
         b.q.St = (int8_t*)take((size_t)Nsp * d.Kb / (c->prec == 0 ? 1 : 8));

@@ -126,7 +126,8 @@ struct QgtBatch {
     void* Sp;        // augmented spins, sample-major: int8 [Nsp][Kq] (FP64) or bits [Nsp][Kq/8]
     int8_t* St;      // augmented spins, site-major: int8 [Kb][Nsp] (FP64) or bits [Kb][Nsp/8]
     void* Th;        // [Ma][Nsp] t~ hidden-major (FP64) or two BF16 planes
-    long Nsp;        // samples padded to a multiple of 256
+    long Nsp;        // samples padded to a multiple of 512
+    int kc;          // samples per contraction-2 chunk (qgt_chunk)
     double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w
 };
 long qgt_padded_samples(long n);
@@ -137,6 +138,7 @@ long qgt_act_rows(long n);
 int qgt_nbu(const Dims& d);
 int qgt_nbr(const Dims& d);   // CG vector blocks (64 entries): head partials per array
 int qgt_ksplit(const QgtBatch& q);
+int qgt_chunk(int prec);
 int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per chunk)
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q);

@@ -589,22 +589,29 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
 // the blocks of one chunk are placed on one XCD, so that chunk's spins are
 // brought into a single L2.
 // ---------------------------------------------------------------------------
-constexpr int OKC = 256;         // samples per chunk
-constexpr int OKD = OKC + 1;     // FP64 LDS row stride of t~ (doubles)
-constexpr int OKP = OKC + 8;     // BF16 LDS row stride of t~ (halves)
+// samples per chunk (FP64: 256, limited by the LDS tile; BF16 forms: 512,
+// which halves the chunk partials) and LDS row strides of the t~ tile
+template <int MODE> struct OC {
+    static constexpr int KC = MODE == 0 ? 256 : 512;
+    static constexpr int KD = KC + 1;  // FP64 stride (doubles): rows in distinct banks
+    static constexpr int KP = KC + 8;  // BF16 stride (halves)
+};
 constexpr int NXCD = 8;
 
 // 16-byte unit e of the t~ tile: global source (elements) and LDS destination (bytes)
 template <int MODE>
 __device__ __forceinline__ void a_unit(int e, long Nsp, long plane, size_t& src, int& dst) {
-    if constexpr (MODE == 0) {  // 16 rows x 128 units (2 doubles each)
-        const int row = e >> 7, c = e & 127;
+    constexpr int KC = OC<MODE>::KC;
+    if constexpr (MODE == 0) {  // 16 rows x KC/2 units (2 doubles each)
+        constexpr int UR = KC / 2;
+        const int row = e / UR, c = e % UR;
         src = (size_t)row * Nsp + 2 * c;
-        dst = (row * OKD + 2 * c) * 8;
-    } else {  // 2 planes x 16 rows x 32 units (8 halves each)
-        const int pl = e >> 9, row = (e >> 5) & 15, c = e & 31;
+        dst = (row * OC<MODE>::KD + 2 * c) * 8;
+    } else {  // 2 planes x 16 rows x KC/8 units (8 halves each)
+        constexpr int UR = KC / 8;
+        const int pl = e / (16 * UR), row = (e / UR) % 16, c = e % UR;
         src = (size_t)pl * plane + (size_t)row * Nsp + 8 * c;
-        dst = ((pl * 16 + row) * OKP + 8 * c) * 2;
+        dst = ((pl * 16 + row) * OC<MODE>::KP + 8 * c) * 2;
     }
 }
 
@@ -617,8 +624,9 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
                                                  double* __restrict__ papart,
                                                  const CgScalars* __restrict__ sc) {
     if (v_mode == 0 && sc->done) return;
+    constexpr int OKC = OC<MODE>::KC, OKD = OC<MODE>::KD, OKP = OC<MODE>::KP;
     constexpr int UA = MODE == 0 ? 16 * OKC * 8 / 16 : 2 * 16 * OKC * 2 / 16;
-    constexpr int BA = MODE == 0 ? 8 : 4;   // t~ units per thread issued up front
+    constexpr int BA = MODE == 0 ? 8 : 5;   // t~ units per thread issued up front
     constexpr int BW = 2;                   // mean-w partials per thread issued up front
     constexpr int KS = MODE == 0 ? OKC / 16 : OKC / 32;  // k-steps per chunk
     // spins of the lane's site row over the chunk: FP64 path int8 (4 per
@@ -664,9 +672,14 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
             for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
         } else {
             const int8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 8) + kbeg / 8;
-            const uint4 x0 = *(const uint4*)Sr, x1 = *(const uint4*)(Sr + 16);
-            sb[0] = x0.x; sb[1] = x0.y; sb[2] = x0.z; sb[3] = x0.w;
-            sb[4] = x1.x; sb[5] = x1.y; sb[6] = x1.z; sb[7] = x1.w;
+#pragma unroll
+            for (int v = 0; v < OKC / 128; ++v) {
+                const uint4 x = *(const uint4*)(Sr + 16 * v);
+                sb[4 * v] = x.x;
+                sb[4 * v + 1] = x.y;
+                sb[4 * v + 2] = x.z;
+                sb[4 * v + 3] = x.w;
+            }
         }
     };
     load_spins(wave);
@@ -973,7 +986,7 @@ __global__ __launch_bounds__(64) void k_init3(Dims d, const double* __restrict__
 // ---------------------------------------------------------------------------
 static inline int nb_of(long n, int b) { return (int)((n + b - 1) / b); }
 
-long qgt_padded_samples(long n) { return (n + 255) / 256 * 256; }
+long qgt_padded_samples(long n) { return (n + 511) / 512 * 512; }
 
 size_t qgt_th_bytes(const Dims& d, int prec, long Nsp) {
     return (size_t)d.Ma * Nsp * (prec == 0 ? 8 : 4);
@@ -1014,7 +1027,8 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
     }
 }
 
-int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / OKC); }
+int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / q.kc); }
+int qgt_chunk(int prec) { return prec == 0 ? OC<0>::KC : OC<1>::KC; }
 
 // waves of a contraction-2 block
 static int outer_waves(const Dims& d) {
