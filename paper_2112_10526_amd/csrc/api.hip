@@ -486,7 +486,8 @@ void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
 // w = J r + beta w; the chunk partials of J^T z; the update, which forms
 // p_new = r + beta p_old (the direction alternates between two buffers, the
 // head partials too) and updates x and r.
-void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
+// With host_flag, the last on-the-fly iteration stores the stop flag there.
+void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host_flag = nullptr) {
     const Dims& d = c->d;
     const int nbv = qgt_nbr(d);
     for (int it = 0; it < iters; ++it) {
@@ -510,7 +511,8 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters) {
             {
                 PROF(NQS_PROF_REDUCE);
                 launch_qgt_update(c->stream, d, c->prec, c->b.q, c->b.part, c->b.x, c->b.r, p_old,
-                                  p_new, c->b.Pop, c->b.pap, aux_next, c->b.sc);
+                                  p_new, c->b.Pop, c->b.pap, aux_next, c->b.sc,
+                                  it + 1 == iters ? host_flag : nullptr);
             }
         } else {
             {
@@ -570,7 +572,7 @@ int capture_batch(nqs_ctx* c, double shift, int every) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        issue_cg_iters(c, NQS_QGT_ONTHEFLY, shift, every);
+        issue_cg_iters(c, NQS_QGT_ONTHEFLY, shift, every, &c->h_flag[0]);
         e = hipStreamEndCapture(c->cap_stream, &graph);
     }
     c->stream = run;
@@ -614,12 +616,14 @@ int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
             }
             HIPCHK(c, hipGraphLaunch(c->cg_graph, c->stream));
             c->cg_iter += every;
+        } else if (kind == NQS_QGT_ONTHEFLY) {
+            issue_cg_iters(c, kind, shift, k, &c->h_flag[0]);
         } else {
             issue_cg_iters(c, kind, shift, k);
+            HIPCHK(c, hipMemcpyAsync(&c->h_flag[slot], &c->b.sc->done, sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, c->stream));
         }
         launched += k;
-        HIPCHK(c, hipMemcpyAsync(&c->h_flag[slot], &c->b.sc->done, sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipEventRecord(c->flag_ev[slot], c->stream));
         ++issued;
         return NQS_OK;
@@ -634,7 +638,9 @@ int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
         }
         const int slot = checked & 1;
         HIPCHK(c, hipEventSynchronize(c->flag_ev[slot]));
-        const bool stop = c->h_flag[slot] != 0;
+        // on-the-fly: the batch's last update stored the flag in word 0 (a later
+        // batch may already have overwritten it with a value just as valid)
+        const bool stop = c->h_flag[kind == NQS_QGT_ONTHEFLY ? 0 : slot] != 0;
         ++checked;
         if (stop) break;
     }

@@ -159,7 +159,7 @@ void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part
 void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
                        const void* part, double* x, double* r, const double* p_old,
                        double* p_new, void* Rop, const double* papart, double* aux_next,
-                       CgScalars* sc);
+                       CgScalars* sc, int32_t* host_flag);
 void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, double* x,
                      double* r, double* p, double* p2, void* Rop, double* aux0, double* w, long n,
                      double tol, int maxiter, double shift, CgScalars* sc);

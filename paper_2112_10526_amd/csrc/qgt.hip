@@ -851,12 +851,14 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
 //   alpha = r.r / p.Ap;  x += alpha p_it;  r -= alpha Ap;
 // writes p_it, r (also in the contraction-1 operand layout) and the block
 // partials of r.r, r.p_it, p_it.p_it for the next head.  Block 0 advances the
-// iteration index.
+// iteration index and, when given a pinned host word, stores the stop flag
+// there (the last update of a batch of iterations does).
 template <typename R>
 __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int ksplit, double* x,
                                                  double* r, const double* p_old, double* p_new,
                                                  void* Rop, const double* papart, int npa,
-                                                 double* aux_next, int nbv, CgScalars* sc) {
+                                                 double* aux_next, int nbv, CgScalars* sc,
+                                                 volatile int32_t* host_flag) {
     __shared__ double ws[4][64];
     __shared__ double sh[4];
     __shared__ double s3[3][4];
@@ -873,7 +875,11 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
     double xa[4];
     pload4(papart, npa, xa);
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
-    if (sc->done) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (sc->done) {
+        if (host_flag && lead) *host_flag = 1;
+        return;
+    }
     const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
     double val = 0.0;
 #pragma unroll
@@ -885,17 +891,19 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
     const double pAp = pGp + shift * pp;
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lead) {
             sc->bad = 1;
             sc->done = 1;
+            if (host_flag) *host_flag = 1;
         }
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lead) {
         sc->alpha = alpha;
         sc->pAp = pAp;
         sc->rr_prev = rr;
         sc->it += 1;  // read by the next head
+        if (host_flag) *host_flag = 0;
     }
     double q[3] = {0.0, 0.0, 0.0};
     if (wave == 0 && e < total) {
@@ -1082,14 +1090,14 @@ int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
 void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
                        const void* part, double* x, double* r, const double* p_old,
                        double* p_new, void* Rop, const double* papart, double* aux_next,
-                       CgScalars* sc) {
+                       CgScalars* sc, int32_t* host_flag) {
     const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q);
     if (prec == 0)
         k_update4<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop,
-                                              papart, npa, aux_next, nb, sc);
+                                              papart, npa, aux_next, nb, sc, host_flag);
     else
         k_update4<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new, Rop,
-                                             papart, npa, aux_next, nb, sc);
+                                             papart, npa, aux_next, nb, sc, host_flag);
 }
 
 }  // namespace nqs
