@@ -45,8 +45,9 @@ def kernel_work(cls: str, w, precision: str):
 
     The two QGT contractions each apply J [Ns x P] (or its transpose) once:
     2 Ns P flops, over the factors of J, which are read once per launch:
-    per sample N spin bytes, M activations (8 B FP64; 4 B in the BF16/FP32
-    forms, FP32 or a BF16 hi/lo pair) and one 8-byte weight (w or z).  FP64
+    per sample the N spins (one bit each in the BF16/FP32 forms), M
+    activations (8 B FP64; 4 B FP32 in the BF16/FP32 forms) and one 8-byte
+    weight (w or z), plus one pass over a P-vector (4 B).  FP64
     runs on the FP64 matrix cores (78.6 TFLOP/s; 23 flop/B, above the 9.8 of
     the HBM ridge: MFMA-bound); the BF16 form (44 flop/B against a ridge of
     312) is HBM-bound.
@@ -57,7 +58,7 @@ def kernel_work(cls: str, w, precision: str):
     if cls in ("outer", "qgt_w"):
         if precision == "fp64":
             return "mfma", 2.0 * Ns * P, "TFLOP/s", PEAK["mfma_fp64"]
-        return "hbm", float(Ns * (N + 4 * M + 8) + 4 * P), "GB/s", PEAK["hbm"]
+        return "hbm", float(Ns * (N / 8.0 + 4 * M + 8) + 4 * P), "GB/s", PEAK["hbm"]
     if cls == "sample":
         # every proposal: M factors (FMA + MUL) of the amplitude ratio
         return "alu", 4.0 * C * K * M, "TFLOP/s", PEAK[vf]
@@ -72,7 +73,7 @@ def kernel_work(cls: str, w, precision: str):
 
 # kernel class -> (source file of its kernel, symbol prefix in profiles)
 KERNELS = {  # (BF16 form, the benchmark's main run)
-    "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer6<1>"),
+    "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer7"),
     "reduce": ("qgt.hip", "k_update4<float>"),
     "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
     "theta": ("theta.hip", "k_theta_bf16"),
@@ -197,7 +198,7 @@ def summarize_waves(counter_dir, cmd):
            "over waves.", "",
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
-    for name in ["nqs::k_w6", "nqs::k_outer6<1>", "nqs::k_update4<float>",
+    for name in ["nqs::k_w6", "nqs::k_outer7", "nqs::k_update4<float>",
                  "nqs::k_sample<float, 4, 0>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
         if name not in agg:
             continue

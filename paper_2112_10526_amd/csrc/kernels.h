@@ -125,7 +125,7 @@ void launch_axpy_update(hipStream_t st, int total, double* x, const double* delt
 struct QgtBatch {
     void* Sp;        // augmented spins, sample-major: int8 [Nsp][Kq] (FP64) or bits [Nsp][Kq/8]
     int8_t* St;      // augmented spins, site-major: int8 [Kb][Nsp] (FP64) or bits [Kb][Nsp/8]
-    void* Th;        // [Ma][Nsp] t~ hidden-major (FP64) or two BF16 planes
+    void* Th;        // [Ma][Nsp] t~ hidden-major: double (FP64 path) or float
     long Nsp;        // samples padded to a multiple of 512
     int kc;          // samples per contraction-2 chunk (qgt_chunk)
     double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w

@@ -14,11 +14,13 @@
 //   Sp  augmented spins, sample-major (contraction 1, A)
 //   St  augmented spins, site-major   (contraction 2, B)
 //       (int8 on the FP64 path; one bit per spin in the BF16 forms)
-//   Th  [Ma][Nsp]       t~ hidden-major: FP64, or two BF16 planes hi/lo
+//   Th  [Ma][Nsp]       t~ hidden-major (FP64 path: double; BF16 forms: float)
 // FP64 path: v_mfma_f64_16x16x4f64.  FP32/BF16 forms: v_mfma_f32_16x16x32_bf16
-// with every FP32 operand split into two BF16 terms (x = hi + lo) and the
-// three leading products hi*hi + hi*lo + lo*hi accumulated in FP32; spins are
-// exact in BF16.
+// with FP32 accumulation and spins exact in BF16 (+1 / -1); the real-valued
+// operand is an FP32 quantity split into two BF16 terms (x = hi + lo), each
+// term contracted with the spins: contraction 1 the direction (both terms of
+// r, with the activations applied in FP32 afterwards), contraction 2 the
+// FP32 product t~ z formed while the tile is staged.
 //
 // No kernel here uses atomics or fences: every reduction is a fixed-order
 // sum of per-block partials done by the consumer kernel (each block of the
@@ -151,15 +153,32 @@ __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s
     }
 }
 
-// 8 spins (bits of byte b) as BF16 +-1, packed as 8 halves
+// 8 spins (bits of the low byte of b; 1 = up) as BF16 +1 / -1, packed as 8
+// halves.  Two equivalent forms; each kernel uses the one that measured
+// faster in it.  Element-wise (contraction 1):
 __device__ __forceinline__ v8s bits_to_bf16(uint32_t b) {
     v8s r;
 #pragma unroll
     for (int e = 0; e < 8; ++e) r[e] = (short)(0xBF80 ^ (((b >> e) & 1u) << 15));
     return r;
 }
+// Word form (contraction 2): two halves per 32-bit word, 0x3F80 (+1) with the
+// sign bits taken from the complemented spin byte nb, bit 2q to bit 15 and
+// bit 2q + 1 to bit 31 of word q (two shifted copies of nb, one mask; nb has
+// no bits past 7, so the copies do not reach each other's sign bit).
+__device__ __forceinline__ v8s bits_to_bf16_words(uint32_t b) {
+    const uint32_t nb = ~b & 0xFFu;
+    uint4 r;
+    r.x = (((nb << 15) | (nb << 30)) & 0x80008000u) | 0x3F803F80u;
+    r.y = (((nb << 13) | (nb << 28)) & 0x80008000u) | 0x3F803F80u;
+    r.z = (((nb << 11) | (nb << 26)) & 0x80008000u) | 0x3F803F80u;
+    r.w = (((nb << 9) | (nb << 24)) & 0x80008000u) | 0x3F803F80u;
+    return __builtin_bit_cast(v8s, r);
+}
 
-template <typename R, int MODE>
+// t~ hidden-major: Th[j][k] = t~_kj (k < Nsp, padding samples 0), in the
+// compute precision (FP64 path: double; BF16 forms: float).
+template <typename R>
 __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long n, int Mw, int Ma,
                                                 long Nsp, void* __restrict__ out) {
     __shared__ R tile[64][65];
@@ -177,14 +196,7 @@ __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long
         const int j = j0 + jl;
         if (j >= Ma) continue;
         const size_t o = (size_t)j * Nsp + k0 + kl;
-        if constexpr (MODE == 0) {
-            ((double*)out)[o] = (double)tile[kl][jl];
-        } else {
-            uint16_t hi, lo;
-            split2((float)tile[kl][jl], hi, lo);
-            ((uint16_t*)out)[o] = hi;
-            ((uint16_t*)out)[(size_t)Ma * Nsp + o] = lo;
-        }
+        ((R*)out)[o] = tile[kl][jl];
     }
 }
 
@@ -337,13 +349,16 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<double>(lk, q)) * Mw + j];
-            v4d acc[RT];
+            // two accumulation chains per sample tile (even / odd k-steps of
+            // 16 sites), added at the end; the next group's operands are
+            // loaded while the current group's MFMAs run
+            v4d acc[RT][2];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4d{0, 0, 0, 0};
+            for (int rt = 0; rt < RT; ++rt) acc[rt][0] = acc[rt][1] = v4d{0, 0, 0, 0};
             const double* Pc = Pt + (size_t)(4 * lk) * Ma + j;
-            for (int g = 0; g < Kq; g += 32) {
-                double b[2][4];
-                uint32_t sb[RT][2];
+            double b[2][4];
+            uint32_t sb[RT][2];
+            auto load_group = [&](int g) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -353,21 +368,36 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
 #pragma unroll
                     for (int u = 0; u < 2; ++u)
                         sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
-                __builtin_amdgcn_sched_barrier(0);  // keep the group's loads together
+            };
+            load_group(0);
+            for (int g = 0; g < Kq; g += 32) {
+                double bc[2][4];
+                uint32_t sc2[RT][2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bc[u][e] = b[u][e];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) sc2[rt][u] = sb[rt][u];
+                if (g + 32 < Kq) load_group(g + 32);
+                __builtin_amdgcn_sched_barrier(0);  // next group's loads ahead of the MFMAs
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int rt = 0; rt < RT; ++rt) {
-                            const double a = (double)(int8_t)(sb[rt][u] >> (8 * e));
-                            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u][e], acc[rt], 0, 0, 0);
+                            const double a = (double)(int8_t)(sc2[rt][u] >> (8 * e));
+                            acc[rt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc[u][e], acc[rt][u], 0, 0, 0);
                         }
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) rs[rt][q] += tv[rt][q] * acc[rt][q];
+                for (int q = 0; q < 4; ++q)
+                    rs[rt][q] += tv[rt][q] * (acc[rt][0][q] + acc[rt][1][q]);
         }
     } else {
         const uint16_t* Ph = (const uint16_t*)Pop;
@@ -579,74 +609,57 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
 // contraction 2: part[kc][j][i] = sum_{k in chunk kc} t~_kj z_k s~_ki
 // v_mode 0: z_k = (w_k - mean w) / n with mean w from the contraction-1
 // partials, and the blocks of hidden tile 0 write their chunk's partial of
-// p . G p without the shift; v_mode 1: z_k = v_k.
-// One block per (hidden tile jt, chunk kc of
-// 256 samples); the tile's t~ rows and the chunk's z are staged in LDS and
-// wave w computes site tiles w, w + nw, ..., holding its spins in registers.
-// All global loads of a block are issued before any of them is consumed
-// (clamped indices, so they are unconditional).
+// p . G p without the shift (sum_k z_k (w_k - mean w)); v_mode 1: z_k = v_k.
+// One block per (hidden tile jt, chunk kc); the tile's t~ rows are staged in
+// LDS and wave w computes site tile w, holding its spins in registers.  All
+// global loads of a block are issued before any of them is consumed (clamped
+// indices, so they are unconditional).
 // Block order: the hardware deals consecutive blocks to the 8 XCDs in turn;
 // the blocks of one chunk are placed on one XCD, so that chunk's spins are
 // brought into a single L2.
 // ---------------------------------------------------------------------------
-// samples per chunk (FP64: 256, limited by the LDS tile; BF16 forms: 512,
-// which halves the chunk partials) and LDS row strides of the t~ tile
-template <int MODE> struct OC {
-    static constexpr int KC = MODE == 0 ? 256 : 512;
-    static constexpr int KD = KC + 1;  // FP64 stride (doubles): rows in distinct banks
-    static constexpr int KP = KC + 8;  // BF16 stride (halves)
-};
 constexpr int NXCD = 8;
+// FP64 path: 256 samples per chunk (limited by the LDS tile); rows of the
+// staged tile 257 doubles apart, so that the 16 rows fall in distinct banks
+constexpr int O64_KC = 256, O64_KD = O64_KC + 1;
+// BF16 forms: 512 samples per chunk; BF16 rows 520 halves apart
+constexpr int O16_KC = 512, O16_KP = O16_KC + 8;
 
-// 16-byte unit e of the t~ tile: global source (elements) and LDS destination (bytes)
-template <int MODE>
-__device__ __forceinline__ void a_unit(int e, long Nsp, long plane, size_t& src, int& dst) {
-    constexpr int KC = OC<MODE>::KC;
-    if constexpr (MODE == 0) {  // 16 rows x KC/2 units (2 doubles each)
-        constexpr int UR = KC / 2;
-        const int row = e / UR, c = e % UR;
-        src = (size_t)row * Nsp + 2 * c;
-        dst = (row * OC<MODE>::KD + 2 * c) * 8;
-    } else {  // 2 planes x 16 rows x KC/8 units (8 halves each)
-        constexpr int UR = KC / 8;
-        const int pl = e / (16 * UR), row = (e / UR) % 16, c = e % UR;
-        src = (size_t)pl * plane + (size_t)row * Nsp + 8 * c;
-        dst = ((pl * 16 + row) * OC<MODE>::KP + 8 * c) * 2;
-    }
+// block -> (hidden tile, chunk), chunks grouped by XCD
+__device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
+    const int L = blockIdx.x, x = L % NXCD, m = L / NXCD;
+    jt = m % nj;
+    kc = x + NXCD * (m / nj);
 }
 
-template <int MODE>
+// FP64 path: t~ (FP64, [Ma][Nsp]) and z staged in LDS, spins int8; the
+// FP64 MFMA takes A = t~ tile, B = s z (sign applied to z per element).
 __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restrict__ St,
-                                                 const void* __restrict__ Th, long Nsp, long n,
+                                                 const double* __restrict__ Th, long Nsp, long n,
                                                  const double* __restrict__ v, int v_mode,
                                                  const double* __restrict__ wpart, int nbw,
-                                                 void* __restrict__ part_v, int ksplit,
+                                                 double* __restrict__ part, int ksplit,
                                                  double* __restrict__ papart,
                                                  const CgScalars* __restrict__ sc) {
     if (v_mode == 0 && sc->done) return;
-    constexpr int OKC = OC<MODE>::KC, OKD = OC<MODE>::KD, OKP = OC<MODE>::KP;
-    constexpr int UA = MODE == 0 ? 16 * OKC * 8 / 16 : 2 * 16 * OKC * 2 / 16;
-    constexpr int BA = MODE == 0 ? 8 : 5;   // t~ units per thread issued up front
-    constexpr int BW = 2;                   // mean-w partials per thread issued up front
-    constexpr int KS = MODE == 0 ? OKC / 16 : OKC / 32;  // k-steps per chunk
-    // spins of the lane's site row over the chunk: FP64 path int8 (4 per
-    // k-step), BF16 forms one bit each (byte 4 u + lk of k-step u)
-    __shared__ __align__(16) char lds6[MODE == 0 ? 16 * OKD * 8 + OKC * 8
-                                                  : 2 * 16 * OKP * 2 + 2 * OKC * 2];
+    constexpr int KC = O64_KC, KD = O64_KD;
+    constexpr int UR = KC / 2;         // 16-byte units per row (2 doubles)
+    constexpr int UA = 16 * UR;        // units in the tile
+    constexpr int BA = 8;              // units per thread issued up front
+    constexpr int BW = 2;              // mean-w partials per thread issued up front
+    constexpr int KS = KC / 16;        // k-steps (4 samples per lane quad x 4 quads)
+    __shared__ __align__(16) double As[16 * KD + KC];  // t~ tile, then z
     __shared__ double sh[16];
-    // block -> (jt, kc), chunks grouped by XCD
     const int nj = d.Ma / 16;
-    const int L = blockIdx.x, x = L % NXCD, m = L / NXCD;
-    const int jt = m % nj, kc = x + NXCD * (m / nj);
+    int jt, kc;
+    outer_block(nj, jt, kc);
     if (kc >= ksplit) return;  // no chunk for this block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nth = blockDim.x, nw = nth >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const long kbeg = (long)kc * OKC;
+    const long kbeg = (long)kc * KC;
     const int nit = d.Na / 16;
-    const long plane = (long)d.Ma * Nsp;
-    const char* Ab = (const char*)Th;
-    const size_t abase = (size_t)jt * 16 * Nsp + kbeg;
+    const double* Ab = Th + (size_t)jt * 16 * Nsp + kbeg;
     // ---- issue: mean-w partials, t~ tile, z source, this wave's first spins
     double wp[BW];
 #pragma unroll
@@ -654,33 +667,18 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         const int b = u * nth + tid;
         wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
     }
-    uint4 ra[BA];
+    double2 ra[BA];
 #pragma unroll
     for (int u = 0; u < BA; ++u) {
         const int e = min(u * nth + tid, UA - 1);
-        size_t src;
-        int dst;
-        a_unit<MODE>(e, Nsp, plane, src, dst);
-        ra[u] = *(const uint4*)(Ab + (abase + src) * (MODE == 0 ? 8 : 2));
+        ra[u] = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * (e % UR));
     }
-    const double vz = v[min(kbeg + (tid & (OKC - 1)), n - 1)];
-    uint32_t sb[KS];
+    const double vz = v[min(kbeg + (tid & (KC - 1)), n - 1)];
+    uint32_t sb[KS];  // int8 spins of the lane's site row: 4 per k-step
     auto load_spins = [&](int it) {
-        if constexpr (MODE == 0) {
-            const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
+        const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
 #pragma unroll
-            for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
-        } else {
-            const int8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 8) + kbeg / 8;
-#pragma unroll
-            for (int v = 0; v < OKC / 128; ++v) {
-                const uint4 x = *(const uint4*)(Sr + 16 * v);
-                sb[4 * v] = x.x;
-                sb[4 * v + 1] = x.y;
-                sb[4 * v + 2] = x.z;
-                sb[4 * v + 3] = x.w;
-            }
-        }
+        for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
     };
     load_spins(wave);
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
@@ -694,42 +692,30 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         shift = bsum_waves(a, sh, nw) / (double)n;
         scale = 1.0 / (double)n;
     }
+    // LDS rows are KD (odd) doubles apart: 8-byte stores
 #pragma unroll
     for (int u = 0; u < BA; ++u) {
         const int e = u * nth + tid;
         if (e < UA) {
-            size_t src;
-            int dst;
-            a_unit<MODE>(e, Nsp, plane, src, dst);
-            uint2* q = (uint2*)(lds6 + dst);
-            q[0] = make_uint2(ra[u].x, ra[u].y);
-            q[1] = make_uint2(ra[u].z, ra[u].w);
+            double* q = As + (e / UR) * KD + 2 * (e % UR);
+            q[0] = ra[u].x;
+            q[1] = ra[u].y;
         }
     }
     for (int e = BA * nth + tid; e < UA; e += nth) {  // small blocks only
-        size_t src;
-        int dst;
-        a_unit<MODE>(e, Nsp, plane, src, dst);
-        const uint4 q4 = *(const uint4*)(Ab + (abase + src) * (MODE == 0 ? 8 : 2));
-        uint2* q = (uint2*)(lds6 + dst);
-        q[0] = make_uint2(q4.x, q4.y);
-        q[1] = make_uint2(q4.z, q4.w);
+        const double2 t2 = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * (e % UR));
+        double* q = As + (e / UR) * KD + 2 * (e % UR);
+        q[0] = t2.x;
+        q[1] = t2.y;
     }
+    double* zs = As + 16 * KD;
     double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
-    for (int t = tid; t < OKC; t += nth) {
+    for (int t = tid; t < KC; t += nth) {
         const long k = kbeg + t;
-        const double vk = t == (tid & (OKC - 1)) ? vz : v[min(k, n - 1)];
+        const double vk = t == (tid & (KC - 1)) ? vz : v[min(k, n - 1)];
         const double z = k < n ? (vk - shift) * scale : 0.0;
         zw += z * (vk - shift);
-        if constexpr (MODE == 0) {
-            ((double*)(lds6 + 16 * OKD * 8))[t] = z;
-        } else {
-            uint16_t h, l;
-            split2((float)z, h, l);
-            uint16_t* zh = (uint16_t*)(lds6 + 2 * 16 * OKP * 2);
-            zh[t] = h;
-            zh[OKC + t] = l;
-        }
+        zs[t] = z;
     }
     // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
     // chunk, from the blocks of hidden tile 0
@@ -740,59 +726,180 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
     __syncthreads();
     for (int it = wave; it < nit; it += nw) {
         if (it != wave) load_spins(it);
-        if constexpr (MODE == 0) {
-            const double* As = (const double*)lds6;
-            const double* zs = As + 16 * OKD;
-            v4d acc = v4d{0, 0, 0, 0};
+        // four independent accumulation chains (one per sample of a k-step's
+        // quad), added in a fixed order at the end
+        v4d acc[4];
 #pragma unroll
-            for (int u = 0; u < KS; ++u) {
+        for (int e = 0; e < 4; ++e) acc[e] = v4d{0, 0, 0, 0};
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int kl = 16 * u + 4 * lk + e;
-                    const int sv = (int8_t)(sb[u] >> (8 * e));
-                    const double z = zs[kl];
-                    const double b = sv > 0 ? z : (sv < 0 ? -z : 0.0);
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * OKD + kl], b, acc, 0, 0, 0);
-                }
-                __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
+        for (int u = 0; u < KS; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kl = 16 * u + 4 * lk + e;
+                const int sv = (int8_t)(sb[u] >> (8 * e));
+                const double z = zs[kl];
+                const double b = sv > 0 ? z : (sv < 0 ? -z : 0.0);
+                acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * KD + kl], b, acc[e], 0, 0, 0);
             }
-            double* out = (double*)part_v + (size_t)kc * d.Ma * d.Na;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                out[(size_t)(jt * 16 + acc_row<double>(lk, q)) * d.Na + it * 16 + lr] = acc[q];
-        } else {
-            const uint16_t* Ah = (const uint16_t*)lds6;
-            const uint16_t* Al = Ah + 16 * OKP;
-            const uint16_t* zh = Al + 16 * OKP;
-            const uint16_t* zl = zh + OKC;
-            v4f acc = v4f{0, 0, 0, 0};
-#pragma unroll
-            for (int u = 0; u < KS; ++u) {
-                const int kk = 32 * u + 8 * lk;
-                const v8bf ah = __builtin_bit_cast(v8bf, *(const v8s*)(Ah + lr * OKP + kk));
-                const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(Al + lr * OKP + kk));
-                const v8s zhv = *(const v8s*)(zh + kk);
-                const v8s zlv = *(const v8s*)(zl + kk);
-                const uint32_t bits = sb[u] >> (8 * lk);
-                v8s bh, bl;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {  // spin down: flip the sign of z
-                    const short sgn = (short)((~(bits >> e) & 1u) << 15);
-                    bh[e] = (short)(zhv[e] ^ sgn);
-                    bl[e] = (short)(zlv[e] ^ sgn);
-                }
-                const v8bf b1 = __builtin_bit_cast(v8bf, bh);
-                const v8bf b2 = __builtin_bit_cast(v8bf, bl);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b1, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b2, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b1, acc, 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
-            }
-            float* out = (float*)part_v + (size_t)kc * d.Ma * d.Na;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                out[(size_t)(jt * 16 + acc_row<float>(lk, q)) * d.Na + it * 16 + lr] = acc[q];
+            __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
         }
+        double* out = part + (size_t)kc * d.Ma * d.Na;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            out[(size_t)(jt * 16 + acc_row<double>(lk, q)) * d.Na + it * 16 + lr] =
+                (acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q]);
+    }
+}
+
+// BF16 forms: t~ (FP32, [Ma][Nsp]) is scaled by z while it is staged: the
+// LDS tile holds a_kj = t~_kj z_k (FP32 product) as two BF16 terms hi + lo,
+// and B is the spin matrix itself, +1 / -1, exact in BF16 and expanded from
+// the spin bits.  Two MFMAs per k-step (hi and lo) with FP32 accumulation;
+// the error of a product is that of the two-term split of a, about 2^-17
+// relative.
+__global__ __launch_bounds__(1024) void k_outer7(Dims d, const uint8_t* __restrict__ St,
+                                                 const float* __restrict__ Th, long Nsp, long n,
+                                                 const double* __restrict__ v, int v_mode,
+                                                 const double* __restrict__ wpart, int nbw,
+                                                 float* __restrict__ part, int ksplit,
+                                                 double* __restrict__ papart,
+                                                 const CgScalars* __restrict__ sc) {
+    if (v_mode == 0 && sc->done) return;
+    constexpr int KC = O16_KC, KP = O16_KP;
+    constexpr int UR = KC / 4;         // 16-byte units per row (4 floats)
+    constexpr int UA = 16 * UR;        // units in the tile
+    constexpr int BA = 5;              // units per thread issued up front (448 threads)
+    constexpr int BW = 2;              // mean-w partials per thread issued up front
+    constexpr int BV = 2;              // chunk values of v per thread issued up front
+    constexpr int KS = KC / 32;        // k-steps (32 samples each)
+    __shared__ __align__(16) uint16_t As[2 * 16 * KP];  // hi rows, then lo rows
+    __shared__ __align__(16) float zs[KC];
+    __shared__ double sh[16];
+    const int nj = d.Ma / 16;
+    int jt, kc;
+    outer_block(nj, jt, kc);
+    if (kc >= ksplit) return;  // no chunk for this block
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nth = blockDim.x, nw = nth >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long kbeg = (long)kc * KC;
+    const int nit = d.Na / 16;
+    const float* Ab = Th + (size_t)jt * 16 * Nsp + kbeg;
+    // ---- issue: mean-w partials, t~ tile, the chunk's v, this wave's spins
+    double wp[BW];
+#pragma unroll
+    for (int u = 0; u < BW; ++u) {
+        const int b = u * nth + tid;
+        wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
+    }
+    float4 ra[BA];
+#pragma unroll
+    for (int u = 0; u < BA; ++u) {
+        const int e = min(u * nth + tid, UA - 1);
+        ra[u] = *(const float4*)(Ab + (size_t)(e / UR) * Nsp + 4 * (e % UR));
+    }
+    double vk[BV];
+#pragma unroll
+    for (int u = 0; u < BV; ++u) vk[u] = v[min(kbeg + min(u * nth + tid, KC - 1), n - 1)];
+    uint32_t sb[KS];  // spin bits of the lane's site row: one byte per lane quad per k-step
+    auto load_spins = [&](int it) {
+        const uint8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 8) + kbeg / 8;
+#pragma unroll
+        for (int q = 0; q < KC / 128; ++q) {
+            const uint4 x = *(const uint4*)(Sr + 16 * q);
+            sb[4 * q] = x.x;
+            sb[4 * q + 1] = x.y;
+            sb[4 * q + 2] = x.z;
+            sb[4 * q + 3] = x.w;
+        }
+    };
+    load_spins(wave);
+    __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
+    // ---- mean w over the batch; z of the chunk into LDS between the two barriers
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < BW; ++u) a += wp[u];
+    if (v_mode == 0)
+        for (int b = BW * nth + tid; b < nbw; b += nth) a += wpart[b];
+    a = wave_sum(a);
+    if (lane == 0) sh[wave] = a;
+    __syncthreads();  // (v_mode 1: a = 0, unused)
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (q < nw) tot += sh[q];
+    const double shift = v_mode == 0 ? tot / (double)n : 0.0;
+    const double scale = v_mode == 0 ? 1.0 / (double)n : 1.0;
+    double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+        const int t = u * nth + tid;
+        if (t < KC) {
+            const double z = kbeg + t < n ? (vk[u] - shift) * scale : 0.0;
+            zw += z * (vk[u] - shift);
+            zs[t] = (float)z;
+        }
+    }
+    for (int t = BV * nth + tid; t < KC; t += nth) {  // small blocks only
+        const long k = kbeg + t;
+        const double vt = v[min(k, n - 1)];
+        const double z = k < n ? (vt - shift) * scale : 0.0;
+        zw += z * (vt - shift);
+        zs[t] = (float)z;
+    }
+    __syncthreads();
+    // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
+    // chunk, from the blocks of hidden tile 0 (wave sums parked in sh, added
+    // after the staging barrier)
+    if (v_mode == 0 && jt == 0) {
+        zw = wave_sum(zw);
+        if (lane == 0) sh[wave] = zw;
+    }
+    // ---- stage a = t~ z as hi / lo BF16 rows
+    auto stage = [&](int e, float4 t4) {
+        const int row = e / UR, c = e % UR;
+        const float4 z4 = *(const float4*)(zs + 4 * c);
+        const float av[4] = {t4.x * z4.x, t4.y * z4.y, t4.z * z4.z, t4.w * z4.w};
+        uint16_t h[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split2(av[q], h[q], l[q]);
+        *(uint2*)(As + row * KP + 4 * c) =
+            make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
+        *(uint2*)(As + (16 + row) * KP + 4 * c) =
+            make_uint2(l[0] | (uint32_t)l[1] << 16, l[2] | (uint32_t)l[3] << 16);
+    };
+#pragma unroll
+    for (int u = 0; u < BA; ++u) {
+        const int e = u * nth + tid;
+        if (e < UA) stage(e, ra[u]);
+    }
+    for (int e = BA * nth + tid; e < UA; e += nth)  // small blocks only
+        stage(e, *(const float4*)(Ab + (size_t)(e / UR) * Nsp + 4 * (e % UR)));
+    __syncthreads();
+    if (v_mode == 0 && jt == 0 && tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q < nw) t += sh[q];
+        papart[kc] = t;
+    }
+    for (int it = wave; it < nit; it += nw) {
+        if (it != wave) load_spins(it);
+        v4f acc = v4f{0, 0, 0, 0}, acc2 = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int kk = 32 * u + 8 * lk;
+            const v8bf ah = __builtin_bit_cast(v8bf, *(const v8s*)(As + lr * KP + kk));
+            const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(As + (16 + lr) * KP + kk));
+            const v8bf b = __builtin_bit_cast(v8bf, bits_to_bf16_words(sb[u] >> (8 * lk)));
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc2, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
+        }
+        float* out = part + (size_t)kc * d.Ma * d.Na;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            out[(size_t)(jt * 16 + acc_row<float>(lk, q)) * d.Na + it * 16 + lr] = acc[q] + acc2[q];
     }
 }
 
@@ -1006,9 +1113,9 @@ void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s
     k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, prec != 0, (int8_t*)q.Sp, q.St);
     const dim3 gt((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Ma, 64));
     if (prec == 0)
-        k_prep_t<double, 0><<<gt, 256, 0, st>>>((const double*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
+        k_prep_t<double><<<gt, 256, 0, st>>>((const double*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
     else
-        k_prep_t<float, 1><<<gt, 256, 0, st>>>((const float*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
+        k_prep_t<float><<<gt, 256, 0, st>>>((const float*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
 }
 
 int qgt_nbw(long n, int prec) {
@@ -1036,7 +1143,7 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
 }
 
 int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / q.kc); }
-int qgt_chunk(int prec) { return prec == 0 ? OC<0>::KC : OC<1>::KC; }
+int qgt_chunk(int prec) { return prec == 0 ? O64_KC : O16_KC; }
 
 // waves of a contraction-2 block
 static int outer_waves(const Dims& d) {
@@ -1052,11 +1159,11 @@ void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q
     const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
     const int nw = outer_waves(d), nbw = qgt_nbw(n, prec);
     if (prec == 0)
-        k_outer6<0><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
-                                            part, ks, papart, sc);
+        k_outer6<<<nb, 64 * nw, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v, v_mode,
+                                         q.wpart, nbw, (double*)part, ks, papart, sc);
     else
-        k_outer6<1><<<nb, 64 * nw, 0, st>>>(d, q.St, q.Th, q.Nsp, n, v, v_mode, q.wpart, nbw,
-                                            part, ks, papart, sc);
+        k_outer7<<<nb, 64 * nw, 0, st>>>(d, (const uint8_t*)q.St, (const float*)q.Th, q.Nsp, n, v,
+                                         v_mode, q.wpart, nbw, (float*)part, ks, papart, sc);
 }
 
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,

@@ -239,13 +239,15 @@ def test_sr_direction_parity_fp64(wname, chains):
     np.testing.assert_allclose(st.get_params(), params, rtol=0, atol=0)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
-def test_sr_direction_many_sites(precision):
+@pytest.mark.parametrize("precision,eps", [("fp64", 1e-13), ("fp32", 3e-5), ("bf16", 3e-5)])
+def test_sr_direction_many_sites(precision, eps):
     """16x16 Heisenberg (N = 256, M = 256, 66,048 parameters; several site and hidden
     tile groups per block) on a ragged batch of 333 samples: the CG direction
-    satisfies the oracle's SR system.  Bound: the CG tolerance plus the operand
-    rounding of the form (FP64: 1e-15; BF16 split pairs and FP32 sums: 3e-5)
-    times |G| |d| with |G| <= shift + |O_c|_F^2 / n."""
+    satisfies the oracle's SR system up to the CG tolerance plus the rounding of
+    the form's operator, |G d - f| <= 2 tol |f| + eps |G|_2 |d|.  eps: FP64 path;
+    FP32 and BF16 forms (both contractions take their operands as two BF16
+    terms on MFMA with FP32 accumulation, relative error about 2^-16 per
+    Jacobian entry, so 2 x 2^-16 in G, with margin)."""
     torch = _torch()
     w = HEIS2D.replace(sigma=0.05, alpha=1, n_chains=111, samples_per_chain=3)
     params = w.params()
@@ -262,12 +264,18 @@ def test_sr_direction_many_sites(precision):
     f = core.force(O, E)
     d = delta.cpu().numpy()
     res = np.linalg.norm(core.qgt_matvec(O, d, 0.01) - f)
-    Oc = O - O.mean(axis=0)
-    gnorm = 0.01 + (Oc * Oc).sum() / O.shape[0]
-    eps = 1e-15 if precision == "fp64" else 3e-5
+    # |G|_2 by power iteration on the oracle's product
+    v = np.random.default_rng(0).normal(size=d.size)
+    for _ in range(40):
+        v = core.qgt_matvec(O, v, 0.01)
+        v /= np.linalg.norm(v)
+    gnorm = np.linalg.norm(core.qgt_matvec(O, v, 0.01))
     bound = 2 * tol * np.linalg.norm(f) + eps * gnorm * np.linalg.norm(d)
-    print(f"residual {res:.3e} bound {bound:.3e} iterations {info.iterations}")
+    print(f"residual {res:.3e} bound {bound:.3e} |f| {np.linalg.norm(f):.3e} "
+          f"|G| {gnorm:.3e} |d| {np.linalg.norm(d):.3e} iterations {info.iterations}")
     assert res <= bound
+    # the bound is informative: far below |f| (a wrong direction misses by ~|f|)
+    assert bound < 0.2 * np.linalg.norm(f)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16"])
@@ -400,9 +408,12 @@ def test_vmc_steps_track_oracle_fp64():
         assert np.abs(st.get_params() - rbm.params).max() <= 1e-9
 
 
-def test_vmc_converges_tfim_chain_gpu():
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_vmc_converges_tfim_chain_gpu(precision):
+    """SR from small random parameters reaches the exact ground energy of the
+    periodic N = 10 chain (Pfeuty closed form) within 0.3 % in both forms."""
     w = TFIM1D
-    st, w = make_state(w, precision="fp64")
+    st, w = make_state(w, precision=precision)
     st.thermalize(100)
     E = [st.vmc_step(lr=0.05).energy["mean"] for _ in range(150)]
     from oracle import exact
