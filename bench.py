@@ -21,6 +21,7 @@ not the one `value` comes from; its step time is reported too).
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -185,7 +186,6 @@ def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
 
 def summarize_waves(counter_dir, cmd):
     """Markdown table of the wave-state counters (SQ_*) of the BF16 hot-path kernels."""
-    import collections
     rows = _counter_rows(counter_dir)
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
@@ -213,19 +213,45 @@ def summarize_waves(counter_dir, cmd):
     print("\n".join(out))
 
 
+def _full_launch_medians(trace_csv):
+    """Per kernel: median duration (us) and count of the launches that did the work.
+    CG kernels queued after the solve has stopped return at once; launches shorter
+    than 30 % of the kernel's 90th-percentile duration are left out."""
+    import csv
+    durs = collections.defaultdict(list)
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            durs[name].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = {}
+    for name, v in durs.items():
+        a = np.array(v)
+        full = a[a >= 0.3 * np.percentile(a, 90)]
+        out[name] = (float(np.median(full)), len(full))
+    return out
+
+
 def summarize_stats(stats_csv, cmd, title):
-    """Markdown table of a rocprofv3 kernel_stats.csv."""
+    """Markdown table of a rocprofv3 kernel_stats.csv (with the median of the full
+    launches from the kernel_trace.csv beside it, when present)."""
     import csv
     with open(stats_csv) as fh:
         rows = list(csv.DictReader(fh))
+    trace = stats_csv.replace("kernel_stats.csv", "kernel_trace.csv")
+    med = _full_launch_medians(trace) if os.path.exists(trace) else {}
     out = [f"# {title}", "", "Command:", "", f"    {cmd}", "",
-           "| kernel | calls | avg us | min us | max us | total ms | % |",
-           "|---|---:|---:|---:|---:|---:|---:|"]
+           "`full med us`: median duration of the launches that did the work (CG kernels "
+           "queued after a solve has stopped return at once; launches under 30 % of the "
+           "kernel's 90th-percentile duration are left out), over `full` launches.", "",
+           "| kernel | calls | avg us | min us | max us | total ms | % | full | full med us |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         name = r["Name"].split("(")[0].replace("void ", "")
+        m, c = med.get(name, (float("nan"), 0))
         out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
-                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} | "
+                   f"{c} | {m:.2f} |")
     print("\n".join(out))
 
 
