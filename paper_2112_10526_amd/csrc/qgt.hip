@@ -215,55 +215,71 @@ __device__ __forceinline__ double pload1(const double* a, int na) {
     return na > 0 ? a[min((int)threadIdx.x, na - 1)] : 0.0;
 }
 
-// Fixed-order block sums of three partial arrays of length na (nw waves,
-// one barrier); x* hold what pload1 loaded, the rest is read here.
-__device__ __forceinline__ void psum3n(const double* a, const double* b, const double* c, int na,
-                                       int nth, int nw, double xa, double xb, double xc,
-                                       double (&out)[3]) {
-    __shared__ double s3[3][16];
+// CG head of iteration it: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the
+// partials (aux: three arrays of nbv), the stop rule (r.r <= tol^2 r0.r0,
+// it >= maxiter, or non-finite), beta_it = r.r / r_{it-1}.r_{it-1} (0 at it =
+// 0) and p_it.p_it.  Block 0 publishes them; every block takes the same
+// decision.  The CG scalars the head reads are loaded when the kernel starts
+// (earlier kernels wrote them; loading them there takes their latency off
+// the end of the kernel).
+struct HeadIn {
+    int it, maxiter;
+    double rr0, tol, rr_prev;
+};
+__device__ __forceinline__ HeadIn head_in(const CgScalars* sc) {
+    HeadIn h;
+    h.it = sc->it;
+    h.maxiter = sc->maxiter;
+    h.rr0 = sc->rr0;
+    h.tol = sc->tol;
+    h.rr_prev = sc->rr_prev;
+    return h;
+}
+
+// CG head, part 1: this thread's share of the three partial sums (its
+// pre-loaded first entries, then any further ones), reduced over the wave and
+// parked in s3[q][wave]; the caller's barrier follows (it is shared with the
+// contraction's own block reduction).
+__device__ __forceinline__ void head_park(const double* aux, int nbv, int nth, double xa,
+                                          double xb, double xc, double (*s3)[16]) {
     double t[3] = {0.0, 0.0, 0.0};
-    if ((int)threadIdx.x < na) {
+    if ((int)threadIdx.x < nbv) {
         t[0] = xa;
         t[1] = xb;
         t[2] = xc;
     }
-    for (int i = nth + (int)threadIdx.x; i < na; i += nth) {
-        t[0] += a[i];
-        t[1] += b[i];
-        t[2] += c[i];
+    for (int i = nth + (int)threadIdx.x; i < nbv; i += nth) {
+        t[0] += aux[i];
+        t[1] += aux[nbv + i];
+        t[2] += aux[2 * nbv + i];
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const double v = wave_sum(t[q]);
         if ((threadIdx.x & 63) == 0) s3[q][threadIdx.x >> 6] = v;
     }
-    __syncthreads();
+}
+
+// CG head, part 2 (after the barrier): the block sums r.r, r.p_old and
+// p_old.p_old (waves in order, the same in every block), the stop test, beta
+// and p.p; block 0 publishes them.  Returns false when CG stops.
+__device__ __forceinline__ bool head_finish(const double (*s3)[16], int nw, const HeadIn& h,
+                                            CgScalars* sc, double& beta) {
+    double t[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double r = 0.0;
 #pragma unroll
         for (int w = 0; w < 16; ++w)
             if (w < nw) r += s3[q][w];
-        out[q] = r;
+        t[q] = r;
     }
-}
-
-// CG head of iteration it: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the
-// partials (aux: three arrays of nbv), the stop rule (r.r <= tol^2 r0.r0,
-// it >= maxiter, or non-finite), beta_it = r.r / r_{it-1}.r_{it-1} (0 at it =
-// 0) and p_it.p_it.  Block 0 publishes them.  Returns false when the solve
-// stops here (the same in every block).
-__device__ __forceinline__ bool cg_head(const double* aux, int nbv, int nth, int nw, double xa,
-                                        double xb, double xc, CgScalars* sc, double& beta) {
-    double t[3];
-    psum3n(aux, aux + nbv, aux + 2 * nbv, nbv, nth, nw, xa, xb, xc, t);
     const double rr = t[0], rp = t[1], ppo = t[2];
-    const int it = sc->it;
-    const double rr0 = it == 0 ? rr : sc->rr0;
-    const double tol = sc->tol;
-    const double tol2 = tol * tol * rr0;
-    const bool stop = !(rr > tol2) || it >= sc->maxiter || !isfinite(rr);
-    beta = it == 0 ? 0.0 : rr / sc->rr_prev;
+    const int it = h.it;
+    const double rr0 = it == 0 ? rr : h.rr0;  // (sc->rr0 is set by iteration 0's head)
+    const double tol2 = h.tol * h.tol * rr0;
+    const bool stop = !(rr > tol2) || it >= h.maxiter || !isfinite(rr);
+    beta = it == 0 ? 0.0 : rr / h.rr_prev;
     const double pp = rr + 2.0 * beta * rp + beta * beta * ppo;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rr = rr;
@@ -311,20 +327,21 @@ static inline void wave_split(int tiles, int maxw, int& waves, int& per_wave) {
 // products vanish; their activation rows (the activation buffer holds whole
 // blocks of rows) are read but only ever multiply those zeros.
 // ---------------------------------------------------------------------------
-template <int MODE> struct WRows { static constexpr int RT = MODE == 0 ? 2 : 4; };  // k_w5 / k_w6
+constexpr int W5_RT = 2;        // FP64: sample tiles per block (32 samples)
 constexpr int W_ROWS_MAX = 64;  // samples per contraction-1 block, largest form
 
-// FP64 blocks have at most 8 waves (the FP64 fragments need the registers)
-template <int MODE>
-__global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int8_t* __restrict__ Sp,
-                                             const void* __restrict__ tact_v, long n,
-                                             const void* __restrict__ Pop,
-                                             double* __restrict__ w, double* __restrict__ wpart,
-                                             const double* __restrict__ aux, int nbv,
-                                             CgScalars* sc) {
-    constexpr int RT = WRows<MODE>::RT;
+// FP64 path: at most 8 waves per block (the FP64 fragments need the registers)
+__global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ Sp,
+                                            const double* __restrict__ tact, long n,
+                                            const double* __restrict__ Pt,
+                                            double* __restrict__ w, double* __restrict__ wpart,
+                                            const double* __restrict__ aux, int nbv,
+                                            CgScalars* sc) {
+    constexpr int RT = W5_RT;
     if (sc->done) return;
+    const HeadIn hin = head_in(sc);
     __shared__ double wsh[16][16 * RT];
+    __shared__ double s3[3][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * (16 * RT);
@@ -338,140 +355,78 @@ __global__ __launch_bounds__(MODE == 0 ? 512 : 1024) void k_w5(Dims d, const int
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) rs[rt][q] = 0.0;
-    if constexpr (MODE == 0) {
-        const double* Pt = (const double*)Pop;
-        const double* tact = (const double*)tact_v;
-        for (int ct = wave; ct < nct; ct += nw) {
-            const int j = ct * 16 + lr;
-            double tv[RT][4];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<double>(lk, q)) * Mw + j];
-            // two accumulation chains per sample tile (even / odd k-steps of
-            // 16 sites), added at the end; the next group's operands are
-            // loaded while the current group's MFMAs run
-            v4d acc[RT][2];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt][0] = acc[rt][1] = v4d{0, 0, 0, 0};
-            const double* Pc = Pt + (size_t)(4 * lk) * Ma + j;
-            double b[2][4];
-            uint32_t sb[RT][2];
-            auto load_group = [&](int g) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) b[u][e] = Pc[(size_t)(g + 16 * u + e) * Ma];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
-            };
-            load_group(0);
-            for (int g = 0; g < Kq; g += 32) {
-                double bc[2][4];
-                uint32_t sc2[RT][2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) bc[u][e] = b[u][e];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) sc2[rt][u] = sb[rt][u];
-                if (g + 32 < Kq) load_group(g + 32);
-                __builtin_amdgcn_sched_barrier(0);  // next group's loads ahead of the MFMAs
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int rt = 0; rt < RT; ++rt) {
-                            const double a = (double)(int8_t)(sc2[rt][u] >> (8 * e));
-                            acc[rt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc[u][e], acc[rt][u], 0, 0, 0);
-                        }
-            }
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    rs[rt][q] += tv[rt][q] * (acc[rt][0][q] + acc[rt][1][q]);
-        }
-    } else {
-        const uint16_t* Ph = (const uint16_t*)Pop;
-        const uint16_t* Pl = Ph + (size_t)Ma * Kq;
-        const float* tact = (const float*)tact_v;
-        float rsf[RT][4];
+    for (int ct = wave; ct < nct; ct += nw) {
+        const int j = ct * 16 + lr;
+        double tv[RT][4];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
-        for (int ct = wave; ct < nct; ct += nw) {
-            const int j = ct * 16 + lr;
-            float tv[RT][4];
+            for (int q = 0; q < 4; ++q)
+                tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<double>(lk, q)) * Mw + j];
+        // two accumulation chains per sample tile (even / odd k-steps of
+        // 16 sites), added at the end; the next group's operands are
+        // loaded while the current group's MFMAs run
+        v4d acc[RT][2];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt][0] = acc[rt][1] = v4d{0, 0, 0, 0};
+        const double* Pc = Pt + (size_t)(4 * lk) * Ma + j;
+        double b[2][4];
+        uint32_t sb[RT][2];
+        auto load_group = [&](int g) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) b[u][e] = Pc[(size_t)(g + 16 * u + e) * Ma];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<float>(lk, q)) * Mw + j];
-            v4f acc[RT];
+                for (int u = 0; u < 2; ++u)
+                    sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
+        };
+        load_group(0);
+        for (int g = 0; g < Kq; g += 32) {
+            double bc[2][4];
+            uint32_t sc2[RT][2];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
-            const size_t prow = (size_t)j * Kq + 8 * lk;
-            for (int g = 0; g < Kq; g += 128) {
-                v8s bh[4], bl[4];
-                uint64_t sb[RT][4];
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    bh[u] = *(const v8s*)(Ph + prow + g + 32 * u);
-                    bl[u] = *(const v8s*)(Pl + prow + g + 32 * u);
-                }
+                for (int e = 0; e < 4; ++e) bc[u][e] = b[u][e];
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        sb[rt][u] = *(const uint64_t*)(Sbase + (size_t)16 * rt * Kq + g + 32 * u + 8 * lk);
-                __builtin_amdgcn_sched_barrier(0);  // keep the group's loads together
+                for (int u = 0; u < 2; ++u) sc2[rt][u] = sb[rt][u];
+            if (g + 32 < Kq) load_group(g + 32);
+            __builtin_amdgcn_sched_barrier(0);  // next group's loads ahead of the MFMAs
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt) {
-                        v8s av;
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int8_t sv = (int8_t)(sb[rt][u] >> (8 * e));
-                            av[e] = sv > 0 ? (short)0x3F80 : (sv < 0 ? (short)0xBF80 : (short)0);
-                        }
-                        const v8bf a = __builtin_bit_cast(v8bf, av);
-                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh[u]), acc[rt], 0, 0, 0);
-                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl[u]), acc[rt], 0, 0, 0);
+                        const double a = (double)(int8_t)(sc2[rt][u] >> (8 * e));
+                        acc[rt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc[u][e], acc[rt][u], 0, 0, 0);
                     }
-            }
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rs[rt][q] = (double)rsf[rt][q];
+            for (int q = 0; q < 4; ++q)
+                rs[rt][q] += tv[rt][q] * (acc[rt][0][q] + acc[rt][1][q]);
     }
-    double beta;
-    if (!cg_head(aux, nbv, blockDim.x, nw, xa, xb, xc, sc, beta)) return;
-    // sums over the 16 columns of the wave's tiles, then over the waves in order
+    // CG head partials and the sums over the 16 columns of the wave's tiles,
+    // parked in LDS behind one barrier
+    head_park(aux, nbv, blockDim.x, xa, xb, xc, s3);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double v = row16_sum(rs[rt][q]);
-            const int row = MODE == 0 ? acc_row<double>(lk, q) : acc_row<float>(lk, q);
-            if (lr == 0) wsh[wave][16 * rt + row] = v;
+            if (lr == 0) wsh[wave][16 * rt + acc_row<double>(lk, q)] = v;
         }
     __syncthreads();
-    if (wave == 0) {  // one lane per sample, then over the block's samples
+    double beta;
+    if (!head_finish(s3, nw, hin, sc, beta)) return;
+    if (wave == 0) {  // one lane per sample (waves in order), then over the block's samples
         double v = 0.0;
         const long k = r0 + lane;
         if (lane < 16 * RT) {
@@ -503,9 +458,11 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
                                              CgScalars* sc) {
     constexpr int RT = W6_ROWS / 16;
     if (sc->done) return;
+    const HeadIn hin = head_in(sc);
     __shared__ double wsh[16][W6_ROWS];
     __shared__ double wold_s[W6_ROWS];   // previous w of the block's samples
     __shared__ double head_s[3][1024];   // this thread's CG head partials
+    __shared__ double s3[3][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * W6_ROWS;
@@ -578,12 +535,11 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
     };
     tile(wave, std::true_type{});  // every wave has a first tile
     for (int ct = wave + nw; ct < nct; ct += nw) tile(ct, std::false_type{});
-    // CG head (each thread reads back the partials it parked)
-    if (!cg_head(aux, nbv, blockDim.x, nw, head_s[0][tid], head_s[1][tid], head_s[2][tid], sc,
-                 beta))
-        return;
-    // sums over the 16 columns of the wave's tiles, then over the waves in
-    // order (wave 0, one lane per sample), then over the block's samples
+    // CG head partials (each thread reads back the ones it parked) and the
+    // sums over the 16 columns of the wave's tiles, parked in LDS behind one
+    // barrier; then the head, and the sums over the waves in order (wave 0,
+    // one lane per sample) and over the block's samples
+    head_park(aux, nbv, blockDim.x, head_s[0][tid], head_s[1][tid], head_s[2][tid], s3);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -592,6 +548,7 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
             if (lr == 0) wsh[wave][16 * rt + acc_row<float>(lk, q)] = v;
         }
     __syncthreads();
+    if (!head_finish(s3, nw, hin, sc, beta)) return;
     if (wave == 0) {
         double v = 0.0;
 #pragma unroll
@@ -1119,7 +1076,7 @@ void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s
 }
 
 int qgt_nbw(long n, int prec) {
-    return nb_of(n, 16 * (prec == 0 ? WRows<0>::RT : WRows<1>::RT));
+    return nb_of(n, prec == 0 ? 16 * W5_RT : W6_ROWS);
 }
 long qgt_act_rows(long n) { return (n + W_ROWS_MAX - 1) / W_ROWS_MAX * W_ROWS_MAX; }
 int qgt_nbu(const Dims& d) { return nb_of((long)d.Ma * d.Na, 256); }
@@ -1134,8 +1091,8 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
     wave_split(d.Ma / 16, prec == 0 ? 8 : 16, waves, per);
     const int nb = qgt_nbw(n, prec), nbv = qgt_nbr(d);
     if (prec == 0) {
-        k_w5<0><<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, tact, n, Rop, w, q.wpart, aux,
-                                           nbv, sc);
+        k_w5<<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, (const double*)tact, n,
+                                        (const double*)Rop, w, q.wpart, aux, nbv, sc);
     } else {
         k_w6<<<nb, 64 * waves, 0, st>>>(d, (const uint8_t*)q.Sp, (const float*)tact, n,
                                         (const uint16_t*)Rop, w, q.wpart, aux, nbv, sc);
