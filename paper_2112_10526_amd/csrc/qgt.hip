@@ -338,7 +338,9 @@ __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ S
                                             const double* __restrict__ aux, int nbv,
                                             CgScalars* sc) {
     constexpr int RT = W5_RT;
-    if (sc->done) return;
+    // the stop flag and the head's scalars; the flag is tested once the
+    // first tile's loads are in flight
+    const int done = sc->done;
     const HeadIn hin = head_in(sc);
     __shared__ double wsh[16][16 * RT];
     __shared__ double s3[3][16];
@@ -384,6 +386,10 @@ __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ S
                     sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
         };
         load_group(0);
+        if (ct == wave) {
+            asm volatile("" ::: "memory");  // the loads above go out before the stop test
+            if (done) return;               // (uniform over the block, before any barrier)
+        }
         for (int g = 0; g < Kq; g += 32) {
             double bc[2][4];
             uint32_t sc2[RT][2];
@@ -457,7 +463,9 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
                                              const double* __restrict__ aux, int nbv,
                                              CgScalars* sc) {
     constexpr int RT = W6_ROWS / 16;
-    if (sc->done) return;
+    // the stop flag and the head's scalars; the flag is tested once the
+    // first tile's loads are in flight
+    const int done = sc->done;
     const HeadIn hin = head_in(sc);
     __shared__ double wsh[16][W6_ROWS];
     __shared__ double wold_s[W6_ROWS];   // previous w of the block's samples
@@ -481,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
     // one hidden tile; in the wave's first tile (head) the CG head partials
     // and the previous w are fetched behind the first group's loads and
     // parked in LDS, so that no register holds them during the MFMAs
-    auto tile = [&](int ct, auto head) {
+    auto tile = [&](int ct, auto head) -> bool {
         const int j = ct * 16 + lr;
         float tv[RT][4];
 #pragma unroll
@@ -508,6 +516,8 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
                     const double xa = pload1(aux, nbv), xb = pload1(aux + nbv, nbv),
                                  xc = pload1(aux + 2 * nbv, nbv);
                     const double wo = w[min(r0 + lane, n - 1)];
+                    asm volatile("" ::: "memory");  // the loads above go out before the stop test
+                    if (done) return false;         // (uniform over the block, before any barrier)
                     head_s[0][tid] = xa;
                     head_s[1][tid] = xb;
                     head_s[2][tid] = xc;
@@ -532,8 +542,9 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
+        return true;
     };
-    tile(wave, std::true_type{});  // every wave has a first tile
+    if (!tile(wave, std::true_type{})) return;  // every wave has a first tile
     for (int ct = wave + nw; ct < nct; ct += nw) tile(ct, std::false_type{});
     // CG head partials (each thread reads back the ones it parked) and the
     // sums over the 16 columns of the wave's tiles, parked in LDS behind one
@@ -598,7 +609,8 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
                                                  double* __restrict__ part, int ksplit,
                                                  double* __restrict__ papart,
                                                  const CgScalars* __restrict__ sc) {
-    if (v_mode == 0 && sc->done) return;
+    // stop flag of the CG product, tested once the block's loads are in flight
+    const int done = v_mode == 0 ? sc->done : 0;
     constexpr int KC = O64_KC, KD = O64_KD;
     constexpr int UR = KC / 2;         // 16-byte units per row (2 doubles)
     constexpr int UA = 16 * UR;        // units in the tile
@@ -638,6 +650,8 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
     };
     load_spins(wave);
+    asm volatile("" ::: "memory");  // the loads above go out before the stop test
+    if (done) return;               // (uniform over the block, before any barrier)
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
     // ---- consume
     double shift = 0.0, scale = 1.0;
@@ -721,7 +735,8 @@ __global__ __launch_bounds__(1024) void k_outer7(Dims d, const uint8_t* __restri
                                                  float* __restrict__ part, int ksplit,
                                                  double* __restrict__ papart,
                                                  const CgScalars* __restrict__ sc) {
-    if (v_mode == 0 && sc->done) return;
+    // stop flag of the CG product, tested once the block's loads are in flight
+    const int done = v_mode == 0 ? sc->done : 0;
     constexpr int KC = O16_KC, KP = O16_KP;
     constexpr int UR = KC / 4;         // 16-byte units per row (4 floats)
     constexpr int UA = 16 * UR;        // units in the tile
@@ -771,6 +786,8 @@ __global__ __launch_bounds__(1024) void k_outer7(Dims d, const uint8_t* __restri
         }
     };
     load_spins(wave);
+    asm volatile("" ::: "memory");  // the loads above go out before the stop test
+    if (done) return;               // (uniform over the block, before any barrier)
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
     // ---- mean w over the batch; z of the chunk into LDS between the two barriers
     double a = 0.0;
@@ -938,13 +955,15 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
     const double xe = x[ec], re0 = r[ec], po = p_old[ec];
     double xa[4];
     pload4(papart, npa, xa);
+    // the CG scalars with the stop flag (one round trip)
+    const int done = sc->done;
+    const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (sc->done) {
+    if (done) {
         if (host_flag && lead) *host_flag = 1;
         return;
     }
-    const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
     double val = 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u)
