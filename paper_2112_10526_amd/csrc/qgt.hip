@@ -43,53 +43,6 @@ __device__ __forceinline__ double bsum256(double v, double* sh) {
     return r;
 }
 
-// Fixed-order sums of partial arrays in 256-thread blocks (the same order in
-// every block).  The first 4 x 256 entries are loaded by pload4 (clamped,
-// unconditional) so a kernel can issue them together with its other loads;
-// psum adds the rest and reduces over the block.
-__device__ __forceinline__ void pload4(const double* a, int na, double (&x)[4]) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = u * 256 + (int)threadIdx.x;
-        x[u] = na > 0 ? a[min(i, na - 1)] : 0.0;
-    }
-}
-// three sums of psum's kind with one barrier
-__device__ __forceinline__ void psum3(const double* a, int na, const double (&xa)[4],
-                                      const double* b, int nb, const double (&xb)[4],
-                                      const double* c, int nc, const double (&xc)[4],
-                                      double (&out)[3]) {
-    __shared__ double s3[3][4];
-    double t[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = u * 256 + (int)threadIdx.x;
-        if (i < na) t[0] += xa[u];
-        if (i < nb) t[1] += xb[u];
-        if (i < nc) t[2] += xc[u];
-    }
-    for (int i = 1024 + (int)threadIdx.x; i < na; i += 256) t[0] += a[i];
-    for (int i = 1024 + (int)threadIdx.x; i < nb; i += 256) t[1] += b[i];
-    for (int i = 1024 + (int)threadIdx.x; i < nc; i += 256) t[2] += c[i];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double v = wave_sum(t[q]);
-        if ((threadIdx.x & 63) == 0) s3[q][threadIdx.x >> 6] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) out[q] = (s3[q][0] + s3[q][1]) + (s3[q][2] + s3[q][3]);
-}
-
-__device__ __forceinline__ double psum(const double* a, int na, const double (&x)[4], double* sh) {
-    double t = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (u * 256 + (int)threadIdx.x < na) t += x[u];
-    for (int i = 1024 + (int)threadIdx.x; i < na; i += 256) t += a[i];
-    return bsum256(t, sh);
-}
-
 __device__ __forceinline__ uint16_t bf16_rn(float f) { return f32_to_bf16_bits(f); }
 
 // x ~= hi + lo in BF16
@@ -926,7 +879,8 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
 }
 
 // CG update of iteration it, 64 entries per block (wave w sums chunk slabs
-// [w ks/4, (w+1) ks/4)), with r.r, beta and p.p from the head:
+// [w ks/4, (w+1) ks/4); after one barrier wave 0 finishes alone), with r.r,
+// beta and p.p from the head:
 //   p_it = r + beta p_{it-1};  Ap = sum_kc part[kc] + shift p_it (parameter
 //   entries only);  p.Ap = sum of the per-chunk partials of p.G p + shift p.p;
 //   alpha = r.r / p.Ap;  x += alpha p_it;  r -= alpha Ap;
@@ -941,8 +895,6 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
                                                  double* aux_next, int nbv, CgScalars* sc,
                                                  volatile int32_t* host_flag) {
     __shared__ double ws[4][64];
-    __shared__ double sh[4];
-    __shared__ double s3[3][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int total = d.Ma * d.Na;
     const int e = blockIdx.x * 64 + lane;
@@ -953,8 +905,9 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
 #pragma unroll
     for (int u = 0; u < 16; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
     const double xe = x[ec], re0 = r[ec], po = p_old[ec];
-    double xa[4];
-    pload4(papart, npa, xa);
+    double xa[4];  // p.Gp chunk partials lane, lane + 64, ... (summed by wave 0)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xa[u] = npa > 0 ? papart[min(u * 64 + lane, npa - 1)] : 0.0;
     // the CG scalars with the stop flag (one round trip)
     const int done = sc->done;
     const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
@@ -970,7 +923,15 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
         if (kb + u < ke) val += (double)xs[u];
     for (int kc = kb + 16; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
     ws[wave][lane] = val;
-    const double pGp = psum(papart, npa, xa, sh);  // (its barriers also publish ws)
+    __syncthreads();
+    if (wave != 0) return;  // waves 1-3 only summed chunk slabs
+    // p.G p: the chunk partials in a fixed order (the same in every block)
+    double tg = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u * 64 + lane < npa) tg += xa[u];
+    for (int c = 256 + lane; c < npa; c += 64) tg += papart[c];
+    const double pGp = wave_sum(tg);
     const double pAp = pGp + shift * pp;
     const double alpha = rr / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
@@ -989,7 +950,7 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
         if (host_flag) *host_flag = 0;
     }
     double q[3] = {0.0, 0.0, 0.0};
-    if (wave == 0 && e < total) {
+    if (e < total) {
         const int j = e / d.Na, i = e - j * d.Na;
         const bool keep = (j < d.M && i < d.N) || (d.hb && j < d.M && i == d.N) ||
                           (d.vb && j == d.M && i < d.N);
@@ -1012,15 +973,11 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
         q[1] = rn * pn;
         q[2] = pn * pn;
     }
+    // the block's partials of r.r, r.p and p.p for the next head
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double v = wave_sum(q[k]);
-        if (lane == 0) s3[k][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        const int k = threadIdx.x;
-        aux_next[(size_t)k * nbv + blockIdx.x] = (s3[k][0] + s3[k][1]) + (s3[k][2] + s3[k][3]);
+        if (lane == 0) aux_next[(size_t)k * nbv + blockIdx.x] = v;
     }
 }
 
