@@ -262,6 +262,26 @@ def make(w, precision):
     return st
 
 
+def stage_rooflines(w, precision, prof):
+    """Each stage's kernel against its own binding roof (VALU for sampling and local
+    energies, MFMA for theta and the FP64 contractions, HBM for the BF16 ones), from the
+    event-timed warm-up launches: algorithmic work per launch / average launch time."""
+    out = {}
+    for cls in ("sample", "theta", "eloc", "qgt_w", "outer", "reduce"):
+        p = prof.get(cls)
+        if not p or not p["launches"]:
+            continue
+        bound, work, unit, peak = kernel_work(cls, w, precision)
+        if not np.isfinite(work):
+            continue
+        us = p["ms"] * 1e3 / p["launches"]
+        per_s = work / (us * 1e-6)
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        out[cls] = dict(bound=bound, achieved=per_s / scale, peak=peak / scale, unit=unit,
+                        frac=per_s / peak, avg_launch_us=us, launches=p["launches"])
+    return out
+
+
 def run_precision(w, precision, steps, warmup, torch):
     st = make(w, precision)
     # warm-up steps, profiled in full to find the dominant kernel class
@@ -319,6 +339,7 @@ def run_precision(w, precision, steps, warmup, torch):
         dominant=dict(kernel_class=dominant, launches=tp["launches"], total_ms=tp["ms"],
                       timed_pass_ms_per_step=(e1 - e0) / steps * 1e3,
                       timed_pass_cg_iters_mean=float(np.mean(iters_b))),
+        stages=stage_rooflines(w, precision, prof),
     )
     st.close()
     return out
@@ -425,7 +446,7 @@ def main():
         p99_ms=main_run["p99_ms"],
         stage_local_energies_per_s=main_run["stage_local_energies_per_s"],
         cg_iters_mean=main_run["cg_iters_mean"], acceptance=main_run["acceptance_mean"],
-        roofline=roofline, cpu_baseline=cpu,
+        roofline=roofline, stage_roofline=main_run["stages"], cpu_baseline=cpu,
         compare=cmp_run, detail=main_run,
     )
     print(json.dumps(line))

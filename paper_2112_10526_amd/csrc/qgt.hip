@@ -445,10 +445,7 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
     auto tile = [&](int ct, auto head) -> bool {
         const int j = ct * 16 + lr;
         float tv[RT][4];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
+        double hx[4];  // head partials and previous w (head tile only)
         v4f acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
@@ -463,18 +460,23 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) sbits[rt] = *(const uint4*)(sb0 + 16 * rt * KB + g / 8);
+            if (g == 0) {
+                // the activations (needed after the MFMAs) behind the MFMA
+                // operands, so that the MFMAs do not wait for them
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
+            }
             if constexpr (decltype(head)::value) {
                 if (g == 0) {
                     __builtin_amdgcn_sched_barrier(0);  // behind the contraction's loads
-                    const double xa = pload1(aux, nbv), xb = pload1(aux + nbv, nbv),
-                                 xc = pload1(aux + 2 * nbv, nbv);
-                    const double wo = w[min(r0 + lane, n - 1)];
+                    hx[0] = pload1(aux, nbv);
+                    hx[1] = pload1(aux + nbv, nbv);
+                    hx[2] = pload1(aux + 2 * nbv, nbv);
+                    hx[3] = w[min(r0 + lane, n - 1)];
                     asm volatile("" ::: "memory");  // the loads above go out before the stop test
                     if (done) return false;         // (uniform over the block, before any barrier)
-                    head_s[0][tid] = xa;
-                    head_s[1][tid] = xb;
-                    head_s[2][tid] = xc;
-                    if (wave == 0) wold_s[lane] = wo;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);  // the group's loads together
@@ -495,6 +497,12 @@ __global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
+        if constexpr (decltype(head)::value) {  // park the head inputs for the epilogue
+            head_s[0][tid] = hx[0];
+            head_s[1][tid] = hx[1];
+            head_s[2][tid] = hx[2];
+            if (wave == 0) wold_s[lane] = hx[3];
+        }
         return true;
     };
     if (!tile(wave, std::true_type{})) return;  // every wave has a first tile
