@@ -339,8 +339,13 @@ int set_ham(nqs_ctx* c, int kind, int n_sites, int n_bonds, const int32_t* bonds
     return NQS_OK;
 }
 
-int sync_scalars(nqs_ctx* c) {
+int enqueue_scalars(nqs_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->b.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+    return NQS_OK;
+}
+int sync_scalars(nqs_ctx* c) {
+    int st = enqueue_scalars(c);
+    if (st) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return NQS_OK;
 }
@@ -431,10 +436,15 @@ void issue_energy_grad(nqs_ctx* c) {
     c->have_grad = true;
 }
 
-int read_stats(nqs_ctx* c, nqs_stats* E) {
+// Host copies of the energy statistics, the accept counters and the CG scalars are
+// enqueued with enqueue_* and used by take_* after the stream has been synchronised,
+// so that a caller that needs several of them waits for the device once.
+int enqueue_stats(nqs_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->h_stats, c->b.stats, 4 * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NQS_OK;
+}
+int take_stats(nqs_ctx* c, nqs_stats* E) {
     if (E) {
         E->mean = c->h_stats[0];
         E->variance = c->h_stats[1];
@@ -444,15 +454,29 @@ int read_stats(nqs_ctx* c, nqs_stats* E) {
     if (!std::isfinite(c->h_stats[0])) return fail(c, NQS_ENUMERIC, "non-finite energy");
     return NQS_OK;
 }
+int read_stats(nqs_ctx* c, nqs_stats* E) {
+    int st = enqueue_stats(c);
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return take_stats(c, E);
+}
 
-int read_acceptance(nqs_ctx* c) {
+int enqueue_acceptance(nqs_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->h_acc, c->b.acc_count, 4 * (size_t)c->C, hipMemcpyDeviceToHost,
                              c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NQS_OK;
+}
+int take_acceptance(nqs_ctx* c) {
     double acc = 0.0;
     for (int k = 0; k < c->C; ++k) acc += c->h_acc[k];
     c->acceptance = acc / ((double)c->C * c->S * c->K);
     return NQS_OK;
+}
+int read_acceptance(nqs_ctx* c) {
+    int st = enqueue_acceptance(c);
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return take_acceptance(c);
 }
 
 // dense Jacobian form: build G once for this batch and set up CG in packed space
@@ -1096,8 +1120,9 @@ int nqs_expect_and_grad(nqs_ctx* c, nqs_stats* E, double* grad) {
     return NQS_OK;
 }
 
-int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol, int maxiter,
-                  double* delta_out, nqs_sr_info* info) {
+// The SR solve and update, issued; the CG scalars are not read back here.
+static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol,
+                           int maxiter, double* delta_out) {
     int st = need_bound(c);
     if (st) return st;
     if (!c->have_grad) return fail(c, NQS_ESTATE, "no gradient: call nqs_expect_and_grad first");
@@ -1115,7 +1140,12 @@ int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double
     issue_finish_solve(c, kind);
     if (delta_out) launch_pack(c->stream, c->d, c->b.x, delta_out, (int)c->P);
     issue_update(c, lr);
-    st = last_launch(c);
+    return last_launch(c);
+}
+
+int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol, int maxiter,
+                  double* delta_out, nqs_sr_info* info) {
+    int st = sr_update_issue(c, kind, diag_shift, lr, tol, maxiter, delta_out);
     if (st) return st;
     st = sync_scalars(c);
     if (st) return st;
@@ -1128,11 +1158,21 @@ int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
     std::memset(rep, 0, sizeof(*rep));
     int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
     if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
-    if (!st) st = nqs_sr_update(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol,
-                                cfg->cg_maxiter, nullptr, &rep->sr);
+    if (!st) st = sr_update_issue(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol,
+                                  cfg->cg_maxiter, nullptr);
+    // the CG scalars, accept counters and energy statistics come back together
+    // (one wait for the device)
+    if (!st) st = enqueue_scalars(c);
+    if (!st) st = enqueue_acceptance(c);
+    if (!st) st = enqueue_stats(c);
+    if (!st) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            st = fail(c, NQS_EDEVICE, "stream synchronise");
+    }
+    if (!st) st = sr_status(c, &rep->sr);
     if (st == NQS_OK || st == NQS_ENOTCONV) {
-        int s2 = read_acceptance(c);
-        if (!s2) s2 = read_stats(c, &rep->energy);
+        int s2 = take_acceptance(c);
+        if (!s2) s2 = take_stats(c, &rep->energy);
         if (s2) st = s2;
     }
     rep->status = st;
