@@ -180,3 +180,38 @@ def test_tfim2d_full_size_reduced_precision_energy(precision):
     idx = np.random.default_rng(1).choice(w.n_samples, 512, replace=False)
     ref = core.local_energy(rbm, ham, s[idx])
     assert (np.abs(e[idx] - ref) / np.abs(ref)).max() <= 1e-4
+
+
+def test_tfim2d_full_size_sr_direction_bf16():
+    """BF16 form at full size, in the benchmark's configuration: on the batch its own
+    sampler drew, the force is within 2e-4 of the oracle's (FP64) and the CG direction
+    solves the oracle's SR system up to the CG tolerance, the rounding of the form's
+    operator (eps |G|_2 |d|, eps = 3e-5: two-term BF16 operands, FP32 accumulation) and
+    the force difference: |G d - f| <= 2 tol |f| + eps |G|_2 |d| + |g - f|."""
+    w = synth.WORKLOADS["tfim2d_l10"]
+    st = _state(w, precision="bf16")
+    smp, _, _ = st.sample()
+    flat = smp.reshape(-1, w.n_sites).cpu().numpy()
+    _, g = st.expect_and_grad()
+    tol = 1e-6
+    d, info = st.sr_update(diag_shift=w.diag_shift, lr=0.0, tol=tol)
+    assert info.converged, info
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
+    E = core.local_energy(rbm, ham, flat)
+    O = core.jacobian(rbm, flat)
+    f = core.force(O, E)
+    g = g.cpu().numpy()
+    assert np.abs(g - f).max() <= 2e-4 * np.abs(f).max()
+    dd = d.cpu().numpy()
+    v = np.random.default_rng(0).normal(size=dd.size)
+    for _ in range(20):  # |G|_2 by power iteration on the oracle's product
+        v = core.qgt_matvec(O, v, w.diag_shift)
+        v /= np.linalg.norm(v)
+    gnorm = np.linalg.norm(core.qgt_matvec(O, v, w.diag_shift))
+    res = np.linalg.norm(core.qgt_matvec(O, dd, w.diag_shift) - f)
+    bound = 2 * tol * np.linalg.norm(f) + 3e-5 * gnorm * np.linalg.norm(dd) + np.linalg.norm(g - f)
+    print(f"residual {res:.3e} bound {bound:.3e} |f| {np.linalg.norm(f):.3e} |G| {gnorm:.3e} "
+          f"|d| {np.linalg.norm(dd):.3e} |g - f| {np.linalg.norm(g - f):.3e}")
+    assert res <= bound
+    assert bound < 0.05 * np.linalg.norm(f)  # informative: far below |f|
