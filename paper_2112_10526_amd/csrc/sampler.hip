@@ -34,27 +34,72 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename R, int QMAX, int RULE>
+// Lanes of chain h of a wave: 64 / CPW consecutive lanes (CPW = 1 or 2 chains per
+// wave).  With two chains per wave one cross-lane reduction and one accept/update
+// sequence serve two proposals; each chain owns whole 16-lane rows, so the row
+// reductions never mix the chains.
+template <int CPW>
+__device__ __forceinline__ int pick(int v, int q, int h) {  // chain h's lane q
+    if constexpr (CPW == 1) return __builtin_amdgcn_readlane(v, q);
+    else {
+        const int v0 = __builtin_amdgcn_readlane(v, q), v1 = __builtin_amdgcn_readlane(v, 32 + q);
+        return h ? v1 : v0;
+    }
+}
+template <int CPW, typename T>
+__device__ __forceinline__ T pick(T v, int q, int h) {
+    if constexpr (CPW == 1) return readlane(v, q);
+    else {
+        const T v0 = readlane(v, q), v1 = readlane(v, 32 + q);
+        return h ? v1 : v0;
+    }
+}
+// sum / product over the chain's lanes (rows 4h / CPW ..), fixed order
+template <int CPW, typename T>
+__device__ __forceinline__ T chain_sum(T v, int h) {
+    v = row16_sum(v);
+    if constexpr (CPW == 1) return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+    else {
+        const T s0 = readlane(v, 0) + readlane(v, 16), s1 = readlane(v, 32) + readlane(v, 48);
+        return h ? s1 : s0;
+    }
+}
+template <int CPW, typename T>
+__device__ __forceinline__ T chain_prod(T v, int h) {
+    v = row16_prod(v);
+    if constexpr (CPW == 1) return (readlane(v, 0) * readlane(v, 16)) * (readlane(v, 32) * readlane(v, 48));
+    else {
+        const T s0 = readlane(v, 0) * readlane(v, 16), s1 = readlane(v, 32) * readlane(v, 48);
+        return h ? s1 : s0;
+    }
+}
+
+// QMAX: hidden units per lane at one chain per wave (the row covers 64 QMAX).
+template <typename R, int QMAX, int RULE, int CPW>
 __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt,
                                                 const R* __restrict__ Ks, SampleArgs a) {
+    constexpr int LPC = 64 / CPW;  // lanes per chain
+    constexpr int Q = QMAX * CPW;  // hidden units per lane
     extern __shared__ int8_t lds_s[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = blockIdx.x * 4 + wave;
-    if (c >= a.C) return;  // uniform per wave
+    const int h = lane / LPC, hl = lane % LPC;
+    const int c0 = (blockIdx.x * 4 + wave) * CPW;
+    if (c0 >= a.C) return;  // uniform per wave (the launcher makes C a multiple of CPW)
+    const int c = c0 + h;
     const int N = d.N, Mw = d.Mw;
-    int8_t* s = lds_s + wave * round_up(N, 16);
+    int8_t* s = lds_s + (wave * CPW + h) * round_up(N, 16);
     int8_t* sg = a.s + (size_t)c * N;
-    for (int i = lane; i < N; i += 64) s[i] = sg[i];
+    for (int i = hl; i < N; i += LPC) s[i] = sg[i];
     __builtin_amdgcn_wave_barrier();
 
     const R* tc = (const R*)a.tch + (size_t)c * Mw;
-    R t[QMAX];
+    R t[Q];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) t[q] = tc[lane + 64 * q];
+    for (int q = 0; q < Q; ++q) t[q] = tc[hl + LPC * q];
 
     uint32_t n_acc = 0;
-    for (int p0 = 0; p0 < a.K; p0 += 64) {
-        const uint64_t pidx = a.prop_base + (uint64_t)(p0 + lane);
+    for (int p0 = 0; p0 < a.K; p0 += LPC) {
+        const uint64_t pidx = a.prop_base + (uint64_t)(p0 + hl);
         const uint4 x = philox10(make_uint4((uint32_t)pidx, (uint32_t)(pidx >> 32), (uint32_t)c,
                                             TAG_METROPOLIS), a.seed);
         int ia_l, ib_l = 0;
@@ -68,18 +113,18 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
         const double u_l = unit53(x.y, x.z);
         // FP32 path compares logarithms; u = 0 gives -inf and always accepts
         const float lu_l = sizeof(R) == 8 ? 0.0f : logf((float)u_l);
-        const int np = min(64, a.K - p0);
+        const int np = min(LPC, a.K - p0);
         // table rows and site factors of the next proposal are loaded one
         // proposal ahead
-        R Ta[QMAX], Tb[QMAX];
+        R Ta[Q], Tb[Q];
         R ka_n[2], kb_n[2];
         {
-            const int ia0 = __builtin_amdgcn_readlane(ia_l, 0);
-            const int ib0 = __builtin_amdgcn_readlane(ib_l, 0);
+            const int ia0 = pick<CPW>(ia_l, 0, h);
+            const int ib0 = pick<CPW>(ib_l, 0, h);
 #pragma unroll
-            for (int qq = 0; qq < QMAX; ++qq) {
-                Ta[qq] = Tt[(size_t)ia0 * Mw + lane + 64 * qq];
-                Tb[qq] = RULE == 1 ? Tt[(size_t)ib0 * Mw + lane + 64 * qq] : (R)0;
+            for (int qq = 0; qq < Q; ++qq) {
+                Ta[qq] = Tt[(size_t)ia0 * Mw + hl + LPC * qq];
+                Tb[qq] = RULE == 1 ? Tt[(size_t)ib0 * Mw + hl + LPC * qq] : (R)0;
             }
             ka_n[0] = Ks[2 * ia0];
             ka_n[1] = Ks[2 * ia0 + 1];
@@ -87,20 +132,20 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
             kb_n[1] = RULE == 1 ? Ks[2 * ib0 + 1] : (R)0;
         }
         for (int q = 0; q < np; ++q) {
-            const int ia = __builtin_amdgcn_readlane(ia_l, q);
+            const int ia = pick<CPW>(ia_l, q, h);
             const int sa = s[ia];
-            R Tv[QMAX], Tw[QMAX];
+            R Tv[Q], Tw[Q];
 #pragma unroll
-            for (int qq = 0; qq < QMAX; ++qq) { Tv[qq] = Ta[qq]; Tw[qq] = Tb[qq]; }
+            for (int qq = 0; qq < Q; ++qq) { Tv[qq] = Ta[qq]; Tw[qq] = Tb[qq]; }
             const R ka_c[2] = {ka_n[0], ka_n[1]};
             const R kb_c[2] = {kb_n[0], kb_n[1]};
             if (q + 1 < np) {
-                const int ian = __builtin_amdgcn_readlane(ia_l, q + 1);
-                const int ibn = __builtin_amdgcn_readlane(ib_l, q + 1);
+                const int ian = pick<CPW>(ia_l, q + 1, h);
+                const int ibn = pick<CPW>(ib_l, q + 1, h);
 #pragma unroll
-                for (int qq = 0; qq < QMAX; ++qq) {
-                    Ta[qq] = Tt[(size_t)ian * Mw + lane + 64 * qq];
-                    if (RULE == 1) Tb[qq] = Tt[(size_t)ibn * Mw + lane + 64 * qq];
+                for (int qq = 0; qq < Q; ++qq) {
+                    Ta[qq] = Tt[(size_t)ian * Mw + hl + LPC * qq];
+                    if (RULE == 1) Tb[qq] = Tt[(size_t)ibn * Mw + hl + LPC * qq];
                 }
                 ka_n[0] = Ks[2 * ian];
                 ka_n[1] = Ks[2 * ian + 1];
@@ -111,81 +156,95 @@ __global__ __launch_bounds__(256) void k_sample(Dims d, const R* __restrict__ Tt
             }
             bool accept;
             if (RULE == 0) {
-                R f[QMAX];
+                R f[Q];
                 R prod = (R)1;
 #pragma unroll
-                for (int qq = 0; qq < QMAX; ++qq) {
+                for (int qq = 0; qq < Q; ++qq) {
                     f[qq] = (R)1 - (R)sa * t[qq] * Tv[qq];
                     prod *= f[qq];
                 }
                 const R kf = sa < 0 ? ka_c[1] : ka_c[0];
                 if constexpr (sizeof(R) == 8) {
-                    const double r = wave_prod(prod) * kf;
-                    accept = readlane(u_l, q) < r * r;
+                    const double r = chain_prod<CPW>(prod, h) * kf;
+                    accept = pick<CPW>(u_l, q, h) < r * r;
                 } else {
-                    const float lr = wave_sum(__logf(prod)) + kf;
-                    accept = readlane(lu_l, q) < 2.0f * lr;
+                    const float lr = chain_sum<CPW>(__logf(prod), h) + kf;
+                    accept = pick<CPW>(lu_l, q, h) < 2.0f * lr;
                 }
                 if (accept) {
 #pragma unroll
-                    for (int qq = 0; qq < QMAX; ++qq) t[qq] = (t[qq] - (R)sa * Tv[qq]) * recip(f[qq]);
-                    s[ia] = (int8_t)-sa;  // every lane stores the same value
+                    for (int qq = 0; qq < Q; ++qq) t[qq] = (t[qq] - (R)sa * Tv[qq]) * recip(f[qq]);
+                    s[ia] = (int8_t)-sa;  // every lane of the chain stores the same value
                 }
             } else {
-                const int ib = __builtin_amdgcn_readlane(ib_l, q);
+                const int ib = pick<CPW>(ib_l, q, h);
                 const int sb = s[ib];
-                if (sa == sb) {
-                    accept = true;  // identity move, ratio 1
+                // the ratio is formed for every chain of the wave (the cross-lane
+                // reduction runs outside divergent code); a bond with equal spins
+                // is the identity move, accepted with ratio 1
+                R g[Q], TT[Q], Td[Q];
+                R prod = (R)1;
+#pragma unroll
+                for (int qq = 0; qq < Q; ++qq) {
+                    const R ta = Tv[qq], tb = Tw[qq];
+                    TT[qq] = (R)1 - ta * tb;
+                    Td[qq] = (R)sa * (ta - tb);
+                    g[qq] = TT[qq] - t[qq] * Td[qq];
+                    prod *= g[qq];
+                }
+                const R ka = sa < 0 ? ka_c[1] : ka_c[0], kb = sb < 0 ? kb_c[1] : kb_c[0];
+                bool take;
+                if constexpr (sizeof(R) == 8) {
+                    const double r = chain_prod<CPW>(prod, h) * ka * kb;
+                    take = pick<CPW>(u_l, q, h) < r * r;
                 } else {
-                    R g[QMAX], TT[QMAX], Td[QMAX];
-                    R prod = (R)1;
+                    const float lr = chain_sum<CPW>(__logf(prod), h) + ka + kb;
+                    take = pick<CPW>(lu_l, q, h) < 2.0f * lr;
+                }
+                const bool ident = sa == sb;
+                accept = ident || take;
+                if (!ident && take) {
 #pragma unroll
-                    for (int qq = 0; qq < QMAX; ++qq) {
-                        const R ta = Tv[qq], tb = Tw[qq];
-                        TT[qq] = (R)1 - ta * tb;
-                        Td[qq] = (R)sa * (ta - tb);
-                        g[qq] = TT[qq] - t[qq] * Td[qq];
-                        prod *= g[qq];
-                    }
-                    const R ka = sa < 0 ? ka_c[1] : ka_c[0], kb = sb < 0 ? kb_c[1] : kb_c[0];
-                    if constexpr (sizeof(R) == 8) {
-                        const double r = wave_prod(prod) * ka * kb;
-                        accept = readlane(u_l, q) < r * r;
-                    } else {
-                        const float lr = wave_sum(__logf(prod)) + ka + kb;
-                        accept = readlane(lu_l, q) < 2.0f * lr;
-                    }
-                    if (accept) {
-#pragma unroll
-                        for (int qq = 0; qq < QMAX; ++qq)
-                            t[qq] = (t[qq] * TT[qq] - Td[qq]) * recip(g[qq]);
-                        s[ia] = (int8_t)sb;
-                        s[ib] = (int8_t)sa;
-                    }
+                    for (int qq = 0; qq < Q; ++qq) t[qq] = (t[qq] * TT[qq] - Td[qq]) * recip(g[qq]);
+                    s[ia] = (int8_t)sb;
+                    s[ib] = (int8_t)sa;
                 }
             }
             n_acc += accept ? 1u : 0u;
-            if (a.acc_log && lane == 0)
+            if (a.acc_log && hl == 0)
                 a.acc_log[(size_t)c * a.log_stride + a.log_offset + p0 + q] = accept ? 1 : 0;
         }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < N; i += 64) {
+    for (int i = hl; i < N; i += LPC) {
         sg[i] = s[i];
         if (a.record) a.rec[(size_t)c * a.rec_stride + i] = s[i];
     }
-    if (a.acc_count && lane == 0) a.acc_count[c] += n_acc;
+    if (a.acc_count && hl == 0) a.acc_count[c] += n_acc;
 }
 
 template <typename R, int QMAX>
 static void launch_q(hipStream_t st, const Dims& d, int rule, const Tables& t,
                      const SampleArgs& a) {
-    const dim3 grid((a.C + 3) / 4);
-    const size_t lds = 4 * (size_t)round_up(d.N, 16);
+    // two chains per wave when the chains pair up and a lane's registers allow
+    // (FP32 up to 8 x 2 hidden units per lane, FP64 up to 4 x 2)
+    constexpr bool PAIR = QMAX <= (sizeof(R) == 4 ? 8 : 4);
+    const int cpw = (PAIR && a.C % 2 == 0) ? 2 : 1;
+    const dim3 grid((a.C + 4 * cpw - 1) / (4 * cpw));
+    const size_t lds = 4 * cpw * (size_t)round_up(d.N, 16);
+    if constexpr (PAIR) {
+        if (cpw == 2) {
+            if (rule == 0)
+                k_sample<R, QMAX, 0, 2><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+            else
+                k_sample<R, QMAX, 1, 2><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+            return;
+        }
+    }
     if (rule == 0)
-        k_sample<R, QMAX, 0><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+        k_sample<R, QMAX, 0, 1><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
     else
-        k_sample<R, QMAX, 1><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
+        k_sample<R, QMAX, 1, 1><<<grid, 256, lds, st>>>(d, (const R*)t.Tt, (const R*)t.Ks, a);
 }
 
 template <typename R>
