@@ -1,11 +1,12 @@
 // Metropolis-Hastings sampling with a persistent per-chain wave (paper,
 // Monte Carlo samplers section; local and exchange rules).
 //
-// One wave64 owns one chain.  Lane l keeps tanh(theta_j) for hidden units
-// j = l + 64 q (q < QM) in registers for the whole launch, and the chain's
-// configuration sits in LDS.  Random draws are made 64 at a time: lane l
-// evaluates the Philox block of proposal p0 + l, and proposal p0 + q reads
-// lane q's site/bond and uniform with v_readlane.
+// A wave64 owns one chain, or two (32 lanes each) when the chains pair up.
+// Lane l of a chain's L lanes keeps tanh(theta_j) for hidden units j = l + L q
+// in registers for the whole launch, and the chain's configuration sits in
+// LDS.  Random draws are made L at a time: lane l evaluates the Philox block
+// of proposal p0 + l, and proposal p0 + q reads lane q's site/bond and
+// uniform with v_readlane.
 //
 // Single flip of site i (local rule):
 //   psi(s')/psi(s) = K_i(s_i) prod_j f_j,  f_j = 1 - s_i t_j T_ij,
