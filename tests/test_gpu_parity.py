@@ -70,8 +70,10 @@ def test_chain_starts_bit_exact(sz0):
     np.testing.assert_array_equal(got, ref)
 
 
+# (an even chain count pairs two chains per wave; an odd one runs one per wave)
 @pytest.mark.parametrize("wname,chains,sigma", [("tfim1d_n10", 16, 0.01), ("tfim1d_n10", 16, 0.3),
-                                                ("tfim2d_l10", 128, 0.01), ("tfim2d_l10", 64, 0.1)])
+                                                ("tfim2d_l10", 128, 0.01), ("tfim2d_l10", 64, 0.1),
+                                                ("tfim2d_l10", 63, 0.1), ("tfim1d_n10", 15, 0.3)])
 def test_local_sampler_bit_exact_fp64(wname, chains, sigma):
     w = synth.WORKLOADS[wname].replace(sigma=sigma)
     st, w = make_state(w, precision="fp64", n_chains=chains)
@@ -94,9 +96,12 @@ def test_local_sampler_bit_exact_fp64(wname, chains, sigma):
     np.testing.assert_array_equal(smp2.cpu().numpy(), ref2.samples)
 
 
-def test_exchange_sampler_bit_exact_fp64():
-    w = HEIS2D.replace(sigma=0.05, samples_per_chain=2)
-    st, w = make_state(w, precision="fp64", n_chains=64)
+# alpha 4: 1024 hidden units (one chain per wave); alpha 1: 256 (two chains per wave
+# with an even chain count, one with an odd count)
+@pytest.mark.parametrize("alpha,chains", [(4, 64), (1, 64), (1, 63)])
+def test_exchange_sampler_bit_exact_fp64(alpha, chains):
+    w = HEIS2D.replace(sigma=0.05, samples_per_chain=2, alpha=alpha)
+    st, w = make_state(w, precision="fp64", n_chains=chains)
     ch0 = st.get_chains()
     assert (ch0.astype(int).sum(axis=1) == 0).all()
     smp, acc, _ = st.sample(log_accepts=True)
