@@ -262,6 +262,25 @@ def make(w, precision):
     return st
 
 
+def copy_rate_gbps(torch, mib=512, reps=10):
+    """Measured HBM rate of a plain device copy (torch elementwise multiply by 1: one read
+    and one write of a mib-MiB buffer), in GB/s of read + write bytes: context for the
+    roofline fractions, which are taken against the published 8 TB/s."""
+    n = mib * 2 ** 20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return rate
+
+
 def stage_rooflines(w, precision, prof):
     """Each stage's kernel against its own binding roof (VALU for sampling and local
     energies, MFMA for theta and the FP64 contractions, HBM for the BF16 ones), from the
@@ -431,7 +450,8 @@ def main():
     roofline = dict(bound=bound, kernel=dom["kernel_class"], achieved=achieved / scale,
                     peak=peak / scale, unit=unit, frac=achieved / peak,
                     avg_launch_us=avg_s * 1e6, work_per_launch=work,
-                    traffic=read_traffic(dom["kernel_class"], args.precision))
+                    traffic=read_traffic(dom["kernel_class"], args.precision),
+                    measured_copy_GBps=copy_rate_gbps(torch))
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = dict(
         metric=METRIC, value=main_run["value"], unit="local energies/s", n_gpus=1,

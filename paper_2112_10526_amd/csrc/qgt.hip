@@ -561,8 +561,9 @@ __device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
     kc = x + NXCD * (m / nj);
 }
 
-// FP64 path: t~ (FP64, [Ma][Nsp]) and z staged in LDS, spins int8; the
-// FP64 MFMA takes A = t~ tile, B = s z (sign applied to z per element).
+// FP64 path: the t~ tile (FP64, [Ma][Nsp]) is staged in LDS as a = t~ z (z
+// computed first, into LDS); the FP64 MFMA takes A = a and B = the int8 spins
+// as +1 / -1 (0 on padding sites).
 __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restrict__ St,
                                                  const double* __restrict__ Th, long Nsp, long n,
                                                  const double* __restrict__ v, int v_mode,
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
     constexpr int BA = 8;              // units per thread issued up front
     constexpr int BW = 2;              // mean-w partials per thread issued up front
     constexpr int KS = KC / 16;        // k-steps (4 samples per lane quad x 4 quads)
-    __shared__ __align__(16) double As[16 * KD + KC];  // t~ tile, then z
+    __shared__ __align__(16) double As[16 * KD + KC];  // a = t~ z tile, then z
     __shared__ double sh[16];
     const int nj = d.Ma / 16;
     int jt, kc;
@@ -624,22 +625,6 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         shift = bsum_waves(a, sh, nw) / (double)n;
         scale = 1.0 / (double)n;
     }
-    // LDS rows are KD (odd) doubles apart: 8-byte stores
-#pragma unroll
-    for (int u = 0; u < BA; ++u) {
-        const int e = u * nth + tid;
-        if (e < UA) {
-            double* q = As + (e / UR) * KD + 2 * (e % UR);
-            q[0] = ra[u].x;
-            q[1] = ra[u].y;
-        }
-    }
-    for (int e = BA * nth + tid; e < UA; e += nth) {  // small blocks only
-        const double2 t2 = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * (e % UR));
-        double* q = As + (e / UR) * KD + 2 * (e % UR);
-        q[0] = t2.x;
-        q[1] = t2.y;
-    }
     double* zs = As + 16 * KD;
     double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
     for (int t = tid; t < KC; t += nth) {
@@ -650,10 +635,30 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
         zs[t] = z;
     }
     // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
-    // chunk, from the blocks of hidden tile 0
+    // chunk, from the blocks of hidden tile 0 (its barriers also publish z)
     if (v_mode == 0 && jt == 0) {
         const double t = bsum_waves(zw, sh, nw);
         if (tid == 0) papart[kc] = t;
+    } else {
+        __syncthreads();
+    }
+    // the tile as a = t~ z (rows KD (odd) doubles apart: 8-byte stores)
+#pragma unroll
+    for (int u = 0; u < BA; ++u) {
+        const int e = u * nth + tid;
+        if (e < UA) {
+            const int c = e % UR;
+            double* q = As + (e / UR) * KD + 2 * c;
+            q[0] = ra[u].x * zs[2 * c];
+            q[1] = ra[u].y * zs[2 * c + 1];
+        }
+    }
+    for (int e = BA * nth + tid; e < UA; e += nth) {  // small blocks only
+        const int c = e % UR;
+        const double2 t2 = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * c);
+        double* q = As + (e / UR) * KD + 2 * c;
+        q[0] = t2.x * zs[2 * c];
+        q[1] = t2.y * zs[2 * c + 1];
     }
     __syncthreads();
     for (int it = wave; it < nit; it += nw) {
@@ -668,9 +673,7 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int kl = 16 * u + 4 * lk + e;
-                const int sv = (int8_t)(sb[u] >> (8 * e));
-                const double z = zs[kl];
-                const double b = sv > 0 ? z : (sv < 0 ? -z : 0.0);
+                const double b = (double)(int8_t)(sb[u] >> (8 * e));  // spin +1 / -1 (0: padding)
                 acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * KD + kl], b, acc[e], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
