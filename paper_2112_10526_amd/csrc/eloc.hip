@@ -176,8 +176,10 @@ template <typename R, int KIND>
 static void launch_k(hipStream_t st, const Dims& d, const Tables& t, const HamDev& H,
                      const int8_t* s, const void* tact, long n, double* out, size_t lds_limit) {
     const size_t es = sizeof(R);
+    // hidden rows of the table staged per chunk: as many as fit (down to one row,
+    // for the largest lattices)
     int JC = 64;
-    while (JC > 8 && (size_t)JC * d.Nw * es > lds_limit) JC /= 2;
+    while (JC > 1 && (size_t)JC * d.Nw * es > lds_limit) JC /= 2;
     const size_t lds = (size_t)JC * d.Nw * es;
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_eloc<R, KIND>,

@@ -102,9 +102,6 @@ void launch_eloc(hipStream_t st, const Dims& d, int prec, const Tables& t, const
 void launch_stats(hipStream_t st, const double* E, long n, double* out3);
 void launch_center(hipStream_t st, const double* E, const double* stats, double scale, long n,
                    double* v);
-void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
-              const double* r, const double* p_old, double* p_new, double* w, double* wpart,
-              CgScalars* sc, size_t lds_limit);
 int outer_chunk(const Dims& d, int prec, size_t lds_limit);
 int outer_ksplit(long n, int chunk);
 // part: [outer_ksplit(n, chunk)][Ma][Na]

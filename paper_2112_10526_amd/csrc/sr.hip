@@ -85,15 +85,6 @@ __global__ void k_center(const double* __restrict__ E, const double* __restrict_
     if (k < n) v[k] = scale * (E[k] - stats[0]);
 }
 
-// ---------------------------------------------------------------------------
-// contraction 1 with the CG direction update folded in:
-//   p_new = r + beta p_old   (beta = 0 on the first iteration)
-//   w_k   = t~_k . (P s~_k),  P = p_new as the [Ma][Na] matrix
-// One block = 4 waves = 64 samples; the block's spins are staged in LDS once,
-// P is staged 64 hidden rows at a time (converted to the MFMA type), and
-// every wave multiplies its 16 samples against the staged rows.  Block 0 also
-// writes p_new for the other kernels of the iteration.
-// ---------------------------------------------------------------------------
 // Stage rows [k0, k0 + rows) of the augmented spins (s, 1, 0 ...) into
 // LDS [rows][Na]; rows at or beyond kend are zero.  Source rows are
 // contiguous, so the copy is a flat byte stream read 16 bytes per lane.
@@ -125,113 +116,6 @@ __device__ __forceinline__ void stage_spins(int8_t* __restrict__ Ss, const int8_
         Ss[rl * Na + i] = (rl < nrow && i == N) ? (int8_t)1 : (int8_t)0;
     }
     for (long e = nrow * Na + tid; e < (long)rows * Na; e += 256) Ss[e] = 0;
-}
-
-template <typename R>
-__device__ __forceinline__ int8_t spin_aug8(const int8_t* __restrict__ s, int N, long k, long n,
-                                            int i) {
-    if (k >= n || i > N) return 0;
-    return i == N ? (int8_t)1 : s[k * N + i];
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_qgt_w(Dims d, const int8_t* __restrict__ s,
-                                               const R* __restrict__ tact, long n,
-                                               const double* __restrict__ r,
-                                               const double* __restrict__ p_old,
-                                               double* __restrict__ p_new, double* __restrict__ w,
-                                               double* __restrict__ wpart, CgScalars* sc,
-                                               int jrows) {
-    if (sc->done) return;
-    extern __shared__ __align__(16) char lds_raw[];
-    __shared__ double sh[4];
-    const int Na = d.Na, NaP = d.Na + 1;
-    R* Vs = (R*)lds_raw;                      // [jrows][NaP]
-    int8_t* Ss = (int8_t*)(Vs + jrows * NaP); // [64][Na]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const long rowb = (long)blockIdx.x * 64;
-    const double beta = sc->beta;
-    stage_spins(Ss, s, d.N, Na, rowb, 64, n);
-    typedef typename std::conditional<sizeof(R) == 8, v4d, v4f>::type acc_t;
-    R wacc[4] = {0, 0, 0, 0};
-    const int8_t* Sw = Ss + (wave * 16 + lr) * Na;
-    for (int jc = 0; jc < d.Ma; jc += jrows) {
-        __syncthreads();
-        const int rows = min(jrows, d.Ma - jc);
-        {
-            // rows jc.. of P are contiguous: batched loads, then LDS stores
-            const int total = rows * Na;
-            const size_t g0 = (size_t)jc * Na;
-            for (int base = 0; base < total; base += 256 * 8) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = base + u * 256 + tid;
-                    v[u] = e < total ? r[g0 + e] + beta * p_old[g0 + e] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = base + u * 256 + tid;
-                    if (e < total) {
-                        const int jl = e / Na, i = e - jl * Na;
-                        Vs[jl * NaP + i] = (R)v[u];
-                        if (blockIdx.x == 0) p_new[g0 + e] = v[u];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        const int nct = rows / 16;
-        acc_t acc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < Na; k0 += 4) {
-            const R a = (R)Sw[k0 + lk];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c < nct) {
-                    const R b = Vs[(c * 16 + lr) * NaP + k0 + lk];
-                    if constexpr (sizeof(R) == 8)
-                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
-                    else
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c < nct) {
-                const int j = jc + c * 16 + lr;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const long k = rowb + wave * 16 + acc_row<R>(lk, q);
-                    const R t = k < n ? tact[k * d.Mw + j] : (R)0;
-                    wacc[q] += t * acc[c][q];
-                }
-            }
-        }
-    }
-    double wsum = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const double v = row16_sum((double)wacc[q]);
-        const long k = rowb + wave * 16 + acc_row<R>(lk, q);
-        if (lr == 0 && k < n) {
-            w[k] = v;
-            wsum += v;
-        }
-    }
-    // block partial of sum_k w_k; the last block turns the partials into mean(w)
-    wsum = block_sum<256>(wsum, sh);
-    if (tid == 0) wpart[blockIdx.x] = wsum;
-    if (arrive_last(&sc->counter[4])) {
-        const double tot = final_sum(wpart, gridDim.x, sh);
-        if (tid == 0) {
-            sc->wmean = tot / (double)n;
-            sc->counter[4] = 0;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -466,35 +350,11 @@ void launch_center(hipStream_t st, const double* E, const double* stats, double 
                    double* v) {
     k_center<<<nblk(n, 256), 256, 0, st>>>(E, stats, scale, n, v);
 }
-// rows of P staged per pass by contraction 1, within the LDS limit
-static int w_jrows(const Dims& d, int prec, size_t lds_limit) {
-    const size_t es = prec == 0 ? 8 : 4;
-    for (int jr = 64; jr >= 16; jr /= 2)
-        if (es * jr * (size_t)(d.Na + 1) + 64 * (size_t)d.Na <= lds_limit) return jr;
-    return 16;
-}
 template <typename K>
 static void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536)
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)bytes);
-}
-void launch_w(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact, long n,
-              const double* r, const double* p_old, double* p_new, double* w, double* wpart,
-              CgScalars* sc, size_t lds_limit) {
-    const int nb = nblk(n, 64);
-    const size_t es = prec == 0 ? 8 : 4;
-    const int jr = w_jrows(d, prec, lds_limit);
-    const size_t lds = es * jr * (size_t)(d.Na + 1) + 64 * (size_t)d.Na;
-    if (prec == 0) {
-        allow_lds(k_qgt_w<double>, lds);
-        k_qgt_w<double><<<nb, 256, lds, st>>>(d, s, (const double*)tact, n, r, p_old, p_new, w,
-                                              wpart, sc, jr);
-    } else {
-        allow_lds(k_qgt_w<float>, lds);
-        k_qgt_w<float><<<nb, 256, lds, st>>>(d, s, (const float*)tact, n, r, p_old, p_new, w,
-                                             wpart, sc, jr);
-    }
 }
 size_t outer_lds_bytes(const Dims& d, int prec, int chunk) {
     const int KC = (chunk + 3) / 4 * 4;

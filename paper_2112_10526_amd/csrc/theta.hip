@@ -26,65 +26,74 @@ __device__ __forceinline__ R spin_aug(const int8_t* __restrict__ s, int N, int r
     return k == N ? (R)1 : (R)s[(size_t)r * N + k];
 }
 
-// Block = 4 waves = 64 rows x 64 hidden columns.  The block's spins
-// (augmented, [64][Na]) and its 64 columns of W~^T ([Na][64]) are staged in
-// LDS with batched loads, then every wave runs its 16 rows over K = Na.
+// Block = 4 waves = 64 rows x 64 hidden columns.  The sites run in tiles of
+// TK_THETA: each tile's spins (augmented, [64][TK]) and the block's 64 columns
+// of W~^T ([TK][64]) are staged in LDS with batched loads, then every wave runs
+// its 16 rows over the tile (any lattice size fits the fixed LDS footprint).
+constexpr int TK_THETA = 128;
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_theta(Dims d, const int8_t* __restrict__ s, int rows,
                                                const R* __restrict__ Wa, R* __restrict__ dst1,
                                                R* __restrict__ dst2, long dst2_stride) {
-    extern __shared__ __align__(16) char lds_raw[];
+    constexpr int TK = TK_THETA;
+    __shared__ __align__(16) R Bs[TK * 64];     // [TK][64]
+    __shared__ __align__(16) int8_t Ss[64 * TK];  // [64][TK]
     const int Na = d.Na;
-    R* Bs = (R*)lds_raw;                       // [Na][64]
-    int8_t* Ss = (int8_t*)(Bs + (size_t)Na * 64);  // [64][Na]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int rowb = blockIdx.x * 64, row0 = rowb + wave * 16;
     const int col0 = blockIdx.y * 64;
-    for (int base = 0; base < Na * 64; base += 256 * 8) {
-        R v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = base + u * 256 + tid;
-            const int k = e >> 6, cl = e & 63;
-            v[u] = (e < Na * 64 && col0 + cl < d.Mw) ? Wa[(size_t)k * d.Mw + col0 + cl] : (R)0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = base + u * 256 + tid;
-            if (e < Na * 64) Bs[e] = v[u];
-        }
-    }
-    for (int base = 0; base < 64 * Na; base += 256 * 8) {
-        int8_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = base + u * 256 + tid;
-            const int rl = e / Na, k = e - rl * Na;
-            v[u] = (e < 64 * Na) ? (int8_t)spin_aug<R>(s, d.N, rowb + rl, rows, k) : (int8_t)0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = base + u * 256 + tid;
-            if (e < 64 * Na) Ss[e] = v[u];
-        }
-    }
-    __syncthreads();
     typedef typename std::conditional<sizeof(R) == 8, v4d, v4f>::type acc_t;
     acc_t acc[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
-    const int8_t* Sw = Ss + (wave * 16 + lr) * Na;
-    for (int k0 = 0; k0 < Na; k0 += 4) {
-        const R a = (R)Sw[k0 + lk];
-        const R* Bk = Bs + (k0 + lk) * 64 + lr;
+    for (int kt = 0; kt < Na; kt += TK) {
+        const int kn = min(TK, Na - kt);  // a multiple of 16 (Na is)
+        __syncthreads();                  // the previous tile is no longer read
+        for (int base = 0; base < kn * 64; base += 256 * 8) {
+            R v[8];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const R b = Bk[ct * 16];
-            if constexpr (sizeof(R) == 8)
-                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
-            else
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                const int k = e >> 6, cl = e & 63;
+                v[u] = (e < kn * 64 && col0 + cl < d.Mw) ? Wa[(size_t)(kt + k) * d.Mw + col0 + cl]
+                                                         : (R)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                if (e < kn * 64) Bs[e] = v[u];
+            }
+        }
+        for (int base = 0; base < 64 * kn; base += 256 * 8) {
+            int8_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                const int rl = e / kn, k = e - rl * kn;
+                v[u] = (e < 64 * kn) ? (int8_t)spin_aug<R>(s, d.N, rowb + rl, rows, kt + k)
+                                     : (int8_t)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                if (e < 64 * kn) Ss[e] = v[u];
+            }
+        }
+        __syncthreads();
+        const int8_t* Sw = Ss + (wave * 16 + lr) * kn;
+        for (int k0 = 0; k0 < kn; k0 += 4) {
+            const R a = (R)Sw[k0 + lk];
+            const R* Bk = Bs + (k0 + lk) * 64 + lr;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const R b = Bk[ct * 16];
+                if constexpr (sizeof(R) == 8)
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
+                else
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
@@ -193,21 +202,12 @@ void launch_theta(hipStream_t st, const Dims& d, int prec, const Tables& t, cons
                   int rows, void* dst1, void* dst2, long dst2_stride) {
     if (rows <= 0) return;
     dim3 grid((rows + 63) / 64, (d.Mw + 63) / 64);
-    if (prec == 0) {
-        const size_t lds = (size_t)d.Na * 64 * 8 + (size_t)64 * d.Na;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void*)k_theta<double>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_theta<double><<<grid, 256, lds, st>>>(d, s, rows, (const double*)t.Wa, (double*)dst1,
-                                                (double*)dst2, dst2_stride);
-    } else if (prec == 1) {
-        const size_t lds = (size_t)d.Na * 64 * 4 + (size_t)64 * d.Na;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void*)k_theta<float>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_theta<float><<<grid, 256, lds, st>>>(d, s, rows, (const float*)t.Wa, (float*)dst1,
-                                               (float*)dst2, dst2_stride);
-    }
+    if (prec == 0)
+        k_theta<double><<<grid, 256, 0, st>>>(d, s, rows, (const double*)t.Wa, (double*)dst1,
+                                              (double*)dst2, dst2_stride);
+    else if (prec == 1)
+        k_theta<float><<<grid, 256, 0, st>>>(d, s, rows, (const float*)t.Wa, (float*)dst1,
+                                             (float*)dst2, dst2_stride);
     else
         k_theta_bf16<<<grid, 256, 0, st>>>(d, s, rows, t.Whi, t.Wlo, (float*)dst1, (float*)dst2,
                                            dst2_stride);

@@ -1,0 +1,74 @@
+"""GPU tests of the edge cases: empty batches, and the largest sizes the library
+accepts (4096 sites; 2048 hidden units, the sampler's widest register tile),
+checked against the oracle (bit-exact chains in FP64, energies and ln psi)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible HIP device")
+    return torch
+
+
+def _tfim_state(L, lattice, n_hidden, precision, chains, sweep, sigma, seed=2):
+    from paper_2112_10526_amd.nqs import VMCState
+    N = L if lattice == "chain" else L * L
+    bonds = synth.chain_bonds(L) if lattice == "chain" else synth.square_bonds(L)
+    params = synth.rbm_params(N, n_hidden, 1, sigma)
+    print(f"[case] tfim {lattice} L={L} N={N} M={n_hidden} {precision} chains={chains}", flush=True)
+    st = VMCState(model="tfim", n_sites=N, bonds=bonds, J=1.0, h=1.0, n_hidden=n_hidden,
+                  precision=precision, n_chains=chains, samples_per_chain=1, sweep_size=sweep,
+                  seed=seed, params=params)
+    rbm = core.Rbm(N, n_hidden, params)
+    ham = core.Hamiltonian.tfim(N, bonds, 1.0, 1.0)
+    return st, rbm, ham, params, seed
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_empty_batches(precision):
+    torch = _torch()
+    st, rbm, ham, params, _ = _tfim_state(10, "chain", 10, precision, 16, 10, 0.1)
+    s = torch.empty((0, 10), dtype=torch.int8)
+    assert st.local_energy(s).shape[0] == 0
+    assert st.log_psi(s).shape[0] == 0
+    g = torch.empty(0, dtype=st.rdtype, device=st.device)
+    v = st.log_psi_vjp(s, g).cpu().numpy()
+    assert v.shape == (st.n_params,) and not v.any()
+
+
+@pytest.mark.parametrize("lattice,L,n_hidden,chains,sweep", [
+    ("chain", 16, 2048, 8, 16),      # the most hidden units (sampler tile of 32 per lane)
+    ("square", 64, 16, 4, 256),      # the most sites (64 x 64)
+])
+def test_largest_sizes_fp64(lattice, L, n_hidden, chains, sweep):
+    torch = _torch()
+    st, rbm, ham, params, seed = _tfim_state(L, lattice, n_hidden, "fp64", chains, sweep, 0.05)
+    ch0 = st.get_chains()
+    smp, acc, _ = st.sample(log_accepts=True)
+    ref = core.sample(rbm, ch0, 1, sweep, seed, 0, mode="cached", log_accepts=True)
+    assert ref.margins.min() > 1e-12
+    np.testing.assert_array_equal(acc.cpu().numpy(), ref.accepts)
+    np.testing.assert_array_equal(smp.cpu().numpy(), ref.samples)
+    flat = smp.reshape(-1, rbm.N).cpu().numpy()
+    e = st.local_energy(torch.from_numpy(flat)).cpu().numpy()
+    E = core.local_energy(rbm, ham, flat)
+    assert np.abs(e - E).max() <= 1e-10 * np.abs(E).max()
+    lp = st.log_psi(torch.from_numpy(flat)).cpu().numpy()
+    np.testing.assert_allclose(lp, core.log_psi(rbm, flat), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("lattice,L,n_hidden", [("chain", 16, 2048), ("square", 64, 16)])
+def test_largest_sizes_bf16_energy(lattice, L, n_hidden):
+    torch = _torch()
+    st, rbm, ham, params, _ = _tfim_state(L, lattice, n_hidden, "bf16", 4, 16, 0.05)
+    s = synth.random_configs(8, rbm.N, 3)
+    e = st.local_energy(torch.from_numpy(s)).cpu().numpy()
+    E = core.local_energy(rbm, ham, s)
+    assert (np.abs(e - E) / np.abs(E)).max() <= 1e-4
