@@ -72,3 +72,34 @@ def test_largest_sizes_bf16_energy(lattice, L, n_hidden):
     e = st.local_energy(torch.from_numpy(s)).cpu().numpy()
     E = core.local_energy(rbm, ham, s)
     assert (np.abs(e - E) / np.abs(E)).max() <= 1e-4
+
+
+@pytest.mark.parametrize("precision,eps", [("fp64", 1e-13), ("bf16", 3e-5)])
+@pytest.mark.parametrize("lattice,L,n_hidden", [("chain", 16, 2048), ("square", 64, 16)])
+def test_sr_direction_largest_sizes(precision, eps, lattice, L, n_hidden):
+    """The on-the-fly CG at the largest shapes (many site groups, many hidden tiles per
+    wave, head partials beyond one per thread) on 64 samples: |G d - f| <= 2 tol |f| +
+    eps |G|_2 |d| against the oracle's product (eps as for the 256-site test)."""
+    torch = _torch()
+    st, rbm, ham, params, _ = _tfim_state(L, lattice, n_hidden, precision, 64, 4, 0.05)
+    s = synth.random_configs(64, rbm.N, 11)
+    st.load_samples(torch.from_numpy(s))
+    st.expect_and_grad()
+    tol = 1e-6
+    d, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=tol, maxiter=2000)
+    assert info.converged, info
+    O = core.jacobian(rbm, s)
+    E = core.local_energy(rbm, ham, s)
+    f = core.force(O, E)
+    dd = d.cpu().numpy()
+    v = np.random.default_rng(0).normal(size=dd.size)
+    for _ in range(30):
+        v = core.qgt_matvec(O, v, 0.01)
+        v /= np.linalg.norm(v)
+    gnorm = np.linalg.norm(core.qgt_matvec(O, v, 0.01))
+    res = np.linalg.norm(core.qgt_matvec(O, dd, 0.01) - f)
+    bound = 2 * tol * np.linalg.norm(f) + eps * gnorm * np.linalg.norm(dd)
+    print(f"residual {res:.3e} bound {bound:.3e} |f| {np.linalg.norm(f):.3e} |G| {gnorm:.3e} "
+          f"iterations {info.iterations}")
+    assert res <= bound
+    assert bound < 0.2 * np.linalg.norm(f)
