@@ -199,7 +199,7 @@ def summarize_waves(counter_dir, cmd):
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
     for name in ["nqs::k_w6", "nqs::k_outer7", "nqs::k_update4<float>",
-                 "nqs::k_sample<float, 4, 0>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
+                 "nqs::k_sample<float, 4, 0, 2>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
         if name not in agg:
             continue
         d = agg[name]
