@@ -364,6 +364,52 @@ def run_precision(w, precision, steps, warmup, torch):
     return out
 
 
+def dense_qgt_measure(torch, repeats=2):
+    """Dense Jacobian QGT at the N = 64 Heisenberg chain size (alpha = 8, 33,344
+    parameters, 16,384 samples, FP32): one SR solve, each dense kernel event-timed and
+    set against its own roof with its algorithmic work per launch:
+      Jacobian build + centring: N_s P 4 bytes written (the matrix once; HBM),
+      Gram matrix: N_s P (P + 1) flops (the symmetric product; FP32 MFMA),
+      dense product: P^2 4 bytes read (the matrix once; HBM)."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.WORKLOADS["heis1d_n64"]
+    st = VMCState.from_workload(w, precision="fp32", qgt="jacobian_dense")
+    s = torch.from_numpy(synth.sz0_configs(w.n_samples, w.n_sites, 12))
+    P, Ns = w.n_params, w.n_samples
+    work = {"jacobian": ("hbm", Ns * P * 4.0, "GB/s", PEAK["hbm"]),
+            "gram": ("mfma", Ns * P * (P + 1.0), "TFLOP/s", PEAK["mfma_fp32"]),
+            "dense_matvec": ("hbm", P * P * 4.0, "GB/s", PEAK["hbm"])}
+    best = {}
+    for _ in range(repeats):
+        st.load_samples(s)  # (a solve marks the batch and its gradient as used)
+        st.expect_and_grad()
+        st.profile_enable(list(work))
+        t0 = time.perf_counter()
+        _, info = st.sr_update(qgt="jacobian_dense", diag_shift=w.diag_shift, lr=0.0,
+                               tol=w.cg_tol, maxiter=3000)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = st.profile_read()
+        for cls, (bound, wk, unit, peak) in work.items():
+            p = prof[cls]
+            # the product runs once per CG iteration; launches queued after the solve
+            # has stopped return at once and are not counted
+            n = min(p["launches"], info.iterations) if cls == "dense_matvec" else p["launches"]
+            us = p["ms"] * 1e3 / max(n, 1)
+            per_s = wk / (us * 1e-6)
+            scale = 1e12 if unit == "TFLOP/s" else 1e9
+            r = dict(bound=bound, achieved=per_s / scale, peak=peak / scale, unit=unit,
+                     frac=per_s / peak, avg_launch_us=us, launches=n)
+            if cls not in best or r["avg_launch_us"] < best[cls]["avg_launch_us"]:
+                best[cls] = r
+    st.close()
+    return dict(metric="dense QGT kernels (N=64 Heisenberg chain, alpha=8, 16,384 samples)",
+                workload="heis1d_n64: 1D Heisenberg N=64 periodic, Marshall, real RBM alpha=8, "
+                         "33,344 parameters, FP32 Jacobian and Gram, FP64 CG",
+                n_params=P, n_samples=Ns, cg_iterations=info.iterations,
+                solve_wall_ms=wall * 1e3, kernels=best, data="synthetic")
+
+
 def cpu_baseline(w, n_chains=256, steps=2):
     """The oracle (plain FP64 CPU code) on a bounded sample of the workload:
     the first `n_chains` chains, one full SR step each time."""
@@ -397,6 +443,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp64", help="second precision to time ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-qgt", action="store_true",
+                    help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
@@ -425,6 +473,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.dense_qgt:
+        print(json.dumps(dense_qgt_measure(torch)), flush=True)
+        return
     w = synth.WORKLOADS["tfim2d_l10"]
     if args.copy_probe_mib:
         n = args.copy_probe_mib * 2 ** 20 // 4

@@ -486,7 +486,9 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
         PROF(NQS_PROF_JACOBIAN);
         launch_jacobian(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O, P,
                         c->Pld);
-        launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum);
+        // (the Gram matrix's buffer is free until the Gram is formed: column-sum partials)
+        launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum,
+                           (double*)c->b.G, esize(c->prec) * (size_t)c->P * c->Pld);
     }
     {
         PROF(NQS_PROF_GRAM);
@@ -547,7 +549,7 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host
             {
                 PROF(NQS_PROF_CGVEC);
                 launch_cg_update(c->stream, (int)c->P, c->b.xp, c->b.rp, c->b.pp, c->b.App,
-                                 c->b.dpart, c->b.sc, 1);
+                                 c->b.dpart, dense_matvec_blocks((int)c->P), c->b.sc);
             }
         }
     }
@@ -1101,7 +1103,8 @@ int nqs_jacobian(nqs_ctx* c, const int8_t* s, int64_t n, void* O_out, int center
     }
     if (center) {
         if (n > 65535) return fail(c, NQS_EINVAL, "centring supports at most 65535 rows");
-        launch_center_cols(c->stream, c->prec, O_out, n, (long)c->P, (int)c->P, c->b.tmpv);
+        launch_center_cols(c->stream, c->prec, O_out, n, (long)c->P, (int)c->P, c->b.tmpv,
+                           nullptr, 0);
     }
     return last_launch(c);
 }

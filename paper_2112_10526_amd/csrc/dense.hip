@@ -36,26 +36,59 @@ __global__ __launch_bounds__(256) void k_jacobian(Dims d, const int8_t* __restri
 }
 
 // colsum[p] = sum_k O[k][p] (fixed order down each column)
+// Column sums in two fixed-order passes: `splits` slices of rows give partial
+// sums (one thread per column and slice), then each column adds its slices in
+// order.  Then O <- (O - colsum / n) / sqrt(n), four columns per thread where
+// the rows are 16-byte aligned.
+constexpr int CS_SPLIT_MAX = 64;
 template <typename R>
-__global__ void k_colsum(const R* __restrict__ O, long n, long ld, int P, double* __restrict__ cs) {
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_colsum_part(const R* __restrict__ O, long n, long ld,
+                                                     int P, int splits, double* __restrict__ part) {
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const long k0 = n * blockIdx.y / splits, k1 = n * (blockIdx.y + 1) / splits;
+    double acc = 0.0;
+    for (long k = k0; k < k1; ++k) acc += (double)O[k * ld + p];
+    part[(size_t)blockIdx.y * P + p] = acc;
+}
+__global__ __launch_bounds__(256) void k_colsum_fin(const double* __restrict__ part, int P,
+                                                    int splits, double* __restrict__ cs) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     double acc = 0.0;
-    for (long k = 0; k < n; ++k) acc += (double)O[k * ld + p];
+    for (int q = 0; q < splits; ++q) acc += part[(size_t)q * P + p];
     cs[p] = acc;
 }
-
-// O <- (O - colsum / n) / sqrt(n)
 template <typename R>
-__global__ void k_center_scale(R* __restrict__ O, long n, long ld, int P,
-                               const double* __restrict__ cs) {
+__global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n, long ld, int P,
+                                                      const double* __restrict__ cs, int vec) {
     const long k = blockIdx.y;
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int W = vec ? 4 : 1;  // columns per thread
+    const long p = W * ((long)blockIdx.x * 256 + threadIdx.x);
     if (p >= P || k >= n) return;
     const double inv = 1.0 / (double)n;
     const double rs = 1.0 / sqrt((double)n);
     R* e = O + k * ld + p;
-    *e = (R)(((double)*e - cs[p] * inv) * rs);
+    if (vec && p + 4 <= P) {  // (ld a multiple of 4, base 16-byte aligned, p a multiple of 4)
+        if constexpr (sizeof(R) == 4) {
+            float4 t = *(float4*)e;
+            t.x = (float)(((double)t.x - cs[p] * inv) * rs);
+            t.y = (float)(((double)t.y - cs[p + 1] * inv) * rs);
+            t.z = (float)(((double)t.z - cs[p + 2] * inv) * rs);
+            t.w = (float)(((double)t.w - cs[p + 3] * inv) * rs);
+            *(float4*)e = t;
+        } else {
+            double2 a = *(double2*)e, b = *(double2*)(e + 2);
+            a.x = (a.x - cs[p] * inv) * rs;
+            a.y = (a.y - cs[p + 1] * inv) * rs;
+            b.x = (b.x - cs[p + 2] * inv) * rs;
+            b.y = (b.y - cs[p + 3] * inv) * rs;
+            *(double2*)e = a;
+            *(double2*)(e + 2) = b;
+        }
+    } else {
+        for (long q = p; q < P && q < p + W; ++q) e[q - p] = (R)(((double)e[q - p] - cs[q] * inv) * rs);
+    }
 }
 
 // G[p][q] = sum_k A[k][p] A[k][q] for the upper block triangle, mirrored.
@@ -120,45 +153,64 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
     return r;
 }
 
-// out = G v + shift v (FP64 accumulation), one wave per row; last block forms
-// alpha = rr / (v . out).
+// out = G v + shift v (FP64 accumulation) and the block partials of v . out.
+// Each wave handles DMV_RW rows at once, so every 4-element slice of v it loads
+// serves DMV_RW rows of G (4 consecutive entries per lane per step).  No
+// cross-block step: the CG update sums the partials.
+constexpr int DMV_RW = 4;
 template <typename R>
 __global__ __launch_bounds__(256) void k_dense_matvec(const R* __restrict__ G, int P, long ld,
                                                       const double* __restrict__ v, double shift,
                                                       double* __restrict__ out,
-                                                      double* __restrict__ dpart, CgScalars* sc) {
+                                                      double* __restrict__ dpart,
+                                                      const CgScalars* __restrict__ sc) {
     if (sc->done) return;
     __shared__ double sh[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long p = (long)blockIdx.x * 4 + wave;
+    const long p0 = ((long)blockIdx.x * 4 + wave) * DMV_RW;
+    double acc[DMV_RW];
+#pragma unroll
+    for (int r = 0; r < DMV_RW; ++r) acc[r] = 0.0;
+    for (long q = 4 * lane; q < P; q += 256) {
+        if (q + 4 <= P) {
+            const double2 v01 = *(const double2*)(v + q), v23 = *(const double2*)(v + q + 2);
+#pragma unroll
+            for (int r = 0; r < DMV_RW; ++r) {
+                if (p0 + r >= P) break;
+                const R* g = G + (p0 + r) * ld + q;
+                double g0, g1, g2, g3;
+                if constexpr (sizeof(R) == 4) {
+                    const float4 t = *(const float4*)g;
+                    g0 = t.x; g1 = t.y; g2 = t.z; g3 = t.w;
+                } else {
+                    const double2 a = *(const double2*)g, b = *(const double2*)(g + 2);
+                    g0 = a.x; g1 = a.y; g2 = b.x; g3 = b.y;
+                }
+                acc[r] += (g0 * v01.x + g1 * v01.y) + (g2 * v23.x + g3 * v23.y);
+            }
+        } else {  // ragged end of the row
+            for (long qq = q; qq < P; ++qq)
+#pragma unroll
+                for (int r = 0; r < DMV_RW; ++r)
+                    if (p0 + r < P) acc[r] += (double)G[(p0 + r) * ld + qq] * v[qq];
+        }
+    }
     double dot = 0.0;
-    if (p < P) {
-        const R* row = G + p * ld;
-        double acc = 0.0;
-        for (long q = lane; q < P; q += 64) acc += (double)row[q] * v[q];
-        acc = wave_sum(acc) + shift * v[p];
-        if (lane == 0) out[p] = acc;
-        dot = lane == 0 ? acc * v[p] : 0.0;
+#pragma unroll
+    for (int r = 0; r < DMV_RW; ++r) {
+        const double s = wave_sum(acc[r]);
+        if (p0 + r < P) {
+            const double o = s + shift * v[p0 + r];
+            if (lane == 0) out[p0 + r] = o;
+            dot += o * v[p0 + r];
+        }
     }
-    dot = bsum<256>(dot, sh);
-    if (threadIdx.x == 0) dpart[blockIdx.x] = dot;
-    __shared__ int last;
-    __threadfence();
+    if (lane == 0) sh[wave] = dot;
     __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(&sc->counter[3], 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double a = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256) a += *(const volatile double*)&dpart[b];
-    const double pap = bsum<256>(a, sh);
-    if (threadIdx.x == 0) {
-        sc->pAp = pap;
-        sc->alpha = sc->rr / pap;
-        if (!(pap > 0.0) || !isfinite(sc->alpha)) { sc->bad = 1; sc->done = 1; }
-        sc->counter[3] = 0;
-    }
+    if (threadIdx.x == 0) dpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
+
+int dense_matvec_blocks(int P) { return (P + 4 * DMV_RW - 1) / (4 * DMV_RW); }
 
 // ---------------------------------------------------------------------------
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
@@ -172,16 +224,24 @@ void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, c
                                                        (float*)O);
 }
 
-void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs) {
+void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs,
+                        double* scratch, size_t scratch_bytes) {
     const int nb = (P + 255) / 256;
-    const dim3 g2(nb, (unsigned)n);
-    if (prec == 0) {
-        k_colsum<double><<<nb, 256, 0, st>>>((const double*)O, n, ld, P, cs);
-        k_center_scale<double><<<g2, 256, 0, st>>>((double*)O, n, ld, P, cs);
-    } else {
-        k_colsum<float><<<nb, 256, 0, st>>>((const float*)O, n, ld, P, cs);
-        k_center_scale<float><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs);
-    }
+    size_t sp = scratch ? scratch_bytes / (8 * (size_t)P) : 1;
+    const int splits = (int)(sp < 1 ? 1 : (sp > CS_SPLIT_MAX ? CS_SPLIT_MAX : sp));
+    double* part = splits > 1 ? scratch : cs;  // one slice: the sums go straight to cs
+    const dim3 g1(nb, splits);
+    const int vec = (ld % 4 == 0 && ((uintptr_t)O & 15) == 0) ? 1 : 0;
+    const dim3 g2(vec ? (P + 1023) / 1024 : nb, (unsigned)n);
+    if (prec == 0)
+        k_colsum_part<double><<<g1, 256, 0, st>>>((const double*)O, n, ld, P, splits, part);
+    else
+        k_colsum_part<float><<<g1, 256, 0, st>>>((const float*)O, n, ld, P, splits, part);
+    if (splits > 1) k_colsum_fin<<<nb, 256, 0, st>>>(part, P, splits, cs);
+    if (prec == 0)
+        k_center_scale<double><<<g2, 256, 0, st>>>((double*)O, n, ld, P, cs, vec);
+    else
+        k_center_scale<float><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs, vec);
 }
 
 int gram_tiles(int P) {
@@ -207,7 +267,7 @@ void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P
 }
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
                          double shift, double* out, double* dpart, CgScalars* sc) {
-    const int nb = (P + 3) / 4;
+    const int nb = dense_matvec_blocks(P);
     if (prec == 0)
         k_dense_matvec<double><<<nb, 256, 0, st>>>((const double*)G, P, ld, v, shift, out, dpart, sc);
     else

@@ -113,8 +113,10 @@ void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* pa
                          CgScalars* sc, int mode);
 void launch_cg_init(hipStream_t st, int total, const double* f, double* x, double* r, double* p,
                     double* dpart, CgScalars* sc, double tol, int maxiter);
+// dense-form CG iteration after the product: dpart holds the product's npap
+// partials of p.Ap, followed by room for the update's partials of r.r
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, CgScalars* sc, int update_p);
+                      const double* Ap, double* dpart, int npap, CgScalars* sc);
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc);
 
@@ -164,11 +166,15 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
 // dense.hip
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
                      long n, void* O, int P, long ld);
-void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs);
+// centre and scale the columns of O [n][ld] (first P); scratch (may be null)
+// holds column-sum partials, up to 64 row slices of P doubles
+void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs,
+                        double* scratch, size_t scratch_bytes);
 int gram_tiles(int P);
 void fill_gram_tiles(int P, int* host_tiles);
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
                  const int* tiles, int ntiles);
+int dense_matvec_blocks(int P);  // blocks (and p.Ap partials) of one dense product
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
                          double shift, double* out, double* dpart, CgScalars* sc);
 

@@ -255,44 +255,74 @@ __global__ __launch_bounds__(256) void k_reduce_outer(Dims d, const R* __restric
     }
 }
 
-// x += alpha p ; r -= alpha Ap ; rr' = r.r -> beta, convergence test.
+// Dense-form CG, one iteration in three kernels (product, update, direction);
+// each sums the block partials of the kernel before it in a fixed order (the
+// same in every block), so no kernel needs a cross-block step:
+//   update:    p.Ap from the product's partials, alpha = r.r / p.Ap,
+//              x += alpha p, r -= alpha Ap, block partials of the new r.r;
+//   direction: r.r from the update's partials, beta = r.r / r.r_prev,
+//              p = r + beta p; block 0 advances the iteration and the stop flag.
+// Every scalar is written by a different kernel from the one that reads it.
+__device__ __forceinline__ double sum_partials(const double* part, int np, double* sh) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < np; b += 256) a += part[b];
+    return block_sum<256>(a, sh);
+}
 __global__ __launch_bounds__(256) void k_cg_update(int total, double* __restrict__ x,
                                                    double* __restrict__ r,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ Ap,
-                                                   double* __restrict__ dpart, CgScalars* sc) {
+                                                   const double* __restrict__ pap_part, int npap,
+                                                   double* __restrict__ rr_part, CgScalars* sc) {
     if (sc->done) return;
     __shared__ double sh[4];
     const int e = blockIdx.x * 256 + threadIdx.x;
-    const double alpha = sc->alpha;
-    double rr = 0.0;
+    const double rr = sc->rr;
+    const double pAp = sum_partials(pap_part, npap, sh);
+    const double alpha = rr / pAp;
+    if (!(pAp > 0.0) || !isfinite(alpha)) {  // the same decision in every block
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->bad = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    double rn = 0.0;
     if (e < total) {
         x[e] += alpha * p[e];
         const double re = r[e] - alpha * Ap[e];
         r[e] = re;
-        rr = re * re;
+        rn = re * re;
     }
-    rr = block_sum<256>(rr, sh);
-    if (threadIdx.x == 0) dpart[blockIdx.x] = rr;
-    if (arrive_last(&sc->counter[1])) {
-        const double s = final_sum(dpart, gridDim.x, sh);
-        if (threadIdx.x == 0) {
-            sc->beta = s / sc->rr;
-            sc->rr = s;
-            sc->iters += 1;
-            if (!isfinite(s)) { sc->bad = 1; sc->done = 1; }
-            if (s <= sc->tol2 || sc->iters >= sc->maxiter) sc->done = 1;
-            sc->counter[1] = 0;
-        }
+    rn = block_sum<256>(rn, sh);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = rn;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->alpha = alpha;
+        sc->pAp = pAp;
+        sc->rr_prev = rr;
     }
 }
 
-// p = r + beta p
 __global__ __launch_bounds__(256) void k_cg_p(int total, const double* __restrict__ r,
-                                              double* __restrict__ p, const CgScalars* sc) {
+                                              double* __restrict__ p,
+                                              const double* __restrict__ rr_part, int nrr,
+                                              CgScalars* sc) {
     if (sc->done) return;
+    __shared__ double sh[4];
+    const double rr = sum_partials(rr_part, nrr, sh);
+    const double beta = rr / sc->rr_prev;
     const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e < total) p[e] = r[e] + sc->beta * p[e];
+    if (e < total) p[e] = r[e] + beta * p[e];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->beta = beta;
+        sc->rr = rr;
+        sc->iters += 1;
+        if (!isfinite(rr)) {
+            sc->bad = 1;
+            sc->done = 1;
+        }
+        if (rr <= sc->tol2 || sc->iters >= sc->maxiter) sc->done = 1;
+    }
 }
 
 // x = 0, r = p = f, rr = f.f, thresholds.
@@ -405,9 +435,11 @@ void launch_cg_init(hipStream_t st, int total, const double* f, double* x, doubl
     k_cg_init<<<nblk(total, 256), 256, 0, st>>>(total, f, x, r, p, dpart, sc, tol, maxiter);
 }
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, CgScalars* sc, int update_p) {
-    k_cg_update<<<nblk(total, 256), 256, 0, st>>>(total, x, r, p, Ap, dpart, sc);
-    if (update_p) k_cg_p<<<nblk(total, 256), 256, 0, st>>>(total, r, p, sc);
+                      const double* Ap, double* dpart, int npap, CgScalars* sc) {
+    const int nb = nblk(total, 256);
+    double* rr_part = dpart + npap;  // after the product's partials
+    k_cg_update<<<nb, 256, 0, st>>>(total, x, r, p, Ap, dpart, npap, rr_part, sc);
+    k_cg_p<<<nb, 256, 0, st>>>(total, r, p, rr_part, nb, sc);
 }
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc) {
