@@ -364,20 +364,24 @@ def run_precision(w, precision, steps, warmup, torch):
     return out
 
 
-def dense_qgt_measure(torch, repeats=2):
+def dense_qgt_measure(torch, precision="fp32", repeats=2):
     """Dense Jacobian QGT at the N = 64 Heisenberg chain size (alpha = 8, 33,344
-    parameters, 16,384 samples, FP32): one SR solve, each dense kernel event-timed and
-    set against its own roof with its algorithmic work per launch:
+    parameters, 16,384 samples, FP32 matrices): one SR solve, each dense kernel
+    event-timed and set against its own roof with its algorithmic work per launch:
       Jacobian build + centring: N_s P 4 bytes written (the matrix once; HBM),
-      Gram matrix: N_s P (P + 1) flops (the symmetric product; FP32 MFMA),
+      Gram matrix: N_s P (P + 1) flops (the symmetric product) on the FP32 matrix
+        cores; in the BF16 form three BF16 products per FP32 product (hi hi + hi lo
+        + lo hi), 3 N_s P (P + 1) flops on the BF16 matrix cores,
       dense product: P^2 4 bytes read (the matrix once; HBM)."""
     from paper_2112_10526_amd.nqs import VMCState
     w = synth.WORKLOADS["heis1d_n64"]
-    st = VMCState.from_workload(w, precision="fp32", qgt="jacobian_dense")
+    st = VMCState.from_workload(w, precision=precision, qgt="jacobian_dense")
     s = torch.from_numpy(synth.sz0_configs(w.n_samples, w.n_sites, 12))
     P, Ns = w.n_params, w.n_samples
+    gram = (("mfma", 3.0 * Ns * P * (P + 1.0), "TFLOP/s", PEAK["mfma_bf16"])
+            if precision == "bf16" else ("mfma", Ns * P * (P + 1.0), "TFLOP/s", PEAK["mfma_fp32"]))
     work = {"jacobian": ("hbm", Ns * P * 4.0, "GB/s", PEAK["hbm"]),
-            "gram": ("mfma", Ns * P * (P + 1.0), "TFLOP/s", PEAK["mfma_fp32"]),
+            "gram": gram,
             "dense_matvec": ("hbm", P * P * 4.0, "GB/s", PEAK["hbm"])}
     best = {}
     for _ in range(repeats):
@@ -406,6 +410,8 @@ def dense_qgt_measure(torch, repeats=2):
     return dict(metric="dense QGT kernels (N=64 Heisenberg chain, alpha=8, 16,384 samples)",
                 workload="heis1d_n64: 1D Heisenberg N=64 periodic, Marshall, real RBM alpha=8, "
                          "33,344 parameters, FP32 Jacobian and Gram, FP64 CG",
+                precision=precision, gram_matrix_cores="bf16 split" if precision == "bf16"
+                else precision,
                 n_params=P, n_samples=Ns, cg_iterations=info.iterations,
                 solve_wall_ms=wall * 1e3, kernels=best, data="synthetic")
 
@@ -474,7 +480,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.dense_qgt:
-        print(json.dumps(dense_qgt_measure(torch)), flush=True)
+        for prec in ("fp32", "bf16"):
+            print(json.dumps(dense_qgt_measure(torch, prec)), flush=True)
         return
     w = synth.WORKLOADS["tfim2d_l10"]
     if args.copy_probe_mib:

@@ -167,7 +167,10 @@ int nqs_set_sampler(nqs_ctx* ctx, nqs_rule rule, int n_chains, int samples_per_c
  * NQS_QGT_ONTHEFLY (default; no Jacobian stored) or NQS_QGT_JACOBIAN_DENSE
  * (stores the centred Jacobian [N_s][P] and the dense matrix [P][P], both in
  * FP32 for NQS_FP32/NQS_BF16 and FP64 for NQS_FP64; paper, QGT
- * implementation differences).  Must precede nqs_workspace_bytes(). */
+ * implementation differences).  The dense matrix is formed on the FP64 or FP32
+ * matrix cores, and for NQS_BF16 on the BF16 matrix cores from a two-term
+ * BF16 split of each FP32 entry (three products, FP32 accumulation).  Must
+ * precede nqs_workspace_bytes(). */
 int nqs_set_qgt(nqs_ctx* ctx, nqs_qgt kind);
 
 /* Bytes of device workspace the current configuration needs (0 if the

@@ -488,7 +488,8 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
                         c->Pld);
         // (the Gram matrix's buffer is free until the Gram is formed: column-sum partials)
         launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum,
-                           (double*)c->b.G, esize(c->prec) * (size_t)c->P * c->Pld);
+                           (double*)c->b.G, esize(c->prec) * (size_t)c->P * c->Pld,
+                           c->prec == 2);
     }
     {
         PROF(NQS_PROF_GRAM);
@@ -1104,7 +1105,7 @@ int nqs_jacobian(nqs_ctx* c, const int8_t* s, int64_t n, void* O_out, int center
     if (center) {
         if (n > 65535) return fail(c, NQS_EINVAL, "centring supports at most 65535 rows");
         launch_center_cols(c->stream, c->prec, O_out, n, (long)c->P, (int)c->P, c->b.tmpv,
-                           nullptr, 0);
+                           nullptr, 0, false);
     }
     return last_launch(c);
 }

@@ -59,7 +59,21 @@ __global__ __launch_bounds__(256) void k_colsum_fin(const double* __restrict__ p
     for (int q = 0; q < splits; ++q) acc += part[(size_t)q * P + p];
     cs[p] = acc;
 }
-template <typename R>
+// SPLIT (FP32 entries, dense form of the BF16 precision): each centred entry x
+// is stored in its own 4 bytes as the BF16 pair (hi << 16) | lo, hi = bf16(x),
+// lo = bf16(x - hi), the operand form of the BF16 Gram.
+template <typename R, bool SPLIT>
+__device__ __forceinline__ R center_store(double v) {
+    if constexpr (SPLIT) {
+        const float x = (float)v;
+        const uint16_t hi = f32_to_bf16_bits(x);
+        const uint16_t lo = f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
+        return __builtin_bit_cast(float, ((uint32_t)hi << 16) | lo);
+    } else {
+        return (R)v;
+    }
+}
+template <typename R, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n, long ld, int P,
                                                       const double* __restrict__ cs, int vec) {
     const long k = blockIdx.y;
@@ -72,10 +86,10 @@ __global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n,
     if (vec && p + 4 <= P) {  // (ld a multiple of 4, base 16-byte aligned, p a multiple of 4)
         if constexpr (sizeof(R) == 4) {
             float4 t = *(float4*)e;
-            t.x = (float)(((double)t.x - cs[p] * inv) * rs);
-            t.y = (float)(((double)t.y - cs[p + 1] * inv) * rs);
-            t.z = (float)(((double)t.z - cs[p + 2] * inv) * rs);
-            t.w = (float)(((double)t.w - cs[p + 3] * inv) * rs);
+            t.x = center_store<R, SPLIT>(((double)t.x - cs[p] * inv) * rs);
+            t.y = center_store<R, SPLIT>(((double)t.y - cs[p + 1] * inv) * rs);
+            t.z = center_store<R, SPLIT>(((double)t.z - cs[p + 2] * inv) * rs);
+            t.w = center_store<R, SPLIT>(((double)t.w - cs[p + 3] * inv) * rs);
             *(float4*)e = t;
         } else {
             double2 a = *(double2*)e, b = *(double2*)(e + 2);
@@ -87,7 +101,8 @@ __global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n,
             *(double2*)(e + 2) = b;
         }
     } else {
-        for (long q = p; q < P && q < p + W; ++q) e[q - p] = (R)(((double)e[q - p] - cs[q] * inv) * rs);
+        for (long q = p; q < P && q < p + W; ++q)
+            e[q - p] = center_store<R, SPLIT>(((double)e[q - p] - cs[q] * inv) * rs);
     }
 }
 
@@ -134,6 +149,105 @@ __global__ __launch_bounds__(256) void k_gram(const R* __restrict__ A, long n, l
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long p = p0 + a * 16 + acc_row<R>(lk, i), q = q0 + b * 16 + lr;
+                if (p < P && q < P) {
+                    G[p * ld + q] = acc[a][b][i];
+                    if (tp != tq) G[q * ld + p] = acc[a][b][i];
+                }
+            }
+}
+
+// BF16 form: the same Gram on the BF16 matrix cores.  The centring kernel has
+// stored every entry x as the BF16 pair (hi << 16) | lo with x ~= hi + lo;
+// three products (hi hi + hi lo + lo hi) are accumulated in FP32: about 2^-16
+// relative error per product at BF16 rates.  A slice of GS_K samples of the
+// block's two 128-column panels is loaded (each thread: 4 consecutive samples x
+// 4 consecutive columns of each panel, 16 bytes per sample), regrouped into
+// hi and lo planes and stored in LDS transposed ([column][sample], the
+// contracted index contiguous for the MFMA operands, 4 samples per 8-byte
+// store); the next slice's loads are issued before the current slice's MFMAs.
+constexpr int GS_K = 32, GS_KP = GS_K + 8;  // samples per slice; LDS row stride (halves)
+typedef short v8s_g __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_gram_split(const uint32_t* __restrict__ A, long n, long ld,
+                                                    int P, float* __restrict__ G,
+                                                    const int* __restrict__ tiles) {
+    __shared__ __align__(16) uint16_t Ls[2][2][128 * GS_KP];  // [panel p/q][hi/lo][col][sample]
+    const int tp = tiles[2 * blockIdx.x], tq = tiles[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long base[2] = {(long)tp * 128, (long)tq * 128};
+    const int rg = tid & 7, c4 = tid >> 3;  // rows 4 rg .. 4 rg + 3, columns 4 c4 .. 4 c4 + 3
+    uint4 ra[2][4];
+    auto load = [&](long k0) {
+#pragma unroll
+        for (int op = 0; op < 2; ++op)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long k = k0 + 4 * rg + j;
+                ra[op][j] = k < n ? *(const uint4*)(A + k * ld + base[op] + 4 * c4)
+                                  : make_uint4(0u, 0u, 0u, 0u);
+            }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int op = 0; op < 2; ++op)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    w[j] = e == 0 ? ra[op][j].x : e == 1 ? ra[op][j].y : e == 2 ? ra[op][j].z : ra[op][j].w;
+                // samples (j, j + 1) -> one word per plane, the earlier sample in the low half
+                const uint2 hi = make_uint2((w[1] & 0xFFFF0000u) | (w[0] >> 16),
+                                            (w[3] & 0xFFFF0000u) | (w[2] >> 16));
+                const uint2 lo = make_uint2((w[1] << 16) | (w[0] & 0xFFFFu),
+                                            (w[3] << 16) | (w[2] & 0xFFFFu));
+                const int off = (4 * c4 + e) * GS_KP + 4 * rg;
+                *(uint2*)&Ls[op][0][off] = hi;
+                *(uint2*)&Ls[op][1][off] = lo;
+            }
+    };
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+    const int pr = (wave >> 1) * 64, qr = (wave & 1) * 64;  // the wave's quarter
+    load(0);
+    for (long k0 = 0; k0 < n; k0 += GS_K) {
+        __syncthreads();  // the previous slice is no longer read
+        stage();
+        __syncthreads();
+        if (k0 + GS_K < n) load(k0 + GS_K);
+        v8s_g ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int cp = (pr + a * 16 + lr) * GS_KP + 8 * lk;
+            const int cq = (qr + a * 16 + lr) * GS_KP + 8 * lk;
+            ah[a] = *(const v8s_g*)&Ls[0][0][cp];
+            al[a] = *(const v8s_g*)&Ls[0][1][cp];
+            bh[a] = *(const v8s_g*)&Ls[1][0][cq];
+            bl[a] = *(const v8s_g*)&Ls[1][1][cq];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const v8bf xh = __builtin_bit_cast(v8bf, ah[a]), xl = __builtin_bit_cast(v8bf, al[a]);
+                const v8bf yh = __builtin_bit_cast(v8bf, bh[b]), yl = __builtin_bit_cast(v8bf, bl[b]);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc[a][b], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long p = base[0] + pr + a * 16 + acc_row<float>(lk, i);
+                const long q = base[1] + qr + b * 16 + lr;
                 if (p < P && q < P) {
                     G[p * ld + q] = acc[a][b][i];
                     if (tp != tq) G[q * ld + p] = acc[a][b][i];
@@ -225,7 +339,7 @@ void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, c
 }
 
 void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs,
-                        double* scratch, size_t scratch_bytes) {
+                        double* scratch, size_t scratch_bytes, bool split) {
     const int nb = (P + 255) / 256;
     size_t sp = scratch ? scratch_bytes / (8 * (size_t)P) : 1;
     const int splits = (int)(sp < 1 ? 1 : (sp > CS_SPLIT_MAX ? CS_SPLIT_MAX : sp));
@@ -240,6 +354,8 @@ void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int 
     if (splits > 1) k_colsum_fin<<<nb, 256, 0, st>>>(part, P, splits, cs);
     if (prec == 0)
         k_center_scale<double><<<g2, 256, 0, st>>>((double*)O, n, ld, P, cs, vec);
+    else if (split)
+        k_center_scale<float, true><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs, vec);
     else
         k_center_scale<float><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs, vec);
 }
@@ -262,8 +378,10 @@ void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P
                  const int* tiles, int ntiles) {
     if (prec == 0)
         k_gram<double><<<ntiles, 256, 0, st>>>((const double*)A, n, ld, P, (double*)G, tiles);
-    else
+    else if (prec == 1)
         k_gram<float><<<ntiles, 256, 0, st>>>((const float*)A, n, ld, P, (float*)G, tiles);
+    else  // (split pairs from the centring; ld a multiple of 128: panel loads stay in their row)
+        k_gram_split<<<ntiles, 256, 0, st>>>((const uint32_t*)A, n, ld, P, (float*)G, tiles);
 }
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
                          double shift, double* out, double* dpart, CgScalars* sc) {

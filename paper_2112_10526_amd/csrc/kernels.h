@@ -167,9 +167,11 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
                      long n, void* O, int P, long ld);
 // centre and scale the columns of O [n][ld] (first P); scratch (may be null)
-// holds column-sum partials, up to 64 row slices of P doubles
+// holds column-sum partials, up to 64 row slices of P doubles; split (FP32
+// entries only): store each entry as the BF16 pair (hi << 16) | lo that the
+// BF16 Gram reads
 void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int P, double* cs,
-                        double* scratch, size_t scratch_bytes);
+                        double* scratch, size_t scratch_bytes, bool split);
 int gram_tiles(int P);
 void fill_gram_tiles(int P, int* host_tiles);
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,

@@ -67,15 +67,17 @@ def test_autograd_finite_differences_fp64():
         assert abs((fp - fm) / (2 * h) - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
 
 
-def test_dense_qgt_full_size_fp32():
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_dense_qgt_full_size(precision):
     """N = 64 chain, alpha = 8 (33,344 parameters), 16,384 samples: dense
-    Jacobian (2.2 GB) + MFMA Gram (4.4 GB) + CG against the on-the-fly solve."""
+    Jacobian (2.2 GB) + MFMA Gram (4.4 GB; BF16 split in the BF16 form) + CG
+    against the on-the-fly solve of the same form."""
     torch = _torch()
     w = synth.WORKLOADS["heis1d_n64"]
     s = torch.from_numpy(synth.sz0_configs(w.n_samples, w.n_sites, 12))
     out = {}
     for qgt in ("onthefly", "jacobian_dense"):
-        st = _state(w, precision="fp32", qgt=qgt)
+        st = _state(w, precision=precision, qgt=qgt)
         st.load_samples(s)
         st.expect_and_grad()
         d, info = st.sr_update(qgt=qgt, diag_shift=0.01, lr=0.0, tol=1e-6, maxiter=3000)

@@ -372,7 +372,7 @@ def test_vjp_parity(precision, tol):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_dense_qgt_matches_onthefly(precision):
     torch = _torch()
     w = HEIS1D.replace(sigma=0.05, L=16, alpha=2, n_chains=64, samples_per_chain=4)
