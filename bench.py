@@ -416,6 +416,135 @@ def dense_qgt_measure(torch, precision="fp32", repeats=2):
                 solve_wall_ms=wall * 1e3, kernels=best, data="synthetic")
 
 
+def precision_form_measure(torch, steps=5, warmup=1):
+    """Precision form on the 16 x 16 Heisenberg workload (J1 = 1, periodic, Marshall
+    rotated, zero magnetisation, exchange moves; alpha = 4, 1024 hidden units,
+    263,424 parameters; 16,384 chains x 1 sample, 256 proposals between samples).
+    The BF16 form (BF16 theta on the matrix cores with FP32 accumulation, FP32
+    sampler and local energies, FP64 means and CG reductions) and the FP64 path run
+    full SR steps from the same parameters and chains; then, on one sample batch
+    drawn by the FP64 path, both evaluate local energies, energy statistics and the
+    force from identical parameters, and the BF16 form's error against FP64 is
+    reported (per-sample local energies, batch mean, force)."""
+    w = synth.WORKLOADS["heis2d_l16"]
+    runs, states = {}, {}
+    for prec in ("bf16", "fp64"):
+        st = make(w, prec)
+        for _ in range(warmup):
+            st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        lat, iters, acc = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter()
+            rep = st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+            lat.append(time.perf_counter() - a)
+            iters.append(rep.sr.iterations)
+            acc.append(rep.energy["acceptance"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # sampling + local energies alone, event-timed in one more step
+        st.profile_enable(["sample", "theta", "eloc"])
+        st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        sp = st.profile_read()
+        st.profile_enable([])
+        stage_ms = sp["sample"]["ms"] + sp["theta"]["ms"] + sp["eloc"]["ms"]
+        lat_ms = np.array(lat) * 1e3
+        runs[prec] = dict(value=w.n_samples * steps / el, ms_per_step=el / steps * 1e3,
+                          p50_ms=float(np.percentile(lat_ms, 50)),
+                          p99_ms=float(np.percentile(lat_ms, 99)),
+                          cg_iters_mean=float(np.mean(iters)),
+                          acceptance_mean=float(np.mean(acc)),
+                          stage_local_energies_per_s=w.n_samples / (stage_ms * 1e-3),
+                          stage_ms={k: round(sp[k]["ms"], 4) for k in ("sample", "theta", "eloc")})
+        states[prec] = st
+        print(f"[bench] precision form {prec}: {runs[prec]['ms_per_step']:.2f} ms/step",
+              file=sys.stderr, flush=True)
+    # identical batch and parameters: the FP64 path's samples, its parameters
+    ref, low = states["fp64"], states["bf16"]
+    low.set_params(ref.get_params())
+    s, _, _ = ref.sample()
+    s = s.reshape(-1, w.n_sites)
+    e64 = ref.local_energy(s).cpu().numpy()
+    e16 = low.local_energy(s).cpu().numpy()
+    ref.load_samples(s)
+    low.load_samples(s)
+    st64, g64 = ref.expect_and_grad()
+    st16, g16 = low.expect_and_grad()
+    g64, g16 = g64.cpu().numpy(), g16.cpu().numpy()
+    err = dict(
+        n_samples=int(e64.size),
+        local_energy_max_rel=float(np.max(np.abs(e16 - e64) / np.maximum(np.abs(e64), 1.0))),
+        mean_energy_fp64=st64["mean"], mean_energy_bf16=st16["mean"],
+        mean_energy_rel=abs(st16["mean"] - st64["mean"]) / abs(st64["mean"]),
+        error_of_mean_fp64=st64["error"],
+        force_max_abs_err_rel_to_max=float(np.max(np.abs(g16 - g64)) / np.max(np.abs(g64))),
+    )
+    for st in states.values():
+        st.close()
+    return dict(metric="local energies/s, BF16 form vs FP64 path; energy error of the BF16 "
+                       "form on an identical batch",
+                workload="heis2d_l16: 2D Heisenberg J1 16x16 periodic, Marshall rotated, Sz=0, "
+                         "exchange moves, real RBM alpha=4 (1024 hidden, 263,424 parameters), "
+                         "16384 chains x 1 sample, 256 proposals per sample, SR on-the-fly QGT "
+                         "+ CG tol 1e-6 shift 0.01 lr 0.01",
+                unit="local energies/s", steps=steps, warmup=warmup, bf16=runs["bf16"],
+                fp64=runs["fp64"], speedup=runs["bf16"]["value"] / runs["fp64"]["value"],
+                energy_error_bf16_vs_fp64=err, data="synthetic")
+
+
+def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), seed=7,
+                  budget_gib=32, slots=32):
+    """Serving form: a seeded stream of VMC runs (2D TFIM L x L, L ~ U{4..20},
+    h ~ U[0.5, 4], alpha in {1, 2, 4}, 1024..16384 samples per step, BF16 form,
+    n_steps SR steps each) through the continuous-batching server.
+
+    Passes: (1) one run at a time, all present at the start (the single-run
+    service rate mu = runs / wall); (2) continuous batching, all present at the
+    start (capacity); (3) Poisson arrivals at offered loads rho * mu, served in
+    real time.  Each pass reports aggregate local energies/s, p50/p99 SR-step
+    latency (one tick advances every resident run by one SR step), queueing
+    delay, time in system, mean residency and peak HBM footprint."""
+    from paper_2112_10526_amd.serving import Server, requests_from_stream
+    budget = budget_gib << 30
+
+    def summary(out):
+        keys = ("wall_s", "ticks", "local_energies_per_s", "local_energies_per_busy_s",
+                "mean_resident", "sr_steps", "p50_step_ms", "p99_step_ms",
+                "queue_delay_ms_p50", "queue_delay_ms_p99", "run_latency_ms_p50",
+                "run_latency_ms_p99", "peak_hbm_bytes")
+        r = {k: out[k] for k in keys}
+        r["errors"] = sum(1 for x in out["results"].values() if x.error)
+        return r
+
+    import dataclasses
+    # (passes 1 and 2: every request present at time 0)
+    base = [dataclasses.replace(r, arrival=0.0)
+            for r in requests_from_stream(n_runs, seed, 1.0, n_steps=n_steps)]
+    passes = {}
+    serial = Server(budget, max_slots=1).serve(base, realtime=False)
+    passes["one_at_a_time"] = summary(serial)
+    print(f"[bench] serving one at a time: {serial['wall_s']:.2f} s", file=sys.stderr, flush=True)
+    mu = n_runs / serial["wall_s"]
+    cap = Server(budget, max_slots=slots).serve(base, realtime=False)
+    passes["batched_all_present"] = summary(cap)
+    print(f"[bench] serving batched: {cap['wall_s']:.2f} s", file=sys.stderr, flush=True)
+    for rho in loads:
+        reqs = requests_from_stream(n_runs, seed, rho * mu, n_steps=n_steps)
+        out = Server(budget, max_slots=slots).serve(reqs, realtime=True)
+        passes[f"poisson_rho_{rho}"] = dict(summary(out), offered_rate_runs_per_s=rho * mu)
+        print(f"[bench] serving rho={rho}: {out['wall_s']:.2f} s", file=sys.stderr, flush=True)
+    mix = collections.Counter((r.L, r.alpha) for r in base)
+    return dict(metric="serving: aggregate local energies/s and p50/p99 SR-step latency",
+                workload=(f"{n_runs} runs of 2D TFIM LxL, L~U{{4..20}}, h~U[0.5,4], alpha in "
+                          f"{{1,2,4}}, 1024..16384 samples/step, {n_steps} SR steps each, BF16 "
+                          f"form, stream seed {seed}"),
+                unit="local energies/s", max_slots=slots, hbm_budget_bytes=budget,
+                single_run_service_rate_runs_per_s=mu,
+                total_local_energies=int(sum(r.n_samples * r.n_steps for r in base)),
+                distinct_shapes=len(mix), passes=passes, data="synthetic")
+
+
 def cpu_baseline(w, n_chains=256, steps=2):
     """The oracle (plain FP64 CPU code) on a bounded sample of the workload:
     the first `n_chains` chains, one full SR step each time."""
@@ -451,6 +580,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dense-qgt", action="store_true",
                     help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
+    ap.add_argument("--precision-form", action="store_true",
+                    help="measure the BF16 form against FP64 on the 16x16 Heisenberg workload")
+    ap.add_argument("--serve", action="store_true",
+                    help="measure the continuous-batching server on a Poisson stream of runs")
+    ap.add_argument("--serve-runs", type=int, default=256)
+    ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
@@ -482,6 +617,12 @@ def main():
     if args.dense_qgt:
         for prec in ("fp32", "bf16"):
             print(json.dumps(dense_qgt_measure(torch, prec)), flush=True)
+        return
+    if args.precision_form:
+        print(json.dumps(precision_form_measure(torch)), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(serve_measure(torch, args.serve_runs, args.serve_steps)), flush=True)
         return
     w = synth.WORKLOADS["tfim2d_l10"]
     if args.copy_probe_mib:

@@ -484,12 +484,10 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
     const int P = (int)c->P;
     {
         PROF(NQS_PROF_JACOBIAN);
-        launch_jacobian(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O, P,
-                        c->Pld);
         // (the Gram matrix's buffer is free until the Gram is formed: column-sum partials)
-        launch_center_cols(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.colsum,
-                           (double*)c->b.G, esize(c->prec) * (size_t)c->P * c->Pld,
-                           c->prec == 2);
+        launch_jacobian_centred(c->stream, c->d, c->prec, c->b.samples, c->b.tsm, c->Ns, c->b.O,
+                                P, c->Pld, c->b.colsum, (double*)c->b.G,
+                                esize(c->prec) * (size_t)c->P * c->Pld, c->prec == 2);
     }
     {
         PROF(NQS_PROF_GRAM);

@@ -106,6 +106,100 @@ __global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n,
     }
 }
 
+// The Jacobian's entries straight from a sample's spins and activations: the
+// entry of column p is s_i (visible bias), t_j (hidden bias) or t_j s_i (W_ji),
+// with the packed order [a | b | W] and W row-major (p = off + j N + i).
+struct JacCol {
+    int kind, j, i;  // kind 0: s_i, 1: t_j, 2: t_j s_i, 3: padding (zero)
+};
+__device__ __forceinline__ JacCol jac_col(const Dims& d, long p, int P) {
+    JacCol c{3, 0, 0};
+    if (p >= P) return c;
+    long idx = p;
+    if (d.vb) {
+        if (idx < d.N) return JacCol{0, 0, (int)idx};
+        idx -= d.N;
+    }
+    if (d.hb) {
+        if (idx < d.M) return JacCol{1, (int)idx, 0};
+        idx -= d.M;
+    }
+    const int j = (int)(idx / d.N);
+    return JacCol{2, j, (int)(idx - (long)j * d.N)};
+}
+template <typename R>
+__device__ __forceinline__ double jac_val(const JacCol& c, const int8_t* sk, const R* tk) {
+    // (t_j s_i with s_i = +-1 is exact in R, so this is the stored entry's value)
+    switch (c.kind) {
+        case 0: return (double)sk[c.i];
+        case 1: return (double)tk[c.j];
+        case 2: return (double)tk[c.j] * (double)sk[c.i];
+        default: return 0.0;
+    }
+}
+
+// Column sums over the same row slices, in the same order, as k_colsum_part,
+// read from the spins and activations instead of a materialised Jacobian.
+template <typename R>
+__global__ __launch_bounds__(256) void k_colsum_st(Dims d, const int8_t* __restrict__ s,
+                                                   const R* __restrict__ tact, long n, int P,
+                                                   int splits, double* __restrict__ part) {
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const JacCol c = jac_col(d, p, P);
+    const long k0 = n * blockIdx.y / splits, k1 = n * (blockIdx.y + 1) / splits;
+    double acc = 0.0;
+    for (long k = k0; k < k1; ++k) acc += jac_val<R>(c, s + k * d.N, tact + k * d.Mw);
+    part[(size_t)blockIdx.y * P + p] = acc;
+}
+
+// Centred, scaled Jacobian written in one pass: dJ[k][p] = (O[k][p] - cs[p] / n)
+// / sqrt(n) (the same expression as k_center_scale over a materialised O), zero
+// in the padding columns P <= p < ld.  Four columns per thread, JC_ROWS rows per
+// block; vec: ld a multiple of 4 and O 16-byte aligned (one 16-byte store per
+// FP32 row, two per FP64 row).
+constexpr int JC_ROWS = 8;
+template <typename R, bool SPLIT>
+__global__ __launch_bounds__(256) void k_jacobian_centred(Dims d, const int8_t* __restrict__ s,
+                                                          const R* __restrict__ tact, long n,
+                                                          long rows, int P, long ld,
+                                                          const double* __restrict__ cs, int vec,
+                                                          R* __restrict__ O) {
+    const long p = 4 * ((long)blockIdx.x * 256 + threadIdx.x);
+    if (p >= ld) return;
+    const double inv = 1.0 / (double)n;  // (n: all samples; rows: this launch's)
+    const double rs = 1.0 / sqrt((double)n);
+    JacCol c[4];
+    double mean[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        c[e] = jac_col(d, p + e, P);
+        mean[e] = c[e].kind != 3 ? cs[p + e] * inv : 0.0;
+    }
+    const long k0 = (long)blockIdx.y * JC_ROWS;
+    const long k1 = k0 + JC_ROWS < rows ? k0 + JC_ROWS : rows;
+    for (long k = k0; k < k1; ++k) {
+        const int8_t* sk = s + k * d.N;
+        const R* tk = tact + k * d.Mw;
+        R v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v[e] = c[e].kind != 3 ? center_store<R, SPLIT>((jac_val<R>(c[e], sk, tk) - mean[e]) * rs)
+                                  : (R)0;
+        R* row = O + k * ld + p;
+        if (vec) {
+            if constexpr (sizeof(R) == 4) {
+                *(float4*)row = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+                *(double2*)row = make_double2(v[0], v[1]);
+                *(double2*)(row + 2) = make_double2(v[2], v[3]);
+            }
+        } else {
+            for (int e = 0; e < 4 && p + e < ld; ++e) row[e] = v[e];
+        }
+    }
+}
+
 // G[p][q] = sum_k A[k][p] A[k][q] for the upper block triangle, mirrored.
 // Block = 4 waves = a 128 x 128 tile of G; each wave a 64 x 64 quarter as
 // 4 x 4 MFMA tiles of 16 x 16 sharing its operand fragments.
@@ -358,6 +452,43 @@ void launch_center_cols(hipStream_t st, int prec, void* O, long n, long ld, int 
         k_center_scale<float, true><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs, vec);
     else
         k_center_scale<float><<<g2, 256, 0, st>>>((float*)O, n, ld, P, cs, vec);
+}
+
+// Centred, scaled Jacobian of n samples in one write pass (column sums from the
+// spins and activations first; scratch holds the slice partials).
+void launch_jacobian_centred(hipStream_t st, const Dims& d, int prec, const int8_t* s,
+                             const void* tact, long n, void* O, int P, long ld, double* cs,
+                             double* scratch, size_t scratch_bytes, bool split) {
+    if (n <= 0) return;
+    const int nb = (P + 255) / 256;
+    size_t sp = scratch ? scratch_bytes / (8 * (size_t)P) : 1;
+    const int splits = (int)(sp < 1 ? 1 : (sp > CS_SPLIT_MAX ? CS_SPLIT_MAX : sp));
+    double* part = splits > 1 ? scratch : cs;
+    const dim3 g1(nb, splits);
+    if (prec == 0)
+        k_colsum_st<double><<<g1, 256, 0, st>>>(d, s, (const double*)tact, n, P, splits, part);
+    else
+        k_colsum_st<float><<<g1, 256, 0, st>>>(d, s, (const float*)tact, n, P, splits, part);
+    if (splits > 1) k_colsum_fin<<<nb, 256, 0, st>>>(part, P, splits, cs);
+    const int vec = (ld % 4 == 0 && ((uintptr_t)O & 15) == 0) ? 1 : 0;
+    const size_t es = prec == 0 ? 8 : 4;
+    const long chunk = 65535L * JC_ROWS;  // rows per launch (grid y limit)
+    for (long r0 = 0; r0 < n; r0 += chunk) {
+        const long m = n - r0 < chunk ? n - r0 : chunk;
+        const dim3 g2((unsigned)((ld + 1023) / 1024), (unsigned)((m + JC_ROWS - 1) / JC_ROWS));
+        const int8_t* sr = s + r0 * d.N;
+        const char* tr = (const char*)tact + es * (size_t)r0 * d.Mw;
+        char* orow = (char*)O + es * (size_t)r0 * ld;
+        if (prec == 0)
+            k_jacobian_centred<double, false><<<g2, 256, 0, st>>>(
+                d, sr, (const double*)tr, n, m, P, ld, cs, vec, (double*)orow);
+        else if (split)
+            k_jacobian_centred<float, true><<<g2, 256, 0, st>>>(
+                d, sr, (const float*)tr, n, m, P, ld, cs, vec, (float*)orow);
+        else
+            k_jacobian_centred<float, false><<<g2, 256, 0, st>>>(
+                d, sr, (const float*)tr, n, m, P, ld, cs, vec, (float*)orow);
+    }
 }
 
 int gram_tiles(int P) {

@@ -164,6 +164,9 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
                      double tol, int maxiter, double shift, CgScalars* sc);
 
 // dense.hip
+void launch_jacobian_centred(hipStream_t st, const Dims& d, int prec, const int8_t* s,
+                             const void* tact, long n, void* O, int P, long ld, double* cs,
+                             double* scratch, size_t scratch_bytes, bool split);
 void launch_jacobian(hipStream_t st, const Dims& d, int prec, const int8_t* s, const void* tact,
                      long n, void* O, int P, long ld);
 // centre and scale the columns of O [n][ld] (first P); scratch (may be null)

@@ -99,6 +99,8 @@ class Server:
         used = 0
         t0 = clock()
         n_tick = 0
+        resident = 0  # sum over ticks of the runs advanced in that tick
+        busy = 0.0    # seconds spent inside ticks
         local_energies = 0
         while pending or active:
             now = clock() - t0
@@ -135,6 +137,8 @@ class Server:
             reps = self.step([x[1] for x in active], [self.cfg] * len(active))
             dt = clock() - a
             n_tick += 1
+            resident += len(active)
+            busy += dt
             still = []
             for (req, st, fp, done), rep in zip(active, reps):
                 res = results[req.id]
@@ -154,15 +158,22 @@ class Server:
             active = still
         total = clock() - t0
         lat = np.array([x for r in results.values() for x in r.step_latency])
+        done = [r for r in results.values() if r.admitted is not None]
+        queue = np.array([(r.admitted - r.arrival) * 1e3 for r in done] or [0.0])
+        in_sys = np.array([(r.finished - r.arrival) * 1e3 for r in done
+                           if r.finished is not None] or [0.0])
+
+        def pct(a, q):
+            return float(np.percentile(a, q)) if a.size else None
         return dict(
             results=results, wall_s=total, ticks=n_tick,
             local_energies_per_s=local_energies / total if total > 0 else 0.0,
+            local_energies_per_busy_s=local_energies / busy if busy > 0 else 0.0,
+            mean_resident=resident / n_tick if n_tick else 0.0,
             sr_steps=int(lat.size),
-            p50_step_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else None,
-            p99_step_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-            queue_delay_ms_p50=float(np.median([(r.admitted - r.arrival) * 1e3
-                                                for r in results.values()
-                                                if r.admitted is not None] or [0.0])),
+            p50_step_ms=pct(lat * 1e3, 50), p99_step_ms=pct(lat * 1e3, 99),
+            queue_delay_ms_p50=pct(queue, 50), queue_delay_ms_p99=pct(queue, 99),
+            run_latency_ms_p50=pct(in_sys, 50), run_latency_ms_p99=pct(in_sys, 99),
             peak_hbm_bytes=self.peak_used,
         )
 

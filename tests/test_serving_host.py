@@ -76,3 +76,16 @@ def test_slot_limit_and_rejection():
         assert len(res[k].energies) == 3
     # never more than two resident runs: each tick steps at most two runs
     assert out["ticks"] >= 3 * 5 / 2
+
+
+def test_residency_and_latency_figures():
+    # three runs present at the start, two slots: ticks advance 2, 2, 1 runs
+    reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=2) for k in range(3)]
+    srv = make_server(budget=1000, slots=2, sizes={k: 10 for k in range(3)})
+    t = iter(range(10_000))
+    out = srv.serve(reqs, clock=lambda: float(next(t)), realtime=False)
+    assert out["sr_steps"] == 6
+    assert out["mean_resident"] == pytest.approx(6 / out["ticks"])
+    assert out["queue_delay_ms_p50"] >= 0 and out["queue_delay_ms_p99"] >= out["queue_delay_ms_p50"]
+    assert out["run_latency_ms_p99"] >= out["run_latency_ms_p50"] > 0
+    assert out["local_energies_per_busy_s"] >= out["local_energies_per_s"] > 0
