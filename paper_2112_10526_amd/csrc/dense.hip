@@ -4,6 +4,8 @@
 // Gram matrix G = dJ^T dJ is formed on MFMA, and CG runs on G v + eps v.
 #include "kernels.h"
 
+#include <vector>
+
 namespace nqs {
 
 // O[k][p] for the packed layout [a | b | W]; row stride ld, zero padding to ld.
@@ -139,7 +141,13 @@ __device__ __forceinline__ double jac_val(const JacCol& c, const int8_t* sk, con
 }
 
 // Column sums over the same row slices, in the same order, as k_colsum_part,
-// read from the spins and activations instead of a materialised Jacobian.
+// read from the spins and activations instead of a materialised Jacobian.  A
+// missing factor (the spin of a hidden-bias column, the activation of a
+// visible-bias column) is read as the constant 1 with stride 0, so the loop has
+// no branch; 1 * x is x exactly, so the sums are unchanged.
+__device__ const int8_t k_one_s = 1;
+template <typename R>
+__device__ const R k_one_t = (R)1;
 template <typename R>
 __global__ __launch_bounds__(256) void k_colsum_st(Dims d, const int8_t* __restrict__ s,
                                                    const R* __restrict__ tact, long n, int P,
@@ -147,9 +155,24 @@ __global__ __launch_bounds__(256) void k_colsum_st(Dims d, const int8_t* __restr
     const long p = (long)blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     const JacCol c = jac_col(d, p, P);
+    const bool has_s = c.kind != 1, has_t = c.kind != 0;
+    const int8_t* sp = has_s ? s + c.i : &k_one_s;
+    const R* tp = has_t ? tact + c.j : &k_one_t<R>;
+    const long ss = has_s ? d.N : 0, ts = has_t ? d.Mw : 0;
     const long k0 = n * blockIdx.y / splits, k1 = n * (blockIdx.y + 1) / splits;
     double acc = 0.0;
-    for (long k = k0; k < k1; ++k) acc += jac_val<R>(c, s + k * d.N, tact + k * d.Mw);
+    long k = k0;
+    for (; k + 4 <= k1; k += 4) {  // (loads of four rows issued together; sum order unchanged)
+        const double t0 = (double)tp[k * ts], t1 = (double)tp[(k + 1) * ts];
+        const double t2 = (double)tp[(k + 2) * ts], t3 = (double)tp[(k + 3) * ts];
+        const double s0 = (double)sp[k * ss], s1 = (double)sp[(k + 1) * ss];
+        const double s2 = (double)sp[(k + 2) * ss], s3 = (double)sp[(k + 3) * ss];
+        acc += t0 * s0;
+        acc += t1 * s1;
+        acc += t2 * s2;
+        acc += t3 * s3;
+    }
+    for (; k < k1; ++k) acc += (double)tp[k * ts] * (double)sp[k * ss];
     part[(size_t)blockIdx.y * P + p] = acc;
 }
 
@@ -495,15 +518,40 @@ int gram_tiles(int P) {
     const int nt = (P + 127) / 128;
     return nt * (nt + 1) / 2;
 }
+// Tile order, XCD-aware.  The hardware deals consecutive blocks to the 8 XCDs
+// in turn, so block 8 i + e runs on XCD e.  The upper block triangle is cut into
+// GT_SUPER x GT_SUPER supertiles, dealt to the XCDs in turn; each XCD runs its
+// supertiles one after the other, so the blocks resident on one XCD at a time
+// (about 64) share GT_SUPER row panels and GT_SUPER column panels in its L2
+// instead of each streaming a panel of its own.  Every tile appears once; the
+// ragged end (XCDs with fewer tiles) is filled in order.
+constexpr int GT_XCD = 8, GT_SUPER = 8;
 void fill_gram_tiles(int P, int* host_tiles) {
-    const int nt = (P + 127) / 128;
-    int e = 0;
-    for (int a = 0; a < nt; ++a)
-        for (int b = a; b < nt; ++b) {
-            host_tiles[2 * e] = a;
-            host_tiles[2 * e + 1] = b;
-            ++e;
+    const int nt = (P + 127) / 128, ns = (nt + GT_SUPER - 1) / GT_SUPER;
+    std::vector<std::vector<int>> seq(GT_XCD);
+    int sid = 0;
+    for (int A = 0; A < ns; ++A)
+        for (int B = A; B < ns; ++B, ++sid) {
+            std::vector<int>& q = seq[sid % GT_XCD];
+            for (int a = A * GT_SUPER; a < (A + 1) * GT_SUPER && a < nt; ++a)
+                for (int b = B * GT_SUPER; b < (B + 1) * GT_SUPER && b < nt; ++b)
+                    if (b >= a) {
+                        q.push_back(a);
+                        q.push_back(b);
+                    }
         }
+    size_t pos[GT_XCD] = {0};
+    const long total = (long)nt * (nt + 1) / 2;
+    long e = 0;
+    while (e < total) {  // slot e goes to XCD e % 8 while that XCD has tiles left
+        int src = (int)(e % GT_XCD);
+        for (int tries = 0; tries < GT_XCD && pos[src] >= seq[src].size(); ++tries)
+            src = (src + 1) % GT_XCD;
+        host_tiles[2 * e] = seq[src][pos[src]];
+        host_tiles[2 * e + 1] = seq[src][pos[src] + 1];
+        pos[src] += 2;
+        ++e;
+    }
 }
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
                  const int* tiles, int ntiles) {
