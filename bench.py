@@ -213,6 +213,57 @@ def summarize_waves(counter_dir, cmd):
     print("\n".join(out))
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES",
+                 "GRBM_GUI_ACTIVE")
+
+
+def summarize_mfma(counter_dir, cmd, title, n_cu=256, n_xcd=8):
+    """Markdown table of matrix-core counters per kernel: MFMA operations (the MOPS
+    counters count flops / 512), matrix-core busy cycles and their share of the
+    kernel's GPU-active cycles over all SIMDs,
+    util = SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) / (GRBM_GUI_ACTIVE / XCDs x CUs x 4):
+    rocprofv3 reports GRBM_GUI_ACTIVE summed over the eight XCDs, each of which counts the
+    kernel's active cycles (eight times 188 ms at the 2.4 GHz clock for a 188 ms kernel)."""
+    rows = _counter_rows(counter_dir)
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for r in rows:
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        names[key] = name
+        per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+    agg = collections.defaultdict(list)
+    for key, c in per.items():
+        mops = sum(c.get(k, 0.0) for k in MFMA_COUNTERS[:3])
+        if mops > 0:
+            agg[names[key]].append(c)
+    out = [f"# {title}", "", "Command:", "", "    " + cmd, "",
+           "Per kernel, median over its dispatches that issued matrix-core work (CG launches "
+           "queued after a solve stopped are left out: under a tenth of the largest). "
+           "`flop` = MOPS x 512 (the MOPS counters count operations / 512); "
+           f"`MFMA busy %` = SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) / (GRBM_GUI_ACTIVE "
+           f"/ {n_xcd} x {n_cu} CUs x 4 SIMDs): GRBM_GUI_ACTIVE comes summed over the "
+           f"{n_xcd} XCDs, each counting the kernel's active cycles.", "",
+           "| kernel | dispatches | flop (BF16) | flop (FP32) | flop (FP64) | MFMA busy cycles | "
+           "GUI active cycles | MFMA busy % |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for name in sorted(agg, key=lambda k: -np.median([c["SQ_VALU_MFMA_BUSY_CYCLES"]
+                                                       for c in agg[k]])):
+        cs = agg[name]
+        tot = np.array([sum(c.get(k, 0.0) for k in MFMA_COUNTERS[:3]) for c in cs])
+        keep = tot >= 0.1 * tot.max()
+        cs = [c for c, k in zip(cs, keep) if k]
+        med = {k: float(np.median([c.get(k, 0.0) for c in cs])) for k in MFMA_COUNTERS}
+        util = med["SQ_VALU_MFMA_BUSY_CYCLES"] / max(med["GRBM_GUI_ACTIVE"] / n_xcd * n_cu * 4, 1.0)
+        out.append(f"| `{name}` | {len(cs)} | {512 * med['SQ_INSTS_VALU_MFMA_MOPS_BF16']:.4g} | "
+                   f"{512 * med['SQ_INSTS_VALU_MFMA_MOPS_F32']:.4g} | "
+                   f"{512 * med['SQ_INSTS_VALU_MFMA_MOPS_F64']:.4g} | "
+                   f"{med['SQ_VALU_MFMA_BUSY_CYCLES']:.4g} | {med['GRBM_GUI_ACTIVE']:.4g} | "
+                   f"{100 * util:.1f} |")
+    print("\n".join(out))
+
+
 def _full_launch_medians(trace_csv):
     """Per kernel: median duration (us) and count of the launches that did the work.
     CG kernels queued after the solve has stopped return at once; launches shorter
@@ -590,6 +641,8 @@ def main():
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
                     help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-mfma", nargs=3, metavar=("COUNTER_DIR", "CMD", "TITLE"),
+                    help="print a markdown table of matrix-core counters and exit")
     ap.add_argument("--summarize-waves", nargs=2, metavar=("COUNTER_DIR", "CMD"),
                     help="print a markdown table of SQ wave-state counters and exit")
     ap.add_argument("--summarize-traffic", nargs=6,
@@ -598,6 +651,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
         return
     if args.summarize_waves:
         summarize_waves(*args.summarize_waves)
