@@ -110,7 +110,8 @@ __global__ __launch_bounds__(256) void k_center_scale(R* __restrict__ O, long n,
 
 // The Jacobian's entries straight from a sample's spins and activations: the
 // entry of column p is s_i (visible bias), t_j (hidden bias) or t_j s_i (W_ji),
-// with the packed order [a | b | W] and W row-major (p = off + j N + i).
+// with the packed order [a | b | W] and W row-major (p = off + j N + i); t_j s_i
+// with s_i = +-1 is exact in FP32, so it is the stored entry's value.
 struct JacCol {
     int kind, j, i;  // kind 0: s_i, 1: t_j, 2: t_j s_i, 3: padding (zero)
 };
@@ -129,17 +130,6 @@ __device__ __forceinline__ JacCol jac_col(const Dims& d, long p, int P) {
     const int j = (int)(idx / d.N);
     return JacCol{2, j, (int)(idx - (long)j * d.N)};
 }
-template <typename R>
-__device__ __forceinline__ double jac_val(const JacCol& c, const int8_t* sk, const R* tk) {
-    // (t_j s_i with s_i = +-1 is exact in R, so this is the stored entry's value)
-    switch (c.kind) {
-        case 0: return (double)sk[c.i];
-        case 1: return (double)tk[c.j];
-        case 2: return (double)tk[c.j] * (double)sk[c.i];
-        default: return 0.0;
-    }
-}
-
 // Column sums over the same row slices, in the same order, as k_colsum_part,
 // read from the spins and activations instead of a materialised Jacobian.  A
 // missing factor (the spin of a hidden-bias column, the activation of a
@@ -180,7 +170,11 @@ __global__ __launch_bounds__(256) void k_colsum_st(Dims d, const int8_t* __restr
 // / sqrt(n) (the same expression as k_center_scale over a materialised O), zero
 // in the padding columns P <= p < ld.  Four columns per thread, JC_ROWS rows per
 // block; vec: ld a multiple of 4 and O 16-byte aligned (one 16-byte store per
-// FP32 row, two per FP64 row).
+// FP32 row, two per FP64 row).  Each column reads its spin and activation through
+// a pointer and a row stride, a missing factor being the constant 1 (or 0 for
+// padding) with stride 0, so a full block of rows issues all its loads before
+// any arithmetic.
+__device__ const int8_t k_zero_s = 0;
 constexpr int JC_ROWS = 8;
 template <typename R, bool SPLIT>
 __global__ __launch_bounds__(256) void k_jacobian_centred(Dims d, const int8_t* __restrict__ s,
@@ -192,23 +186,25 @@ __global__ __launch_bounds__(256) void k_jacobian_centred(Dims d, const int8_t* 
     if (p >= ld) return;
     const double inv = 1.0 / (double)n;  // (n: all samples; rows: this launch's)
     const double rs = 1.0 / sqrt((double)n);
-    JacCol c[4];
+    const int8_t* sp[4];
+    const R* tp[4];
+    long ss[4], ts[4];
     double mean[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        c[e] = jac_col(d, p + e, P);
-        mean[e] = c[e].kind != 3 ? cs[p + e] * inv : 0.0;
+        const JacCol c = jac_col(d, p + e, P);
+        const bool has_s = c.kind == 0 || c.kind == 2, has_t = c.kind == 1 || c.kind == 2;
+        sp[e] = has_s ? s + c.i : (c.kind == 3 ? &k_zero_s : &k_one_s);
+        ss[e] = has_s ? d.N : 0;
+        tp[e] = has_t ? tact + c.j : &k_one_t<R>;
+        ts[e] = has_t ? d.Mw : 0;
+        mean[e] = c.kind != 3 ? cs[p + e] * inv : 0.0;
     }
     const long k0 = (long)blockIdx.y * JC_ROWS;
-    const long k1 = k0 + JC_ROWS < rows ? k0 + JC_ROWS : rows;
-    for (long k = k0; k < k1; ++k) {
-        const int8_t* sk = s + k * d.N;
-        const R* tk = tact + k * d.Mw;
+    auto store = [&](long k, const double* x) {
         R v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            v[e] = c[e].kind != 3 ? center_store<R, SPLIT>((jac_val<R>(c[e], sk, tk) - mean[e]) * rs)
-                                  : (R)0;
+        for (int e = 0; e < 4; ++e) v[e] = center_store<R, SPLIT>((x[e] - mean[e]) * rs);
         R* row = O + k * ld + p;
         if (vec) {
             if constexpr (sizeof(R) == 4) {
@@ -219,6 +215,23 @@ __global__ __launch_bounds__(256) void k_jacobian_centred(Dims d, const int8_t* 
             }
         } else {
             for (int e = 0; e < 4 && p + e < ld; ++e) row[e] = v[e];
+        }
+    };
+    if (k0 + JC_ROWS <= rows) {
+        double x[JC_ROWS][4];
+#pragma unroll
+        for (int r = 0; r < JC_ROWS; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                x[r][e] = (double)tp[e][(k0 + r) * ts[e]] * (double)sp[e][(k0 + r) * ss[e]];
+#pragma unroll
+        for (int r = 0; r < JC_ROWS; ++r) store(k0 + r, x[r]);
+    } else {
+        for (long k = k0; k < rows; ++k) {
+            double x[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = (double)tp[e][k * ts[e]] * (double)sp[e][k * ss[e]];
+            store(k, x);
         }
     }
 }

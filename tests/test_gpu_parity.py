@@ -372,10 +372,15 @@ def test_vjp_parity(precision, tol):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+# (ragged: 39 samples, not a multiple of the centring kernel's 8-row blocks, and
+# N = 10 sites, so 4-column groups of the weight block straddle hidden rows)
+@pytest.mark.parametrize("shape", [dict(L=16, alpha=2, n_chains=64, samples_per_chain=4),
+                                   dict(L=10, alpha=1, n_chains=13, samples_per_chain=3)],
+                         ids=["n16", "ragged"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
-def test_dense_qgt_matches_onthefly(precision):
+def test_dense_qgt_matches_onthefly(precision, shape):
     torch = _torch()
-    w = HEIS1D.replace(sigma=0.05, L=16, alpha=2, n_chains=64, samples_per_chain=4)
+    w = HEIS1D.replace(sigma=0.05, **shape)
     params = w.params()
     s = _batch(w, 8)
     out = {}
