@@ -621,17 +621,29 @@ constexpr uint32_t CG_CLASSES = (1u << NQS_PROF_QGT_W) | (1u << NQS_PROF_OUTER) 
 // flag first).  Full on-the-fly batches are replayed from one captured graph
 // (the iteration kernels take their scalars from the device) unless CG kernel
 // classes are being timed, which needs one event pair per launch and batches
-// of one iteration.
-int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
-    // while CG kernels are timed, the stop flag is read after every iteration
-    // so that almost no launch after the stop is timed
-    const int every = (c->prof_mask & CG_CLASSES) ? 1 : cg_check_interval();
-    // the on-the-fly form tests convergence at the start of an iteration
-    const int limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
-    const bool use_graphs = c->graphs && kind == NQS_QGT_ONTHEFLY && every % 2 == 0 &&
-                            !(c->prof_mask & CG_CLASSES);
+// of one iteration.  One CgRun drives one context; the batched step drives
+// several side by side.
+struct CgRun {
+    nqs_ctx* c = nullptr;
+    int kind = 0, every = 1, limit = 0;
+    double shift = 0.0;
+    bool use_graphs = false, stop = false;
     int launched = 0, issued = 0, checked = 0;
-    auto issue_batch = [&]() -> int {
+
+    void init(nqs_ctx* ctx, int k, double sh, int maxiter) {
+        c = ctx;
+        kind = k;
+        shift = sh;
+        // while CG kernels are timed, the stop flag is read after every iteration
+        // so that almost no launch after the stop is timed
+        every = (c->prof_mask & CG_CLASSES) ? 1 : cg_check_interval();
+        // the on-the-fly form tests convergence at the start of an iteration
+        limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
+        use_graphs = c->graphs && kind == NQS_QGT_ONTHEFLY && every % 2 == 0 &&
+                     !(c->prof_mask & CG_CLASSES);
+    }
+    bool finished() const { return stop || (checked >= issued && launched >= limit); }
+    int issue_batch() {
         const int k = (limit - launched) < every ? (limit - launched) : every;
         const int slot = issued & 1;
         if (use_graphs && k == every && c->cg_iter % 2 == 0) {
@@ -652,22 +664,51 @@ int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
         HIPCHK(c, hipEventRecord(c->flag_ev[slot], c->stream));
         ++issued;
         return NQS_OK;
-    };
-    if (limit <= 0) return NQS_OK;
-    int st = issue_batch();
-    if (st) return st;
-    while (checked < issued) {
-        if (launched < limit && issued - checked < 2) {
-            st = issue_batch();
+    }
+    // keep up to `depth` batches queued (a lone context: two, so the device never
+    // waits for the host; contexts run side by side: one each, the others' work
+    // fills the device and fewer iterations are queued past a context's stop)
+    int top_up(int depth = 2) {
+        while (!stop && launched < limit && issued - checked < depth) {
+            const int st = issue_batch();
             if (st) return st;
         }
+        return NQS_OK;
+    }
+    // read the stop flag of the oldest unchecked batch; without `block`, only
+    // if that batch has finished (progress tells whether it was read)
+    int poll(bool block, bool& progress) {
+        progress = false;
+        if (checked >= issued) return NQS_OK;
         const int slot = checked & 1;
-        HIPCHK(c, hipEventSynchronize(c->flag_ev[slot]));
+        if (block) {
+            HIPCHK(c, hipEventSynchronize(c->flag_ev[slot]));
+        } else {
+            const hipError_t e = hipEventQuery(c->flag_ev[slot]);
+            if (e == hipErrorNotReady) return NQS_OK;
+            HIPCHK(c, e);
+        }
         // on-the-fly: the batch's last update stored the flag in word 0 (a later
         // batch may already have overwritten it with a value just as valid)
-        const bool stop = c->h_flag[kind == NQS_QGT_ONTHEFLY ? 0 : slot] != 0;
+        stop = c->h_flag[kind == NQS_QGT_ONTHEFLY ? 0 : slot] != 0;
         ++checked;
-        if (stop) break;
+        progress = true;
+        return NQS_OK;
+    }
+};
+
+int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
+    CgRun r;
+    r.init(c, kind, shift, maxiter);
+    if (r.limit <= 0) return NQS_OK;
+    int st = r.issue_batch();
+    if (st) return st;
+    while (!r.finished()) {
+        st = r.top_up();
+        if (st) return st;
+        bool progress;
+        st = r.poll(true, progress);
+        if (st) return st;
     }
     return NQS_OK;
 }
@@ -1183,7 +1224,7 @@ int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
 
 int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_step_report* reps) {
     if (!ctxs || n < 0 || (n > 0 && (!cfgs || !reps))) return NQS_EINVAL;
-    std::vector<int> st(n, NQS_OK), mi(n, 0), lim(n, 0), launched(n, 0), active(n, 1);
+    std::vector<int> st(n, NQS_OK), mi(n, 0), active(n, 1);
     for (int k = 0; k < n; ++k) {
         std::memset(&reps[k], 0, sizeof(nqs_step_report));
         nqs_ctx* c = ctxs[k];
@@ -1199,36 +1240,45 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         issue_sample(c, 0, nullptr);
         issue_energy_grad(c);
         mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
-        lim[k] = cfgs[k].qgt == NQS_QGT_ONTHEFLY ? mi[k] + 1 : mi[k];
         if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfgs[k].cg_tol, mi[k]);
         else issue_cg_init(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
         st[k] = last_launch(c);
     }
-    // lock-step CG: a block of iterations on every unconverged context, then
-    // one check per context
-    const int every = cg_check_interval();
+    // CG on every context side by side: each keeps a batch of iterations queued
+    // (two when it runs alone; graph replays where the context allows them) and
+    // its stop flag is read as soon as a batch has finished; the host blocks
+    // only when no context has a finished batch to read
+    std::vector<CgRun> run(n);
+    for (int k = 0; k < n; ++k) {
+        if (st[k]) continue;
+        run[k].init(ctxs[k], cfgs[k].qgt, cfgs[k].diag_shift, mi[k]);
+        if (run[k].limit <= 0) active[k] = 0;
+    }
     bool any = true;
     while (any) {
         any = false;
+        bool progress_any = false;
+        int wait_on = -1;
         for (int k = 0; k < n; ++k) {
             if (st[k] || !active[k]) continue;
-            nqs_ctx* c = ctxs[k];
-            const int b2 = (lim[k] - launched[k]) < every ? (lim[k] - launched[k]) : every;
-            issue_cg_iters(c, cfgs[k].qgt, cfgs[k].diag_shift, b2);
-            launched[k] += b2;
-            if (hipMemcpyAsync(c->h_sc, c->b.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
-                               c->stream) != hipSuccess)
-                st[k] = fail(c, NQS_EDEVICE, "scalar readback");
+            st[k] = run[k].top_up(n > 1 ? 1 : 2);
         }
         for (int k = 0; k < n; ++k) {
             if (st[k] || !active[k]) continue;
-            nqs_ctx* c = ctxs[k];
-            if (hipStreamSynchronize(c->stream) != hipSuccess) {
-                st[k] = fail(c, NQS_EDEVICE, "stream synchronise");
+            bool progress = false;
+            st[k] = run[k].poll(false, progress);
+            progress_any = progress_any || progress;
+            if (st[k] || run[k].finished()) {
+                active[k] = 0;
                 continue;
             }
-            if (c->h_sc->done || launched[k] >= lim[k]) active[k] = 0;
-            else any = true;
+            any = true;
+            if (wait_on < 0) wait_on = k;
+        }
+        if (any && !progress_any && wait_on >= 0) {
+            bool progress = false;
+            st[wait_on] = run[wait_on].poll(true, progress);
+            if (st[wait_on] || run[wait_on].finished()) active[wait_on] = 0;
         }
     }
     for (int k = 0; k < n; ++k) {
