@@ -551,11 +551,14 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
     n_steps SR steps each) through the continuous-batching server.
 
     Passes: (1) one run at a time, all present at the start (the single-run
-    service rate mu = runs / wall); (2) continuous batching, all present at the
-    start (capacity); (3) Poisson arrivals at offered loads rho * mu, served in
-    real time.  Each pass reports aggregate local energies/s, p50/p99 SR-step
-    latency (one tick advances every resident run by one SR step), queueing
-    delay, time in system, mean residency and peak HBM footprint."""
+    service rate mu = runs / wall); (2) all present at the start, up to `slots`
+    resident, in lock-step ticks (every resident run advances one SR step per
+    tick; a step's latency is its tick's) and with asynchronous steps (each run
+    starts its next step when its previous one ends; a step's latency is its
+    own); (3) Poisson arrivals at offered loads rho * mu, served in real time in
+    lock-step ticks.  Each pass reports aggregate local energies/s, p50/p99
+    SR-step latency, queueing delay, time in system, mean residency and peak HBM
+    footprint."""
     from paper_2112_10526_amd.serving import Server, requests_from_stream
     budget = budget_gib << 30
 
@@ -577,9 +580,11 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
     passes["one_at_a_time"] = summary(serial)
     print(f"[bench] serving one at a time: {serial['wall_s']:.2f} s", file=sys.stderr, flush=True)
     mu = n_runs / serial["wall_s"]
-    cap = Server(budget, max_slots=slots).serve(base, realtime=False)
-    passes["batched_all_present"] = summary(cap)
-    print(f"[bench] serving batched: {cap['wall_s']:.2f} s", file=sys.stderr, flush=True)
+    for mode in ("tick", "async"):
+        cap = Server(budget, max_slots=slots, mode=mode).serve(base, realtime=False)
+        passes[f"all_present_{mode}"] = summary(cap)
+        print(f"[bench] serving all present, {mode}: {cap['wall_s']:.2f} s", file=sys.stderr,
+              flush=True)
     for rho in loads:
         reqs = requests_from_stream(n_runs, seed, rho * mu, n_steps=n_steps)
         out = Server(budget, max_slots=slots).serve(reqs, realtime=True)

@@ -297,6 +297,27 @@ int nqs_vmc_step(nqs_ctx* ctx, const nqs_step_cfg* cfg, nqs_step_report* rep);
 int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs,
                    nqs_step_report* reps);
 
+/* Asynchronous steps, for a server that advances many contexts without a
+ * common barrier (each run's next step starts as soon as its previous one has
+ * finished).  nqs_step_begin issues the step's sampling, local energies,
+ * gradient, CG set-up and first batch of CG iterations on the context's stream
+ * and returns at once; nqs_step_poll then advances every context of `ctxs`
+ * that has a step in flight: further CG batches as their stop flags come back,
+ * then the update and the read-back of the step's scalars.  A context whose
+ * step has completed (or failed) gets completed[k] = 1 and its report in
+ * reps[k] (status inside); the others get completed[k] = 0 and reps[k] is left
+ * alone.  wait = 0: return after one pass over the contexts; wait = 1: return
+ * once at least one step has completed or none is in flight.  Each context's
+ * result is identical to an nqs_vmc_step on it alone (same kernels, same
+ * fixed-order reductions).  While a step is in flight, make no other call on
+ * that context except nqs_step_poll and nqs_destroy.  ctxs, reps, completed:
+ * host arrays of n.  Errors: NQS_ESTATE (nqs_step_begin with a step already in
+ * flight), those of nqs_vmc_step; nqs_step_poll returns the first failing
+ * step's status. */
+int nqs_step_begin(nqs_ctx* ctx, const nqs_step_cfg* cfg);
+int nqs_step_poll(nqs_ctx* const* ctxs, int n, int wait, nqs_step_report* reps,
+                  int32_t* completed);
+
 /* ------------------------------------------------------------------------- */
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------- */

@@ -23,7 +23,8 @@ EXPORTS = [
     "nqs_reset_chains", "nqs_get_chains", "nqs_set_chains", "nqs_proposal_count",
     "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_thermalize", "nqs_load_samples", "nqs_local_energy",
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
-    "nqs_vmc_step", "nqs_batch_step", "nqs_profile_enable", "nqs_profile_read",
+    "nqs_vmc_step", "nqs_batch_step", "nqs_step_begin", "nqs_step_poll",
+    "nqs_profile_enable", "nqs_profile_read",
     "nqs_profile_class_name", "nqs_set_cg_graphs",
 ]
 PROF_CLASSES = ["sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
@@ -96,6 +97,9 @@ def load(path: str = LIB_PATH):
         "nqs_vmc_step": (I, [V, ctypes.POINTER(NqsStepCfg), ctypes.POINTER(NqsStepReport)]),
         "nqs_batch_step": (I, [ctypes.POINTER(V), I, ctypes.POINTER(NqsStepCfg),
                                ctypes.POINTER(NqsStepReport)]),
+        "nqs_step_begin": (I, [V, ctypes.POINTER(NqsStepCfg)]),
+        "nqs_step_poll": (I, [ctypes.POINTER(V), I, I, ctypes.POINTER(NqsStepReport),
+                              ctypes.POINTER(ctypes.c_int32)]),
         "nqs_profile_enable": (I, [V, ctypes.c_uint32]),
         "nqs_profile_read": (I, [V, V, V, I]),
         "nqs_profile_class_name": (ctypes.c_char_p, [I]),

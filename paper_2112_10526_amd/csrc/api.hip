@@ -42,6 +42,8 @@ struct Buffers {
 
 }  // namespace
 
+struct CgRun;
+
 struct nqs_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -94,6 +96,12 @@ struct nqs_ctx {
     bool graphs = true;
     hipGraphExec_t cg_graph = nullptr;
     hipStream_t cap_stream = nullptr;
+    // a step issued by nqs_step_begin: 0 none, 1 in CG, 2 update issued, results
+    // on their way to the host (step_ev marks their arrival)
+    int step_phase = 0;
+    nqs_step_cfg step_cfg{};
+    CgRun* step_run = nullptr;
+    hipEvent_t step_ev = nullptr;
 };
 
 namespace {
@@ -623,6 +631,8 @@ constexpr uint32_t CG_CLASSES = (1u << NQS_PROF_QGT_W) | (1u << NQS_PROF_OUTER) 
 // classes are being timed, which needs one event pair per launch and batches
 // of one iteration.  One CgRun drives one context; the batched step drives
 // several side by side.
+}  // namespace
+
 struct CgRun {
     nqs_ctx* c = nullptr;
     int kind = 0, every = 1, limit = 0;
@@ -697,6 +707,8 @@ struct CgRun {
     }
 };
 
+namespace {
+
 int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
     CgRun r;
     r.init(c, kind, shift, maxiter);
@@ -755,7 +767,8 @@ int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
         hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->flag_ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->flag_ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->flag_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->step_ev, hipEventDisableTiming) != hipSuccess) {
         nqs_destroy(c);
         return NQS_EDEVICE;
     }
@@ -771,6 +784,8 @@ void nqs_destroy(nqs_ctx* c) {
     if (c->h_flag) hipHostFree(c->h_flag);
     for (auto& e : c->flag_ev)
         if (e) hipEventDestroy(e);
+    if (c->step_ev) hipEventDestroy(c->step_ev);
+    delete c->step_run;
     if (c->h_acc) hipHostFree(c->h_acc);
     for (auto& e : c->ev) hipEventDestroy(e);
     drop_graphs(c);
@@ -1163,9 +1178,8 @@ int nqs_expect_and_grad(nqs_ctx* c, nqs_stats* E, double* grad) {
     return NQS_OK;
 }
 
-// The SR solve and update, issued; the CG scalars are not read back here.
-static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol,
-                           int maxiter, double* delta_out) {
+// Checks before an SR solve.
+static int sr_check(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol) {
     int st = need_bound(c);
     if (st) return st;
     if (!c->have_grad) return fail(c, NQS_ESTATE, "no gradient: call nqs_expect_and_grad first");
@@ -1173,7 +1187,13 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
         return fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace (nqs_set_qgt)");
     if (!(diag_shift >= 0) || !std::isfinite(lr) || !(tol >= 0))
         return fail(c, NQS_EINVAL, "bad solver settings");
-    st = set_device(c);
+    return set_device(c);
+}
+
+// The SR solve and update, issued; the CG scalars are not read back here.
+static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double tol,
+                           int maxiter, double* delta_out) {
+    int st = sr_check(c, kind, diag_shift, lr, tol);
     if (st) return st;
     const int mi = default_maxiter(c, maxiter);
     if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi);
@@ -1198,6 +1218,7 @@ int nqs_sr_update(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, double
 int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
     if (!c) return NQS_EINVAL;
     if (!cfg || !rep) return fail(c, NQS_EINVAL, "null settings or report");
+    if (c->step_phase) return fail(c, NQS_ESTATE, "a step begun by nqs_step_begin is in flight");
     std::memset(rep, 0, sizeof(*rep));
     int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
     if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
@@ -1229,6 +1250,8 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         std::memset(&reps[k], 0, sizeof(nqs_step_report));
         nqs_ctx* c = ctxs[k];
         st[k] = need_bound(c);
+        if (!st[k] && c->step_phase)
+            st[k] = fail(c, NQS_ESTATE, "a step begun by nqs_step_begin is in flight");
         if (!st[k] && cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
             st[k] = fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace");
         if (!st[k]) st[k] = set_device(c);
@@ -1300,6 +1323,135 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         }
         reps[k].status = st[k];
         if (st[k] && !first) first = st[k];
+    }
+    return first;
+}
+
+// ---- asynchronous steps ---------------------------------------------------
+// Ends the step in flight on c (after an error: its kernels may still be queued
+// on the stream, which later calls wait behind).
+static void step_end(nqs_ctx* c) {
+    c->step_phase = 0;
+    delete c->step_run;
+    c->step_run = nullptr;
+}
+
+// Advances the step in flight on c by what is ready (with block, waits for the
+// next thing it needs).  completed: its results are on the host.
+static int step_advance(nqs_ctx* c, bool block, int depth, bool& progress, bool& completed) {
+    progress = completed = false;
+    if (c->step_phase == 1) {
+        CgRun& r = *c->step_run;
+        if (!r.finished()) {
+            int st = r.top_up(depth);
+            if (st) return st;
+            st = r.poll(block, progress);
+            if (st) return st;
+        }
+        if (!r.finished()) return NQS_OK;
+        issue_finish_solve(c, c->step_cfg.qgt);
+        issue_update(c, c->step_cfg.lr);
+        int st = last_launch(c);
+        if (!st) st = enqueue_scalars(c);
+        if (!st) st = enqueue_acceptance(c);
+        if (!st) st = enqueue_stats(c);
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(c->step_ev, c->stream));
+        c->step_phase = 2;
+        progress = true;
+        block = false;  // (the wait, if any, was for the CG flag)
+    }
+    if (c->step_phase == 2) {
+        const hipError_t e = block ? hipEventSynchronize(c->step_ev) : hipEventQuery(c->step_ev);
+        if (e == hipErrorNotReady) return NQS_OK;
+        HIPCHK(c, e);
+        progress = completed = true;
+    }
+    return NQS_OK;
+}
+
+static void step_report(nqs_ctx* c, nqs_step_report* rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    int st = sr_status(c, &rep->sr);
+    if (st == NQS_OK || st == NQS_ENOTCONV) {
+        int s2 = take_acceptance(c);
+        if (!s2) s2 = take_stats(c, &rep->energy);
+        if (s2) st = s2;
+    }
+    rep->status = st;
+}
+
+int nqs_step_begin(nqs_ctx* c, const nqs_step_cfg* cfg) {
+    if (!c) return NQS_EINVAL;
+    if (!cfg) return fail(c, NQS_EINVAL, "null settings");
+    if (c->step_phase) return fail(c, NQS_ESTATE, "a step is already in flight");
+    int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
+    if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
+    if (!st) st = sr_check(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol);
+    if (st) return st;
+    const int mi = default_maxiter(c, cfg->cg_maxiter);
+    if (cfg->qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfg->cg_tol, mi);
+    else issue_cg_init(c, cfg->cg_tol, mi, cfg->diag_shift);
+    st = last_launch(c);
+    if (st) return st;
+    c->step_cfg = *cfg;
+    c->step_run = new CgRun();
+    c->step_run->init(c, cfg->qgt, cfg->diag_shift, mi);
+    c->step_phase = 1;
+    if (c->step_run->limit > 0) {
+        st = c->step_run->issue_batch();
+        if (st) {
+            step_end(c);
+            return st;
+        }
+    }
+    return NQS_OK;
+}
+
+int nqs_step_poll(nqs_ctx* const* ctxs, int n, int wait, nqs_step_report* reps,
+                  int32_t* completed) {
+    if (!ctxs || n < 0 || (n > 0 && (!reps || !completed))) return NQS_EINVAL;
+    for (int k = 0; k < n; ++k) completed[k] = 0;
+    const int depth = n > 1 ? 1 : 2;
+    int first = NQS_OK;
+    auto finish = [&](int k, int st) {
+        nqs_ctx* c = ctxs[k];
+        if (st) {
+            std::memset(&reps[k], 0, sizeof(nqs_step_report));
+            reps[k].status = st;
+        } else {
+            step_report(c, &reps[k]);
+        }
+        step_end(c);
+        completed[k] = 1;
+        if (reps[k].status && !first) first = reps[k].status;
+    };
+    for (;;) {
+        bool any_done = false, progress_any = false, inflight = false;
+        int wait_on = -1;
+        for (int k = 0; k < n; ++k) {
+            nqs_ctx* c = ctxs[k];
+            if (!c || !c->step_phase || completed[k]) continue;
+            bool progress = false, done = false;
+            const int st = step_advance(c, false, depth, progress, done);
+            if (st || done) {
+                finish(k, st);
+                any_done = true;
+                continue;
+            }
+            inflight = true;
+            progress_any = progress_any || progress;
+            if (wait_on < 0) wait_on = k;
+        }
+        if (!wait || any_done || !inflight) break;
+        if (!progress_any) {  // nothing ready anywhere: wait for one context
+            bool progress = false, done = false;
+            const int st = step_advance(ctxs[wait_on], true, depth, progress, done);
+            if (st || done) {
+                finish(wait_on, st);
+                break;
+            }
+        }
     }
     return first;
 }

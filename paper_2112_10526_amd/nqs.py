@@ -289,6 +289,40 @@ VMCState.profile_read = _profile_read
 VMCState.set_cg_graphs = _set_cg_graphs
 
 
+def _step_cfg(c: dict) -> NqsStepCfg:
+    return NqsStepCfg(_lib.QGTS[c.get("qgt", "onthefly")], c.get("diag_shift", 0.01),
+                      c.get("lr", 0.01), c.get("tol", 1e-6), c.get("maxiter", 0))
+
+
+def _step_report(lib, st: VMCState, r) -> StepReport:
+    if r.status not in (_lib.NQS_OK, _lib.NQS_ENOTCONV):
+        raise NqsError(r.status, lib.nqs_last_error(st.ctx).decode())
+    return StepReport(_stats_dict(r.energy),
+                      SrInfo(r.sr.iterations, bool(r.sr.converged), r.sr.rel_residual), r.status)
+
+
+def step_begin(state: VMCState, cfg: dict) -> None:
+    """Issue one VMC step on the state's stream and return at once
+    (``nqs_step_begin``); ``step_poll`` advances it and reports its end."""
+    c = _step_cfg(cfg)
+    state._check(state.lib.nqs_step_begin(state.ctx, ctypes.byref(c)))
+
+
+def step_poll(states: Sequence[VMCState], wait: bool = True) -> dict:
+    """Advance the steps in flight on ``states`` (``nqs_step_poll``); returns
+    {index: StepReport} for the steps that have completed (with ``wait``, at
+    least one unless none is in flight)."""
+    n = len(states)
+    if n == 0:
+        return {}
+    lib = states[0].lib
+    ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in states])
+    reps = (NqsStepReport * n)()
+    done = (ctypes.c_int32 * n)()
+    lib.nqs_step_poll(ctxs, n, 1 if wait else 0, reps, done)
+    return {k: _step_report(lib, states[k], reps[k]) for k in range(n) if done[k]}
+
+
 def batch_step(states: Sequence[VMCState], cfgs: Sequence[dict]) -> list:
     """One SR step for every state, issued in lock-step across their streams."""
     n = len(states)

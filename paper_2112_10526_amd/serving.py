@@ -9,9 +9,11 @@ samples per step, number of SR steps).  The server
     join at the next tick;
   * keeps every admitted run's chains, parameters and tables resident in its
     own device workspace until the run finishes, then frees it;
-  * advances all resident runs by one SR step per tick with
-    ``nqs_batch_step``, which issues every run's kernels on that run's own
-    HIP stream in lock-step, so the runs' kernels overlap on the device.
+  * advances the resident runs on their own HIP streams, so the runs' kernels
+    overlap on the device.  Default (mode "tick"): all resident runs advance by
+    one SR step per tick with ``nqs_batch_step``; mode "async": every run starts
+    its next SR step as soon as its previous one has finished
+    (``nqs_step_begin`` / ``nqs_step_poll``), with no barrier between runs.
 
 Every run's arithmetic is independent of the others (its own Philox stream,
 fixed-order reductions), so a run's trajectory in the mix is identical to the
@@ -28,7 +30,7 @@ import torch
 
 import synth
 
-from .nqs import VMCState, batch_step
+from .nqs import VMCState, batch_step, step_begin, step_poll
 
 
 @dataclasses.dataclass
@@ -70,7 +72,13 @@ class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 64, n_streams: int = 4,
                  precision: str = "bf16", device: int = 0, thermalize_segments: int = 20,
                  diag_shift: float = 0.01, lr: float = 0.01, cg_tol: float = 1e-6,
-                 keep_params: bool = False, state_factory=None, step_fn=None, streams=None):
+                 keep_params: bool = False, state_factory=None, step_fn=None, streams=None,
+                 mode: str = "tick", begin_fn=None, poll_fn=None):
+        if mode not in ("async", "tick"):
+            raise ValueError(f"unknown serving mode {mode!r}")
+        self.mode = mode
+        self.begin = begin_fn or step_begin
+        self.poll = poll_fn or step_poll
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
         self.precision = precision
@@ -95,67 +103,53 @@ class Server:
         (all requests are present at the start)."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.id))
         results = {r.id: RunResult(r.id, r.arrival) for r in requests}
-        active = []  # (request, state, footprint, steps_done)
-        used = 0
+        active = []  # [request, state, footprint, steps done, step start or None]
+        self._used = 0
         t0 = clock()
         n_tick = 0
-        resident = 0  # sum over ticks of the runs advanced in that tick
-        busy = 0.0    # seconds spent inside ticks
+        resident = 0  # sum over ticks (polls) of the runs resident
+        busy = 0.0    # seconds spent inside ticks (polls)
         local_energies = 0
         while pending or active:
-            now = clock() - t0
-            # admission in arrival order
-            while pending and len(active) < self.max_slots and (
-                    not realtime or pending[0].arrival <= now):
-                req = pending[0]
-                stream = self.streams[req.id % len(self.streams)]
-                st = self.make_state(req, stream)
-                fp = st.workspace_bytes
-                if fp > self.budget:
-                    results[req.id].error = f"footprint {fp} B exceeds the budget {self.budget} B"
-                    st.close()
-                    pending.pop(0)
-                    continue
-                if used + fp > self.budget:
-                    st.close()
-                    break  # wait for memory to free up
-                pending.pop(0)
-                st.bind()
-                st.thermalize(self.therm)
-                used += fp
-                self.peak_used = max(self.peak_used, used)
-                res = results[req.id]
-                res.admitted = clock() - t0
-                res.footprint = fp
-                active.append([req, st, fp, 0])
+            self._admit(pending, active, results, clock, t0, realtime)
             if not active:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
                 continue
-            # one tick: one SR step for every resident run
             a = clock()
-            reps = self.step([x[1] for x in active], [self.cfg] * len(active))
-            dt = clock() - a
+            if self.mode == "tick":
+                # one tick: one SR step for every resident run
+                reps = self.step([x[1] for x in active], [self.cfg] * len(active))
+                t1 = clock()
+                finished = [(x, rep, t1 - a) for x, rep in zip(active, reps)]
+            else:
+                # every idle run starts its next step; then wait for any to end
+                for x in active:
+                    if x[4] is None:
+                        self.begin(x[1], self.cfg)
+                        x[4] = clock()
+                done = self.poll([x[1] for x in active], True)
+                t1 = clock()
+                finished = [(active[k], rep, t1 - active[k][4]) for k, rep in done.items()]
             n_tick += 1
             resident += len(active)
-            busy += dt
-            still = []
-            for (req, st, fp, done), rep in zip(active, reps):
+            busy += t1 - a
+            for x, rep, dt in finished:
+                req, st = x[0], x[1]
                 res = results[req.id]
                 res.energies.append(rep.energy["mean"])
                 res.cg_iters.append(rep.sr.iterations)
                 res.step_latency.append(dt)
                 local_energies += st.n_samples
-                done += 1
-                if done >= req.n_steps:
+                x[3] += 1
+                x[4] = None
+                if x[3] >= req.n_steps:
                     if self.keep_params:
                         res.params = st.get_params()
                     st.close()
-                    used -= fp
+                    self._used -= x[2]
                     res.finished = clock() - t0
-                else:
-                    still.append([req, st, fp, done])
-            active = still
+            active[:] = [x for x in active if x[3] < x[0].n_steps]
         total = clock() - t0
         lat = np.array([x for r in results.values() for x in r.step_latency])
         done = [r for r in results.values() if r.admitted is not None]
@@ -166,7 +160,7 @@ class Server:
         def pct(a, q):
             return float(np.percentile(a, q)) if a.size else None
         return dict(
-            results=results, wall_s=total, ticks=n_tick,
+            results=results, wall_s=total, ticks=n_tick, mode=self.mode,
             local_energies_per_s=local_energies / total if total > 0 else 0.0,
             local_energies_per_busy_s=local_energies / busy if busy > 0 else 0.0,
             mean_resident=resident / n_tick if n_tick else 0.0,
@@ -176,6 +170,34 @@ class Server:
             run_latency_ms_p50=pct(in_sys, 50), run_latency_ms_p99=pct(in_sys, 99),
             peak_hbm_bytes=self.peak_used,
         )
+
+    def _admit(self, pending, active, results, clock, t0, realtime):
+        """Admission in arrival order while a slot is free and the run's footprint
+        fits in what is left of the budget."""
+        now = clock() - t0
+        while pending and len(active) < self.max_slots and (
+                not realtime or pending[0].arrival <= now):
+            req = pending[0]
+            stream = self.streams[req.id % len(self.streams)]
+            st = self.make_state(req, stream)
+            fp = st.workspace_bytes
+            if fp > self.budget:
+                results[req.id].error = f"footprint {fp} B exceeds the budget {self.budget} B"
+                st.close()
+                pending.pop(0)
+                continue
+            if self._used + fp > self.budget:
+                st.close()
+                break  # wait for memory to free up
+            pending.pop(0)
+            st.bind()
+            st.thermalize(self.therm)
+            self._used += fp
+            self.peak_used = max(self.peak_used, self._used)
+            res = results[req.id]
+            res.admitted = clock() - t0
+            res.footprint = fp
+            active.append([req, st, fp, 0, None])
 
 
 def requests_from_stream(n_runs: int, seed: int, rate: float, n_steps: int = 50, **kw) -> List[Request]:

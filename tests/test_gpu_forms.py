@@ -93,13 +93,15 @@ def test_dense_qgt_full_size(precision):
 # ----------------------------------------------------------------------------
 # serving form
 # ----------------------------------------------------------------------------
-def _serve(reqs, budget, slots=16, precision="bf16"):
+def _serve(reqs, budget, slots=16, precision="bf16", mode="async"):
     from paper_2112_10526_amd.serving import Server
     srv = Server(budget, max_slots=slots, n_streams=4, precision=precision,
-                 thermalize_segments=5, keep_params=True)
+                 thermalize_segments=5, keep_params=True, mode=mode)
     return srv.serve(reqs, realtime=False)
 
 
+# alone: one run at a time in lock-step mode; mixes: all four together, in
+# both modes, and with a budget that fits one run at a time
 @pytest.mark.parametrize("precision", ["bf16", "fp64"])
 def test_serving_result_same_alone_and_in_mix(precision):
     _torch()
@@ -108,24 +110,26 @@ def test_serving_result_same_alone_and_in_mix(precision):
             Request(2, 0.0, 5, 1.7, 4, 1024, 5, 13, 23), Request(3, 0.0, 7, 2.5, 1, 4096, 2, 14, 24)]
     alone = {}
     for r in reqs:
-        out = _serve([r], 1 << 34, precision=precision)
+        out = _serve([r], 1 << 34, precision=precision, mode="tick")
         alone[r.id] = out["results"][r.id]
-    mix = _serve(reqs, 1 << 34, precision=precision)["results"]
+    mixes = [_serve(reqs, 1 << 34, precision=precision, mode=m)["results"]
+             for m in ("tick", "async")]
     tight = _serve(reqs, max(x.footprint for x in alone.values()) + 1, precision=precision)
     for r in reqs:
         a = alone[r.id]
-        for other in (mix[r.id], tight["results"][r.id]):
+        for other in [m[r.id] for m in mixes] + [tight["results"][r.id]]:
             assert other.energies == a.energies, r.id
             np.testing.assert_array_equal(other.params, a.params)
     assert tight["peak_hbm_bytes"] <= max(x.footprint for x in alone.values()) + 1
 
 
-def test_serving_poisson_stream_smoke():
+@pytest.mark.parametrize("mode", ["tick", "async"])
+def test_serving_poisson_stream_smoke(mode):
     _torch()
     from paper_2112_10526_amd.serving import requests_from_stream
     reqs = requests_from_stream(8, seed=5, rate=200.0, n_steps=3, L_range=(4, 8),
                                 samples=(1024, 2048))
-    out = _serve(reqs, 2 << 30)
+    out = _serve(reqs, 2 << 30, mode=mode)
     assert out["sr_steps"] == 24
     assert out["p99_step_ms"] >= out["p50_step_ms"] > 0
     for r in out["results"].values():
@@ -217,3 +221,34 @@ def test_tfim2d_full_size_sr_direction_bf16():
           f"|d| {np.linalg.norm(dd):.3e} |g - f| {np.linalg.norm(g - f):.3e}")
     assert res <= bound
     assert bound < 0.05 * np.linalg.norm(f)  # informative: far below |f|
+
+
+def test_async_step_same_as_vmc_step():
+    """nqs_step_begin / nqs_step_poll give the same step as nqs_vmc_step (twin
+    states, same seeds), and a second begin while a step is in flight, or a
+    fused step on that context, is refused with NQS_ESTATE."""
+    torch = _torch()
+    from paper_2112_10526_amd import _lib
+    from paper_2112_10526_amd.nqs import NqsError, VMCState, step_begin, step_poll
+    w = synth.WORKLOADS["tfim2d_l10"].replace(n_chains=256, sigma=0.05)
+    a = VMCState.from_workload(w, precision="bf16")
+    b = VMCState.from_workload(w, precision="bf16")
+    cfg = dict(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    for _ in range(3):
+        ra = a.vmc_step(**{"diag_shift": w.diag_shift, "lr": w.lr, "tol": w.cg_tol})
+        step_begin(b, cfg)
+        with pytest.raises(NqsError) as e:
+            step_begin(b, cfg)
+        assert e.value.status == _lib.NQS_ESTATE
+        with pytest.raises(NqsError):
+            b.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        done = {}
+        while not done:
+            done = step_poll([b], wait=True)
+        rb = done[0]
+        assert rb.energy["mean"] == ra.energy["mean"]
+        assert rb.sr.iterations == ra.sr.iterations
+        np.testing.assert_array_equal(b.get_params(), a.get_params())
+    assert step_poll([a, b], wait=True) == {}  # nothing in flight
+    a.close()
+    b.close()

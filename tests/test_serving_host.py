@@ -1,6 +1,7 @@
 """Host logic of the continuous-batching server (no GPU): admission by HBM
 footprint in arrival order, slot limits, freeing on completion, rejection of
-runs that can never fit."""
+runs that can never fit; in both serving modes (lock-step ticks, and
+asynchronous steps where runs of different step lengths finish out of order)."""
 import types
 
 import pytest
@@ -44,17 +45,40 @@ def fake_step(states, cfgs):
     return out
 
 
-def make_server(budget, slots, sizes):
+def fake_begin(state, cfg):
+    assert state.bound and not getattr(state, "inflight", False)
+    state.inflight = True
+    state.left = 1 + state.req.id % 3  # polls until this step ends (runs differ)
+
+
+def fake_poll(states, wait):
+    assert any(getattr(s, "inflight", False) for s in states)
+    out = {}
+    while not out:
+        for k, s in enumerate(states):
+            if getattr(s, "inflight", False):
+                s.left -= 1
+                if s.left == 0:
+                    s.inflight = False
+                    out[k] = types.SimpleNamespace(energy=dict(mean=-float(s.req.id)),
+                                                   sr=types.SimpleNamespace(iterations=3))
+        if not wait:
+            break
+    return out
+
+
+def make_server(budget, slots, sizes, mode="tick"):
     FakeState.live = FakeState.peak = 0
     return Server(budget, max_slots=slots, streams=[None, None],
                   state_factory=lambda req, stream: FakeState(req, sizes[req.id]),
-                  step_fn=fake_step)
+                  step_fn=fake_step, begin_fn=fake_begin, poll_fn=fake_poll, mode=mode)
 
 
-def test_admission_respects_budget_and_order():
+@pytest.mark.parametrize("mode", ["tick", "async"])
+def test_admission_respects_budget_and_order(mode):
     reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=2 + k % 3) for k in range(12)]
     sizes = {k: 100 + 10 * k for k in range(12)}
-    srv = make_server(budget=400, slots=8, sizes=sizes)
+    srv = make_server(budget=400, slots=8, sizes=sizes, mode=mode)
     out = srv.serve(reqs, realtime=False)
     assert FakeState.peak <= 400
     assert FakeState.live == 0
@@ -65,10 +89,11 @@ def test_admission_respects_budget_and_order():
     assert out["sr_steps"] == sum(r.n_steps for r in reqs)
 
 
-def test_slot_limit_and_rejection():
+@pytest.mark.parametrize("mode", ["tick", "async"])
+def test_slot_limit_and_rejection(mode):
     reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=3) for k in range(6)]
     sizes = {0: 10, 1: 10, 2: 10_000, 3: 10, 4: 10, 5: 10}
-    srv = make_server(budget=1000, slots=2, sizes=sizes)
+    srv = make_server(budget=1000, slots=2, sizes=sizes, mode=mode)
     out = srv.serve(reqs, realtime=False)
     res = out["results"]
     assert res[2].error is not None and not res[2].energies
@@ -76,12 +101,13 @@ def test_slot_limit_and_rejection():
         assert len(res[k].energies) == 3
     # never more than two resident runs: each tick steps at most two runs
     assert out["ticks"] >= 3 * 5 / 2
+    assert out["mean_resident"] <= 2
 
 
 def test_residency_and_latency_figures():
     # three runs present at the start, two slots: ticks advance 2, 2, 1 runs
     reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=2) for k in range(3)]
-    srv = make_server(budget=1000, slots=2, sizes={k: 10 for k in range(3)})
+    srv = make_server(budget=1000, slots=2, sizes={k: 10 for k in range(3)}, mode="tick")
     t = iter(range(10_000))
     out = srv.serve(reqs, clock=lambda: float(next(t)), realtime=False)
     assert out["sr_steps"] == 6
@@ -89,3 +115,17 @@ def test_residency_and_latency_figures():
     assert out["queue_delay_ms_p50"] >= 0 and out["queue_delay_ms_p99"] >= out["queue_delay_ms_p50"]
     assert out["run_latency_ms_p99"] >= out["run_latency_ms_p50"] > 0
     assert out["local_energies_per_busy_s"] >= out["local_energies_per_s"] > 0
+
+
+def test_async_runs_finish_out_of_order_and_refill_slots():
+    # run 0 takes one poll per step, run 1 two, run 2 three: with two slots the
+    # short run finishes first and run 2 takes its slot while run 1 is mid-step
+    reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=2) for k in range(3)]
+    srv = make_server(budget=1000, slots=2, sizes={k: 10 for k in range(3)}, mode="async")
+    t = iter(range(10_000))
+    out = srv.serve(reqs, clock=lambda: float(next(t)), realtime=False)
+    res = out["results"]
+    assert all(len(r.energies) == 2 for r in res.values())
+    assert res[0].finished < res[1].finished
+    assert res[2].admitted < res[1].finished  # admitted before run 1 was done
+    assert FakeState.live == 0 and FakeState.peak <= 20
