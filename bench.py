@@ -601,6 +601,48 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
                 distinct_shapes=len(mix), passes=passes, data="synthetic")
 
 
+def paper_workload_measure(torch, steps=10, warmup=2):
+    """The workload closest to the one timed in the paper's comparison with jVMC (1D
+    TFIM, L = 64, J = h = 1, periodic; RBM alpha = 1; 2^14 samples from 2^10 chains;
+    dense Jacobian QGT with CG), with this library's real RBM (4,224 real parameters,
+    where the paper's is complex) and 64 proposals between samples: full SR steps
+    (sampling, local energies, gradient, QGT solve, update) with the dense and the
+    on-the-fly QGT, FP64 path and BF16 form.  Context only: the model, precision and
+    solver settings differ from the paper's."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.Workload("tfim1d_n64", "tfim", "chain", 64, 1.0, 1.0, 1, 1024, 16, 64, "local",
+                       "fp64")
+    runs = {}
+    for prec in ("fp64", "bf16"):
+        for qgt in ("jacobian_dense", "onthefly"):
+            st = VMCState.from_workload(w, precision=prec, qgt=qgt)
+            st.thermalize(w.thermalize_segments)
+            for _ in range(warmup):
+                st.vmc_step(qgt=qgt, diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters = []
+            for _ in range(steps):
+                rep = st.vmc_step(qgt=qgt, diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+                iters.append(rep.sr.iterations)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            runs[f"{prec}_{qgt}"] = dict(s_per_step=el, local_energies_per_s=w.n_samples / el,
+                                         cg_iters_mean=float(np.mean(iters)))
+            st.close()
+            print(f"[bench] paper workload {prec} {qgt}: {el * 1e3:.2f} ms/step", file=sys.stderr,
+                  flush=True)
+    return dict(metric="seconds per VMC step, workload closest to the paper's timed one",
+                workload="tfim1d_n64: 1D TFIM L=64 periodic J=h=1, real RBM alpha=1 (4,224 "
+                         "parameters), 1024 chains x 16 samples, 64 proposals per sample, SR CG "
+                         "tol 1e-6 shift 0.01",
+                steps=steps, warmup=warmup, runs=runs,
+                paper_context=dict(s_per_step=3.9, hardware="1x NVIDIA RTX 3090",
+                                   model="complex RBM alpha=1, QGTJacobianDense(holomorphic) + CG",
+                                   local_energies_per_s=16384 / 3.9),
+                data="synthetic")
+
+
 def cpu_baseline(w, n_chains=256, steps=2):
     """The oracle (plain FP64 CPU code) on a bounded sample of the workload:
     the first `n_chains` chains, one full SR step each time."""
@@ -638,6 +680,8 @@ def main():
                     help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
     ap.add_argument("--precision-form", action="store_true",
                     help="measure the BF16 form against FP64 on the 16x16 Heisenberg workload")
+    ap.add_argument("--paper-workload", action="store_true",
+                    help="time full SR steps on the workload closest to the paper's timed one")
     ap.add_argument("--serve", action="store_true",
                     help="measure the continuous-batching server on a Poisson stream of runs")
     ap.add_argument("--serve-runs", type=int, default=256)
@@ -684,6 +728,9 @@ def main():
         return
     if args.serve:
         print(json.dumps(serve_measure(torch, args.serve_runs, args.serve_steps)), flush=True)
+        return
+    if args.paper_workload:
+        print(json.dumps(paper_workload_measure(torch)), flush=True)
         return
     w = synth.WORKLOADS["tfim2d_l10"]
     if args.copy_probe_mib:
