@@ -712,7 +712,7 @@ def main():
         summarize_traffic(fd, wd, cls, args.precision, int(mib), (c1, c2))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this library has "
               "no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
