@@ -184,14 +184,16 @@ def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
     print(path)
 
 
-def summarize_waves(counter_dir, cmd):
+def summarize_waves(counter_dir, cmd,
+                    title="Wave-state counters of the hot-path kernels (10x10 TFIM workload, "
+                          "BF16 form)"):
     """Markdown table of the wave-state counters (SQ_*) of the BF16 hot-path kernels."""
     rows = _counter_rows(counter_dir)
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
         agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    out = ["# Wave-state counters of the hot-path kernels (10x10 TFIM workload, BF16 form)", "",
+    out = [f"# {title}", "",
            "Command:", "", "    " + cmd, "",
            "Median over the dispatches of one kernel (dispatches that return at once after a "
            "CG solve has stopped are left out); WAVE_CYCLES, WAIT_* and ACTIVE_* are summed "
@@ -199,7 +201,8 @@ def summarize_waves(counter_dir, cmd):
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
     for name in ["nqs::k_w6", "nqs::k_outer7", "nqs::k_update4<float>",
-                 "nqs::k_sample<float, 4, 0, 2>", "nqs::k_eloc<float, 0>", "nqs::k_theta_bf16"]:
+                 "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
+                 "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16"]:
         if name not in agg:
             continue
         d = agg[name]
@@ -692,7 +695,7 @@ def main():
                     help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--summarize-mfma", nargs=3, metavar=("COUNTER_DIR", "CMD", "TITLE"),
                     help="print a markdown table of matrix-core counters and exit")
-    ap.add_argument("--summarize-waves", nargs=2, metavar=("COUNTER_DIR", "CMD"),
+    ap.add_argument("--summarize-waves", nargs="+", metavar="COUNTER_DIR CMD [TITLE]",
                     help="print a markdown table of SQ wave-state counters and exit")
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_DIR", "WRITE_DIR", "CLASS", "COPY_MIB", "FETCH_CMD", "WRITE_CMD"),
