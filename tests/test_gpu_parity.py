@@ -418,6 +418,28 @@ def test_vmc_steps_track_oracle_fp64():
         assert np.abs(st.get_params() - rbm.params).max() <= 1e-9
 
 
+def test_vmc_steps_track_oracle_heisenberg_exchange_fp64():
+    """Three whole steps of the Heisenberg chain (N = 10, Marshall-rotated, zero
+    magnetisation, exchange moves over the bonds): chains bit-exact, energies within
+    1e-10 and parameters within 1e-9 of the oracle's steps."""
+    w = HEIS1D.replace(L=10, alpha=2, n_chains=32, samples_per_chain=8, sweep_size=10,
+                       sigma=0.05)
+    st, w = make_state(w, precision="fp64")
+    rbm, ham = oracle_model(w, w.params())
+    ch = st.get_chains()
+    assert (ch.astype(int).sum(axis=1) == 0).all()
+    prop = 0
+    for step in range(3):
+        rep = st.vmc_step(diag_shift=w.diag_shift, lr=0.02, tol=1e-10, maxiter=2000)
+        rbm, ch, orep = core.vmc_step(rbm, ham, ch, w.samples_per_chain, w.sweep_size,
+                                      w.chain_seed, prop, "exchange", w.diag_shift, 0.02, 1e-10,
+                                      2000)
+        prop += w.samples_per_chain * w.sweep_size
+        np.testing.assert_array_equal(st.get_chains(), ch)
+        assert abs(rep.energy["mean"] - orep.energy["mean"]) <= 1e-10 * abs(orep.energy["mean"])
+        assert np.abs(st.get_params() - rbm.params).max() <= 1e-9
+
+
 @pytest.mark.parametrize("precision", ["fp64", "bf16"])
 def test_vmc_converges_tfim_chain_gpu(precision):
     """SR from small random parameters reaches the exact ground energy of the
