@@ -579,18 +579,27 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
     base = [dataclasses.replace(r, arrival=0.0)
             for r in requests_from_stream(n_runs, seed, 1.0, n_steps=n_steps)]
     passes = {}
-    serial = Server(budget, max_slots=1).serve(base, realtime=False)
+    last = [time.perf_counter()]
+
+    def progress(done, total, steps):  # a line every 20 s during long passes
+        now = time.perf_counter()
+        if now - last[0] >= 20.0:
+            last[0] = now
+            print(f"[bench] serving: {done}/{total} runs finished, {steps} SR steps",
+                  file=sys.stderr, flush=True)
+    serial = Server(budget, max_slots=1).serve(base, realtime=False, progress=progress)
     passes["one_at_a_time"] = summary(serial)
     print(f"[bench] serving one at a time: {serial['wall_s']:.2f} s", file=sys.stderr, flush=True)
     mu = n_runs / serial["wall_s"]
     for mode in ("tick", "async"):
-        cap = Server(budget, max_slots=slots, mode=mode).serve(base, realtime=False)
+        cap = Server(budget, max_slots=slots, mode=mode).serve(base, realtime=False,
+                                                               progress=progress)
         passes[f"all_present_{mode}"] = summary(cap)
         print(f"[bench] serving all present, {mode}: {cap['wall_s']:.2f} s", file=sys.stderr,
               flush=True)
     for rho in loads:
         reqs = requests_from_stream(n_runs, seed, rho * mu, n_steps=n_steps)
-        out = Server(budget, max_slots=slots).serve(reqs, realtime=True)
+        out = Server(budget, max_slots=slots).serve(reqs, realtime=True, progress=progress)
         passes[f"poisson_rho_{rho}"] = dict(summary(out), offered_rate_runs_per_s=rho * mu)
         print(f"[bench] serving rho={rho}: {out['wall_s']:.2f} s", file=sys.stderr, flush=True)
     mix = collections.Counter((r.L, r.alpha) for r in base)

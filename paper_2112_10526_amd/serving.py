@@ -98,9 +98,11 @@ class Server:
         return VMCState.from_workload(w, stream=stream, device=self.device, allocate=False)
 
     def serve(self, requests: List[Request], clock: Callable[[], float] = time.perf_counter,
-              realtime: bool = True) -> dict:
+              realtime: bool = True, progress: Optional[Callable[[int, int, int], None]] = None
+              ) -> dict:
         """Serve every request; with realtime=False arrival times are ignored
-        (all requests are present at the start)."""
+        (all requests are present at the start).  progress, if given, is called
+        after every tick with (runs finished, runs in total, SR steps done)."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.id))
         results = {r.id: RunResult(r.id, r.arrival) for r in requests}
         active = []  # [request, state, footprint, steps done, step start or None]
@@ -150,6 +152,9 @@ class Server:
                     self._used -= x[2]
                     res.finished = clock() - t0
             active[:] = [x for x in active if x[3] < x[0].n_steps]
+            if progress is not None:
+                progress(sum(1 for r in results.values() if r.finished is not None),
+                         len(requests), sum(len(r.energies) for r in results.values()))
         total = clock() - t0
         lat = np.array([x for r in results.values() for x in r.step_latency])
         done = [r for r in results.values() if r.admitted is not None]

@@ -109,8 +109,11 @@ def test_residency_and_latency_figures():
     reqs = [Request(k, 0.0, 4, 1.0, 1, 1024, n_steps=2) for k in range(3)]
     srv = make_server(budget=1000, slots=2, sizes={k: 10 for k in range(3)}, mode="tick")
     t = iter(range(10_000))
-    out = srv.serve(reqs, clock=lambda: float(next(t)), realtime=False)
+    calls = []
+    out = srv.serve(reqs, clock=lambda: float(next(t)), realtime=False,
+                    progress=lambda *a: calls.append(a))
     assert out["sr_steps"] == 6
+    assert len(calls) == out["ticks"] and calls[-1] == (3, 3, 6)
     assert out["mean_resident"] == pytest.approx(6 / out["ticks"])
     assert out["queue_delay_ms_p50"] >= 0 and out["queue_delay_ms_p99"] >= out["queue_delay_ms_p50"]
     assert out["run_latency_ms_p99"] >= out["run_latency_ms_p50"] > 0
