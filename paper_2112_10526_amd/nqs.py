@@ -319,7 +319,9 @@ def step_poll(states: Sequence[VMCState], wait: bool = True) -> dict:
     ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in states])
     reps = (NqsStepReport * n)()
     done = (ctypes.c_int32 * n)()
-    lib.nqs_step_poll(ctxs, n, 1 if wait else 0, reps, done)
+    st = lib.nqs_step_poll(ctxs, n, 1 if wait else 0, reps, done)
+    if st == _lib.NQS_EINVAL and not any(done):
+        raise NqsError(st, "nqs_step_poll: invalid arguments")
     return {k: _step_report(lib, states[k], reps[k]) for k in range(n) if done[k]}
 
 
