@@ -613,6 +613,48 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
                 distinct_shapes=len(mix), passes=passes, data="synthetic")
 
 
+def plain_measure(torch, steps=300, lr=0.05):
+    """The small plain workload: periodic TFIM chain N = 10, J = h = 1, RBM alpha = 1,
+    16 chains x 64 samples, 10 proposals between samples, SR shift 0.01.  SR steps
+    from the N(0, 0.01^2) start (learning rate 0.05), timed one by one; the energy of
+    the last 20 steps is set against the exact ground energy of the periodic chain,
+    E0 = -(2 / sin(pi / 2N)) for J = h = 1 (free-fermion closed form).  At 1024 samples
+    a step is launch-bound, so no roofline figure is given."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.WORKLOADS["tfim1d_n10"]
+    e0 = -2.0 / np.sin(np.pi / (2 * w.n_sites))
+    out = {}
+    for prec in ("fp64", "bf16"):
+        st = VMCState.from_workload(w, precision=prec)
+        st.thermalize(w.thermalize_segments)
+        lat, energies, iters = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter()
+            rep = st.vmc_step(diag_shift=w.diag_shift, lr=lr, tol=w.cg_tol)
+            lat.append(time.perf_counter() - a)
+            energies.append(rep.energy["mean"])
+            iters.append(rep.sr.iterations)
+        el = time.perf_counter() - t0
+        st.close()
+        e_last = float(np.mean(energies[-20:]))
+        lat_ms = np.array(lat) * 1e3
+        out[prec] = dict(ms_per_step=el / steps * 1e3, local_energies_per_s=w.n_samples * steps / el,
+                         p50_ms=float(np.percentile(lat_ms, 50)),
+                         p99_ms=float(np.percentile(lat_ms, 99)),
+                         cg_iters_mean=float(np.mean(iters)), energy_first=energies[0],
+                         energy_last20=e_last, rel_error_vs_exact=abs(e_last - e0) / abs(e0))
+        print(f"[bench] plain {prec}: {out[prec]['ms_per_step']:.2f} ms/step, E = {e_last:.5f}",
+              file=sys.stderr, flush=True)
+    return dict(metric="SR steps on the N=10 TFIM chain: time per step and energy against the "
+                       "exact ground energy",
+                workload="tfim1d_n10: 1D TFIM N=10 periodic J=h=1, real RBM alpha=1 (120 "
+                         "parameters), 16 chains x 64 samples, 10 proposals per sample, SR CG "
+                         f"tol 1e-6 shift 0.01 lr {lr}",
+                steps=steps, exact_ground_energy=e0, runs=out, data="synthetic")
+
+
 def paper_workload_measure(torch, steps=10, warmup=2):
     """The workload closest to the one timed in the paper's comparison with jVMC (1D
     TFIM, L = 64, J = h = 1, periodic; RBM alpha = 1; 2^14 samples from 2^10 chains;
@@ -692,6 +734,8 @@ def main():
                     help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
     ap.add_argument("--precision-form", action="store_true",
                     help="measure the BF16 form against FP64 on the 16x16 Heisenberg workload")
+    ap.add_argument("--plain", action="store_true",
+                    help="SR steps on the N=10 TFIM chain: time and energy against the exact one")
     ap.add_argument("--paper-workload", action="store_true",
                     help="time full SR steps on the workload closest to the paper's timed one")
     ap.add_argument("--serve", action="store_true",
@@ -743,6 +787,9 @@ def main():
         return
     if args.paper_workload:
         print(json.dumps(paper_workload_measure(torch)), flush=True)
+        return
+    if args.plain:
+        print(json.dumps(plain_measure(torch)), flush=True)
         return
     w = synth.WORKLOADS["tfim2d_l10"]
     if args.copy_probe_mib:
