@@ -59,3 +59,16 @@ def test_python_layer_has_no_cpu_fallback():
     from paper_2112_10526_amd.nqs import VMCState
     with pytest.raises(RuntimeError):
         VMCState.from_workload(synth.WORKLOADS["tfim1d_n10"])
+
+
+def test_header_is_plain_c():
+    """The boundary header compiles as C99 (and as C++): plain types only, no C++."""
+    import shutil
+    import subprocess
+    for cc, lang, std in (("gcc", "c", "-std=c99"), ("g++", "c++", "-std=c++17")):
+        exe = shutil.which(cc)
+        if exe is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([exe, "-fsyntax-only", "-Wall", "-Werror", "-x", lang, std, HEADER],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
