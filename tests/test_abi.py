@@ -72,3 +72,39 @@ def test_header_is_plain_c():
         r = subprocess.run([exe, "-fsyntax-only", "-Wall", "-Werror", "-x", lang, std, HEADER],
                            capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_plain_c_program_links_and_calls(tmp_path):
+    """A plain C program includes the header, links libnqs and calls it: without a
+    device, nqs_create returns NQS_EINVAL and leaves the context null; the null-context
+    queries answer as documented."""
+    import shutil
+    import subprocess
+    from paper_2112_10526_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2112_10526_amd import build
+        build.build()
+    src = tmp_path / "main.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "nqs.h"\n'
+        "int main(void) {\n"
+        "    nqs_ctx* ctx = 0;\n"
+        "    int st = nqs_create(&ctx, 0, 0);\n"
+        '    printf("%d %d %s %zu\\n", st, ctx == 0, nqs_last_error(0), nqs_num_params(0));\n'
+        "    return 0;\n}\n")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = tmp_path / "main"
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                        str(src), "-L", libdir, "-lnqs", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    st, null_ctx, msg = r.stdout.split()[:3]
+    # no device visible here: NQS_EINVAL (a GPU box would create the context)
+    if st != "0":
+        assert int(st) == _lib.NQS_EINVAL and null_ctx == "1"
+    assert r.stdout.strip().endswith("null context 0")
