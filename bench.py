@@ -72,241 +72,7 @@ def kernel_work(cls: str, w, precision: str):
     return "hbm", float("nan"), "GB/s", PEAK["hbm"]
 
 
-# kernel class -> (source file of its kernel, symbol prefix in profiles)
-KERNELS = {  # (BF16 form, the benchmark's main run)
-    "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer7"),
-    "reduce": ("qgt.hip", "k_update4<float>"),
-    "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
-    "theta": ("theta.hip", "k_theta_bf16"),
-}
-CSRC = os.path.join(ROOT, "paper_2112_10526_amd", "csrc")
-PROFILES = os.path.join(ROOT, "profiles")
-
-
-def source_digest(cls: str) -> str:
-    """Digest of the sources a kernel class is built from (its file + shared headers)."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("common.h", "kernels.h", KERNELS.get(cls, ("qgt.hip",))[0]):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def traffic_file(cls: str, precision: str) -> str:
-    sym = KERNELS.get(cls, (None, cls))[1].split("<")[0]
-    return os.path.join(PROFILES, f"traffic_{sym}_tfim2d_l10_{precision}.md")
-
-
-def read_traffic(cls: str, precision: str):
-    """HBM bytes per launch from the committed counter summary, or None when it is
-    missing or was taken on other kernel sources."""
-    path = traffic_file(cls, precision)
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                kv[k.strip()] = v.strip().strip("`")
-    if kv.get("source_digest") != source_digest(cls):
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
-def _counter_rows(d):
-    import csv
-    import glob
-    rows = []
-    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-        with open(f) as fh:
-            rows += list(csv.DictReader(fh))
-    if not rows:
-        raise SystemExit(f"no counter_collection.csv under {d}")
-    return rows
-
-
-def _per_dispatch(rows, counter, match):
-    """Mean over dispatches of kernels whose name contains `match` of the counter (summed
-    over its instances within one dispatch).  Dispatches below a tenth of the largest one
-    are left out: they are the CG launches queued after a solve had stopped, which
-    return at once."""
-    per = {}
-    for r in rows:
-        if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
-            continue
-        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
-        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
-    if not per:
-        names = sorted({r.get("Kernel_Name", "")[:80] for r in rows})
-        raise SystemExit(f"no {counter} rows for a kernel matching {match!r}; kernels: {names}")
-    vals = np.array(list(per.values()))
-    vals = vals[vals >= 0.1 * vals.max()]
-    return float(vals.mean()), len(vals)
-
-
-def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
-    """Write the traffic summary of one kernel class from two counter runs (FETCH_SIZE,
-    WRITE_SIZE; KiB per dispatch), each scaled by the same counter on a plain copy of
-    copy_mib MiB (torch's elementwise multiply by 1: one read, one write)."""
-    sym = KERNELS[cls][1]
-    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
-    copy_bytes = copy_mib * 2.0 ** 20
-    cf, _ = _per_dispatch(fr, "FETCH_SIZE", "MulFunctor")
-    cw, _ = _per_dispatch(wr, "WRITE_SIZE", "MulFunctor")
-    kf, nf = _per_dispatch(fr, "FETCH_SIZE", sym)
-    kw, nw = _per_dispatch(wr, "WRITE_SIZE", sym)
-    f_scale, w_scale = copy_bytes / cf, copy_bytes / cw
-    fetch_b, write_b = kf * f_scale, kw * w_scale
-    lines = [
-        f"# HBM traffic of `{sym}` (10x10 TFIM workload, {precision})", "",
-        "Two rocprofv3 counter runs of the same command, one counter each:", "",
-        f"    {cmds[0]}", f"    {cmds[1]}", "",
-        f"Counters are KiB per dispatch; each is scaled by what it reads for a plain copy of "
-        f"{copy_mib} MiB (torch elementwise multiply by 1, one read and one write) run in the "
-        f"same process.", "",
-        f"- kernel_class: {cls}",
-        f"- source_digest: `{source_digest(cls)}`",
-        f"- copy_fetch_kib: {cf:.1f}", f"- copy_write_kib: {cw:.1f}",
-        f"- fetch_scale: {f_scale:.4f}", f"- write_scale: {w_scale:.4f}",
-        f"- dispatches counted: {nf} (fetch run), {nw} (write run)",
-        f"- fetch_kib_per_launch: {kf:.1f}", f"- write_kib_per_launch: {kw:.1f}",
-        f"- fetch_bytes_per_launch: {fetch_b:.0f}", f"- write_bytes_per_launch: {write_b:.0f}",
-        f"- hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
-    ]
-    path = traffic_file(cls, precision)
-    with open(path, "w") as fh:
-        fh.write("\n".join(lines) + "\n")
-    print(path)
-
-
-def summarize_waves(counter_dir, cmd,
-                    title="Wave-state counters of the hot-path kernels (10x10 TFIM workload, "
-                          "BF16 form)"):
-    """Markdown table of the wave-state counters (SQ_*) of the BF16 hot-path kernels."""
-    rows = _counter_rows(counter_dir)
-    agg = collections.defaultdict(lambda: collections.defaultdict(list))
-    for r in rows:
-        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    out = [f"# {title}", "",
-           "Command:", "", "    " + cmd, "",
-           "Median over the dispatches of one kernel (dispatches that return at once after a "
-           "CG solve has stopped are left out); WAVE_CYCLES, WAIT_* and ACTIVE_* are summed "
-           "over waves.", "",
-           "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
-           "|---|---:|---:|---:|---:|---:|"]
-    for name in ["nqs::k_w6", "nqs::k_outer7", "nqs::k_update4<float>",
-                 "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
-                 "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16"]:
-        if name not in agg:
-            continue
-        d = agg[name]
-        wc = np.array(d["SQ_WAVE_CYCLES"])
-        keep = wc >= 0.1 * wc.max()
-        med = {k: float(np.median(np.array(v)[keep])) for k, v in d.items() if len(v) == len(wc)}
-        w = med["SQ_WAVE_CYCLES"]
-        out.append(f"| `{name}` | {med['SQ_WAVES']:.0f} | {w / med['SQ_WAVES']:.0f} | "
-                   f"{100 * med['SQ_WAIT_ANY'] / w:.0f} | {100 * med['SQ_WAIT_INST_ANY'] / w:.0f} | "
-                   f"{100 * med['SQ_ACTIVE_INST_ANY'] / w:.0f} |")
-    print("\n".join(out))
-
-
-MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
-                 "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES",
-                 "GRBM_GUI_ACTIVE")
-
-
-def summarize_mfma(counter_dir, cmd, title, n_cu=256, n_xcd=8):
-    """Markdown table of matrix-core counters per kernel: MFMA operations (the MOPS
-    counters count flops / 512), matrix-core busy cycles and their share of the
-    kernel's GPU-active cycles over all SIMDs,
-    util = SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) / (GRBM_GUI_ACTIVE / XCDs x CUs x 4):
-    rocprofv3 reports GRBM_GUI_ACTIVE summed over the eight XCDs, each of which counts the
-    kernel's active cycles (eight times 188 ms at the 2.4 GHz clock for a 188 ms kernel)."""
-    rows = _counter_rows(counter_dir)
-    per = collections.defaultdict(lambda: collections.defaultdict(float))
-    names = {}
-    for r in rows:
-        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
-        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        names[key] = name
-        per[key][r["Counter_Name"]] += float(r["Counter_Value"])
-    agg = collections.defaultdict(list)
-    for key, c in per.items():
-        mops = sum(c.get(k, 0.0) for k in MFMA_COUNTERS[:3])
-        if mops > 0:
-            agg[names[key]].append(c)
-    out = [f"# {title}", "", "Command:", "", "    " + cmd, "",
-           "Per kernel, median over its dispatches that issued matrix-core work (CG launches "
-           "queued after a solve stopped are left out: under a tenth of the largest). "
-           "`flop` = MOPS x 512 (the MOPS counters count operations / 512); "
-           f"`MFMA busy %` = SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) / (GRBM_GUI_ACTIVE "
-           f"/ {n_xcd} x {n_cu} CUs x 4 SIMDs): GRBM_GUI_ACTIVE comes summed over the "
-           f"{n_xcd} XCDs, each counting the kernel's active cycles.", "",
-           "| kernel | dispatches | flop (BF16) | flop (FP32) | flop (FP64) | MFMA busy cycles | "
-           "GUI active cycles | MFMA busy % |",
-           "|---|---:|---:|---:|---:|---:|---:|---:|"]
-    for name in sorted(agg, key=lambda k: -np.median([c["SQ_VALU_MFMA_BUSY_CYCLES"]
-                                                       for c in agg[k]])):
-        cs = agg[name]
-        tot = np.array([sum(c.get(k, 0.0) for k in MFMA_COUNTERS[:3]) for c in cs])
-        keep = tot >= 0.1 * tot.max()
-        cs = [c for c, k in zip(cs, keep) if k]
-        med = {k: float(np.median([c.get(k, 0.0) for c in cs])) for k in MFMA_COUNTERS}
-        util = med["SQ_VALU_MFMA_BUSY_CYCLES"] / max(med["GRBM_GUI_ACTIVE"] / n_xcd * n_cu * 4, 1.0)
-        out.append(f"| `{name}` | {len(cs)} | {512 * med['SQ_INSTS_VALU_MFMA_MOPS_BF16']:.4g} | "
-                   f"{512 * med['SQ_INSTS_VALU_MFMA_MOPS_F32']:.4g} | "
-                   f"{512 * med['SQ_INSTS_VALU_MFMA_MOPS_F64']:.4g} | "
-                   f"{med['SQ_VALU_MFMA_BUSY_CYCLES']:.4g} | {med['GRBM_GUI_ACTIVE']:.4g} | "
-                   f"{100 * util:.1f} |")
-    print("\n".join(out))
-
-
-def _full_launch_medians(trace_csv):
-    """Per kernel: median duration (us) and count of the launches that did the work.
-    CG kernels queued after the solve has stopped return at once; launches shorter
-    than 30 % of the kernel's 90th-percentile duration are left out."""
-    import csv
-    durs = collections.defaultdict(list)
-    with open(trace_csv) as fh:
-        for r in csv.DictReader(fh):
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
-            durs[name].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    out = {}
-    for name, v in durs.items():
-        a = np.array(v)
-        full = a[a >= 0.3 * np.percentile(a, 90)]
-        out[name] = (float(np.median(full)), len(full))
-    return out
-
-
-def summarize_stats(stats_csv, cmd, title):
-    """Markdown table of a rocprofv3 kernel_stats.csv (with the median of the full
-    launches from the kernel_trace.csv beside it, when present)."""
-    import csv
-    with open(stats_csv) as fh:
-        rows = list(csv.DictReader(fh))
-    trace = stats_csv.replace("kernel_stats.csv", "kernel_trace.csv")
-    med = _full_launch_medians(trace) if os.path.exists(trace) else {}
-    out = [f"# {title}", "", "Command:", "", f"    {cmd}", "",
-           "`full med us`: median duration of the launches that did the work (CG kernels "
-           "queued after a solve has stopped return at once; launches under 30 % of the "
-           "kernel's 90th-percentile duration are left out), over `full` launches.", "",
-           "| kernel | calls | avg us | min us | max us | total ms | % | full | full med us |",
-           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
-    for r in rows:
-        name = r["Name"].split("(")[0].replace("void ", "")
-        m, c = med.get(name, (float("nan"), 0))
-        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
-                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} | "
-                   f"{c} | {m:.2f} |")
-    print("\n".join(out))
+from paper_2112_10526_amd.rocprof_summary import read_traffic  # noqa: E402
 
 
 def make(w, precision):
@@ -355,7 +121,26 @@ def stage_rooflines(w, precision, prof):
     return out
 
 
-def run_precision(w, precision, steps, warmup, torch):
+def trajectory(w, warmup, lat, iters, settle=20):
+    """Where on the optimisation trajectory the timed steps lie.  The CG iteration
+    count, and with it the step time, grows as the parameters move away from their
+    start, so the rate is given for the timed steps within the first `settle` SR
+    steps from the initial parameters ("init") and for those after them ("steady")."""
+    idx = np.arange(len(lat)) + warmup + 1  # SR step number of each timed step
+    out = dict(timed_sr_steps=[int(idx[0]), int(idx[-1])] if len(idx) else None,
+               settle_steps=settle)
+    for name, sel in (("init", idx <= settle), ("steady", idx > settle)):
+        if sel.any():
+            t = float(np.sum(np.asarray(lat)[sel]))
+            out[name] = dict(steps=int(sel.sum()), local_energies_per_s=w.n_samples * sel.sum() / t,
+                             ms_per_step=t / sel.sum() * 1e3,
+                             cg_iters_mean=float(np.mean(np.asarray(iters)[sel])))
+        else:
+            out[name] = None
+    return out
+
+
+def run_precision(w, precision, steps, warmup, torch, step_log=None):
     st = make(w, precision)
     # warm-up steps, profiled in full to find the dominant kernel class
     st.profile_enable(None)
@@ -365,6 +150,8 @@ def run_precision(w, precision, steps, warmup, torch):
     dominant = max(prof, key=lambda k: prof[k]["ms"])
     # timed region: no event timing, CG batches replayed from graphs
     st.profile_enable([])
+    if step_log:
+        st.open_step_log(step_log)
     lat, iters, acc, energies = [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -377,6 +164,8 @@ def run_precision(w, precision, steps, warmup, torch):
         energies.append(rep.energy["mean"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if step_log:
+        st.close_step_log()
     # the same number of steps again with every launch of the dominant kernel
     # class bracketed by HIP events on its stream (launched one by one)
     st.profile_enable([dominant])
@@ -406,6 +195,7 @@ def run_precision(w, precision, steps, warmup, torch):
         cg_iters_mean=float(np.mean(iters)),
         acceptance_mean=float(np.mean(acc)),
         energy_first=energies[0], energy_last=energies[-1],
+        trajectory=trajectory(w, warmup, lat, iters),
         stage_local_energies_per_s=w.n_samples / (stage_ms * 1e-3) if stage_ms > 0 else None,
         warmup_profile_ms={k: round(v["ms"] / max(warmup, 1), 4) for k, v in prof.items()
                            if v["launches"]},
@@ -697,29 +487,51 @@ def paper_workload_measure(torch, steps=10, warmup=2):
                 data="synthetic")
 
 
-def cpu_baseline(w, n_chains=256, steps=2):
-    """The oracle (plain FP64 CPU code) on a bounded sample of the workload:
-    the first `n_chains` chains, one full SR step each time."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, n_chains=1024, steps=5):
+    """The oracle (plain FP64 CPU code, OpenMP over all host threads) on a bounded
+    sample of the workload: the first `n_chains` of its chains (a quarter of the
+    batch), thermalised, then one untimed warm-up SR step and `steps` timed full SR
+    steps (sampling, local energies, Jacobian, force, CG solve, update); median and
+    minimum of the timed steps, as the paper times its own runs."""
     from oracle import core
     rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
     ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
     ch = core.init_chains(w.n_sites, n_chains, w.chain_seed)
     th = core.sample(rbm, ch, 1, 10 * w.sweep_size, w.chain_seed, 0, mode="cached")
     ch, prop = th.chains, 10 * w.sweep_size
-    times = []
-    for _ in range(steps):
+    times, iters = [], []
+    for k in range(steps + 1):
         t0 = time.perf_counter()
         rbm, ch, rep = core.vmc_step(rbm, ham, ch, w.samples_per_chain, w.sweep_size,
                                      w.chain_seed, prop, "local", w.diag_shift, w.lr, w.cg_tol)
-        times.append(time.perf_counter() - t0)
+        dt = time.perf_counter() - t0
         prop += w.samples_per_chain * w.sweep_size
+        if k > 0:  # the first step is the warm-up
+            times.append(dt)
+            iters.append(rep.cg_iters)
     n = n_chains * w.samples_per_chain
-    return dict(value=n / float(np.median(times)), unit="local energies/s",
-                cores=core.num_threads(), kind="oracle",
-                sample=(f"{n_chains} of 4096 chains x {w.samples_per_chain} samples "
-                        f"({n} local energies) of the same 10x10 workload, full SR step "
-                        f"(sampling, local energies, Jacobian, force, CG), median of {steps}"),
-                seconds_per_step=float(np.median(times)))
+    med, best = float(np.median(times)), float(np.min(times))
+    return dict(value=n / med, unit="local energies/s", cores=core.num_threads(),
+                kind="oracle", cpu_model=cpu_model(),
+                sample=(f"{n_chains} of the {w.n_chains} chains x {w.samples_per_chain} samples "
+                        f"({n} of the {w.n_samples} local energies per SR step) of the same "
+                        f"10x10 workload; 1 warm-up and {steps} timed full SR steps (sampling, "
+                        f"local energies, Jacobian, force, CG, update); value from the median "
+                        f"step, the CG iteration count is that of the smaller batch"),
+                seconds_per_step_median=med, seconds_per_step_min=best,
+                value_from_min=n / best, cg_iters_mean=float(np.mean(iters)))
 
 
 def main():
@@ -730,6 +542,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp64", help="second precision to time ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-log", default="",
+                    help="append one JSON line per timed SR step of the main run to this file")
     ap.add_argument("--dense-qgt", action="store_true",
                     help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
     ap.add_argument("--precision-form", action="store_true",
@@ -744,29 +558,7 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
-    ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "CMD", "TITLE"),
-                    help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
-    ap.add_argument("--summarize-mfma", nargs=3, metavar=("COUNTER_DIR", "CMD", "TITLE"),
-                    help="print a markdown table of matrix-core counters and exit")
-    ap.add_argument("--summarize-waves", nargs="+", metavar="COUNTER_DIR CMD [TITLE]",
-                    help="print a markdown table of SQ wave-state counters and exit")
-    ap.add_argument("--summarize-traffic", nargs=6,
-                    metavar=("FETCH_DIR", "WRITE_DIR", "CLASS", "COPY_MIB", "FETCH_CMD", "WRITE_CMD"),
-                    help="write profiles/traffic_*.md from two counter runs and exit")
     args = ap.parse_args()
-    if args.summarize_stats:
-        summarize_stats(*args.summarize_stats)
-        return
-    if args.summarize_mfma:
-        summarize_mfma(*args.summarize_mfma)
-        return
-    if args.summarize_waves:
-        summarize_waves(*args.summarize_waves)
-        return
-    if args.summarize_traffic:
-        fd, wd, cls, mib, c1, c2 = args.summarize_traffic
-        summarize_traffic(fd, wd, cls, args.precision, int(mib), (c1, c2))
-        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this library has "
               "no multi-GPU path", file=sys.stderr)
@@ -800,7 +592,8 @@ def main():
             torch.mul(src, 1.0, out=dst)  # one read + one write of the buffer
         torch.cuda.synchronize()
         del src, dst
-    main_run = run_precision(w, args.precision, args.steps, args.warmup, torch)
+    main_run = run_precision(w, args.precision, args.steps, args.warmup, torch,
+                             step_log=args.step_log or None)
     print(f"[bench] {args.precision}: {main_run['value']:.4g} local energies/s", file=sys.stderr,
           flush=True)
     cmp_run = None
@@ -832,6 +625,7 @@ def main():
         p99_ms=main_run["p99_ms"],
         stage_local_energies_per_s=main_run["stage_local_energies_per_s"],
         cg_iters_mean=main_run["cg_iters_mean"], acceptance=main_run["acceptance_mean"],
+        trajectory=main_run["trajectory"],
         roofline=roofline, stage_roofline=main_run["stages"], cpu_baseline=cpu,
         compare=cmp_run, detail=main_run,
     )

@@ -137,10 +137,17 @@ int nqs_set_heisenberg(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bo
 
 /* RBM ansatz with n_hidden = alpha * n_sites hidden units (paper, table of
  * models).  visible_bias / hidden_bias switch a and b on or off.  prec
- * selects the arithmetic of the sampler, local energies and QGT products:
- * NQS_FP64 everywhere FP64; NQS_FP32 FP32 with FP64 means and CG inner
- * products; NQS_BF16 the Wσ+b contraction on BF16 MFMA with FP32
- * accumulation (W split into two BF16 terms), the rest as NQS_FP32.
+ * selects the arithmetic:
+ *  - NQS_FP64: FP64 everywhere (theta and the QGT contractions on the FP64
+ *    matrix cores).
+ *  - NQS_FP32: theta on the FP32 matrix cores; FP32 sampler and local
+ *    energies; the on-the-fly QGT contractions and the force take each FP32
+ *    operand as the sum of two BF16 terms on the BF16 matrix cores with FP32
+ *    accumulation (about 2^-17 relative error per product, the accuracy of an
+ *    FP32 product); energy means, variances and every CG inner product and
+ *    scalar in FP64.
+ *  - NQS_BF16: as NQS_FP32, except that the W s + b contraction runs on the
+ *    BF16 matrix cores with FP32 accumulation (W split into two BF16 terms).
  * Requires a Hamiltonian.  Errors: NQS_EINVAL (n_hidden < 1, bad prec),
  * NQS_ESTATE. */
 int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,

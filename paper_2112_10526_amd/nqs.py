@@ -8,6 +8,8 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import json
+import time
 from typing import Optional, Sequence
 
 import numpy as np
@@ -106,7 +108,10 @@ class VMCState:
     def from_workload(cls, w, precision: Optional[str] = None, qgt: str = "onthefly",
                       device: int = 0, stream=None, params=None, n_chains: Optional[int] = None,
                       allocate: bool = True):
-        """Build the state of a ``synth.Workload`` (initial parameters included)."""
+        """Build the state described by ``w`` (initial parameters included): any
+        object with the attributes of ``lattice.RunSpec`` (model, n_sites,
+        bonds(), J, h, sublattice(), n_hidden, precision, rule, n_chains,
+        samples_per_chain, sweep_size, chain_seed, total_sz_zero, params())."""
         return cls(model=w.model, n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
                    sublattice=w.sublattice(), n_hidden=w.n_hidden,
                    precision=precision or w.precision, rule=w.rule,
@@ -123,6 +128,10 @@ class VMCState:
 
     def close(self):
         """Destroy the context and release its workspace."""
+        log = getattr(self, "_step_log", None)
+        if log is not None:
+            log["fh"].close()
+            self._step_log = None
         if getattr(self, "ctx", None):
             self.lib.nqs_destroy(self.ctx)
             self.ctx = None
@@ -253,12 +262,51 @@ class VMCState:
                  tol: float = 1e-6, maxiter: int = 0) -> StepReport:
         cfg = NqsStepCfg(_lib.QGTS[qgt], diag_shift, lr, tol, maxiter)
         rep = NqsStepReport()
+        log = getattr(self, "_step_log", None)
+        if log is not None and log["stages"]:
+            self.profile_enable(None)
+        t0 = time.perf_counter()
         st = self.lib.nqs_vmc_step(self.ctx, ctypes.byref(cfg), ctypes.byref(rep))
+        wall = time.perf_counter() - t0
         if st not in (_lib.NQS_OK, _lib.NQS_ENOTCONV):
             self._check(st)
-        return StepReport(_stats_dict(rep.energy),
-                          SrInfo(rep.sr.iterations, bool(rep.sr.converged), rep.sr.rel_residual),
-                          rep.status)
+        out = StepReport(_stats_dict(rep.energy),
+                         SrInfo(rep.sr.iterations, bool(rep.sr.converged), rep.sr.rel_residual),
+                         rep.status)
+        if log is not None:
+            self._write_step_log(out, wall)
+        return out
+
+    # ------------------------------------------------------------------
+    def open_step_log(self, path: str, stage_times: bool = False) -> None:
+        """Append one JSON line per ``vmc_step`` to ``path``: step number, energy
+        mean / variance / error, acceptance, CG iterations, residual and status,
+        wall time; with ``stage_times`` also every kernel class's event-timed
+        milliseconds in that step (the profiler then launches CG kernels one by
+        one instead of replaying graphs, so those steps run slower)."""
+        self.close_step_log()
+        self._step_log = dict(fh=open(path, "a"), stages=stage_times, step=0)
+
+    def close_step_log(self) -> None:
+        log = getattr(self, "_step_log", None)
+        if log is not None:
+            log["fh"].close()
+            if log["stages"]:
+                self.profile_enable([])
+        self._step_log = None
+
+    def _write_step_log(self, rep: StepReport, wall: float) -> None:
+        log = self._step_log
+        log["step"] += 1
+        rec = dict(step=log["step"], energy=rep.energy["mean"], variance=rep.energy["variance"],
+                   error=rep.energy["error"], acceptance=rep.energy["acceptance"],
+                   cg_iters=rep.sr.iterations, cg_rel_residual=rep.sr.rel_residual,
+                   converged=rep.sr.converged, status=rep.status, wall_ms=wall * 1e3,
+                   n_samples=self.n_samples, precision=self.precision)
+        if log["stages"]:
+            rec["stage_ms"] = {k: v["ms"] for k, v in self.profile_read().items() if v["launches"]}
+        log["fh"].write(json.dumps(rec) + "\n")
+        log["fh"].flush()
 
 
 def _profile_enable(self, classes=None):

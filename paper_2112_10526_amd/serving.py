@@ -28,8 +28,7 @@ from typing import Callable, List, Optional
 import numpy as np
 import torch
 
-import synth
-
+from .lattice import RunSpec
 from .nqs import VMCState, batch_step, step_begin, step_poll
 
 
@@ -46,12 +45,11 @@ class Request:
     chain_seed: int = 2
     samples_per_chain: int = 4
 
-    def workload(self, precision: str) -> synth.Workload:
+    def workload(self, precision: str) -> RunSpec:
         n_chains = max(1, self.n_samples // self.samples_per_chain)
-        return synth.Workload(f"serve{self.id}", "tfim", "square", self.L, 1.0, self.h,
-                              self.alpha, n_chains, self.samples_per_chain, self.L * self.L,
-                              "local", precision, param_seed=self.param_seed,
-                              chain_seed=self.chain_seed)
+        return RunSpec("tfim", "square", self.L, 1.0, self.h, self.alpha, n_chains,
+                       self.samples_per_chain, self.L * self.L, "local", precision,
+                       param_seed=self.param_seed, chain_seed=self.chain_seed)
 
 
 @dataclasses.dataclass
@@ -205,10 +203,25 @@ class Server:
             active.append([req, st, fp, 0, None])
 
 
-def requests_from_stream(n_runs: int, seed: int, rate: float, n_steps: int = 50, **kw) -> List[Request]:
-    """Requests of a seeded Poisson stream (see ``synth.serve_stream``)."""
+def poisson_stream(n_runs: int, seed: int, rate: float, L_range=(4, 20), h_range=(0.5, 4.0),
+                   alphas=(1, 2, 4), samples=(1024, 2048, 4096, 8192, 16384),
+                   n_steps: int = 50) -> List[Request]:
+    """A seeded Poisson stream of run requests: exponential inter-arrival times
+    with mean 1/rate seconds; per run L ~ U{L_range}, h ~ U[h_range], alpha and
+    the number of samples drawn uniformly from the given choices, and its own
+    parameter and chain seeds."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
     out = []
-    for d in synth.serve_stream(n_runs, seed, rate, n_steps=n_steps, **kw):
-        out.append(Request(d["id"], d["arrival"], d["L"], d["h"], d["alpha"], d["n_samples"],
-                           d["n_steps"], d["param_seed"], d["chain_seed"]))
+    for k in range(n_runs):
+        t += rng.exponential(1.0 / rate)
+        L = int(rng.integers(L_range[0], L_range[1] + 1))
+        n_s = int(rng.choice(samples))
+        h = float(rng.uniform(*h_range))
+        alpha = int(rng.choice(alphas))
+        out.append(Request(k, t, L, h, alpha, n_s, n_steps, int(rng.integers(1, 2**31)),
+                           int(rng.integers(1, 2**31))))
     return out
+
+
+requests_from_stream = poisson_stream

@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "chain_bonds", "square_bonds", "chain_sublattice", "square_sublattice",
     "n_params", "rbm_params", "random_configs", "sz0_configs", "Workload",
-    "WORKLOADS", "serve_stream",
+    "WORKLOADS",
 ]
 
 
@@ -168,26 +168,3 @@ WORKLOADS = {
     "heis1d_n64": Workload("heis1d_n64", "heisenberg", "chain", 64, 1.0, 0.0, 8, 4096, 4,
                            64, "exchange", "fp32", marshall=True, total_sz_zero=True),
 }
-
-
-def serve_stream(n_runs: int, seed: int, rate: float, L_range=(4, 20),
-                 h_range=(0.5, 4.0), alphas=(1, 2, 4),
-                 samples=(1024, 2048, 4096, 8192, 16384), n_steps: int = 50):
-    """Poisson stream of VMC run requests for the serving loop.
-
-    Returns a list of dicts with arrival time (seconds from start), lattice side
-    L, field h, alpha, number of samples and SR steps.  Inputs only; nothing
-    of the method is computed here.
-    """
-    rng = np.random.default_rng(seed)
-    t = 0.0
-    runs = []
-    for k in range(n_runs):
-        t += rng.exponential(1.0 / rate)
-        L = int(rng.integers(L_range[0], L_range[1] + 1))
-        n_s = int(rng.choice(samples))
-        runs.append(dict(id=k, arrival=t, L=L, h=float(rng.uniform(*h_range)),
-                         alpha=int(rng.choice(alphas)), n_samples=n_s,
-                         n_steps=n_steps, param_seed=int(rng.integers(1, 2**31)),
-                         chain_seed=int(rng.integers(1, 2**31))))
-    return runs

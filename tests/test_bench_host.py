@@ -14,6 +14,7 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
 import synth  # noqa: E402
+from paper_2112_10526_amd import rocprof_summary  # noqa: E402
 
 
 def test_more_than_one_gpu_is_refused():
@@ -58,7 +59,7 @@ def test_mfma_summary_busy_share(tmp_path, capsys):
                          ("SQ_VALU_MFMA_BUSY_CYCLES", 0.5 * active * 1024),
                          ("SQ_BUSY_CU_CYCLES", active * 256), ("GRBM_GUI_ACTIVE", 8 * active)]]
     _write_counters(str(tmp_path), rows)
-    bench.summarize_mfma(str(tmp_path), "cmd", "title")
+    rocprof_summary.summarize_mfma(str(tmp_path), "cmd", "title")
     out = capsys.readouterr().out
     line = [ln for ln in out.splitlines() if "k_gram" in ln][0]
     cells = [c.strip() for c in line.strip("|").split("|")]
@@ -67,12 +68,12 @@ def test_mfma_summary_busy_share(tmp_path, capsys):
 
 
 def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
-    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
-    path = bench.traffic_file("outer", "bf16")
+    monkeypatch.setattr(rocprof_summary, "PROFILES", str(tmp_path))
+    path = rocprof_summary.traffic_file("outer", "bf16")
     body = "- kernel_class: outer\n- hbm_bytes_per_launch: 12345\n"
     with open(path, "w") as fh:
-        fh.write(body + f"- source_digest: `{bench.source_digest('outer')}`\n")
-    assert bench.read_traffic("outer", "bf16") == 12345.0
+        fh.write(body + f"- source_digest: `{rocprof_summary.source_digest('outer')}`\n")
+    assert rocprof_summary.read_traffic("outer", "bf16") == 12345.0
     with open(path, "w") as fh:
         fh.write(body + "- source_digest: `0000000000000000`\n")
-    assert bench.read_traffic("outer", "bf16") is None
+    assert rocprof_summary.read_traffic("outer", "bf16") is None

@@ -252,3 +252,24 @@ def test_async_step_same_as_vmc_step():
     assert step_poll([a, b], wait=True) == {}  # nothing in flight
     a.close()
     b.close()
+
+
+def test_step_log_lines(tmp_path):
+    """The per-step JSON-lines log: one line per SR step with the step's energy
+    statistics, acceptance and CG figures, and per-stage kernel times on request."""
+    import json
+    _torch()
+    w = synth.WORKLOADS["tfim2d_l10"].replace(n_chains=256, sigma=0.05)
+    st = _state(w, precision="bf16")
+    path = tmp_path / "steps.jsonl"
+    st.open_step_log(str(path), stage_times=True)
+    reps = [st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol) for _ in range(3)]
+    st.close_step_log()
+    st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)  # not logged
+    st.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert [x["step"] for x in lines] == [1, 2, 3]
+    for x, r in zip(lines, reps):
+        assert x["energy"] == r.energy["mean"] and x["cg_iters"] == r.sr.iterations
+        assert x["acceptance"] == r.energy["acceptance"] and x["wall_ms"] > 0
+        assert {"sample", "eloc", "qgt_w", "outer"} <= set(x["stage_ms"])

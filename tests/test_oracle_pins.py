@@ -18,8 +18,10 @@ Pin map (oracle function -> pins):
   jacobian ................. central finite differences of log_psi
   force .................... finite-difference gradient of the exact energy;
                              Monte Carlo estimate within 5 sigma of enumeration
-  qgt_dense / qgt_matvec ... the QGT definition from wave-function derivatives;
-                             W = 0 closed form diag(1 / cosh^2 2a)
+  qgt_dense / qgt_matvec ... numpy.cov (biased) of the log-derivatives; Monte
+                             Carlo estimate on exact draws within 5 sigma of the
+                             enumerated QGT, which is pinned to the QGT
+                             definition from wave-function derivatives
   cg / cholesky_solve ...... numpy.linalg.solve
   sample ................... zero parameters accept every move; detailed
                              balance (chi^2 against |psi|^2); definition and
@@ -353,6 +355,46 @@ def test_qgt_onthefly_equals_dense_and_cg_solves(oracle_lib):
     ref = np.linalg.solve(S + 0.01 * np.eye(S.shape[0]), f)
     np.testing.assert_allclose(x, ref, atol=1e-7 * np.abs(ref).max())
     np.testing.assert_allclose(core.cholesky_solve(S, f, 0.01), ref, atol=1e-9 * np.abs(ref).max())
+
+
+def test_qgt_estimators_are_the_sample_covariance(oracle_lib):
+    """qgt_dense is the biased (1/N_s) sample covariance of the log-derivatives
+    (numpy.cov with bias=True, a library routine), and qgt_matvec applies it."""
+    N, M = 6, 9
+    rbm = core.Rbm(N, M, synth.rbm_params(N, M, 2, sigma=0.3))
+    s = synth.random_configs(257, N, 3)
+    O = core.jacobian(rbm, s)
+    C = np.cov(O.T, bias=True)
+    np.testing.assert_allclose(core.qgt_dense(O), C, rtol=0, atol=1e-13)
+    v = np.random.default_rng(4).normal(size=rbm.n_params)
+    np.testing.assert_allclose(core.qgt_matvec(O, v, 0.03), C @ v + 0.03 * v, rtol=0, atol=1e-12)
+
+
+def test_qgt_monte_carlo_estimate_matches_enumeration(oracle_lib):
+    """The estimator on independent draws from |psi|^2 / Z (drawn by enumeration,
+    so no Markov chain is involved) agrees with the exact QGT of the full sum
+    within 5 standard errors, entry by entry, and so does its product with a
+    vector; dropping the centring or a factor would miss by many errors."""
+    N, M = 8, 8
+    rbm = core.Rbm(N, M, synth.rbm_params(N, M, 6, sigma=0.3))
+    ham = core.Hamiltonian.tfim(N, synth.chain_bonds(N), 1.0, 1.0)
+    es = exact.ExactState(rbm, ham)
+    n = 40000
+    idx = np.random.default_rng(8).choice(es.p.size, size=n, p=es.p)
+    O = core.jacobian(rbm, es.configs[idx])
+    S = core.qgt_dense(O)
+    G = es.qgt()
+    dO = O - O.mean(axis=0)
+    se = np.sqrt(np.einsum("ki,kj->ij", dO ** 2, dO ** 2) / n - S ** 2) / np.sqrt(n)
+    z = np.abs(S - G) / (se + 1e-15)
+    assert (z < 5).mean() > 0.995, np.sort(z.ravel())[-10:]
+    v = np.random.default_rng(9).normal(size=rbm.n_params)
+    Gv = core.qgt_matvec(O, v, 0.0)
+    t = dO @ v
+    se_v = np.sqrt(((dO * t[:, None]) ** 2).mean(axis=0) - Gv ** 2) / np.sqrt(n)
+    assert (np.abs(Gv - G @ v) < 5 * se_v + 1e-12).mean() > 0.99
+    # the uncentred second moment is far outside the errors (the centring matters)
+    assert np.median(np.abs(O.T @ O / n - G) / (se + 1e-15)) > 20
 
 
 def test_cg_stopping_rule(oracle_lib):

@@ -132,3 +132,39 @@ def test_async_runs_finish_out_of_order_and_refill_slots():
     assert res[0].finished < res[1].finished
     assert res[2].admitted < res[1].finished  # admitted before run 1 was done
     assert FakeState.live == 0 and FakeState.peak <= 20
+
+
+def test_package_problem_definitions_match_the_test_inputs():
+    """The library's own bond lists, sublattices and initial parameters (it does
+    not import the test-input module) equal the test inputs' independent ones."""
+    import numpy as np
+
+    import synth
+    from paper_2112_10526_amd import lattice
+    for L in (3, 4, 7, 10, 16):
+        np.testing.assert_array_equal(lattice.square_bonds(L), synth.square_bonds(L))
+        np.testing.assert_array_equal(lattice.square_sublattice(L), synth.square_sublattice(L))
+    for n in (3, 10, 64):
+        np.testing.assert_array_equal(lattice.chain_bonds(n), synth.chain_bonds(n))
+        np.testing.assert_array_equal(lattice.chain_sublattice(n), synth.chain_sublattice(n))
+    np.testing.assert_array_equal(lattice.init_params(100, 200, 1), synth.rbm_params(100, 200, 1))
+
+
+def test_poisson_stream_is_seeded():
+    import numpy as np
+
+    from paper_2112_10526_amd.serving import poisson_stream
+    a = poisson_stream(64, seed=7, rate=10.0, n_steps=5)
+    b = poisson_stream(64, seed=7, rate=10.0, n_steps=5)
+    assert [dataclasses_tuple(r) for r in a] == [dataclasses_tuple(r) for r in b]
+    t = np.array([r.arrival for r in a])
+    assert np.all(np.diff(t) > 0)
+    assert all(4 <= r.L <= 20 and 0.5 <= r.h <= 4.0 and r.alpha in (1, 2, 4) for r in a)
+    # mean inter-arrival time 1 / rate within 5 standard errors
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 0.1) < 5 * 0.1 / np.sqrt(gaps.size)
+
+
+def dataclasses_tuple(r):
+    import dataclasses
+    return dataclasses.astuple(r)
