@@ -197,10 +197,11 @@ size_t layout(nqs_ctx* c, char* base) {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
         b.q.kc = qgt_chunk(c->prec);
-        // FP64: int8 spins; BF16 forms: one bit per spin
-        b.q.Sp = take((size_t)Nsp * d.Kq / (c->prec == 0 ? 1 : 8));
-        b.q.St = (int8_t*)take((size_t)Nsp * d.Kb / (c->prec == 0 ? 1 : 8));
+        // FP64: int8 spins; BF16 forms: one FP4 code per spin
+        b.q.Sp = take(qgt_spin_bytes(d, c->prec, Nsp));
+        b.q.St = (int8_t*)take(qgt_spin_bytes(d, c->prec, Nsp));
         b.q.Th = take(qgt_th_bytes(d, c->prec, Nsp));
+        b.q.Tf = c->prec == 0 ? nullptr : (float*)take(4 * (size_t)Nsp * d.Ma);
         b.q.wpart = (double*)take(8 * (size_t)qgt_nbw(Nsp, c->prec));
         // CG head partials (r.r, r.p, p.p), one set per iteration parity
         b.rrp = (double*)take(8 * 2 * 3 * (size_t)qgt_nbr(d));
@@ -522,7 +523,7 @@ void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
 // With host_flag, the last on-the-fly iteration stores the stop flag there.
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host_flag = nullptr) {
     const Dims& d = c->d;
-    const int nbv = qgt_nbr(d);
+    const int nbv = qgt_nbv(d, c->prec);
     for (int it = 0; it < iters; ++it) {
         if (kind == NQS_QGT_ONTHEFLY) {
             const long k = c->cg_iter;

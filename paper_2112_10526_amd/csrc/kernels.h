@@ -122,9 +122,10 @@ void launch_axpy_update(hipStream_t st, int total, double* x, const double* delt
 
 // qgt.hip: force and on-the-fly QGT products of one SR step, and CG
 struct QgtBatch {
-    void* Sp;        // augmented spins, sample-major: int8 [Nsp][Kq] (FP64) or bits [Nsp][Kq/8]
-    int8_t* St;      // augmented spins, site-major: int8 [Kb][Nsp] (FP64) or bits [Kb][Nsp/8]
+    void* Sp;        // augmented spins, sample-major: int8 [Nsp][Kq] (FP64) or FP4 [Nsp][Kq/2]
+    int8_t* St;      // augmented spins, site-major: int8 [Kb][Nsp] (FP64) or FP4 [Kb][Nsp/2]
     void* Th;        // [Ma][Nsp] t~ hidden-major: double (FP64 path) or float
+    float* Tf;       // BF16 forms: t~ in contraction-1 fragment order (Nsp * Ma floats)
     long Nsp;        // samples padded to a multiple of 512
     int kc;          // samples per contraction-2 chunk (qgt_chunk)
     double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w
@@ -135,7 +136,9 @@ int qgt_nbw(long n, int prec);
 // activation rows to allocate for n samples (whole contraction-1 blocks)
 long qgt_act_rows(long n);
 int qgt_nbu(const Dims& d);
-int qgt_nbr(const Dims& d);   // CG vector blocks (64 entries): head partials per array
+int qgt_nbr(const Dims& d);   // 64-entry blocks of a CG vector (the largest partial count)
+int qgt_nbv(const Dims& d, int prec);  // CG update blocks = head partials per array
+size_t qgt_spin_bytes(const Dims& d, int prec, long Nsp);  // bytes of Sp (and of St)
 int qgt_ksplit(const QgtBatch& q);
 int qgt_chunk(int prec);
 int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per chunk)

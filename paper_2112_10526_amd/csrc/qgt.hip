@@ -11,16 +11,18 @@
 //
 // Once per SR step the batch is laid out for the matrix cores with the
 // contracted (sample or site) index contiguous:
-//   Sp  augmented spins, sample-major (contraction 1, A)
-//   St  augmented spins, site-major   (contraction 2, B)
-//       (int8 on the FP64 path; one bit per spin in the BF16 forms)
+//   Sp  augmented spins, sample-major (contraction 1)
+//   St  augmented spins, site-major   (contraction 2)
+//       (int8 on the FP64 path; in the BF16 forms one FP4 (E2M1) code per
+//       spin, +1 = 0x2, -1 = 0xA, padding 0, so that one conversion
+//       instruction turns two spins into two exact BF16 values)
 //   Th  [Ma][Nsp]       t~ hidden-major (FP64 path: double; BF16 forms: float)
 // FP64 path: v_mfma_f64_16x16x4f64.  FP32/BF16 forms: v_mfma_f32_16x16x32_bf16
 // with FP32 accumulation and spins exact in BF16 (+1 / -1); the real-valued
 // operand is an FP32 quantity split into two BF16 terms (x = hi + lo), each
-// term contracted with the spins: contraction 1 the direction (both terms of
-// r, with the activations applied in FP32 afterwards), contraction 2 the
-// FP32 product t~ z formed while the tile is staged.
+// term contracted with the spins: contraction 1 the CG residual (the update
+// writes it split), contraction 2 the FP32 product t~ z formed while the tile
+// is staged.
 //
 // No kernel here uses atomics or fences: every reduction is a fixed-order
 // sum of per-block partials done by the consumer kernel (each block of the
@@ -43,24 +45,15 @@ __device__ __forceinline__ double bsum256(double v, double* sh) {
     return r;
 }
 
-__device__ __forceinline__ uint16_t bf16_rn(float f) { return f32_to_bf16_bits(f); }
-
-// x ~= hi + lo in BF16
-__device__ __forceinline__ void split2(float x, uint16_t& hi, uint16_t& lo) {
-    hi = bf16_rn(x);
-    lo = bf16_rn(x - bf16_bits_to_f32(hi));
-}
 
 // ---------------------------------------------------------------------------
 // per-step layout kernels
 // ---------------------------------------------------------------------------
-// FP64 path: int8 spins, Sp [Nsp][Kq] and St [Kb][Nsp].
-// BF16 forms: one bit per spin (1 = up, also for the constant column i = N;
-// 0 for padding rows and columns, whose products are zero or discarded):
-// Sp [Nsp][Kq / 8] bytes, bit e of byte b = site 8 b + e;
-// St [Kb][Nsp / 8] bytes, bit e of byte c = sample 8 c + e.
+// FP64 path: int8 spins, Sp [Nsp][Kq] and St [Kb][Nsp] (the constant column
+// i = N holds 1; padding rows and columns 0, whose products are zero or
+// discarded).
 __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s, int N, long n,
-                                                    int Kb, int Kq, long Nsp, int bits,
+                                                    int Kb, int Kq, long Nsp,
                                                     int8_t* __restrict__ Sp,
                                                     int8_t* __restrict__ St) {
     __shared__ int8_t tile[64][68];
@@ -73,60 +66,122 @@ __global__ __launch_bounds__(256) void k_prep_spins(const int8_t* __restrict__ s
         int8_t v = 0;
         if (k < n) v = i < N ? s[k * N + i] : (i == N ? (int8_t)1 : (int8_t)0);
         tile[kl][il] = v;
-        if (!bits && i < Kq) Sp[k * Kq + i] = v;
+        if (i < Kq) Sp[k * Kq + i] = v;
     }
     __syncthreads();
-    if (!bits) {
-        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-            const int il = e >> 6, kl = e & 63;
-            const int i = i0 + il;
-            if (i < Kb) St[(long)i * Nsp + k0 + kl] = tile[kl][il];
-        }
-        return;
-    }
-    for (int e = threadIdx.x; e < 64 * 8; e += 256) {
-        // sample-major byte: sample k0 + (e >> 3), sites i0 + 8 (e & 7) + 0..7
-        {
-            const int kl = e >> 3, b = e & 7;
-            uint32_t v = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v |= (uint32_t)(tile[kl][8 * b + q] > 0) << q;
-            const int i = i0 + 8 * b;
-            if (i < Kq) Sp[(k0 + kl) * (Kq / 8) + i / 8] = (int8_t)v;
-        }
-        // site-major byte: site i0 + (e >> 3), samples k0 + 8 (e & 7) + 0..7
-        {
-            const int il = e >> 3, c = e & 7;
-            uint32_t v = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v |= (uint32_t)(tile[8 * c + q][il] > 0) << q;
-            const int i = i0 + il;
-            if (i < Kb) St[(long)i * (Nsp / 8) + (k0 + 8 * c) / 8] = (int8_t)v;
-        }
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int il = e >> 6, kl = e & 63;
+        const int i = i0 + il;
+        if (i < Kb) St[(long)i * Nsp + k0 + kl] = tile[kl][il];
     }
 }
 
-// 8 spins (bits of the low byte of b; 1 = up) as BF16 +1 / -1, packed as 8
-// halves.  Two equivalent forms; each kernel uses the one that measured
-// faster in it.  Element-wise (contraction 1):
-__device__ __forceinline__ v8s bits_to_bf16(uint32_t b) {
-    v8s r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (short)(0xBF80 ^ (((b >> e) & 1u) << 15));
-    return r;
-}
-// Word form (contraction 2): two halves per 32-bit word, 0x3F80 (+1) with the
-// sign bits taken from the complemented spin byte nb, bit 2q to bit 15 and
-// bit 2q + 1 to bit 31 of word q (two shifted copies of nb, one mask; nb has
-// no bits past 7, so the copies do not reach each other's sign bit).
-__device__ __forceinline__ v8s bits_to_bf16_words(uint32_t b) {
-    const uint32_t nb = ~b & 0xFFu;
+// ---------------------------------------------------------------------------
+// BF16 forms: spins as FP4 (E2M1) codes, two per byte (element 2m in the low
+// nibble of byte m).  Sites are stored in an order that makes each lane's
+// operand run contiguous: within a group of 128 sites, site 32 u + 8 q + e
+// (u, q < 4, e < 8) sits at position 32 q + 8 u + e (bit fields 3-4 and 5-6
+// swapped), so that lane quad q reads the 32 codes of its four k-steps u in
+// one 16-byte load.  In the site-major copy the samples of each 512-sample
+// chunk are ordered the same way: local sample 32 u + 8 q + e (u < 16) sits
+// at position 128 q + 8 u + e.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fp4_code(int s) { return s > 0 ? 0x2u : (s < 0 ? 0xAu : 0u); }
+
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+// 8 FP4 spin codes (one 32-bit word) as 8 BF16 values (+1, -1 or 0), exact
+__device__ __forceinline__ v8bf fp4x8_to_bf16(uint32_t x) {
     uint4 r;
-    r.x = (((nb << 15) | (nb << 30)) & 0x80008000u) | 0x3F803F80u;
-    r.y = (((nb << 13) | (nb << 28)) & 0x80008000u) | 0x3F803F80u;
-    r.z = (((nb << 11) | (nb << 26)) & 0x80008000u) | 0x3F803F80u;
-    r.w = (((nb << 9) | (nb << 24)) & 0x80008000u) | 0x3F803F80u;
-    return __builtin_bit_cast(v8s, r);
+    r.x = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(x, 1.0f, 0));
+    r.y = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(x, 1.0f, 1));
+    r.z = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(x, 1.0f, 2));
+    r.w = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(x, 1.0f, 3));
+    return __builtin_bit_cast(v8bf, r);
+}
+__device__ __forceinline__ uint32_t word_of(const uint4& v, int u) {
+    return u == 0 ? v.x : (u == 1 ? v.y : (u == 2 ? v.z : v.w));
+}
+
+// Two FP32 values as the BF16 pairs hi (round to nearest even) and
+// lo = bf16(x - hi), each packed two to a 32-bit word (element 0 low).
+__device__ __forceinline__ void split_pk(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+    v2bf h;
+    h[0] = (__bf16)x0;
+    h[1] = (__bf16)x1;
+    hi = __builtin_bit_cast(uint32_t, h);
+    v2bf l;
+    l[0] = (__bf16)(x0 - __uint_as_float(hi << 16));
+    l[1] = (__bf16)(x1 - __uint_as_float(hi & 0xFFFF0000u));
+    lo = __builtin_bit_cast(uint32_t, l);
+}
+
+// Contraction-1 operands of the BF16 forms in matrix-core fragment order, so
+// that every load instruction of a wave reads 1 KB of contiguous memory:
+//   residual (two BF16 planes): entry (j, i) of plane h at
+//     ((((j / 16) * (Kq / 128) + i / 128) * 4 + u) * 64 + 16 q + j % 16) * 8 + e,
+//     with i % 128 = 32 u + 8 q + e (the operand of lane 16 q + j % 16 in k-step u);
+//   activations: t~ of sample k = 64 b + 16 rt + r and hidden unit
+//     j = 16 c + 4 q + v at (((b * (Ma / 16) + c) * 4 + rt) * 64 + 16 q + r) * 4 + v
+//     (the four hidden rows lane 16 q + r of hidden tile c needs for sample tile rt).
+__host__ __device__ __forceinline__ size_t pfrag_off(int j, int i, int ng) {
+    const int l = i & 127;
+    return ((((size_t)(j >> 4) * ng + (i >> 7)) * 4 + (l >> 5)) * 64 + 16 * ((l >> 3) & 3) +
+            (j & 15)) * 8 + (l & 7);
+}
+
+// BF16 forms: Sp [Nsp][Kq / 2] bytes (sample-major, sites in the order above) and
+// St [Kb][Nsp / 2] bytes (site-major, samples of each chunk in the order
+// above).  One block: 64 samples x one 128-site group, staged in LDS.
+__global__ __launch_bounds__(256) void k_prep_spins4(const int8_t* __restrict__ s, int N, long n,
+                                                     int Kb, int Kq, long Nsp,
+                                                     uint8_t* __restrict__ Sp,
+                                                     uint8_t* __restrict__ St) {
+    __shared__ int8_t tile[64][132];
+    const long k0 = (long)blockIdx.x * 64;
+    const int i0 = blockIdx.y * 128;
+    for (int e = threadIdx.x; e < 64 * 128; e += 256) {
+        const int kl = e >> 7, il = e & 127;
+        const long k = k0 + kl;
+        const int i = i0 + il;
+        int8_t v = 0;
+        if (k < n) v = i < N ? s[k * N + i] : (i == N ? (int8_t)1 : (int8_t)0);
+        tile[kl][il] = v;
+    }
+    __syncthreads();
+    {   // sample-major: thread -> sample kl, positions 32 q .. 32 q + 31 (16 bytes)
+        const int kl = threadIdx.x >> 2, q = threadIdx.x & 3;
+        uint32_t wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x |= fp4_code(tile[kl][32 * u + 8 * q + e]) << (4 * e);
+            wv[u] = x;  // positions 32 q + 8 u + e
+        }
+        *(uint4*)(Sp + (k0 + kl) * (Kq / 2) + i0 / 2 + 16 * q) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    }
+    {   // site-major: thread -> site il, lane quads q = 2 h, 2 h + 1: positions
+        // 128 q + 16 a + (0..15) of the chunk hold local samples 32 (2 a + (p >> 3)) + 8 q + (p & 7)
+        const int il = threadIdx.x >> 1, h = threadIdx.x & 1;
+        const int i = i0 + il;
+        if (i < Kb) {
+            const long c0 = k0 & ~511L;         // chunk start
+            const int a = (int)((k0 & 511) >> 6);  // which 64-sample slice of the chunk
+#pragma unroll
+            for (int qq = 0; qq < 2; ++qq) {
+                const int q = 2 * h + qq;
+                uint32_t x0 = 0, x1 = 0;
+#pragma unroll
+                for (int p = 0; p < 16; ++p) {
+                    const int kl = 32 * (p >> 3) + 8 * q + (p & 7);  // sample k0 + kl
+                    const uint32_t c = fp4_code(tile[kl][il]);
+                    if (p < 8) x0 |= c << (4 * p);
+                    else x1 |= c << (4 * (p - 8));
+                }
+                *(uint2*)(St + (size_t)i * (Nsp / 2) + c0 / 2 + 64 * q + 8 * a) = make_uint2(x0, x1);
+            }
+        }
+    }
 }
 
 // t~ hidden-major: Th[j][k] = t~_kj (k < Nsp, padding samples 0), in the
@@ -151,6 +206,18 @@ __global__ __launch_bounds__(256) void k_prep_t(const R* __restrict__ tact, long
         const size_t o = (size_t)j * Nsp + k0 + kl;
         ((R*)out)[o] = tile[kl][jl];
     }
+}
+
+// BF16 forms: the activations in contraction-1 fragment order (zero past n).
+// Block (b, c): 64 samples x hidden tile c; thread = (sample tile, lane).
+__global__ __launch_bounds__(256) void k_prep_tf(const float* __restrict__ tact, long n, int Mw,
+                                                 float* __restrict__ Tf) {
+    const int b = blockIdx.x, c = blockIdx.y, nct = gridDim.y;
+    const int rt = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const long k = 64L * b + 16 * rt + r;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < n) v = *(const float4*)(tact + k * Mw + 16 * c + 4 * q);
+    *(float4*)(Tf + ((((size_t)b * nct + c) * 4 + rt) * 64 + lane) * 4) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -401,137 +468,163 @@ __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ S
 }
 
 // ---------------------------------------------------------------------------
-// contraction 1, BF16 form, 64 samples per block (four sample tiles): wave w
-// keeps the fragments of its hidden tile of the contracted vector (the CG
-// residual, two BF16 planes) in registers and applies them to the four tiles,
-// whose spins (one bit each) it reads directly.  All of a wave's global loads
-// are issued together.
+// contraction 1, BF16 forms, 64 samples per block (four sample tiles).  Waves
+// 0 .. nw - 2 take hidden tiles w, w + nw - 1, ...; the matrix cores compute
+// the 16 x 16 blocks of P S^T with the hidden index as the row (A = the
+// residual, two BF16 planes, B = the spins as FP4 codes converted to BF16),
+// so that a lane holds four hidden rows of one sample: it weights them with
+// that sample's activations and sums them in its own registers.  Both the
+// residual and the activations are read in fragment order (pfrag_off,
+// k_prep_tf).  The last wave runs the CG head meanwhile (the update's
+// partials, stop test, beta) and after the barrier forms w = J r + beta w.
 // ---------------------------------------------------------------------------
-constexpr int W6_ROWS = 64;
+constexpr int W7_ROWS = 64;
 
-__global__ __launch_bounds__(1024) void k_w6(Dims d, const uint8_t* __restrict__ Sp,
-                                             const float* __restrict__ tact, long n,
+// CG head from the three sums: stop test, beta and p.p; block 0 publishes.
+// Returns false when CG stops.
+__device__ __forceinline__ bool head_decide(double rr, double rp, double ppo, const HeadIn& h,
+                                            CgScalars* sc, double& beta) {
+    const int it = h.it;
+    const double rr0 = it == 0 ? rr : h.rr0;
+    const double tol2 = h.tol * h.tol * rr0;
+    const bool stop = !(rr > tol2) || it >= h.maxiter || !isfinite(rr);
+    beta = it == 0 ? 0.0 : rr / h.rr_prev;
+    const double pp = rr + 2.0 * beta * rp + beta * beta * ppo;
+    if (blockIdx.x == 0 && (threadIdx.x & 63) == 0) {
+        sc->rr = rr;
+        sc->iters = it;
+        sc->beta = beta;
+        sc->pp = pp;
+        if (it == 0) {
+            sc->rr0 = rr0;
+            sc->tol2 = tol2;
+        }
+        if (stop) {
+            sc->done = 1;
+            if (!isfinite(rr)) sc->bad = 1;
+        }
+    }
+    return !stop;
+}
+
+__global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__ Sp,
+                                             const float* __restrict__ Tf, long n,
                                              const uint16_t* __restrict__ Ph,
                                              double* __restrict__ w, double* __restrict__ wpart,
                                              const double* __restrict__ aux, int nbv,
                                              CgScalars* sc) {
-    constexpr int RT = W6_ROWS / 16;
-    // the stop flag and the head's scalars; the flag is tested once the
-    // first tile's loads are in flight
+    constexpr int RT = W7_ROWS / 16;
+    constexpr int HB = 4;  // head partials per lane issued up front, per sum
+    // the stop flag; it is tested once the first loads are in flight
     const int done = sc->done;
-    const HeadIn hin = head_in(sc);
-    __shared__ double wsh[16][W6_ROWS];
-    __shared__ double wold_s[W6_ROWS];   // previous w of the block's samples
-    __shared__ double head_s[3][1024];   // this thread's CG head partials
-    __shared__ double s3[3][16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    __shared__ double wsh[15][W7_ROWS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = (blockDim.x >> 6) - 1;  // contraction waves; wave nw runs the head
     const int lr = lane & 15, lk = lane >> 4;
-    const long r0 = (long)blockIdx.x * W6_ROWS;
-    const int Kq = d.Kq, KB = d.Kq / 8, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
-    const uint16_t* Pl = Ph + (size_t)Ma * Kq;
-    // 32-bit offsets from block-uniform bases
-    const uint8_t* sb0 = Sp + r0 * KB + lr * KB;  // sample tile rt: + 16 rt KB
-    const float* tb = tact + r0 * Mw;
-    const int toff = acc_row<float>(lk, 0) * Mw;  // rows 4 lk + q of each sample tile
-    float rsf[RT][4];
+    const long r0 = (long)blockIdx.x * W7_ROWS;
+    const int Kq = d.Kq, KB2 = d.Kq / 2, nct = d.Ma / 16, ng = d.Kq / 128;
+    if (wave == nw) {
+        // ---- the CG head: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the update's
+        // block partials (lane stride 64, then the wave: the same order in every block)
+        const HeadIn hin = head_in(sc);
+        double x[3][HB];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+        for (int u = 0; u < HB; ++u) {
+            const int i = 64 * u + lane;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rsf[rt][q] = 0.0f;
-    double beta = 0.0;
-    // one hidden tile; in the wave's first tile (head) the CG head partials
-    // and the previous w are fetched behind the first group's loads and
-    // parked in LDS, so that no register holds them during the MFMAs
-    auto tile = [&](int ct, auto head) -> bool {
-        const int j = ct * 16 + lr;
-        float tv[RT][4];
-        double hx[4];  // head partials and previous w (head tile only)
+            for (int k = 0; k < 3; ++k) x[k][u] = i < nbv ? aux[k * nbv + i] : 0.0;
+        }
+        const double wold = w[min(r0 + lane, n - 1)];
+        asm volatile("" ::: "memory");  // the loads above go out before the stop test
+        if (done) return;               // (uniform over the block, before any barrier)
+        double t[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double a = 0.0;
+#pragma unroll
+            for (int u = 0; u < HB; ++u) a += x[k][u];
+            for (int i = 64 * HB + lane; i < nbv; i += 64) a += aux[k * nbv + i];
+            t[k] = wave_sum(a);
+        }
+        double beta;
+        const bool go = head_decide(t[0], t[1], t[2], hin, sc, beta);
+        __syncthreads();
+        if (!go) return;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 15; ++q)
+            if (q < nw) v += wsh[q][lane];
+        v += beta * wold;  // J p = J r + beta J p_old
+        const long k = r0 + lane;
+        if (k < n) w[k] = v;
+        const double s = wave_sum(k < n ? v : 0.0);
+        if (lane == 0) wpart[blockIdx.x] = s;
+        return;
+    }
+    const uint16_t* Pl = Ph + (size_t)d.Ma * Kq;
+    const uint8_t* sb = Sp + (r0 + lr) * KB2 + 16 * lk;  // sample tile rt: + 16 rt KB2
+    float rs[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) rs[rt] = 0.0f;
+    bool first = true;
+    for (int ct = wave; ct < nct; ct += nw) {
         v4f acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0, 0, 0, 0};
-        const int prow = j * Kq + 8 * lk;
-        for (int g = 0; g < Kq; g += 128) {
+        float4 tv[RT];
+        for (int g = 0; g < ng; ++g) {
             v8s bh[4], bl[4];
-            uint4 sbits[RT];  // 128 sites of each of the lane's sample rows
+            uint4 sp[RT];  // 32 sites of the lane's sample in each tile, FP4
+            const size_t po = (((size_t)ct * ng + g) * 4 * 64 + lane) * 8;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                bh[u] = *(const v8s*)(Ph + prow + g + 32 * u);
-                bl[u] = *(const v8s*)(Pl + prow + g + 32 * u);
+                bh[u] = *(const v8s*)(Ph + po + 512 * u);
+                bl[u] = *(const v8s*)(Pl + po + 512 * u);
             }
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) sbits[rt] = *(const uint4*)(sb0 + 16 * rt * KB + g / 8);
+            for (int rt = 0; rt < RT; ++rt) sp[rt] = *(const uint4*)(sb + 16 * rt * KB2 + 64 * g);
             if (g == 0) {
-                // the activations (needed after the MFMAs) behind the MFMA
-                // operands, so that the MFMAs do not wait for them
+                // the activations (needed after the MFMAs) behind the MFMA operands
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) tv[rt][q] = tb[toff + (16 * rt + q) * Mw + j];
-            }
-            if constexpr (decltype(head)::value) {
-                if (g == 0) {
-                    __builtin_amdgcn_sched_barrier(0);  // behind the contraction's loads
-                    hx[0] = pload1(aux, nbv);
-                    hx[1] = pload1(aux + nbv, nbv);
-                    hx[2] = pload1(aux + 2 * nbv, nbv);
-                    hx[3] = w[min(r0 + lane, n - 1)];
+                    tv[rt] = *(const float4*)(Tf + ((((size_t)blockIdx.x * nct + ct) * RT + rt) * 64 + lane) * 4);
+                if (first) {
                     asm volatile("" ::: "memory");  // the loads above go out before the stop test
-                    if (done) return false;         // (uniform over the block, before any barrier)
+                    if (done) return;               // (uniform over the block, before any barrier)
+                    first = false;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);  // the group's loads together
+            // two sample tiles at a time: their hi products, then their lo products
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    // sites g + 32 u + 8 lk + e: byte 4 u + lk of the group
-                    const uint32_t word = u == 0 ? sbits[rt].x : u == 1 ? sbits[rt].y
-                                        : u == 2 ? sbits[rt].z : sbits[rt].w;
-                    const v8bf a = __builtin_bit_cast(v8bf, bits_to_bf16(word >> (8 * lk)));
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh[u]), acc[rt], 0, 0, 0);
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl[u]), acc[rt], 0, 0, 0);
+                for (int rt = 0; rt < RT; rt += 2) {
+                    const v8bf b0 = fp4x8_to_bf16(word_of(sp[rt], u));
+                    const v8bf b1 = fp4x8_to_bf16(word_of(sp[rt + 1], u));
+                    const v8bf ah = __builtin_bit_cast(v8bf, bh[u]), al = __builtin_bit_cast(v8bf, bl[u]);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b0, acc[rt], 0, 0, 0);
+                    acc[rt + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b1, acc[rt + 1], 0, 0, 0);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b0, acc[rt], 0, 0, 0);
+                    acc[rt + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b1, acc[rt + 1], 0, 0, 0);
                 }
             }
         }
+        // acc[rt][q]: hidden row ct 16 + 4 lk + q of sample 16 rt + lr
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) rsf[rt][q] += tv[rt][q] * acc[rt][q];
-        if constexpr (decltype(head)::value) {  // park the head inputs for the epilogue
-            head_s[0][tid] = hx[0];
-            head_s[1][tid] = hx[1];
-            head_s[2][tid] = hx[2];
-            if (wave == 0) wold_s[lane] = hx[3];
-        }
-        return true;
-    };
-    if (!tile(wave, std::true_type{})) return;  // every wave has a first tile
-    for (int ct = wave + nw; ct < nct; ct += nw) tile(ct, std::false_type{});
-    // CG head partials (each thread reads back the ones it parked) and the
-    // sums over the 16 columns of the wave's tiles, parked in LDS behind one
-    // barrier; then the head, and the sums over the waves in order (wave 0,
-    // one lane per sample) and over the block's samples
-    head_park(aux, nbv, blockDim.x, head_s[0][tid], head_s[1][tid], head_s[2][tid], s3);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double v = row16_sum((double)rsf[rt][q]);
-            if (lr == 0) wsh[wave][16 * rt + acc_row<float>(lk, q)] = v;
-        }
-    __syncthreads();
-    if (!head_finish(s3, nw, hin, sc, beta)) return;
-    if (wave == 0) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (q < nw) v += wsh[q][lane];
-        v += beta * wold_s[lane];  // J p = J r + beta J p_old
-        const long k = r0 + lane;
-        if (k < n) w[k] = v;
-        const double t = wave_sum(k < n ? v : 0.0);
-        if (lane == 0) wpart[blockIdx.x] = t;
+            rs[rt] += ((tv[rt].x * acc[rt][0] + tv[rt].y * acc[rt][1]) +
+                       (tv[rt].z * acc[rt][2] + tv[rt].w * acc[rt][3]));
     }
+    // each sample's rows summed over the four lane quads, parked for the head wave
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        float v = rs[rt];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lk == 0) wsh[wave][16 * rt + lr] = (double)v;
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -687,152 +780,114 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
 }
 
 // BF16 forms: t~ (FP32, [Ma][Nsp]) is scaled by z while it is staged: the
-// LDS tile holds a_kj = t~_kj z_k (FP32 product) as two BF16 terms hi + lo,
-// and B is the spin matrix itself, +1 / -1, exact in BF16 and expanded from
-// the spin bits.  Two MFMAs per k-step (hi and lo) with FP32 accumulation;
-// the error of a product is that of the two-term split of a, about 2^-17
-// relative.
-__global__ __launch_bounds__(1024) void k_outer7(Dims d, const uint8_t* __restrict__ St,
-                                                 const float* __restrict__ Th, long Nsp, long n,
-                                                 const double* __restrict__ v, int v_mode,
-                                                 const double* __restrict__ wpart, int nbw,
-                                                 float* __restrict__ part, int ksplit,
-                                                 double* __restrict__ papart,
-                                                 const CgScalars* __restrict__ sc) {
+// LDS tile holds a_kj = t~_kj z_k (FP32 product) as two BF16 terms hi + lo
+// (hardware round-to-nearest conversion), and B is the spin matrix itself,
+// +1 / -1, exact in BF16 (FP4 codes, converted two per instruction).  Two
+// MFMAs per k-step (hi and lo) with FP32 accumulation; the error of a
+// product is that of the two-term split of a, about 2^-17 relative.
+// 512 threads: for the staging, thread t takes samples 4 (t % 128) .. + 3 of
+// rows 4 (t / 128) .. + 3 and forms their z itself; for the contraction, wave
+// w takes site tiles w, w + 8, ...
+constexpr int O8_THREADS = 512;
+__global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8(Dims d, const uint8_t* __restrict__ St,
+                                                       const float* __restrict__ Th, long Nsp, long n,
+                                                       const double* __restrict__ v, int v_mode,
+                                                       const double* __restrict__ wpart, int nbw,
+                                                       float* __restrict__ part, int ksplit,
+                                                       double* __restrict__ papart,
+                                                       const CgScalars* __restrict__ sc) {
     // stop flag of the CG product, tested once the block's loads are in flight
     const int done = v_mode == 0 ? sc->done : 0;
     constexpr int KC = O16_KC, KP = O16_KP;
-    constexpr int UR = KC / 4;         // 16-byte units per row (4 floats)
-    constexpr int UA = 16 * UR;        // units in the tile
-    constexpr int BA = 5;              // units per thread issued up front (448 threads)
-    constexpr int BW = 2;              // mean-w partials per thread issued up front
-    constexpr int BV = 2;              // chunk values of v per thread issued up front
-    constexpr int KS = KC / 32;        // k-steps (32 samples each)
+    constexpr int NW = O8_THREADS / 64;
     __shared__ __align__(16) uint16_t As[2 * 16 * KP];  // hi rows, then lo rows
-    __shared__ __align__(16) float zs[KC];
-    __shared__ double sh[16];
+    __shared__ double sh[NW];
+    __shared__ double mean_s;
     const int nj = d.Ma / 16;
     int jt, kc;
     outer_block(nj, jt, kc);
     if (kc >= ksplit) return;  // no chunk for this block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nth = blockDim.x, nw = nth >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long kbeg = (long)kc * KC;
     const int nit = d.Na / 16;
-    const float* Ab = Th + (size_t)jt * 16 * Nsp + kbeg;
-    // ---- issue: mean-w partials, t~ tile, the chunk's v, this wave's spins
-    double wp[BW];
+    const int c = tid & 127, rg = tid >> 7;  // staging: samples 4 c.., rows 4 rg..
+    // ---- issue: t~ rows, the four samples' v, mean-w partials (wave 0), spins
+    const float* Ab = Th + (size_t)(jt * 16 + 4 * rg) * Nsp + kbeg + 4 * c;
+    float4 ta[4];
 #pragma unroll
-    for (int u = 0; u < BW; ++u) {
-        const int b = u * nth + tid;
-        wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
-    }
-    float4 ra[BA];
+    for (int q = 0; q < 4; ++q) ta[q] = *(const float4*)(Ab + (size_t)q * Nsp);
+    double vk[4];
 #pragma unroll
-    for (int u = 0; u < BA; ++u) {
-        const int e = min(u * nth + tid, UA - 1);
-        ra[u] = *(const float4*)(Ab + (size_t)(e / UR) * Nsp + 4 * (e % UR));
-    }
-    double vk[BV];
+    for (int e = 0; e < 4; ++e) vk[e] = v[min(kbeg + 4 * c + e, n - 1)];
+    double wp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (v_mode == 0 && wave == 0) {
 #pragma unroll
-    for (int u = 0; u < BV; ++u) vk[u] = v[min(kbeg + min(u * nth + tid, KC - 1), n - 1)];
-    uint32_t sb[KS];  // spin bits of the lane's site row: one byte per lane quad per k-step
-    auto load_spins = [&](int it) {
-        const uint8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 8) + kbeg / 8;
-#pragma unroll
-        for (int q = 0; q < KC / 128; ++q) {
-            const uint4 x = *(const uint4*)(Sr + 16 * q);
-            sb[4 * q] = x.x;
-            sb[4 * q + 1] = x.y;
-            sb[4 * q + 2] = x.z;
-            sb[4 * q + 3] = x.w;
+        for (int u = 0; u < 4; ++u) {
+            const int b = 64 * u + lane;
+            wp[u] = b < nbw ? wpart[b] : 0.0;
         }
+    }
+    uint4 sp[4];  // FP4 spins of the lane's site in the chunk, positions 128 lk ..
+    auto load_spins = [&](int it) {
+        const uint8_t* Sr = St + (size_t)(it * 16 + lr) * (Nsp / 2) + kbeg / 2 + 64 * lk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sp[q] = *(const uint4*)(Sr + 16 * q);
     };
-    load_spins(wave);
+    if (wave < nit) load_spins(wave);
     asm volatile("" ::: "memory");  // the loads above go out before the stop test
     if (done) return;               // (uniform over the block, before any barrier)
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
-    // ---- mean w over the batch; z of the chunk into LDS between the two barriers
-    double a = 0.0;
-#pragma unroll
-    for (int u = 0; u < BW; ++u) a += wp[u];
-    if (v_mode == 0)
-        for (int b = BW * nth + tid; b < nbw; b += nth) a += wpart[b];
-    a = wave_sum(a);
-    if (lane == 0) sh[wave] = a;
-    __syncthreads();  // (v_mode 1: a = 0, unused)
-    double tot = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        if (q < nw) tot += sh[q];
-    const double shift = v_mode == 0 ? tot / (double)n : 0.0;
-    const double scale = v_mode == 0 ? 1.0 / (double)n : 1.0;
-    double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
-#pragma unroll
-    for (int u = 0; u < BV; ++u) {
-        const int t = u * nth + tid;
-        if (t < KC) {
-            const double z = kbeg + t < n ? (vk[u] - shift) * scale : 0.0;
-            zw += z * (vk[u] - shift);
-            zs[t] = (float)z;
-        }
-    }
-    for (int t = BV * nth + tid; t < KC; t += nth) {  // small blocks only
-        const long k = kbeg + t;
-        const double vt = v[min(k, n - 1)];
-        const double z = k < n ? (vt - shift) * scale : 0.0;
-        zw += z * (vt - shift);
-        zs[t] = (float)z;
+    // ---- mean w over the batch (wave 0, fixed order), through LDS
+    if (wave == 0) {
+        double a = (wp[0] + wp[1]) + (wp[2] + wp[3]);
+        if (v_mode == 0)
+            for (int b = 256 + lane; b < nbw; b += 64) a += wpart[b];
+        a = wave_sum(a);
+        if (lane == 0) mean_s = v_mode == 0 ? a / (double)n : 0.0;
     }
     __syncthreads();
+    const double shift = mean_s;
+    const double scale = v_mode == 0 ? 1.0 / (double)n : 1.0;
+    float z[4];
+    double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) (row group 0)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double zz = kbeg + 4 * c + e < n ? (vk[e] - shift) * scale : 0.0;
+        zw += zz * (vk[e] - shift);
+        z[e] = (float)zz;
+    }
+    // ---- stage a = t~ z as hi / lo BF16 rows
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t h0, l0, h1, l1;
+        split_pk(ta[q].x * z[0], ta[q].y * z[1], h0, l0);
+        split_pk(ta[q].z * z[2], ta[q].w * z[3], h1, l1);
+        const int row = 4 * rg + q;
+        *(uint2*)(As + row * KP + 4 * c) = make_uint2(h0, h1);
+        *(uint2*)(As + (16 + row) * KP + 4 * c) = make_uint2(l0, l1);
+    }
     // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
-    // chunk, from the blocks of hidden tile 0 (wave sums parked in sh, added
-    // after the staging barrier)
-    if (v_mode == 0 && jt == 0) {
+    // chunk, from the blocks of hidden tile 0 (row group 0 = waves 0 and 1)
+    const bool pgp = v_mode == 0 && jt == 0;
+    if (pgp && rg == 0) {
         zw = wave_sum(zw);
         if (lane == 0) sh[wave] = zw;
     }
-    // ---- stage a = t~ z as hi / lo BF16 rows
-    auto stage = [&](int e, float4 t4) {
-        const int row = e / UR, c = e % UR;
-        const float4 z4 = *(const float4*)(zs + 4 * c);
-        const float av[4] = {t4.x * z4.x, t4.y * z4.y, t4.z * z4.z, t4.w * z4.w};
-        uint16_t h[4], l[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) split2(av[q], h[q], l[q]);
-        *(uint2*)(As + row * KP + 4 * c) =
-            make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
-        *(uint2*)(As + (16 + row) * KP + 4 * c) =
-            make_uint2(l[0] | (uint32_t)l[1] << 16, l[2] | (uint32_t)l[3] << 16);
-    };
-#pragma unroll
-    for (int u = 0; u < BA; ++u) {
-        const int e = u * nth + tid;
-        if (e < UA) stage(e, ra[u]);
-    }
-    for (int e = BA * nth + tid; e < UA; e += nth)  // small blocks only
-        stage(e, *(const float4*)(Ab + (size_t)(e / UR) * Nsp + 4 * (e % UR)));
     __syncthreads();
-    if (v_mode == 0 && jt == 0 && tid == 0) {
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (q < nw) t += sh[q];
-        papart[kc] = t;
-    }
-    for (int it = wave; it < nit; it += nw) {
+    if (pgp && tid == 0) papart[kc] = sh[0] + sh[1];
+    for (int it = wave; it < nit; it += NW) {
         if (it != wave) load_spins(it);
         v4f acc = v4f{0, 0, 0, 0}, acc2 = v4f{0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < KS; ++u) {
+        for (int u = 0; u < KC / 32; ++u) {
             const int kk = 32 * u + 8 * lk;
             const v8bf ah = __builtin_bit_cast(v8bf, *(const v8s*)(As + lr * KP + kk));
             const v8bf al = __builtin_bit_cast(v8bf, *(const v8s*)(As + (16 + lr) * KP + kk));
-            const v8bf b = __builtin_bit_cast(v8bf, bits_to_bf16_words(sb[u] >> (8 * lk)));
+            const v8bf b = fp4x8_to_bf16(word_of(sp[u >> 2], u & 3));
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, acc, 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc2, 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
+            if (u & 1) __builtin_amdgcn_sched_barrier(0);  // two k-steps of operands live at a time
         }
         float* out = part + (size_t)kc * d.Ma * d.Na;
 #pragma unroll
@@ -889,7 +944,7 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
     if (threadIdx.x == 0) pap[blockIdx.x] = dot;
 }
 
-// CG update of iteration it, 64 entries per block (wave w sums chunk slabs
+// CG update of iteration it (FP64 path), 64 entries per block (wave w sums chunk slabs
 // [w ks/4, (w+1) ks/4); after one barrier wave 0 finishes alone), with r.r,
 // beta and p.p from the head:
 //   p_it = r + beta p_{it-1};  Ap = sum_kc part[kc] + shift p_it (parameter
@@ -899,8 +954,7 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
 // partials of r.r, r.p_it, p_it.p_it for the next head.  Block 0 advances the
 // iteration index and, when given a pinned host word, stores the stop flag
 // there (the last update of a batch of iterations does).
-template <typename R>
-__global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int ksplit, double* x,
+__global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int ksplit, double* x,
                                                  double* r, const double* p_old, double* p_new,
                                                  void* Rop, const double* papart, int npa,
                                                  double* aux_next, int nbv, CgScalars* sc,
@@ -912,7 +966,7 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
     const int ec = e < total ? e : total - 1;
     // every load that does not depend on the scalars, issued up front
     const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
-    R xs[16];
+    double xs[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
     const double xe = x[ec], re0 = r[ec], po = p_old[ec];
@@ -972,14 +1026,7 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
         x[e] = xe + alpha * pn;
         r[e] = rn;
         p_new[e] = pn;
-        if constexpr (sizeof(R) == 8) {
-            ((double*)Rop)[(size_t)i * d.Ma + j] = rn;
-        } else {
-            uint16_t hi, lo;
-            split2((float)rn, hi, lo);
-            ((uint16_t*)Rop)[(size_t)j * d.Kq + i] = hi;
-            ((uint16_t*)Rop)[(size_t)d.Ma * d.Kq + (size_t)j * d.Kq + i] = lo;
-        }
+        ((double*)Rop)[(size_t)i * d.Ma + j] = rn;
         q[0] = rn * rn;
         q[1] = rn * pn;
         q[2] = pn * pn;
@@ -992,14 +1039,132 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const R* part, int kspl
     }
 }
 
+// BF16 forms: the CG update as above with 128 entries per block, two per
+// lane (FP32 chunk partial pairs; FP64 vectors as pairs), the residual
+// written to the contraction-1 operand as its two BF16 terms in fragment
+// order (pfrag_off).
+__global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int ksplit, double* x,
+                                                 double* r, const double* p_old, double* p_new,
+                                                 uint16_t* Rop, const double* papart, int npa,
+                                                 double* aux_next, int nbv, CgScalars* sc,
+                                                 volatile int32_t* host_flag) {
+    __shared__ double2 ws[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int total = d.Ma * d.Na;  // even (Na is a multiple of 16)
+    const int e = blockIdx.x * 128 + 2 * lane;
+    const int ec = e < total ? e : total - 2;
+    // every load that does not depend on the scalars, issued up front
+    const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
+    float2 xs[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        xs[u] = *(const float2*)(part + (size_t)min(kb + u, ksplit - 1) * total + ec);
+    const double2 xe = *(const double2*)(x + ec), re0 = *(const double2*)(r + ec),
+                  po = *(const double2*)(p_old + ec);
+    double xa[4];  // p.Gp chunk partials lane, lane + 64, ... (summed by wave 0)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xa[u] = npa > 0 ? papart[min(u * 64 + lane, npa - 1)] : 0.0;
+    // the CG scalars with the stop flag (one round trip)
+    const int done = sc->done;
+    const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
+    asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (done) {
+        if (host_flag && lead) *host_flag = 1;
+        return;
+    }
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        if (kb + u < ke) {
+            v0 += (double)xs[u].x;
+            v1 += (double)xs[u].y;
+        }
+    for (int kc = kb + 16; kc < ke; ++kc) {
+        const float2 t = *(const float2*)(part + (size_t)kc * total + ec);
+        v0 += (double)t.x;
+        v1 += (double)t.y;
+    }
+    ws[wave][lane] = make_double2(v0, v1);
+    __syncthreads();
+    if (wave != 0) return;  // waves 1-3 only summed chunk slabs
+    // p.G p: the chunk partials in a fixed order (the same in every block)
+    double tg = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u * 64 + lane < npa) tg += xa[u];
+    for (int c = 256 + lane; c < npa; c += 64) tg += papart[c];
+    const double pGp = wave_sum(tg);
+    const double pAp = pGp + shift * pp;
+    const double alpha = rr / pAp;
+    if (!(pAp > 0.0) || !isfinite(alpha)) {
+        if (lead) {
+            sc->bad = 1;
+            sc->done = 1;
+            if (host_flag) *host_flag = 1;
+        }
+        return;
+    }
+    if (lead) {
+        sc->alpha = alpha;
+        sc->pAp = pAp;
+        sc->rr_prev = rr;
+        sc->it += 1;  // read by the next head
+        if (host_flag) *host_flag = 0;
+    }
+    double q[3] = {0.0, 0.0, 0.0};
+    if (e < total) {
+        const int j = e / d.Na, i = e - j * d.Na;  // entries (j, i) and (j, i + 1)
+        auto keep = [&](int ii) {
+            return (j < d.M && ii < d.N) || (d.hb && j < d.M && ii == d.N) ||
+                   (d.vb && j == d.M && ii < d.N);
+        };
+        const bool k0 = keep(i), k1 = keep(i + 1);
+        const double2 s0 = ws[0][lane], s1 = ws[1][lane], s2 = ws[2][lane], s3 = ws[3][lane];
+        const double pn0 = re0.x + beta * po.x, pn1 = re0.y + beta * po.y;
+        const double ap0 = k0 ? (s0.x + s1.x) + (s2.x + s3.x) + shift * pn0 : 0.0;
+        const double ap1 = k1 ? (s0.y + s1.y) + (s2.y + s3.y) + shift * pn1 : 0.0;
+        const double rn0 = re0.x - alpha * ap0, rn1 = re0.y - alpha * ap1;
+        *(double2*)(x + e) = make_double2(xe.x + alpha * pn0, xe.y + alpha * pn1);
+        *(double2*)(r + e) = make_double2(rn0, rn1);
+        *(double2*)(p_new + e) = make_double2(pn0, pn1);
+        uint32_t hi, lo;
+        split_pk((float)rn0, (float)rn1, hi, lo);
+        const size_t o = pfrag_off(j, i, d.Kq / 128);
+        *(uint32_t*)(Rop + o) = hi;
+        *(uint32_t*)(Rop + (size_t)d.Ma * d.Kq + o) = lo;
+        q[0] = rn0 * rn0 + rn1 * rn1;
+        q[1] = rn0 * pn0 + rn1 * pn1;
+        q[2] = pn0 * pn0 + pn1 * pn1;
+    }
+    // the block's partials of r.r, r.p and p.p for the next head
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(q[k]);
+        if (lane == 0) aux_next[(size_t)k * nbv + blockIdx.x] = v;
+    }
+}
+
 // CG start (x0 = 0): r = f, both direction buffers 0, r in the contraction-1
 // operand layout (its padding is cleared beforehand), head partials
-// (f.f, 0, 0), 64 entries per block; scalars for the iteration kernels.
-template <typename R>
+// (f.f, 0, 0); scalars for the iteration kernels.  FP64 path: 64 entries per
+// block; BF16 forms: 128 (two per lane, split into BF16 terms in fragment
+// order), matching the blocks of the update.
+__device__ __forceinline__ void init_scalars(CgScalars* sc, double tol, int maxiter, double shift) {
+    sc->done = 0;
+    sc->bad = 0;
+    sc->iters = 0;
+    sc->it = 0;
+    sc->tol = tol;
+    sc->maxiter = maxiter;
+    sc->shift = shift;
+    sc->rr_prev = 0.0;
+}
+
 __global__ __launch_bounds__(64) void k_init3(Dims d, const double* __restrict__ f,
                                               double* __restrict__ x, double* __restrict__ r,
                                               double* __restrict__ p, double* __restrict__ p2,
-                                              void* __restrict__ Rop, double* __restrict__ aux0,
+                                              double* __restrict__ Rop, double* __restrict__ aux0,
                                               int nbv, double tol, int maxiter, double shift,
                                               CgScalars* sc) {
     const int total = d.Ma * d.Na;
@@ -1012,14 +1177,7 @@ __global__ __launch_bounds__(64) void k_init3(Dims d, const double* __restrict__
         r[e] = fe;
         p[e] = 0.0;
         p2[e] = 0.0;
-        if constexpr (sizeof(R) == 8) {
-            ((double*)Rop)[(size_t)i * d.Ma + j] = fe;
-        } else {
-            uint16_t hi, lo;
-            split2((float)fe, hi, lo);
-            ((uint16_t*)Rop)[(size_t)j * d.Kq + i] = hi;
-            ((uint16_t*)Rop)[(size_t)d.Ma * d.Kq + (size_t)j * d.Kq + i] = lo;
-        }
+        Rop[(size_t)i * d.Ma + j] = fe;
         q = fe * fe;
     }
     q = wave_sum(q);
@@ -1028,16 +1186,40 @@ __global__ __launch_bounds__(64) void k_init3(Dims d, const double* __restrict__
         aux0[nbv + blockIdx.x] = 0.0;
         aux0[2 * (size_t)nbv + blockIdx.x] = 0.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->done = 0;
-        sc->bad = 0;
-        sc->iters = 0;
-        sc->it = 0;
-        sc->tol = tol;
-        sc->maxiter = maxiter;
-        sc->shift = shift;
-        sc->rr_prev = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) init_scalars(sc, tol, maxiter, shift);
+}
+
+__global__ __launch_bounds__(64) void k_init4(Dims d, const double* __restrict__ f,
+                                              double* __restrict__ x, double* __restrict__ r,
+                                              double* __restrict__ p, double* __restrict__ p2,
+                                              uint16_t* __restrict__ Rop,
+                                              double* __restrict__ aux0, int nbv, double tol,
+                                              int maxiter, double shift, CgScalars* sc) {
+    const int total = d.Ma * d.Na;
+    const int e = blockIdx.x * 128 + 2 * threadIdx.x;
+    double q = 0.0;
+    if (e < total) {
+        const double2 fe = *(const double2*)(f + e);
+        const int j = e / d.Na, i = e - j * d.Na;
+        const double2 z = make_double2(0.0, 0.0);
+        *(double2*)(x + e) = z;
+        *(double2*)(r + e) = fe;
+        *(double2*)(p + e) = z;
+        *(double2*)(p2 + e) = z;
+        uint32_t hi, lo;
+        split_pk((float)fe.x, (float)fe.y, hi, lo);
+        const size_t o = pfrag_off(j, i, d.Kq / 128);
+        *(uint32_t*)(Rop + o) = hi;
+        *(uint32_t*)(Rop + (size_t)d.Ma * d.Kq + o) = lo;
+        q = fe.x * fe.x + fe.y * fe.y;
     }
+    q = wave_sum(q);
+    if (threadIdx.x == 0) {
+        aux0[blockIdx.x] = q;
+        aux0[nbv + blockIdx.x] = 0.0;
+        aux0[2 * (size_t)nbv + blockIdx.x] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) init_scalars(sc, tol, maxiter, shift);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,21 +1235,36 @@ size_t qgt_th_bytes(const Dims& d, int prec, long Nsp) {
 
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q) {
-    const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Kq, 64));
-    k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, prec != 0, (int8_t*)q.Sp, q.St);
+    if (prec == 0) {
+        const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Kq, 64));
+        k_prep_spins<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, (int8_t*)q.Sp, q.St);
+    } else {
+        const dim3 gs((unsigned)(q.Nsp / 64), (unsigned)(d.Kq / 128));
+        k_prep_spins4<<<gs, 256, 0, st>>>(s, d.N, n, d.Kb, d.Kq, q.Nsp, (uint8_t*)q.Sp,
+                                          (uint8_t*)q.St);
+    }
     const dim3 gt((unsigned)(q.Nsp / 64), (unsigned)nb_of(d.Ma, 64));
-    if (prec == 0)
+    if (prec == 0) {
         k_prep_t<double><<<gt, 256, 0, st>>>((const double*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
-    else
+    } else {
         k_prep_t<float><<<gt, 256, 0, st>>>((const float*)tact, n, d.Mw, d.Ma, q.Nsp, q.Th);
+        const dim3 gf((unsigned)(q.Nsp / 64), (unsigned)(d.Ma / 16));
+        k_prep_tf<<<gf, 256, 0, st>>>((const float*)tact, n, d.Mw, q.Tf);
+    }
+}
+
+size_t qgt_spin_bytes(const Dims& d, int prec, long Nsp) {
+    // Sp and St: one byte per spin (FP64 path) or one FP4 code (BF16 forms)
+    return (size_t)Nsp * d.Kq / (prec == 0 ? 1 : 2);
 }
 
 int qgt_nbw(long n, int prec) {
-    return nb_of(n, prec == 0 ? 16 * W5_RT : W6_ROWS);
+    return nb_of(n, prec == 0 ? 16 * W5_RT : W7_ROWS);
 }
 long qgt_act_rows(long n) { return (n + W_ROWS_MAX - 1) / W_ROWS_MAX * W_ROWS_MAX; }
 int qgt_nbu(const Dims& d) { return nb_of((long)d.Ma * d.Na, 256); }
 int qgt_nbr(const Dims& d) { return nb_of((long)d.Ma * d.Na, 64); }
+int qgt_nbv(const Dims& d, int prec) { return nb_of((long)d.Ma * d.Na, prec == 0 ? 64 : 128); }
 size_t qgt_pop_bytes(const Dims& d, int prec) {
     return prec == 0 ? (size_t)d.Kq * d.Ma * 8 : (size_t)2 * d.Ma * d.Kq * 2;
 }
@@ -1075,14 +1272,14 @@ size_t qgt_pop_bytes(const Dims& d, int prec) {
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
                   long n, const void* Rop, double* w, const double* aux, CgScalars* sc) {
     int waves, per;
-    wave_split(d.Ma / 16, prec == 0 ? 8 : 16, waves, per);
-    const int nb = qgt_nbw(n, prec), nbv = qgt_nbr(d);
+    wave_split(d.Ma / 16, prec == 0 ? 8 : 15, waves, per);
+    const int nb = qgt_nbw(n, prec), nbv = qgt_nbv(d, prec);
     if (prec == 0) {
         k_w5<<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, (const double*)tact, n,
                                         (const double*)Rop, w, q.wpart, aux, nbv, sc);
-    } else {
-        k_w6<<<nb, 64 * waves, 0, st>>>(d, (const uint8_t*)q.Sp, (const float*)tact, n,
-                                        (const uint16_t*)Rop, w, q.wpart, aux, nbv, sc);
+    } else {  // one more wave for the CG head
+        k_w7<<<nb, 64 * (waves + 1), 0, st>>>(d, (const uint8_t*)q.Sp, q.Tf, n,
+                                              (const uint16_t*)Rop, w, q.wpart, aux, nbv, sc);
     }
 }
 
@@ -1106,8 +1303,8 @@ void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q
         k_outer6<<<nb, 64 * nw, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v, v_mode,
                                          q.wpart, nbw, (double*)part, ks, papart, sc);
     else
-        k_outer7<<<nb, 64 * nw, 0, st>>>(d, (const uint8_t*)q.St, (const float*)q.Th, q.Nsp, n, v,
-                                         v_mode, q.wpart, nbw, (float*)part, ks, papart, sc);
+        k_outer8<<<nb, O8_THREADS, 0, st>>>(d, (const uint8_t*)q.St, (const float*)q.Th, q.Nsp, n,
+                                            v, v_mode, q.wpart, nbw, (float*)part, ks, papart, sc);
 }
 
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
@@ -1127,13 +1324,13 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
                      double tol, int maxiter, double shift, CgScalars* sc) {
     launch_zero(st, Rop, qgt_pop_bytes(d, prec));
     launch_zero(st, w, 8 * (size_t)n);
-    const int nb = qgt_nbr(d);
+    const int nb = qgt_nbv(d, prec);
     if (prec == 0)
-        k_init3<double><<<nb, 64, 0, st>>>(d, f, x, r, p, p2, Rop, aux0, nb, tol, maxiter, shift,
-                                           sc);
+        k_init3<<<nb, 64, 0, st>>>(d, f, x, r, p, p2, (double*)Rop, aux0, nb, tol, maxiter, shift,
+                                   sc);
     else
-        k_init3<float><<<nb, 64, 0, st>>>(d, f, x, r, p, p2, Rop, aux0, nb, tol, maxiter, shift,
-                                          sc);
+        k_init4<<<nb, 64, 0, st>>>(d, f, x, r, p, p2, (uint16_t*)Rop, aux0, nb, tol, maxiter,
+                                   shift, sc);
 }
 
 int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
@@ -1142,13 +1339,13 @@ void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& 
                        const void* part, double* x, double* r, const double* p_old,
                        double* p_new, void* Rop, const double* papart, double* aux_next,
                        CgScalars* sc, int32_t* host_flag) {
-    const int nb = qgt_nbr(d), ks = qgt_ksplit(q), npa = qgt_nbo(d, q);
+    const int nb = qgt_nbv(d, prec), ks = qgt_ksplit(q), npa = qgt_nbo(d, q);
     if (prec == 0)
-        k_update4<double><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop,
-                                              papart, npa, aux_next, nb, sc, host_flag);
+        k_update4<<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop, papart,
+                                      npa, aux_next, nb, sc, host_flag);
     else
-        k_update4<float><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new, Rop,
-                                             papart, npa, aux_next, nb, sc, host_flag);
+        k_update5<<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new,
+                                      (uint16_t*)Rop, papart, npa, aux_next, nb, sc, host_flag);
 }
 
 }  // namespace nqs
