@@ -255,6 +255,24 @@ int nqs_load_samples(nqs_ctx* ctx, const int8_t* samples, int64_t n_samples);
  * eloc_out: device float64 [n].  Any n >= 0. */
 int nqs_local_energy(nqs_ctx* ctx, const int8_t* s, int64_t n, double* eloc_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * local energies as nqs_local_energy, bit for bit, computed without the
+ * context's workspace staging.  The batch's hidden activations go to a
+ * static scratch array of 64 MiB that every GPU the library runs on holds
+ * from module load until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  Needs
+ * n * Mw * (8 for NQS_FP64, 4 otherwise) <= 64 MiB, where Mw, the padded
+ * hidden width, is the larger of n_hidden + 1 rounded up to a multiple of
+ * 16 and 64 * q, q the smallest power of two >= ceil(n_hidden / 64) (256
+ * for 200 hidden units, so 16,384 samples of that model fit in FP64);
+ * larger batches are rejected with NQS_EINVAL (split them).  All calls on one GPU
+ * share its scratch, which keeps the last call's contents (nothing in it
+ * needs to start at zero): calls that overlap on one GPU, from different
+ * streams or contexts, race.  s: device int8 [n][n_sites]; eloc_out:
+ * device float64 [n]; n >= 0. */
+int nqs_local_energy_noalloc(nqs_ctx* ctx, const int8_t* s, int64_t n, double* eloc_out);
+
 /* ln psi(s) for n configurations.  out: device, float64 [n] for NQS_FP64,
  * float32 [n] otherwise. */
 int nqs_log_psi(nqs_ctx* ctx, const int8_t* s, int64_t n, void* out);

@@ -22,6 +22,7 @@ EXPORTS = [
     "nqs_workspace_bytes", "nqs_bind_workspace", "nqs_set_params", "nqs_get_params",
     "nqs_reset_chains", "nqs_get_chains", "nqs_set_chains", "nqs_proposal_count",
     "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_thermalize", "nqs_load_samples", "nqs_local_energy",
+    "nqs_local_energy_noalloc",
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
     "nqs_vmc_step", "nqs_batch_step", "nqs_step_begin", "nqs_step_poll",
     "nqs_profile_enable", "nqs_profile_read",
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
         "nqs_thermalize": (I, [V, I]),
         "nqs_load_samples": (I, [V, V, I64]),
         "nqs_local_energy": (I, [V, V, I64, V]),
+        "nqs_local_energy_noalloc": (I, [V, V, I64, V]),
         "nqs_log_psi": (I, [V, V, I64, V]),
         "nqs_log_psi_vjp": (I, [V, V, I64, V, V]),
         "nqs_jacobian": (I, [V, V, I64, V, I]),

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,6 +103,8 @@ struct nqs_ctx {
     nqs_step_cfg step_cfg{};
     CgRun* step_run = nullptr;
     hipEvent_t step_ev = nullptr;
+    // device address of this GPU's static scratch (nqs_local_energy_noalloc)
+    void* scratch_dev = nullptr;
 };
 
 namespace {
@@ -746,6 +749,37 @@ __global__ void k_check_finite(const double* a, long n, int* flag) {
 
 }  // namespace
 
+// Static scratch of nqs_local_energy_noalloc, for callers that cannot
+// allocate device memory: the hidden activations tanh(theta) of the batch.
+// Every GPU the library runs on holds its own copy from module load until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): kernels get the device address
+// that hipGetSymbolAddress returns for the current device, looked up once per
+// device when a context is created there.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the static scratch on `device`, which must be current.
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_dev[device] = ptr;
+    }
+    return g_scratch_dev[device];
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -769,7 +803,8 @@ int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
         hipHostMalloc((void**)&c->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->flag_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->flag_ev[1], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->step_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->step_ev, hipEventDisableTiming) != hipSuccess ||
+        !(c->scratch_dev = scratch_address(device))) {
         nqs_destroy(c);
         return NQS_EDEVICE;
     }
@@ -1101,6 +1136,27 @@ int nqs_local_energy(nqs_ctx* c, const int8_t* s, int64_t n, double* eloc_out) {
         launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), sk, c->b.tx, m, eloc_out + k0,
                     c->lds_limit);
     }
+    return last_launch(c);
+}
+
+int nqs_local_energy_noalloc(nqs_ctx* c, const int8_t* s, int64_t n, double* eloc_out) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!s || !eloc_out))) return fail(c, NQS_EINVAL, "bad batch");
+    const size_t need = esize(c->prec) * (size_t)n * (size_t)c->d.Mw;
+    if (need > kNoallocScratchBytes) {
+        char msg[160];
+        snprintf(msg, sizeof msg,
+                 "batch needs %zu bytes of static scratch, more than its %zu bytes; split it",
+                 need, kNoallocScratchBytes);
+        return fail(c, NQS_EINVAL, msg);
+    }
+    if (n == 0) return NQS_OK;
+    // the same two kernels as nqs_local_energy, over the whole batch at once
+    // (each sample's result does not depend on how the batch is cut)
+    launch_theta(c->stream, c->d, c->prec, c->b.tab, s, (int)n, c->scratch_dev, nullptr, 0);
+    launch_eloc(c->stream, c->d, c->prec, c->b.tab, ham_dev(c), s, c->scratch_dev, (long)n,
+                eloc_out, c->lds_limit);
     return last_launch(c);
 }
 

@@ -222,6 +222,17 @@ class VMCState:
         self._check(self.lib.nqs_local_energy(self.ctx, _ptr(s), s.shape[0], _ptr(out)))
         return out
 
+    def local_energy_noalloc(self, s: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """Local energies into the caller's `out` (float64 [n] on the device) through
+        the entry point that allocates nothing (its staging is the library's static
+        scratch)."""
+        s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
+        if (out.dtype != torch.float64 or out.device != s.device or not out.is_contiguous()
+                or out.numel() < s.shape[0]):
+            raise ValueError("out must be a float64 device tensor with a slot per sample")
+        self._check(self.lib.nqs_local_energy_noalloc(self.ctx, _ptr(s), s.shape[0], _ptr(out)))
+        return out
+
     def log_psi(self, s: torch.Tensor) -> torch.Tensor:
         s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
         out = torch.empty(s.shape[0], dtype=self.rdtype, device=self.device)
