@@ -190,8 +190,10 @@ size_t layout(nqs_ctx* c, char* base) {
     b.tsm = take(es * (size_t)qgt_act_rows(c->Ns) * d.Mw);
     b.tx = take(es * (size_t)c->Bx * d.Mw);
     b.eloc = (double*)take(8 * (size_t)c->Bx);
-    b.vvec = (double*)take(8 * (size_t)c->Bx);
-    b.wbuf = (double*)take(8 * (size_t)c->Bx);
+    // per-sample vectors the contractions read in whole 512-sample chunks
+    const long Nvec = c->Bx > qgt_padded_samples(c->Ns) ? c->Bx : qgt_padded_samples(c->Ns);
+    b.vvec = (double*)take(8 * (size_t)Nvec);
+    b.wbuf = (double*)take(8 * (size_t)Nvec);
     b.stats = (double*)take(8 * 8);
     b.dpart = (double*)take(8 * (size_t)c->ndpart);
     b.acc_count = (uint32_t*)take(4 * (size_t)c->C);

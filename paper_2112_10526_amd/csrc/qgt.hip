@@ -786,8 +786,9 @@ __global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restric
 // MFMAs per k-step (hi and lo) with FP32 accumulation; the error of a
 // product is that of the two-term split of a, about 2^-17 relative.
 // 512 threads: for the staging, thread t takes samples 4 (t % 128) .. + 3 of
-// rows 4 (t / 128) .. + 3 and forms their z itself; for the contraction, wave
-// w takes site tiles w, w + 8, ...
+// rows 4 (t / 128) .. + 3 and forms their z itself (every wave sums the mean
+// of w in the same order, so no barrier precedes the staging); for the
+// contraction, wave w takes site tiles w, w + 8, ...
 constexpr int O8_THREADS = 512;
 __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8(Dims d, const uint8_t* __restrict__ St,
                                                        const float* __restrict__ Th, long Nsp, long n,
@@ -802,7 +803,6 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     constexpr int NW = O8_THREADS / 64;
     __shared__ __align__(16) uint16_t As[2 * 16 * KP];  // hi rows, then lo rows
     __shared__ double sh[NW];
-    __shared__ double mean_s;
     const int nj = d.Ma / 16;
     int jt, kc;
     outer_block(nj, jt, kc);
@@ -817,16 +817,14 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     float4 ta[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ta[q] = *(const float4*)(Ab + (size_t)q * Nsp);
-    double vk[4];
+    const double2 v01 = *(const double2*)(v + kbeg + 4 * c);  // v has Nsp slots
+    const double2 v23 = *(const double2*)(v + kbeg + 4 * c + 2);
+    const double vk[4] = {v01.x, v01.y, v23.x, v23.y};
+    double wp[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) vk[e] = v[min(kbeg + 4 * c + e, n - 1)];
-    double wp[4] = {0.0, 0.0, 0.0, 0.0};
-    if (v_mode == 0 && wave == 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int b = 64 * u + lane;
-            wp[u] = b < nbw ? wpart[b] : 0.0;
-        }
+    for (int u = 0; u < 4; ++u) {
+        const int b = 64 * u + lane;
+        wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
     }
     uint4 sp[4];  // FP4 spins of the lane's site in the chunk, positions 128 lk ..
     auto load_spins = [&](int it) {
@@ -838,23 +836,21 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     asm volatile("" ::: "memory");  // the loads above go out before the stop test
     if (done) return;               // (uniform over the block, before any barrier)
     __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
-    // ---- mean w over the batch (wave 0, fixed order), through LDS
-    if (wave == 0) {
+    // ---- mean w over the batch, summed by every wave in the same fixed order
+    double shift = 0.0, scale = 1.0;
+    if (v_mode == 0) {
         double a = (wp[0] + wp[1]) + (wp[2] + wp[3]);
-        if (v_mode == 0)
-            for (int b = 256 + lane; b < nbw; b += 64) a += wpart[b];
-        a = wave_sum(a);
-        if (lane == 0) mean_s = v_mode == 0 ? a / (double)n : 0.0;
+        for (int b = 256 + lane; b < nbw; b += 64) a += wpart[b];
+        shift = wave_sum(a) / (double)n;
+        scale = 1.0 / (double)n;
     }
-    __syncthreads();
-    const double shift = mean_s;
-    const double scale = v_mode == 0 ? 1.0 / (double)n : 1.0;
     float z[4];
     double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) (row group 0)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const double zz = kbeg + 4 * c + e < n ? (vk[e] - shift) * scale : 0.0;
-        zw += zz * (vk[e] - shift);
+    for (int e = 0; e < 4; ++e) {  // (v past n is not read as a number)
+        const bool in = kbeg + 4 * c + e < n;
+        const double zz = in ? (vk[e] - shift) * scale : 0.0;
+        zw += in ? zz * (vk[e] - shift) : 0.0;
         z[e] = (float)zz;
     }
     // ---- stage a = t~ z as hi / lo BF16 rows
@@ -887,7 +883,7 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
             const v8bf b = fp4x8_to_bf16(word_of(sp[u >> 2], u & 3));
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, acc, 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc2, 0, 0, 0);
-            if (u & 1) __builtin_amdgcn_sched_barrier(0);  // two k-steps of operands live at a time
+            if ((u & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four k-steps of operands live at a time
         }
         float* out = part + (size_t)kc * d.Ma * d.Na;
 #pragma unroll
