@@ -23,8 +23,8 @@ PROFILES = os.path.join(os.path.dirname(HERE), "profiles")
 
 # kernel class -> (source file of its kernel, symbol prefix in profiles)
 KERNELS = {  # (BF16 form, the benchmark's main run)
-    "qgt_w": ("qgt.hip", "k_w6"), "outer": ("qgt.hip", "k_outer7"),
-    "reduce": ("qgt.hip", "k_update4<float>"),
+    "qgt_w": ("qgt.hip", "k_w7"), "outer": ("qgt.hip", "k_outer8"),
+    "reduce": ("qgt.hip", "k_update5"),
     "sample": ("sampler.hip", "k_sample<float"), "eloc": ("eloc.hip", "k_eloc<float"),
     "theta": ("theta.hip", "k_theta_bf16"),
 }
@@ -147,7 +147,7 @@ def summarize_waves(counter_dir, cmd,
            "over waves.", "",
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
-    for name in ["nqs::k_w6", "nqs::k_outer7", "nqs::k_update4<float>",
+    for name in ["nqs::k_w7", "nqs::k_outer8", "nqs::k_update5",
                  "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
                  "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16"]:
         if name not in agg:
