@@ -12,6 +12,7 @@
 //
 // Spin configurations are int8 with values +1 / -1.
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -144,6 +145,71 @@ double local_energy(const Rbm& r, const Ham& H, const int8_t* s) {
             sp[a] = s[b];
             sp[b] = s[a];
             e += elem * std::exp(log_psi(r, sp.data()) - lp);
+            sp[a] = s[a];
+            sp[b] = s[b];
+        }
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Complex RBM (paper: complex parameters, holomorphic mapping theta -> psi):
+// the same log-amplitude with a, b, W complex,
+//   ln psi(s) = sum_i a_i s_i + sum_j ln cosh( b_j + sum_i W_ji s_i ).
+// ln cosh is multivalued for complex arguments; every use below goes through
+// a difference of two values inside exp() or a real part, which do not
+// depend on the branch.  Parameters: the full layout [a | b | W] of complex
+// numbers, each stored as (real, imaginary) doubles.
+// ---------------------------------------------------------------------------
+typedef std::complex<double> cplx;
+
+struct RbmC {
+    int N, M;
+    const cplx* a;
+    const cplx* b;
+    const cplx* W;
+};
+
+RbmC make_rbm_c(int N, int M, const double* p) {
+    const cplx* c = reinterpret_cast<const cplx*>(p);
+    return RbmC{N, M, c, c + N, c + N + M};
+}
+
+cplx theta_jc(const RbmC& r, const int8_t* s, int j) {
+    cplx th = r.b[j];
+    for (int i = 0; i < r.N; ++i) th += r.W[(size_t)j * r.N + i] * (double)s[i];
+    return th;
+}
+
+cplx log_psi_c(const RbmC& r, const int8_t* s) {
+    cplx v = 0.0;
+    for (int i = 0; i < r.N; ++i) v += r.a[i] * (double)s[i];
+    for (int j = 0; j < r.M; ++j) v += std::log(std::cosh(theta_jc(r, s, j)));
+    return v;
+}
+
+// Local estimator with complex amplitudes: sum_{s'} <s|H|s'> psi(s')/psi(s),
+// every ratio evaluated as exp(ln psi(s') - ln psi(s)).
+cplx local_energy_c(const RbmC& r, const Ham& H, const int8_t* s) {
+    const int N = r.N;
+    std::vector<int8_t> sp(s, s + N);
+    const cplx lp = log_psi_c(r, s);
+    cplx e = diagonal(H, s);
+    if (H.kind == 0) {
+        for (int i = 0; i < N; ++i) {
+            sp[i] = (int8_t)-sp[i];
+            e += -H.h * std::exp(log_psi_c(r, sp.data()) - lp);
+            sp[i] = s[i];
+        }
+    } else {
+        for (int k = 0; k < H.n_bonds; ++k) {
+            const int a = H.bonds[2 * k], b = H.bonds[2 * k + 1];
+            if (s[a] == s[b]) continue;
+            double elem = 2.0 * H.J;
+            if (H.sub && ((H.sub[a] + H.sub[b]) & 1)) elem = -elem;
+            sp[a] = s[b];
+            sp[b] = s[a];
+            e += elem * std::exp(log_psi_c(r, sp.data()) - lp);
             sp[a] = s[a];
             sp[b] = s[b];
         }
@@ -325,6 +391,133 @@ void ora_jacobian(int N, int M, const double* params, const int8_t* s, int64_t n
             const double t = std::tanh(theta_j(r, sk, j));
             o[N + j] = t;
             for (int i = 0; i < N; ++i) o[N + M + (size_t)j * N + i] = t * sk[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Complex RBM entry points.  params: 2 (N + M + M N) doubles, the full layout
+// of complex numbers as (real, imaginary) pairs; complex outputs likewise.
+// ---------------------------------------------------------------------------
+void ora_log_psi_c(int N, int M, const double* params, const int8_t* s, int64_t n, double* out) {
+    const RbmC r = make_rbm_c(N, M, params);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        const cplx v = log_psi_c(r, s + (size_t)k * N);
+        out[2 * k] = v.real();
+        out[2 * k + 1] = v.imag();
+    }
+}
+
+// Metropolis sampling of |psi|^2 for the complex RBM: the same proposals,
+// draws and recording as ora_sample (local or exchange rule); a move is
+// accepted iff u < |psi(s')/psi(s)|^2 = exp(2 Re[ln psi(s') - ln psi(s)]).
+// mode 0: ln psi(s') from scratch at every proposal; mode 1: complex theta kept
+// per chain, updated on acceptance and recomputed after every recorded sample.
+void ora_sample_c(int N, int M, const double* params, int rule, int n_bonds,
+                  const int32_t* bonds, int C, int S, int K, uint64_t seed,
+                  uint64_t prop_base, int chain_offset, int mode, int8_t* chains,
+                  int8_t* samples, uint8_t* accept_log, double* margins, int64_t* n_acc) {
+    const RbmC r = make_rbm_c(N, M, params);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < C; ++c) {
+        const uint32_t g = (uint32_t)(chain_offset + c);
+        int8_t* s = chains + (size_t)c * N;
+        std::vector<int8_t> sp(N);
+        std::vector<cplx> theta(M), thetap(M);
+        cplx lp = log_psi_c(r, s);
+        if (mode == 1)
+            for (int j = 0; j < M; ++j) theta[j] = theta_jc(r, s, j);
+        double margin = INFINITY;
+        int64_t acc = 0;
+        for (int q = 0; q < S * K; ++q) {
+            const uint64_t p = prop_base + (uint64_t)q;
+            Words4 x = draw(p, g, 0, seed);
+            const double u = uniform53(x.w[1], x.w[2]);
+            int f0 = -1, f1 = -1;
+            if (rule == 0) {
+                f0 = pick(x.w[0], N);
+            } else {
+                const int k = pick(x.w[0], n_bonds);
+                const int a = bonds[2 * k], b = bonds[2 * k + 1];
+                if (s[a] != s[b]) { f0 = a; f1 = b; }
+            }
+            bool accept;
+            if (f0 < 0) {
+                accept = true;
+            } else {
+                std::memcpy(sp.data(), s, N);
+                sp[f0] = (int8_t)-sp[f0];
+                if (f1 >= 0) sp[f1] = (int8_t)-sp[f1];
+                cplx lpp = 0.0, dlog;
+                if (mode == 0) {
+                    lpp = log_psi_c(r, sp.data());
+                    dlog = lpp - lp;
+                } else {
+                    dlog = 0.0;
+                    for (int i = 0; i < N; ++i) dlog += r.a[i] * (double)(sp[i] - s[i]);
+                    for (int j = 0; j < M; ++j) {
+                        cplx th = theta[j];
+                        th += r.W[(size_t)j * N + f0] * (double)(sp[f0] - s[f0]);
+                        if (f1 >= 0) th += r.W[(size_t)j * N + f1] * (double)(sp[f1] - s[f1]);
+                        thetap[j] = th;
+                        dlog += std::log(std::cosh(th)) - std::log(std::cosh(theta[j]));
+                    }
+                }
+                const double ratio2 = std::exp(2.0 * dlog.real());
+                const double m = std::fabs(u - ratio2);
+                if (m < margin) margin = m;
+                accept = u < ratio2;
+                if (accept) {
+                    std::memcpy(s, sp.data(), N);
+                    if (mode == 0) lp = lpp;
+                    else theta.swap(thetap);
+                }
+            }
+            if (accept) ++acc;
+            if (accept_log) accept_log[(size_t)c * S * K + q] = accept ? 1 : 0;
+            if ((q + 1) % K == 0) {
+                const int sample = (q + 1) / K - 1;
+                if (samples) std::memcpy(samples + ((size_t)c * S + sample) * N, s, N);
+                if (mode == 1)
+                    for (int j = 0; j < M; ++j) theta[j] = theta_jc(r, s, j);
+                else
+                    lp = log_psi_c(r, s);
+            }
+        }
+        if (margins) margins[c] = margin;
+        if (n_acc) n_acc[c] = acc;
+    }
+}
+
+void ora_local_energy_c(int N, int M, const double* params, int kind, int n_bonds,
+                        const int32_t* bonds, double J, double h, const int8_t* sub,
+                        const int8_t* s, int64_t n, double* out) {
+    const RbmC r = make_rbm_c(N, M, params);
+    const Ham H{kind, n_bonds, bonds, J, h, sub};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; ++k) {
+        const cplx e = local_energy_c(r, H, s + (size_t)k * N);
+        out[2 * k] = e.real();
+        out[2 * k + 1] = e.imag();
+    }
+}
+
+// Holomorphic log-derivatives O_k(s) = d ln psi(s) / d p_k (complex):
+//   O_a_i = s_i,  O_b_j = tanh theta_j,  O_W_ji = tanh(theta_j) s_i.
+void ora_jacobian_c(int N, int M, const double* params, const int8_t* s, int64_t n,
+                    double* O) {
+    const RbmC r = make_rbm_c(N, M, params);
+    const size_t P = (size_t)N + M + (size_t)M * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        const int8_t* sk = s + (size_t)k * N;
+        cplx* o = reinterpret_cast<cplx*>(O) + (size_t)k * P;
+        for (int i = 0; i < N; ++i) o[i] = (double)sk[i];
+        for (int j = 0; j < M; ++j) {
+            const cplx t = std::tanh(theta_jc(r, sk, j));
+            o[N + j] = t;
+            for (int i = 0; i < N; ++i) o[N + M + (size_t)j * N + i] = t * (double)sk[i];
         }
     }
 }
