@@ -57,7 +57,7 @@ typedef enum {
     NQS_ESTATE = 6     /* call out of order (e.g. no Hamiltonian set yet) */
 } nqs_status;
 
-typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2 } nqs_precision;
+typedef enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_C128 = 3 } nqs_precision;
 typedef enum { NQS_RULE_LOCAL = 0, NQS_RULE_EXCHANGE = 1 } nqs_rule;
 typedef enum { NQS_QGT_ONTHEFLY = 0, NQS_QGT_JACOBIAN_DENSE = 1 } nqs_qgt;
 
@@ -92,6 +92,30 @@ typedef struct {
     nqs_sr_info sr;
     int status;         /* status of this context's step (batched calls) */
 } nqs_step_report;
+
+/* Runge-Kutta schemes of the TDVP step. */
+typedef enum { NQS_RK_EULER = 0, NQS_RK_HEUN = 1 } nqs_rk_scheme;
+
+/* Settings of one TDVP step (complex-parameter models only). */
+typedef struct {
+    nqs_rk_scheme scheme;
+    double dt;              /* time step */
+    double gamma_re;        /* gamma in G theta_dot = gamma f: -i for real time */
+    double gamma_im;        /*   (gamma_re 0, gamma_im -1), -1 for imaginary time */
+    double diag_shift;      /* epsilon added to G's diagonal */
+    double cg_tol;          /* relative residual tolerance of each solve */
+    int cg_maxiter;         /* <= 0: min(2 P, 10000) */
+} nqs_tdvp_cfg;
+
+/* What one TDVP step reports: one entry per evaluation of the equation of
+ * motion (1 for Euler, 2 for Heun). */
+typedef struct {
+    int stages;
+    nqs_stats energy[2];    /* energy[l].mean: real part of the mean local energy */
+    double energy_im[2];    /* imaginary part of that mean */
+    nqs_sr_info solve[2];
+    int status;
+} nqs_tdvp_report;
 
 /* ------------------------------------------------------------------------- */
 /* Context lifetime                                                          */
@@ -148,8 +172,18 @@ int nqs_set_heisenberg(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bo
  *    scalar in FP64.
  *  - NQS_BF16: as NQS_FP32, except that the W s + b contraction runs on the
  *    BF16 matrix cores with FP32 accumulation (W split into two BF16 terms).
- * Requires a Hamiltonian.  Errors: NQS_EINVAL (n_hidden < 1, bad prec),
- * NQS_ESTATE. */
+ *  - NQS_C128: complex parameters a, b, W with the holomorphic mapping
+ *    theta -> psi (paper, complex parameters; complex co-gradient and SR
+ *    equations; TDVP), complex FP64 throughout.  Parameter, gradient and
+ *    direction vectors hold 2 P doubles, (real, imaginary) pairs in the
+ *    packed order; local energies and ln psi are (real, imaginary) pairs.
+ *    The QGT is the dense holomorphic one, G = dJ^H dJ (dense Jacobian form
+ *    only), solved as the equivalent real symmetric system of size 2 P on
+ *    the FP64 matrix cores.  Supported with the TFIM, the local rule, both
+ *    biases and n_hidden <= 512; nqs_log_psi_vjp, the batched and
+ *    asynchronous steps and nqs_local_energy_noalloc reject it.
+ * Requires a Hamiltonian.  Errors: NQS_EINVAL (n_hidden < 1, bad prec, or a
+ * combination NQS_C128 does not support), NQS_ESTATE. */
 int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,
                 nqs_precision prec);
 
@@ -313,6 +347,19 @@ int nqs_sr_update(nqs_ctx* ctx, nqs_qgt kind, double diag_shift, double lr, doub
 /* One VMC step: nqs_sample -> nqs_expect_and_grad -> nqs_sr_update (paper,
  * ground-state search with the SR preconditioner).  rep: host, required. */
 int nqs_vmc_step(nqs_ctx* ctx, const nqs_step_cfg* cfg, nqs_step_report* rep);
+
+/* One step of time-dependent variational Monte Carlo for a complex (NQS_C128)
+ * model (paper, time propagation: the TDVP equation of motion
+ * G theta_dot = gamma f and the Runge-Kutta step).  Each evaluation of the
+ * equation of motion samples the current parameters (nqs_sample semantics,
+ * the chains continue), forms the local energies, the force f and the dense
+ * holomorphic QGT, and solves (G + diag_shift I) x = f by CG from x = 0;
+ * theta_dot = gamma x.  Euler: theta <- theta + dt k1.  Heun: k1 at theta,
+ * k2 at theta + dt k1, theta <- theta + dt (k1 + k2) / 2.  gamma = -i gives
+ * real-time evolution, -1 imaginary time.  rep: host, required.  Errors:
+ * NQS_EINVAL (not a complex model, bad settings), NQS_ENOTCONV (a solve hit
+ * maxiter; the step is still taken), NQS_ENUMERIC. */
+int nqs_tdvp_step(nqs_ctx* ctx, const nqs_tdvp_cfg* cfg, nqs_tdvp_report* rep);
 
 /* One VMC step for each of n contexts (each on its own stream), issued in
  * lock-step so that the contexts' kernels overlap on the device.  Each

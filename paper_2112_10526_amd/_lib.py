@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(HERE, "libnqs.so")
 NQS_OK, NQS_EINVAL, NQS_ENOMEM, NQS_EDEVICE, NQS_ENUMERIC, NQS_ENOTCONV, NQS_ESTATE = range(7)
 STATUS_NAMES = {0: "NQS_OK", 1: "NQS_EINVAL", 2: "NQS_ENOMEM", 3: "NQS_EDEVICE",
                 4: "NQS_ENUMERIC", 5: "NQS_ENOTCONV", 6: "NQS_ESTATE"}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "c128": 3}
+RK_SCHEMES = {"euler": 0, "heun": 1}
 RULES = {"local": 0, "exchange": 1}
 QGTS = {"onthefly": 0, "jacobian_dense": 1}
 
@@ -24,7 +25,7 @@ EXPORTS = [
     "nqs_get_state", "nqs_set_state", "nqs_sample", "nqs_thermalize", "nqs_load_samples", "nqs_local_energy",
     "nqs_local_energy_noalloc",
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
-    "nqs_vmc_step", "nqs_batch_step", "nqs_step_begin", "nqs_step_poll",
+    "nqs_vmc_step", "nqs_tdvp_step", "nqs_batch_step", "nqs_step_begin", "nqs_step_poll",
     "nqs_profile_enable", "nqs_profile_read",
     "nqs_profile_class_name", "nqs_set_cg_graphs",
 ]
@@ -49,6 +50,18 @@ class NqsStepCfg(ctypes.Structure):
 
 class NqsStepReport(ctypes.Structure):
     _fields_ = [("energy", NqsStats), ("sr", NqsSrInfo), ("status", ctypes.c_int)]
+
+
+class NqsTdvpCfg(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("dt", ctypes.c_double), ("gamma_re", ctypes.c_double),
+                ("gamma_im", ctypes.c_double), ("diag_shift", ctypes.c_double),
+                ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int)]
+
+
+class NqsTdvpReport(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int), ("energy", NqsStats * 2),
+                ("energy_im", ctypes.c_double * 2), ("solve", NqsSrInfo * 2),
+                ("status", ctypes.c_int)]
 
 
 _lib = None
@@ -97,6 +110,7 @@ def load(path: str = LIB_PATH):
         "nqs_expect_and_grad": (I, [V, ctypes.POINTER(NqsStats), V]),
         "nqs_sr_update": (I, [V, I, D, D, D, I, V, ctypes.POINTER(NqsSrInfo)]),
         "nqs_vmc_step": (I, [V, ctypes.POINTER(NqsStepCfg), ctypes.POINTER(NqsStepReport)]),
+        "nqs_tdvp_step": (I, [V, ctypes.POINTER(NqsTdvpCfg), ctypes.POINTER(NqsTdvpReport)]),
         "nqs_batch_step": (I, [ctypes.POINTER(V), I, ctypes.POINTER(NqsStepCfg),
                                ctypes.POINTER(NqsStepReport)]),
         "nqs_step_begin": (I, [V, ctypes.POINTER(NqsStepCfg)]),

@@ -39,6 +39,11 @@ struct Buffers {
     void* G;
     double *colsum, *fp, *xp, *rp, *pp, *App;
     int* tiles;
+    // complex (holomorphic) model: parameters (and a saved copy), tables,
+    // activations of the chains, of the sample batch and of a local-energy
+    // batch, local energies, Jacobian column means, the TDVP's first slope
+    double2 *hp, *hp0, *hT, *hK, *htch, *htsm, *htx, *heloc, *hmean;
+    double* hk1;
 };
 
 }  // namespace
@@ -59,6 +64,8 @@ struct nqs_ctx {
     // model
     bool has_model = false;
     int M = 0, vb = 1, hb = 1, prec = 0;
+    bool cplx = false;  // complex parameters (NQS_C128)
+    int Pd = 0;         // size of the dense SR system: P, or 2 P (real embedding)
     Dims d{};
     size_t P = 0;
     // sampler
@@ -149,8 +156,11 @@ int last_launch(nqs_ctx* c) {
 
 size_t esize(int prec) { return prec == 0 ? 8 : 4; }
 
+size_t layout_holo(nqs_ctx* c, char* base);
+
 // Walk the workspace; with base == nullptr only the size is computed.
 size_t layout(nqs_ctx* c, char* base) {
+    if (c->cplx) return layout_holo(c, base);
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
         off = (off + ALIGN - 1) / ALIGN * ALIGN;
@@ -233,6 +243,53 @@ size_t layout(nqs_ctx* c, char* base) {
     return (off + ALIGN - 1) / ALIGN * ALIGN;
 }
 
+// The complex model's workspace: its own parameter, table and activation
+// buffers; chains, samples, scalars and the dense-QGT buffers as in the real
+// layout, with the embedded Jacobian Y [2 Ns][Pld] in O and the Gram matrix
+// of the 2 P-dimensional embedded system in G (whose buffer first holds the
+// slice partials of the column sums and of the force).
+size_t layout_holo(nqs_ctx* c, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + ALIGN - 1) / ALIGN * ALIGN;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t P = c->P, N = (size_t)c->N, M = (size_t)c->M, C = (size_t)c->C;
+    const size_t Ns = (size_t)c->Ns, Bx = (size_t)c->Bx, Pld = (size_t)c->Pld;
+    Buffers& b = c->b;
+    b = Buffers{};
+    b.hp = (double2*)take(16 * P);
+    b.hp0 = (double2*)take(16 * P);
+    b.hT = (double2*)take(16 * N * M);
+    b.hK = (double2*)take(16 * 2 * N);
+    b.bonds = (int32_t*)take(8 * c->bonds.size() / 2 + 8);
+    b.sub = (int8_t*)take(N + 16);
+    b.chains = (int8_t*)take(C * N);
+    b.htch = (double2*)take(16 * C * M);
+    b.samples = (int8_t*)take(Ns * N);
+    b.htsm = (double2*)take(16 * Ns * M);
+    b.htx = (double2*)take(16 * Bx * M);
+    b.heloc = (double2*)take(16 * (Ns > Bx ? Ns : Bx));
+    b.stats = (double*)take(8 * 8);
+    b.dpart = (double*)take(8 * (size_t)c->ndpart);
+    b.acc_count = (uint32_t*)take(4 * C);
+    b.sc = (CgScalars*)take(sizeof(CgScalars));
+    b.O = take(8 * 2 * Ns * Pld);
+    const size_t gb = 8 * (size_t)c->Pd * Pld, sb = h_slice_bytes((int)P);
+    b.G = take(gb > sb ? gb : sb);
+    b.hmean = (double2*)take(16 * P);
+    b.fp = (double*)take(8 * Pld);
+    b.xp = (double*)take(8 * Pld);
+    b.rp = (double*)take(8 * Pld);
+    b.pp = (double*)take(8 * Pld);
+    b.App = (double*)take(8 * Pld);
+    b.hk1 = (double*)take(8 * Pld);
+    b.tiles = (int*)take(8 * (size_t)c->ntiles);
+    return (off + ALIGN - 1) / ALIGN * ALIGN;
+}
+
 bool configured(const nqs_ctx* c) { return c->ham_kind >= 0 && c->has_model && c->has_sampler; }
 
 void derive(nqs_ctx* c) {
@@ -253,15 +310,17 @@ void derive(nqs_ctx* c) {
     d.vb = c->vb;
     d.hb = c->hb;
     c->P = (size_t)(c->vb ? c->N : 0) + (c->hb ? c->M : 0) + (size_t)c->M * c->N;
+    c->cplx = c->prec == NQS_C128;
+    c->Pd = (int)(c->cplx ? 2 * c->P : c->P);
     if (c->has_sampler) {
         c->Ns = (long)c->C * c->S;
         c->Bx = c->Ns > 1024 ? c->Ns : 1024;
         c->chunk = outer_chunk(d, c->prec, c->lds_limit);
         c->ksplit = outer_ksplit(c->Bx, c->chunk);
-        c->Pld = round_up((int)c->P, 128);
-        c->ntiles = gram_tiles((int)c->P);
+        c->Pld = round_up(c->Pd, 128);
+        c->ntiles = gram_tiles(c->Pd);
         long nd = (long)d.Ma * d.Na / 256 + 2;
-        const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->P / 4 + 2;
+        const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->Pd / 4 + 2;
         if (nd2 > nd) nd = nd2;
         if (nd3 > nd) nd = nd3;
         c->ndpart = (int)nd;
@@ -556,13 +615,13 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host
         } else {
             {
                 PROF(NQS_PROF_DENSE_MV);
-                launch_dense_matvec(c->stream, c->prec, c->b.G, (int)c->P, c->Pld, c->b.pp, shift,
+                launch_dense_matvec(c->stream, c->cplx ? 0 : c->prec, c->b.G, c->Pd, c->Pld, c->b.pp, shift,
                                     c->b.App, c->b.dpart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_CGVEC);
-                launch_cg_update(c->stream, (int)c->P, c->b.xp, c->b.rp, c->b.pp, c->b.App,
-                                 c->b.dpart, dense_matvec_blocks((int)c->P), c->b.sc);
+                launch_cg_update(c->stream, c->Pd, c->b.xp, c->b.rp, c->b.pp, c->b.App,
+                                 c->b.dpart, dense_matvec_blocks(c->Pd), c->b.sc);
             }
         }
     }
@@ -733,7 +792,119 @@ int run_cg(nqs_ctx* c, int kind, double shift, int maxiter) {
 
 int default_maxiter(const nqs_ctx* c, int maxiter) {
     if (maxiter > 0) return maxiter;
-    return c->P < 10000 ? (int)c->P : 10000;
+    return c->Pd < 10000 ? c->Pd : 10000;
+}
+
+// ---- the complex (holomorphic) model ----------------------------------------
+size_t param_doubles(const nqs_ctx* c) { return c->cplx ? 2 * c->P : c->P; }
+
+int h_check(nqs_ctx* c) {
+    if (c->ham_kind != 0) return fail(c, NQS_EINVAL, "complex models take the TFIM");
+    if (c->has_sampler && c->rule != NQS_RULE_LOCAL)
+        return fail(c, NQS_EINVAL, "complex models take the local rule");
+    return NQS_OK;
+}
+
+void h_tables(nqs_ctx* c) { launch_h_tables(c->stream, c->N, c->M, c->b.hp, c->b.hT, c->b.hK); }
+
+void h_refresh_chains(nqs_ctx* c) {
+    if (!c->chains_dirty) return;
+    {
+        PROF(NQS_PROF_THETA);
+        launch_h_theta(c->stream, c->N, c->M, c->b.hp, c->b.chains, c->C, c->b.htch, nullptr, 0);
+    }
+    c->chains_dirty = false;
+}
+
+// n_discard unrecorded segments, then S recorded ones (as issue_sample); the
+// activations are recomputed from the configurations after every segment
+void h_issue_sample(nqs_ctx* c, int n_discard, int n_record, uint8_t* accept_log) {
+    h_refresh_chains(c);
+    SampleArgs a{};
+    a.C = c->C;
+    a.K = c->K;
+    a.seed = c->seed;
+    a.s = c->b.chains;
+    for (int q = 0; q < n_discard; ++q) {
+        a.prop_base = c->prop;
+        a.record = 0;
+        {
+            PROF(NQS_PROF_SAMPLE);
+            launch_h_sample(c->stream, c->N, c->M, c->b.hT, c->b.hK, a, c->b.htch);
+        }
+        c->prop += (uint64_t)c->K;
+        {
+            PROF(NQS_PROF_THETA);
+            launch_h_theta(c->stream, c->N, c->M, c->b.hp, c->b.chains, c->C, c->b.htch, nullptr, 0);
+        }
+    }
+    if (!n_record) return;
+    launch_zero(c->stream, c->b.acc_count, 4 * (size_t)c->C);
+    a.acc_count = c->b.acc_count;
+    a.acc_log = accept_log;
+    a.log_stride = (long)c->S * c->K;
+    for (int q = 0; q < c->S; ++q) {
+        a.prop_base = c->prop;
+        a.record = 1;
+        a.rec = c->b.samples + (size_t)q * c->N;
+        a.rec_stride = (long)c->S * c->N;
+        a.log_offset = (long)q * c->K;
+        {
+            PROF(NQS_PROF_SAMPLE);
+            launch_h_sample(c->stream, c->N, c->M, c->b.hT, c->b.hK, a, c->b.htch);
+        }
+        c->prop += (uint64_t)c->K;
+        {
+            PROF(NQS_PROF_THETA);
+            launch_h_theta(c->stream, c->N, c->M, c->b.hp, c->b.chains, c->C, c->b.htch,
+                           c->b.htsm + (size_t)q * c->M, (long)c->S * c->M);
+        }
+    }
+    c->have_samples = true;
+    c->have_grad = false;
+}
+
+// local energies, statistics, the embedded Jacobian and the embedded force
+void h_issue_energy_grad(nqs_ctx* c) {
+    const long n = c->Ns;
+    {
+        PROF(NQS_PROF_ELOC);
+        launch_h_eloc(c->stream, c->N, c->M, c->b.hT, c->b.hK, ham_dev(c), c->b.samples, c->b.htsm,
+                      n, c->b.heloc);
+    }
+    {
+        PROF(NQS_PROF_STATS);
+        launch_h_stats(c->stream, c->b.heloc, n, c->b.stats);
+    }
+    {
+        PROF(NQS_PROF_JACOBIAN);
+        launch_h_jacobian_emb(c->stream, c->N, c->M, c->b.samples, c->b.htsm, n, (int)c->P, c->Pld,
+                              (double*)c->b.O, c->b.hmean, (double*)c->b.G);
+        launch_h_force(c->stream, (const double*)c->b.O, n, c->Pld, c->Pd, c->b.heloc, c->b.stats,
+                       c->b.fp, (double*)c->b.G);
+    }
+    c->have_grad = true;
+}
+
+// the Gram matrix of the embedded system and its CG solve (x in xp)
+int h_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
+    const int mi = default_maxiter(c, maxiter);
+    {
+        PROF(NQS_PROF_GRAM);
+        launch_gram(c->stream, 0, c->b.O, 2 * c->Ns, c->Pld, c->Pd, c->b.G, c->b.tiles, c->ntiles);
+    }
+    launch_cg_init(c->stream, c->Pd, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
+                   mi);
+    return run_cg(c, NQS_QGT_JACOBIAN_DENSE, diag_shift, mi);
+}
+
+// new parameters: the tables follow; the chains' activations and the held batch
+// belong to the old ones
+void h_params_changed(nqs_ctx* c) {
+    h_tables(c);
+    c->chains_dirty = true;
+    c->have_grad = false;
+    c->have_samples = false;
 }
 
 __global__ void k_f32_to_f64(const float* a, double* b, long n) {
@@ -855,8 +1026,17 @@ int nqs_set_rbm(nqs_ctx* c, int n_hidden, int visible_bias, int hidden_bias, nqs
     if (!c) return NQS_EINVAL;
     if (c->ham_kind < 0) return fail(c, NQS_ESTATE, "set a Hamiltonian first");
     if (n_hidden < 1 || n_hidden > 2048) return fail(c, NQS_EINVAL, "n_hidden must be in [1, 2048]");
-    if (prec < NQS_FP64 || prec > NQS_BF16) return fail(c, NQS_EINVAL, "bad precision");
+    if (prec < NQS_FP64 || prec > NQS_C128) return fail(c, NQS_EINVAL, "bad precision");
     if (c->N > 4096) return fail(c, NQS_EINVAL, "at most 4096 sites");
+    if (prec == NQS_C128) {
+        if (!visible_bias || !hidden_bias)
+            return fail(c, NQS_EINVAL, "complex models keep both biases");
+        if (n_hidden > h_max_hidden())
+            return fail(c, NQS_EINVAL, "complex models take at most " +
+                                           std::to_string(h_max_hidden()) + " hidden units");
+        if (c->ham_kind != 0) return fail(c, NQS_EINVAL, "complex models take the TFIM");
+        c->qgt = NQS_QGT_JACOBIAN_DENSE;
+    }
     c->M = n_hidden;
     c->vb = visible_bias ? 1 : 0;
     c->hb = hidden_bias ? 1 : 0;
@@ -879,6 +1059,8 @@ int nqs_set_sampler(nqs_ctx* c, nqs_rule rule, int n_chains, int samples_per_cha
         return fail(c, NQS_EINVAL, "chains, samples and sweep size must be positive");
     if ((long)n_chains * samples_per_chain > (1L << 26)) return fail(c, NQS_EINVAL, "too many samples");
     if (total_sz_zero && (c->N % 2)) return fail(c, NQS_EINVAL, "total_sz_zero needs even n_sites");
+    if (c->cplx && rule != NQS_RULE_LOCAL)
+        return fail(c, NQS_EINVAL, "complex models take the local rule");
     c->rule = (int)rule;
     c->C = n_chains;
     c->S = samples_per_chain;
@@ -899,6 +1081,8 @@ int nqs_set_qgt(nqs_ctx* c, nqs_qgt kind) {
     if (!c) return NQS_EINVAL;
     if (kind != NQS_QGT_ONTHEFLY && kind != NQS_QGT_JACOBIAN_DENSE)
         return fail(c, NQS_EINVAL, "bad QGT kind");
+    if (c->cplx && kind != NQS_QGT_JACOBIAN_DENSE)
+        return fail(c, NQS_EINVAL, "complex models use the dense holomorphic QGT");
     if (c->qgt != (int)kind) {
         c->qgt = (int)kind;
         invalidate_binding(c);
@@ -919,6 +1103,10 @@ size_t nqs_workspace_bytes(const nqs_ctx* c) {
 int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
     if (!c) return NQS_EINVAL;
     if (!configured(c)) return fail(c, NQS_ESTATE, "Hamiltonian, RBM and sampler must be set");
+    if (c->cplx) {
+        const int st = h_check(c);
+        if (st) return st;
+    }
     const size_t need = layout(c, nullptr);
     if (!dev_ptr || bytes < need)
         return fail(c, NQS_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
@@ -936,7 +1124,7 @@ int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
                              c->stream));
     if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
         std::vector<int> t(2 * (size_t)c->ntiles);
-        fill_gram_tiles((int)c->P, t.data());
+        fill_gram_tiles(c->Pd, t.data());
         HIPCHK(c, hipMemcpyAsync(c->b.tiles, t.data(), 4 * t.size(), hipMemcpyHostToDevice,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -957,15 +1145,29 @@ int nqs_set_params(nqs_ctx* c, const double* p, int on_device) {
     if (!p) return fail(c, NQS_EINVAL, "null parameters");
     int st = set_device(c);
     if (st) return st;
-    std::vector<double> h(c->P);
+    const size_t np = param_doubles(c);
+    std::vector<double> h(np);
     if (on_device) {
-        HIPCHK(c, hipMemcpyAsync(h.data(), p, 8 * c->P, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(h.data(), p, 8 * np, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     } else {
-        std::memcpy(h.data(), p, 8 * c->P);
+        std::memcpy(h.data(), p, 8 * np);
     }
-    for (size_t k = 0; k < c->P; ++k)
+    for (size_t k = 0; k < np; ++k)
         if (!std::isfinite(h[k])) return fail(c, NQS_ENUMERIC, "non-finite parameter");
+    if (c->cplx) {
+        HIPCHK(c, hipMemcpyAsync(c->b.hp, h.data(), 8 * np, hipMemcpyHostToDevice, c->stream));
+        const bool held = c->have_samples;
+        h_params_changed(c);
+        if (held) {  // activations of the held batch follow the new parameters
+            launch_h_theta(c->stream, c->N, c->M, c->b.hp, c->b.samples, c->Ns, c->b.htsm,
+                           nullptr, 0);
+            c->have_samples = true;
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->params_set = true;
+        return last_launch(c);
+    }
     HIPCHK(c, hipMemcpyAsync(c->b.tmpv, h.data(), 8 * c->P, hipMemcpyHostToDevice, c->stream));
     launch_unpack(c->stream, c->d, c->b.tmpv, c->b.Pm, (int)c->P);
     launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
@@ -983,6 +1185,13 @@ int nqs_get_params(nqs_ctx* c, double* p, int on_device) {
     int st = need_bound(c);
     if (st) return st;
     if (!p) return fail(c, NQS_EINVAL, "null output");
+    if (c->cplx) {
+        HIPCHK(c, hipMemcpyAsync(p, c->b.hp, 16 * c->P,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return last_launch(c);
+    }
     launch_pack(c->stream, c->d, c->b.Pm, c->b.tmpv, (int)c->P);
     HIPCHK(c, hipMemcpyAsync(p, c->b.tmpv, 8 * c->P,
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
@@ -1024,7 +1233,7 @@ int nqs_get_state(nqs_ctx* c, void* blob, size_t* bytes) {
     int st = need_bound(c);
     if (st) return st;
     if (!bytes) return fail(c, NQS_EINVAL, "null size");
-    const size_t need = 32 + 8 * c->P + (size_t)c->C * c->N;
+    const size_t need = 32 + 8 * param_doubles(c) + (size_t)c->C * c->N;
     if (!blob) {
         *bytes = need;
         return NQS_OK;
@@ -1036,7 +1245,7 @@ int nqs_get_state(nqs_ctx* c, void* blob, size_t* bytes) {
     std::memcpy(o, hdr, 32);
     st = nqs_get_params(c, (double*)(o + 32), 0);
     if (st) return st;
-    st = nqs_get_chains(c, (int8_t*)(o + 32 + 8 * c->P), 0);
+    st = nqs_get_chains(c, (int8_t*)(o + 32 + 8 * param_doubles(c)), 0);
     if (st) return st;
     *bytes = need;
     return NQS_OK;
@@ -1045,7 +1254,7 @@ int nqs_get_state(nqs_ctx* c, void* blob, size_t* bytes) {
 int nqs_set_state(nqs_ctx* c, const void* blob, size_t bytes) {
     if (!c) return NQS_EINVAL;
     if (!c->bound) return fail(c, NQS_ESTATE, "no workspace bound");
-    const size_t need = 32 + 8 * c->P + (size_t)c->C * c->N;
+    const size_t need = 32 + 8 * param_doubles(c) + (size_t)c->C * c->N;
     if (!blob || bytes < need) return fail(c, NQS_EINVAL, "blob too small");
     uint64_t hdr[4];
     std::memcpy(hdr, blob, 32);
@@ -1055,7 +1264,7 @@ int nqs_set_state(nqs_ctx* c, const void* blob, size_t bytes) {
     const char* in = (const char*)blob;
     int st = nqs_set_params(c, (const double*)(in + 32), 0);
     if (st) return st;
-    st = nqs_set_chains(c, (const int8_t*)(in + 32 + 8 * c->P), 0);
+    st = nqs_set_chains(c, (const int8_t*)(in + 32 + 8 * param_doubles(c)), 0);
     if (st) return st;
     c->prop = hdr[3];
     c->have_samples = c->have_grad = false;
@@ -1069,7 +1278,8 @@ int nqs_sample(nqs_ctx* c, int n_discard_segments, int8_t* samples_out, uint8_t*
     if (n_discard_segments < 0) return fail(c, NQS_EINVAL, "negative discard count");
     st = set_device(c);
     if (st) return st;
-    issue_sample(c, n_discard_segments, accept_log);
+    if (c->cplx) h_issue_sample(c, n_discard_segments, 1, accept_log);
+    else issue_sample(c, n_discard_segments, accept_log);
     if (samples_out)
         HIPCHK(c, hipMemcpyAsync(samples_out, c->b.samples, (size_t)c->Ns * c->N,
                                  hipMemcpyDeviceToDevice, c->stream));
@@ -1089,6 +1299,10 @@ int nqs_thermalize(nqs_ctx* c, int n_segments) {
     if (n_segments < 0) return fail(c, NQS_EINVAL, "negative segment count");
     st = set_device(c);
     if (st) return st;
+    if (c->cplx) {
+        h_issue_sample(c, n_segments, 0, nullptr);
+        return last_launch(c);
+    }
     refresh_chains(c);
     SampleArgs a{};
     a.C = c->C;
@@ -1121,7 +1335,11 @@ int nqs_load_samples(nqs_ctx* c, const int8_t* samples, int64_t n_samples) {
         return fail(c, NQS_EINVAL, "n_samples must equal n_chains * samples_per_chain");
     HIPCHK(c, hipMemcpyAsync(c->b.samples, samples, (size_t)c->Ns * c->N, hipMemcpyDeviceToDevice,
                              c->stream));
-    launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.samples, (int)c->Ns, c->b.tsm, nullptr, 0);
+    if (c->cplx)
+        launch_h_theta(c->stream, c->N, c->M, c->b.hp, c->b.samples, c->Ns, c->b.htsm, nullptr, 0);
+    else
+        launch_theta(c->stream, c->d, c->prec, c->b.tab, c->b.samples, (int)c->Ns, c->b.tsm,
+                     nullptr, 0);
     c->have_samples = true;
     c->have_grad = false;
     return last_launch(c);
@@ -1131,6 +1349,16 @@ int nqs_local_energy(nqs_ctx* c, const int8_t* s, int64_t n, double* eloc_out) {
     int st = need_bound(c);
     if (st) return st;
     if (n < 0 || (n > 0 && (!s || !eloc_out))) return fail(c, NQS_EINVAL, "bad batch");
+    if (c->cplx) {  // complex energies: (real, imaginary) pairs
+        for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+            const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+            const int8_t* sk = s + (size_t)k0 * c->N;
+            launch_h_theta(c->stream, c->N, c->M, c->b.hp, sk, m, c->b.htx, nullptr, 0);
+            launch_h_eloc(c->stream, c->N, c->M, c->b.hT, c->b.hK, ham_dev(c), sk, c->b.htx, m,
+                          (double2*)eloc_out + k0);
+        }
+        return last_launch(c);
+    }
     for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
         const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
         const int8_t* sk = s + (size_t)k0 * c->N;
@@ -1145,6 +1373,7 @@ int nqs_local_energy_noalloc(nqs_ctx* c, const int8_t* s, int64_t n, double* elo
     int st = need_bound(c);
     if (st) return st;
     if (n < 0 || (n > 0 && (!s || !eloc_out))) return fail(c, NQS_EINVAL, "bad batch");
+    if (c->cplx) return fail(c, NQS_EINVAL, "complex models are not supported here");
     const size_t need = esize(c->prec) * (size_t)n * (size_t)c->d.Mw;
     if (need > kNoallocScratchBytes) {
         char msg[160];
@@ -1166,7 +1395,8 @@ int nqs_log_psi(nqs_ctx* c, const int8_t* s, int64_t n, void* out) {
     int st = need_bound(c);
     if (st) return st;
     if (n < 0 || (n > 0 && (!s || !out))) return fail(c, NQS_EINVAL, "bad batch");
-    launch_log_psi(c->stream, c->d, c->prec, c->b.Pm, c->b.tab, s, n, out);
+    if (c->cplx) launch_h_log_psi(c->stream, c->N, c->M, c->b.hp, s, n, (double2*)out);
+    else launch_log_psi(c->stream, c->d, c->prec, c->b.Pm, c->b.tab, s, n, out);
     return last_launch(c);
 }
 
@@ -1174,6 +1404,7 @@ int nqs_log_psi_vjp(nqs_ctx* c, const int8_t* s, int64_t n, const void* g, void*
     int st = need_bound(c);
     if (st) return st;
     if (n < 0 || (n > 0 && (!s || !g)) || !grad_out) return fail(c, NQS_EINVAL, "bad batch");
+    if (c->cplx) return fail(c, NQS_EINVAL, "complex models are not supported here");
     const int PV = c->d.Ma * c->d.Na;
     launch_zero(c->stream, c->b.gacc, 8 * (size_t)PV);
     for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
@@ -1207,6 +1438,17 @@ int nqs_jacobian(nqs_ctx* c, const int8_t* s, int64_t n, void* O_out, int center
     int st = need_bound(c);
     if (st) return st;
     if (n < 1 || !s || !O_out) return fail(c, NQS_EINVAL, "bad batch");
+    if (c->cplx) {  // complex O [n][P], (real, imaginary) pairs
+        if (center) return fail(c, NQS_EINVAL, "complex models: uncentred Jacobian only");
+        for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+            const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+            const int8_t* sk = s + (size_t)k0 * c->N;
+            launch_h_theta(c->stream, c->N, c->M, c->b.hp, sk, m, c->b.htx, nullptr, 0);
+            launch_h_jacobian(c->stream, c->N, c->M, sk, c->b.htx, m, (int)c->P,
+                              (double2*)O_out + (size_t)k0 * c->P);
+        }
+        return last_launch(c);
+    }
     const size_t es = esize(c->prec);
     for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
         const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
@@ -1229,8 +1471,13 @@ int nqs_expect_and_grad(nqs_ctx* c, nqs_stats* E, double* grad) {
     if (!c->have_samples) return fail(c, NQS_ESTATE, "no samples: call nqs_sample first");
     st = set_device(c);
     if (st) return st;
-    issue_energy_grad(c);
-    if (grad) launch_pack(c->stream, c->d, c->b.grad, grad, (int)c->P);
+    if (c->cplx) {
+        h_issue_energy_grad(c);
+        if (grad) launch_h_join(c->stream, (int)c->P, c->b.fp, (double2*)grad);
+    } else {
+        issue_energy_grad(c);
+        if (grad) launch_pack(c->stream, c->d, c->b.grad, grad, (int)c->P);
+    }
     st = last_launch(c);
     if (st) return st;
     if (E) return read_stats(c, E);
@@ -1254,6 +1501,18 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
                            int maxiter, double* delta_out) {
     int st = sr_check(c, kind, diag_shift, lr, tol);
     if (st) return st;
+    if (c->cplx) {  // G delta = f (complex holomorphic SR), p <- p - lr delta
+        st = h_issue_solve(c, diag_shift, tol, maxiter);
+        if (st) return st;
+        if (delta_out) launch_h_join(c->stream, (int)c->P, c->b.xp, (double2*)delta_out);
+        {
+            PROF(NQS_PROF_UPDATE);
+            launch_h_axpy(c->stream, (int)c->P, c->b.hp, -lr, 0.0, c->b.xp, 0.0, 0.0, nullptr,
+                          c->b.hp);
+            h_params_changed(c);
+        }
+        return last_launch(c);
+    }
     const int mi = default_maxiter(c, maxiter);
     if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi);
     else issue_cg_init(c, tol, mi, diag_shift);
@@ -1302,6 +1561,65 @@ int nqs_vmc_step(nqs_ctx* c, const nqs_step_cfg* cfg, nqs_step_report* rep) {
     return st;
 }
 
+int nqs_tdvp_step(nqs_ctx* c, const nqs_tdvp_cfg* cfg, nqs_tdvp_report* rep) {
+    int st = need_bound(c);
+    if (st) return st;
+    if (!cfg || !rep) return fail(c, NQS_EINVAL, "null settings or report");
+    if (!c->cplx) return fail(c, NQS_EINVAL, "TDVP needs a complex (NQS_C128) model");
+    if (c->step_phase) return fail(c, NQS_ESTATE, "a step begun by nqs_step_begin is in flight");
+    if ((cfg->scheme != NQS_RK_EULER && cfg->scheme != NQS_RK_HEUN) || !std::isfinite(cfg->dt) ||
+        !std::isfinite(cfg->gamma_re) || !std::isfinite(cfg->gamma_im) ||
+        !(cfg->diag_shift >= 0) || !(cfg->cg_tol >= 0))
+        return fail(c, NQS_EINVAL, "bad TDVP settings");
+    st = set_device(c);
+    if (st) return st;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->stages = cfg->scheme == NQS_RK_HEUN ? 2 : 1;
+    const int P = (int)c->P;
+    const double gr = cfg->gamma_re * cfg->dt, gi = cfg->gamma_im * cfg->dt;
+    HIPCHK(c, hipMemcpyAsync(c->b.hp0, c->b.hp, 16 * c->P, hipMemcpyDeviceToDevice, c->stream));
+    int worst = NQS_OK;
+    for (int l = 0; l < rep->stages; ++l) {
+        // one evaluation of the equation of motion: x = (G + eps I)^-1 f
+        h_issue_sample(c, 0, 1, nullptr);
+        h_issue_energy_grad(c);
+        st = h_issue_solve(c, cfg->diag_shift, cfg->cg_tol, cfg->cg_maxiter);
+        if (!st) st = enqueue_scalars(c);
+        if (!st) st = enqueue_acceptance(c);
+        if (!st) st = enqueue_stats(c);
+        if (!st && hipStreamSynchronize(c->stream) != hipSuccess)
+            st = fail(c, NQS_EDEVICE, "stream synchronise");
+        if (st) break;
+        st = sr_status(c, &rep->solve[l]);
+        if (st != NQS_OK && st != NQS_ENOTCONV) break;
+        if (st) worst = st;
+        take_acceptance(c);
+        st = take_stats(c, &rep->energy[l]);
+        if (st) break;
+        rep->energy_im[l] = c->h_stats[3];
+        // theta_dot = gamma x; Euler / Heun's predictor: theta0 + dt gamma x1;
+        // Heun's corrector: theta0 + dt gamma (x1 + x2) / 2
+        {
+            PROF(NQS_PROF_UPDATE);
+            if (l == 0) {
+                launch_h_axpy(c->stream, P, c->b.hp0, gr, gi, c->b.xp, 0.0, 0.0, nullptr, c->b.hp);
+                if (rep->stages == 2)
+                    HIPCHK(c, hipMemcpyAsync(c->b.hk1, c->b.xp, 8 * (size_t)c->Pd,
+                                             hipMemcpyDeviceToDevice, c->stream));
+            } else {
+                launch_h_axpy(c->stream, P, c->b.hp0, 0.5 * gr, 0.5 * gi, c->b.hk1, 0.5 * gr,
+                              0.5 * gi, c->b.xp, c->b.hp);
+            }
+            h_params_changed(c);
+        }
+        st = last_launch(c);
+        if (st) break;
+    }
+    if (!st) st = worst;
+    rep->status = st;
+    return st;
+}
+
 int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_step_report* reps) {
     if (!ctxs || n < 0 || (n > 0 && (!cfgs || !reps))) return NQS_EINVAL;
     std::vector<int> st(n, NQS_OK), mi(n, 0), active(n, 1);
@@ -1313,6 +1631,7 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
             st[k] = fail(c, NQS_ESTATE, "a step begun by nqs_step_begin is in flight");
         if (!st[k] && cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
             st[k] = fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace");
+        if (!st[k] && c->cplx) st[k] = fail(c, NQS_EINVAL, "complex models step one at a time");
         if (!st[k]) st[k] = set_device(c);
     }
     // sampling, energies and gradients for every context, then CG init
@@ -1444,6 +1763,7 @@ int nqs_step_begin(nqs_ctx* c, const nqs_step_cfg* cfg) {
     if (!c) return NQS_EINVAL;
     if (!cfg) return fail(c, NQS_EINVAL, "null settings");
     if (c->step_phase) return fail(c, NQS_ESTATE, "a step is already in flight");
+    if (c->cplx) return fail(c, NQS_EINVAL, "complex models step one at a time");
     int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
     if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
     if (!st) st = sr_check(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol);

@@ -186,4 +186,33 @@ int dense_matvec_blocks(int P);  // blocks (and p.Ap partials) of one dense prod
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
                          double shift, double* out, double* dpart, CgScalars* sc);
 
+// holo.hip: complex-parameter (holomorphic) RBM, complex FP64 (double2)
+int h_max_hidden();
+void launch_h_tables(hipStream_t st, int N, int M, const double2* p, double2* T, double2* K);
+// tanh(theta) of `rows` configurations into t [rows][M] (and t2 with row stride t2_stride)
+void launch_h_theta(hipStream_t st, int N, int M, const double2* p, const int8_t* s, long rows,
+                    double2* t, double2* t2, long t2_stride);
+void launch_h_log_psi(hipStream_t st, int N, int M, const double2* p, const int8_t* s, long n,
+                      double2* out);
+void launch_h_sample(hipStream_t st, int N, int M, const double2* T, const double2* K,
+                     const SampleArgs& a, const double2* tch);
+void launch_h_eloc(hipStream_t st, int N, int M, const double2* T, const double2* K,
+                   const HamDev& H, const int8_t* s, const double2* tact, long n, double2* out);
+void launch_h_stats(hipStream_t st, const double2* E, long n, double* out);
+// scratch bytes the Jacobian embedding and the force need (slice partials)
+size_t h_slice_bytes(int P);
+void launch_h_jacobian(hipStream_t st, int N, int M, const int8_t* s, const double2* t, long n,
+                       int P, double2* O);
+// Y [2n][ld] = the real embedding of (O - mean O) / sqrt(n); mean: complex [P]
+void launch_h_jacobian_emb(hipStream_t st, int N, int M, const int8_t* s, const double2* t,
+                           long n, int P, long ld, double* Y, double2* mean, double* scratch);
+// f [2P] = Y^T [Re dE; Im dE] / sqrt(n) (the embedded force)
+void launch_h_force(hipStream_t st, const double* Y, long n, long ld, int P2, const double2* E,
+                    const double* stats, double* f, double* scratch);
+// out = in + c x (+ c2 x2), x and x2 embedded [re | im], c complex
+void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
+                   double c2r, double c2i, const double* x2, double2* out);
+void launch_h_split(hipStream_t st, int P, const double2* z, double* emb);
+void launch_h_join(hipStream_t st, int P, const double* emb, double2* z);
+
 }  // namespace nqs

@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NqsError, NqsSrInfo, NqsStats, NqsStepCfg, NqsStepReport
+from ._lib import (NqsError, NqsSrInfo, NqsStats, NqsStepCfg, NqsStepReport, NqsTdvpCfg,
+                   NqsTdvpReport)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -42,7 +43,10 @@ def _stats_dict(s: NqsStats) -> dict:
 
 
 class VMCState:
-    """A real RBM variational state with a Metropolis sampler on one GPU."""
+    """An RBM variational state with a Metropolis sampler on one GPU: real
+    parameters (precision fp64, fp32 or bf16) or complex parameters with a
+    holomorphic mapping (precision c128: parameters, gradients, directions,
+    local energies, ln psi and Jacobians are complex128)."""
 
     def __init__(self, *, model: str, n_sites: int, bonds, J: float, h: float = 0.0,
                  sublattice=None, n_hidden: int, visible_bias: bool = True,
@@ -58,7 +62,11 @@ class VMCState:
         self.precision = precision
         self.n_sites, self.n_hidden = n_sites, n_hidden
         self.n_chains, self.samples_per_chain, self.sweep_size = n_chains, samples_per_chain, sweep_size
-        self.rdtype = torch.float64 if precision == "fp64" else torch.float32
+        self.complex = precision == "c128"
+        self.rdtype = (torch.complex128 if self.complex else
+                       torch.float64 if precision == "fp64" else torch.float32)
+        if self.complex:
+            qgt = "jacobian_dense"
         h_ctx = ctypes.c_void_p()
         st = self.lib.nqs_create(ctypes.byref(h_ctx), device, ctypes.c_void_p(self.stream.cuda_stream))
         if st:
@@ -152,6 +160,16 @@ class VMCState:
 
     # ------------------------------------------------------------------
     def set_params(self, p):
+        if self.complex:  # complex128 values, passed as (real, imaginary) pairs
+            if torch.is_tensor(p):
+                p = torch.view_as_real(self._dev(p, torch.complex128)).contiguous()
+                self._check(self.lib.nqs_set_params(self.ctx, _ptr(p), 1))
+                return
+            p = np.ascontiguousarray(np.asarray(p, dtype=np.complex128))
+            if p.size != self.n_params:
+                raise ValueError(f"expected {self.n_params} parameters")
+            self._check(self.lib.nqs_set_params(self.ctx, p.ctypes.data_as(ctypes.c_void_p), 0))
+            return
         p = np.ascontiguousarray(np.asarray(p, dtype=np.float64)) if not torch.is_tensor(p) else p
         if torch.is_tensor(p):
             p = self._dev(p, torch.float64)
@@ -162,7 +180,7 @@ class VMCState:
             self._check(self.lib.nqs_set_params(self.ctx, p.ctypes.data_as(ctypes.c_void_p), 0))
 
     def get_params(self) -> np.ndarray:
-        out = np.zeros(self.n_params)
+        out = np.zeros(self.n_params, dtype=np.complex128 if self.complex else np.float64)
         self._check(self.lib.nqs_get_params(self.ctx, out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
 
@@ -218,7 +236,8 @@ class VMCState:
 
     def local_energy(self, s: torch.Tensor) -> torch.Tensor:
         s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
-        out = torch.empty(s.shape[0], dtype=torch.float64, device=self.device)
+        out = torch.empty(s.shape[0], dtype=torch.complex128 if self.complex else torch.float64,
+                          device=self.device)
         self._check(self.lib.nqs_local_energy(self.ctx, _ptr(s), s.shape[0], _ptr(out)))
         return out
 
@@ -254,7 +273,8 @@ class VMCState:
 
     def expect_and_grad(self, want_grad: bool = True):
         st = NqsStats()
-        g = torch.empty(self.n_params, dtype=torch.float64, device=self.device) if want_grad else None
+        gt = torch.complex128 if self.complex else torch.float64
+        g = torch.empty(self.n_params, dtype=gt, device=self.device) if want_grad else None
         self._check(self.lib.nqs_expect_and_grad(self.ctx, ctypes.byref(st), _ptr(g)))
         return _stats_dict(st), g
 
@@ -262,7 +282,10 @@ class VMCState:
                   tol: float = 1e-6, maxiter: int = 0, want_delta: bool = True,
                   allow_notconv: bool = False):
         info = NqsSrInfo()
-        d = torch.empty(self.n_params, dtype=torch.float64, device=self.device) if want_delta else None
+        if self.complex:
+            qgt = "jacobian_dense"
+        dt = torch.complex128 if self.complex else torch.float64
+        d = torch.empty(self.n_params, dtype=dt, device=self.device) if want_delta else None
         st = self.lib.nqs_sr_update(self.ctx, _lib.QGTS[qgt], diag_shift, lr, tol, maxiter, _ptr(d),
                                     ctypes.byref(info))
         if not (st == _lib.NQS_OK or (allow_notconv and st == _lib.NQS_ENOTCONV)):
@@ -271,6 +294,8 @@ class VMCState:
 
     def vmc_step(self, qgt: str = "onthefly", diag_shift: float = 0.01, lr: float = 0.01,
                  tol: float = 1e-6, maxiter: int = 0) -> StepReport:
+        if self.complex:
+            qgt = "jacobian_dense"
         cfg = NqsStepCfg(_lib.QGTS[qgt], diag_shift, lr, tol, maxiter)
         rep = NqsStepReport()
         log = getattr(self, "_step_log", None)
@@ -286,6 +311,26 @@ class VMCState:
                          rep.status)
         if log is not None:
             self._write_step_log(out, wall)
+        return out
+
+    def tdvp_step(self, dt: float, gamma: complex = -1j, scheme: str = "heun",
+                  diag_shift: float = 0.0, tol: float = 1e-8, maxiter: int = 0):
+        """One TDVP step (complex models): returns a list with, per evaluation of
+        the equation of motion, its energy (complex mean, variance, error,
+        acceptance) and solve (iterations, converged, residual)."""
+        g = complex(gamma)
+        cfg = NqsTdvpCfg(_lib.RK_SCHEMES[scheme], dt, g.real, g.imag, diag_shift, tol, maxiter)
+        rep = NqsTdvpReport()
+        st = self.lib.nqs_tdvp_step(self.ctx, ctypes.byref(cfg), ctypes.byref(rep))
+        if st not in (_lib.NQS_OK, _lib.NQS_ENOTCONV):
+            self._check(st)
+        out = []
+        for l in range(rep.stages):
+            e = _stats_dict(rep.energy[l])
+            e["mean"] = complex(e["mean"], rep.energy_im[l])
+            s = rep.solve[l]
+            out.append(dict(energy=e, solve=SrInfo(s.iterations, bool(s.converged),
+                                                   s.rel_residual)))
         return out
 
     # ------------------------------------------------------------------

@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "chain_bonds", "square_bonds", "chain_sublattice", "square_sublattice",
-    "n_params", "rbm_params", "random_configs", "sz0_configs", "Workload",
+    "n_params", "rbm_params", "rbm_params_c", "random_configs", "sz0_configs", "Workload",
     "WORKLOADS",
 ]
 
@@ -76,6 +76,15 @@ def rbm_params(n_sites: int, n_hidden: int, seed: int, sigma: float = 0.01,
     return rng.normal(0.0, sigma, size=P).astype(np.float64)
 
 
+def rbm_params_c(n_sites: int, n_hidden: int, seed: int, sigma: float = 0.01) -> np.ndarray:
+    """Complex initial parameters (both biases): real and imaginary parts drawn
+    i.i.d. normal(0, sigma), as one [P, 2] array of (real, imaginary) pairs."""
+    rng = np.random.default_rng(seed)
+    P = n_params(n_sites, n_hidden)
+    z = rng.normal(0.0, sigma, size=(P, 2))
+    return (z[:, 0] + 1j * z[:, 1]).astype(np.complex128)
+
+
 def random_configs(n: int, n_sites: int, seed: int) -> np.ndarray:
     """Uniform random spin configurations, int8 [n, n_sites] in {+1,-1}."""
     rng = np.random.default_rng(seed)
@@ -108,7 +117,7 @@ class Workload:
     samples_per_chain: int
     sweep_size: int        # proposals between recorded samples
     rule: str              # "local" or "exchange"
-    precision: str         # "fp64", "fp32" or "bf16"
+    precision: str         # "fp64", "fp32", "bf16" or "c128" (complex parameters)
     param_seed: int = 1
     chain_seed: int = 2
     sigma: float = 0.01
@@ -144,6 +153,8 @@ class Workload:
         return chain_sublattice(self.L) if self.lattice == "chain" else square_sublattice(self.L)
 
     def params(self) -> np.ndarray:
+        if self.precision == "c128":
+            return rbm_params_c(self.n_sites, self.n_hidden, self.param_seed, self.sigma)
         return rbm_params(self.n_sites, self.n_hidden, self.param_seed, self.sigma)
 
     def replace(self, **kw) -> "Workload":
@@ -167,4 +178,12 @@ WORKLOADS = {
     # 16384 samples, FP32 (dense Jacobian / Gram form).
     "heis1d_n64": Workload("heis1d_n64", "heisenberg", "chain", 64, 1.0, 0.0, 8, 4096, 4,
                            64, "exchange", "fp32", marshall=True, total_sz_zero=True),
+    # 1D TFIM chain L=64, J=h=1, complex RBM alpha=1 (holomorphic), 1024 chains x
+    # 16 samples = 2^14, L proposals between samples; dense holomorphic QGT.
+    "tfim1d_n64_c": Workload("tfim1d_n64_c", "tfim", "chain", 64, 1.0, 1.0, 1, 1024, 16, 64,
+                             "local", "c128"),
+    # 1D TFIM chain L=20 after a quench to h=1 (J=1), complex RBM alpha=1,
+    # 4096 samples (256 chains x 16), L proposals between samples.
+    "tfim1d_n20_quench": Workload("tfim1d_n20_quench", "tfim", "chain", 20, 1.0, 1.0, 1, 256,
+                                  16, 20, "local", "c128"),
 }
