@@ -445,46 +445,57 @@ def plain_measure(torch, steps=300, lr=0.05):
                 steps=steps, exact_ground_energy=e0, runs=out, data="synthetic")
 
 
-def paper_workload_measure(torch, steps=10, warmup=2):
-    """The workload closest to the one timed in the paper's comparison with jVMC (1D
-    TFIM, L = 64, J = h = 1, periodic; RBM alpha = 1; 2^14 samples from 2^10 chains;
-    dense Jacobian QGT with CG), with this library's real RBM (4,224 real parameters,
-    where the paper's is complex) and 64 proposals between samples: full SR steps
-    (sampling, local energies, gradient, QGT solve, update) with the dense and the
-    on-the-fly QGT, FP64 path and BF16 form.  Context only: the model, precision and
-    solver settings differ from the paper's."""
+def paper_workload_measure(torch, steps=5, warmup=2):
+    """The workload timed in the paper's comparison with jVMC (table of VMC step
+    times): 1D TFIM, L = 64, J = h = 1, periodic; complex RBM alpha = 1 with a
+    holomorphic mapping (4,224 complex parameters); 2^14 samples from 2^10 chains
+    (64 proposals between samples); the dense holomorphic QGT with CG.  Full SR
+    steps: sampling, local energies, the embedded Jacobian, the force, the Gram
+    matrix, CG and the update.  The Gram matrix is priced at the algorithmic
+    4 N_s P^2 real flops of the Hermitian product dJ^H dJ (its upper triangle)."""
     from paper_2112_10526_amd.nqs import VMCState
-    w = synth.Workload("tfim1d_n64", "tfim", "chain", 64, 1.0, 1.0, 1, 1024, 16, 64, "local",
-                       "fp64")
-    runs = {}
-    for prec in ("fp64", "bf16"):
-        for qgt in ("jacobian_dense", "onthefly"):
-            st = VMCState.from_workload(w, precision=prec, qgt=qgt)
-            st.thermalize(w.thermalize_segments)
-            for _ in range(warmup):
-                st.vmc_step(qgt=qgt, diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            iters = []
-            for _ in range(steps):
-                rep = st.vmc_step(qgt=qgt, diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
-                iters.append(rep.sr.iterations)
-            torch.cuda.synchronize()
-            el = (time.perf_counter() - t0) / steps
-            runs[f"{prec}_{qgt}"] = dict(s_per_step=el, local_energies_per_s=w.n_samples / el,
-                                         cg_iters_mean=float(np.mean(iters)))
-            st.close()
-            print(f"[bench] paper workload {prec} {qgt}: {el * 1e3:.2f} ms/step", file=sys.stderr,
-                  flush=True)
-    return dict(metric="seconds per VMC step, workload closest to the paper's timed one",
-                workload="tfim1d_n64: 1D TFIM L=64 periodic J=h=1, real RBM alpha=1 (4,224 "
-                         "parameters), 1024 chains x 16 samples, 64 proposals per sample, SR CG "
-                         "tol 1e-6 shift 0.01",
-                steps=steps, warmup=warmup, runs=runs,
-                paper_context=dict(s_per_step=3.9, hardware="1x NVIDIA RTX 3090",
-                                   model="complex RBM alpha=1, QGTJacobianDense(holomorphic) + CG",
-                                   local_energies_per_s=16384 / 3.9),
-                data="synthetic")
+    w = synth.WORKLOADS["tfim1d_n64_c"]
+    st = VMCState.from_workload(w)
+    st.thermalize(w.thermalize_segments)
+    st.profile_enable(None)
+    for _ in range(warmup):
+        st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    prof = st.profile_read()
+    st.profile_enable([])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, energies = [], []
+    for _ in range(steps):
+        rep = st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        iters.append(rep.sr.iterations)
+        energies.append(rep.energy["mean"])
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st.close()
+    P, Ns = w.n_params, w.n_samples
+    g = prof["gram"]
+    gram_us = g["ms"] * 1e3 / max(g["launches"], 1)
+    gram_flops = 4.0 * Ns * P * P
+    print(f"[bench] paper workload (complex): {el * 1e3:.2f} ms/step, Gram {gram_us:.0f} us",
+          file=sys.stderr, flush=True)
+    return dict(metric="seconds per VMC step on the paper's timed workload",
+                value=el, unit="s/step", higher_is_better=False, steps=steps, warmup=warmup,
+                dtype="c128", data="synthetic",
+                config=dict(workload="tfim1d_n64_c: 1D TFIM L=64 periodic J=h=1, complex RBM "
+                                     "alpha=1 (4,224 complex parameters), 1024 chains x 16 "
+                                     "samples, 64 proposals per sample, dense holomorphic QGT "
+                                     f"+ CG tol {w.cg_tol} shift {w.diag_shift} lr {w.lr}",
+                            n_samples=Ns, n_params=P),
+                local_energies_per_s=Ns / el, cg_iters_mean=float(np.mean(iters)),
+                energy_first=energies[0], energy_last=energies[-1],
+                warmup_profile_ms={k: round(v["ms"] / warmup, 4) for k, v in prof.items()
+                                   if v["launches"]},
+                gram=dict(bound="mfma", avg_launch_us=gram_us, algorithmic_flops=gram_flops,
+                          achieved=gram_flops / (gram_us * 1e-6) / 1e12, peak=78.6,
+                          unit="TFLOP/s", frac=gram_flops / (gram_us * 1e-6) / 78.6e12),
+                paper_context=dict(hardware="1x NVIDIA RTX 3090 (paper's table)",
+                                   s_per_step_cg=3.9, s_per_step_svd=24.0,
+                                   s_per_step_cg_2gpu=1.7))
 
 
 def cpu_model() -> str:
@@ -551,7 +562,7 @@ def main():
     ap.add_argument("--plain", action="store_true",
                     help="SR steps on the N=10 TFIM chain: time and energy against the exact one")
     ap.add_argument("--paper-workload", action="store_true",
-                    help="time full SR steps on the workload closest to the paper's timed one")
+                    help="time full SR steps on the paper's timed workload (complex RBM)")
     ap.add_argument("--serve", action="store_true",
                     help="measure the continuous-batching server on a Poisson stream of runs")
     ap.add_argument("--serve-runs", type=int, default=256)

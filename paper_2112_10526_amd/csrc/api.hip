@@ -44,6 +44,7 @@ struct Buffers {
     // batch, local energies, Jacobian column means, the TDVP's first slope
     double2 *hp, *hp0, *hT, *hK, *htch, *htsm, *htx, *heloc, *hmean;
     double* hk1;
+    double* hgp;  // complex: Gram slice partials
 };
 
 }  // namespace
@@ -65,6 +66,8 @@ struct nqs_ctx {
     bool has_model = false;
     int M = 0, vb = 1, hb = 1, prec = 0;
     bool cplx = false;  // complex parameters (NQS_C128)
+    long Plc = 0;       // complex: row stride of the stacked Jacobian U and of Re G, Im G
+    int hS = 1;         // complex: row slices of the Gram
     int Pd = 0;         // size of the dense SR system: P, or 2 P (real embedding)
     Dims d{};
     size_t P = 0;
@@ -276,9 +279,11 @@ size_t layout_holo(nqs_ctx* c, char* base) {
     b.dpart = (double*)take(8 * (size_t)c->ndpart);
     b.acc_count = (uint32_t*)take(4 * C);
     b.sc = (CgScalars*)take(sizeof(CgScalars));
-    b.O = take(8 * 2 * Ns * Pld);
-    const size_t gb = 8 * (size_t)c->Pd * Pld, sb = h_slice_bytes((int)P);
+    const size_t Plc = (size_t)c->Plc;
+    b.O = take(8 * 2 * (size_t)h_half_rows((long)Ns) * Plc);  // U: two halves
+    const size_t gb = 8 * 2 * P * Plc, sb = h_slice_bytes((int)P);
     b.G = take(gb > sb ? gb : sb);
+    b.hgp = (double*)take(h_gram_part_bytes(c->ntiles, c->hS));
     b.hmean = (double2*)take(16 * P);
     b.fp = (double*)take(8 * Pld);
     b.xp = (double*)take(8 * Pld);
@@ -319,6 +324,11 @@ void derive(nqs_ctx* c) {
         c->ksplit = outer_ksplit(c->Bx, c->chunk);
         c->Pld = round_up(c->Pd, 128);
         c->ntiles = gram_tiles(c->Pd);
+        if (c->cplx) {  // Re G and Im G are P x P
+            c->Plc = round_up((long)c->P, 128);
+            c->ntiles = gram_tiles((int)c->P);
+            c->hS = h_gram_slices(c->ntiles, c->Ns);
+        }
         long nd = (long)d.Ma * d.Na / 256 + 2;
         const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->Pd / 4 + 2;
         if (nd2 > nd) nd = nd2;
@@ -615,13 +625,18 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host
         } else {
             {
                 PROF(NQS_PROF_DENSE_MV);
-                launch_dense_matvec(c->stream, c->cplx ? 0 : c->prec, c->b.G, c->Pd, c->Pld, c->b.pp, shift,
-                                    c->b.App, c->b.dpart, c->b.sc);
+                if (c->cplx)
+                    launch_h_matvec(c->stream, (const double*)c->b.G, (int)c->P, c->Plc, c->b.pp,
+                                    shift, c->b.App, c->b.dpart, c->b.sc);
+                else
+                    launch_dense_matvec(c->stream, c->prec, c->b.G, c->Pd, c->Pld, c->b.pp, shift,
+                                        c->b.App, c->b.dpart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_CGVEC);
-                launch_cg_update(c->stream, c->Pd, c->b.xp, c->b.rp, c->b.pp, c->b.App,
-                                 c->b.dpart, dense_matvec_blocks(c->Pd), c->b.sc);
+                launch_cg_update(c->stream, c->Pd, c->b.xp, c->b.rp, c->b.pp, c->b.App, c->b.dpart,
+                                 c->cplx ? h_matvec_blocks((int)c->P) : dense_matvec_blocks(c->Pd),
+                                 c->b.sc);
             }
         }
     }
@@ -878,10 +893,10 @@ void h_issue_energy_grad(nqs_ctx* c) {
     }
     {
         PROF(NQS_PROF_JACOBIAN);
-        launch_h_jacobian_emb(c->stream, c->N, c->M, c->b.samples, c->b.htsm, n, (int)c->P, c->Pld,
+        launch_h_jacobian_emb(c->stream, c->N, c->M, c->b.samples, c->b.htsm, n, (int)c->P, c->Plc,
                               (double*)c->b.O, c->b.hmean, (double*)c->b.G);
-        launch_h_force(c->stream, (const double*)c->b.O, n, c->Pld, c->Pd, c->b.heloc, c->b.stats,
-                       c->b.fp, (double*)c->b.G);
+        launch_h_force(c->stream, (const double*)c->b.O, n, c->Plc, (int)c->P, c->b.heloc,
+                       c->b.stats, c->b.fp, (double*)c->b.G);
     }
     c->have_grad = true;
 }
@@ -891,7 +906,8 @@ int h_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
     const int mi = default_maxiter(c, maxiter);
     {
         PROF(NQS_PROF_GRAM);
-        launch_gram(c->stream, 0, c->b.O, 2 * c->Ns, c->Pld, c->Pd, c->b.G, c->b.tiles, c->ntiles);
+        launch_h_gram(c->stream, (const double*)c->b.O, c->Ns, c->Plc, (int)c->P, c->b.tiles,
+                      c->ntiles, c->hS, c->b.hgp, (double*)c->b.G);
     }
     launch_cg_init(c->stream, c->Pd, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
                    mi);
@@ -1124,7 +1140,7 @@ int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
                              c->stream));
     if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
         std::vector<int> t(2 * (size_t)c->ntiles);
-        fill_gram_tiles(c->Pd, t.data());
+        fill_gram_tiles(c->cplx ? (int)c->P : c->Pd, t.data());
         HIPCHK(c, hipMemcpyAsync(c->b.tiles, t.data(), 4 * t.size(), hipMemcpyHostToDevice,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -11,12 +11,15 @@
 // (cosh(theta - 2 s W) = cosh(theta) cosh(2W) (1 - s tanh(theta) tanh(2W))).
 //
 // The dense holomorphic QGT G = dJ^H dJ (dJ = (O - mean O) / sqrt(N_s)) and the
-// system (G + eps I) x = f are solved over the reals: with
-//   Y = [[Re dJ, -Im dJ], [Im dJ, Re dJ]]   (2 N_s x 2 P)
-// Y^T Y = [[Re G, -Im G], [Im G, Re G]], symmetric positive semi-definite, and
-// [Re x; Im x] solves the embedded system exactly when x solves the complex
-// one; conjugate gradients on it take the same iterates as complex CG.  Y is
-// written once per batch; the Gram and the CG are the real dense kernels.
+// system (G + eps I) x = f are solved over the reals.  With X = Re dJ, Z = Im dJ,
+//   G = A + i B,  A = X^T X + Z^T Z (symmetric),  B = X^T Z - Z^T X (antisymmetric),
+// and the real system [[A, -B], [B, A]] [Re x; Im x] = [Re f; Im f] is symmetric
+// positive semi-definite and solved exactly when x solves the complex one;
+// conjugate gradients on it take the same iterates as complex CG.  The batch is
+// stored once, stacked: U = [X; Z] (2 N_s x P), so that A = U^T U and B = U^T V
+// with V = [Z; -X] (the row halves of U swapped, one negated): the Gram kernel
+// forms both from the same loads of U, 4 N_s P^2 flops for the two triangles, the
+// cost of the Hermitian product itself.
 #include "kernels.h"
 
 namespace nqs {
@@ -337,54 +340,54 @@ __global__ void k_h_colsum_fin(const double2* __restrict__ part, int P, int slic
     mean[p] = make_double2(a.x / (double)n, a.y / (double)n);
 }
 
-// The real embedding of the centred, scaled Jacobian: for sample k and column
-// p, v = (O_kp - mean_p) / sqrt(n);
-//   Y[k][p] = Re v, Y[k][P + p] = -Im v, Y[n + k][p] = Im v, Y[n + k][P + p] = Re v;
-// columns 2P .. ld - 1 are zero.  Block: 256 columns x 4 rows, rows k0 + ...
+// The stacked, centred, scaled Jacobian: for sample k and column p,
+// v = (O_kp - mean_p) / sqrt(n);  U[k][p] = Re v, U[n8 + k][p] = Im v with
+// n8 = n rounded up to a multiple of 8; columns P .. ld - 1 and rows n .. n8 - 1,
+// n8 + n .. 2 n8 - 1 are zero (the latter never written: the workspace starts
+// zeroed).  Block: 256 columns x 4 rows, rows k0 + ...
 __global__ __launch_bounds__(256) void k_h_jac_emb(int N, int M, const int8_t* __restrict__ s,
                                                    const double2* __restrict__ t, long n, long k0,
                                                    int P, const double2* __restrict__ mean,
-                                                   long ld, double* __restrict__ Y) {
+                                                   long ld, double* __restrict__ U) {
     const long col = (long)blockIdx.x * 256 + threadIdx.x;  // in [0, ld)
     const double rs = 1.0 / sqrt((double)n);
+    const long n8 = h_half_rows(n);
     for (int r = 0; r < 4; ++r) {
         const long k = k0 + (long)blockIdx.y * 4 + r;
         if (k >= n || col >= ld) continue;
-        double top = 0.0, bot = 0.0;
-        if (col < 2L * P) {
-            const long p = col < P ? col : col - P;
-            const double2 o = h_jac(N, M, s + k * N, t + k * M, p);
-            const double vr = (o.x - mean[p].x) * rs, vi = (o.y - mean[p].y) * rs;
-            if (col < P) {
-                top = vr;
-                bot = vi;
-            } else {
-                top = -vi;
-                bot = vr;
-            }
+        double re = 0.0, im = 0.0;
+        if (col < P) {
+            const double2 o = h_jac(N, M, s + k * N, t + k * M, col);
+            re = (o.x - mean[col].x) * rs;
+            im = (o.y - mean[col].y) * rs;
         }
-        Y[k * ld + col] = top;
-        Y[(n + k) * ld + col] = bot;
+        U[k * ld + col] = re;
+        U[(n8 + k) * ld + col] = im;
     }
 }
 
-// The force in the embedding: f[p'] = sum_r Y[r][p'] e_r, e = [Re dE; Im dE] / sqrt(n),
-// dE = E - mean E (the stats' mean): slice partials over rows, then their sum
-// in order (part: [slices][2P]).
-__global__ __launch_bounds__(256) void k_h_force(const double* __restrict__ Y, long n, long ld,
-                                                 int P2, const double2* __restrict__ E,
+// The force f~ = dJ^H (E - mean E) / sqrt(n), embedded [Re | Im]:
+//   Re f~ = X^T eR + Z^T eI,  Im f~ = X^T eI - Z^T eR,  e = (E - mean E) / sqrt(n),
+// one pass over U = [X; Z] with two sums per column; slice partials over
+// samples, then their sum in order (part: [slices][2P]).
+__global__ __launch_bounds__(256) void k_h_force(const double* __restrict__ U, long n, long ld,
+                                                 int P, const double2* __restrict__ E,
                                                  const double* __restrict__ stats, int slices,
                                                  double* __restrict__ part) {
     const long p = (long)blockIdx.x * 256 + threadIdx.x;
-    if (p >= P2) return;
-    const long r0 = 2 * n * blockIdx.y / slices, r1 = 2 * n * (blockIdx.y + 1) / slices;
+    if (p >= P) return;
+    const long k0 = n * blockIdx.y / slices, k1 = n * (blockIdx.y + 1) / slices;
+    const long n8 = h_half_rows(n);
     const double mr = stats[0], mi = stats[3], rs = 1.0 / sqrt((double)n);
-    double acc = 0.0;
-    for (long r = r0; r < r1; ++r) {
-        const double e = r < n ? (E[r].x - mr) * rs : (E[r - n].y - mi) * rs;
-        acc += Y[r * ld + p] * e;
+    double fr = 0.0, fi = 0.0;
+    for (long k = k0; k < k1; ++k) {
+        const double x = U[k * ld + p], z = U[(n8 + k) * ld + p];
+        const double er = (E[k].x - mr) * rs, ei = (E[k].y - mi) * rs;
+        fr += x * er + z * ei;
+        fi += x * ei - z * er;
     }
-    part[(size_t)blockIdx.y * P2 + p] = acc;
+    part[(size_t)blockIdx.y * 2 * P + p] = fr;
+    part[(size_t)blockIdx.y * 2 * P + P + p] = fi;
 }
 __global__ void k_h_sum_slices(const double* __restrict__ part, int P2, int slices,
                                double* __restrict__ out) {
@@ -393,6 +396,256 @@ __global__ void k_h_sum_slices(const double* __restrict__ part, int P2, int slic
     double a = 0.0;
     for (int q = 0; q < slices; ++q) a += part[(size_t)q * P2 + p];
     out[p] = a;
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrices A = U^T U and B = U^T V on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  One block of 8 waves per (128 x 128 tile of the
+// upper block triangle, slice of rows); wave w owns rows 32 (w / 2) .. + 31 and
+// columns 64 (w % 2) .. + 63 of the tile, for A and for B, from the same loads
+// of U (the B operand of B's products is V = [Z; -X], read from U with the row
+// halves swapped).  The next 4 rows' operands are loaded before the current
+// ones are multiplied.  Row slices spread the triangle's few hundred tiles over
+// all compute units; each slice writes its tile partials [2][128][128], which
+// k_h_gram_fin sums in slice order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int HG_TILE = 128;
+constexpr int HG_ROWS = 16;                  // rows of U per LDS stage
+constexpr int HG_LD = 3 * HG_TILE + 2;       // LDS row: p panel | q panel | V's q panel (+pad)
+
+// U: [2 n8][ld], n8 = n rounded up to 8 (zero rows pad both halves), so every
+// slice is whole 16-row stages and every 4-row step lies in one half: V's sign
+// is uniform per step.  Per stage each thread moves 6 x 16 B from U into
+// registers, at the top of the stage, while the waves multiply the previous
+// stage out of LDS; the registers go to the other LDS buffer after the
+// products (the barriers keep the loads where they are issued).
+__global__ __launch_bounds__(512) void k_h_gram(const double* __restrict__ U, long n, long ld,
+                                                int ntiles, long rows_per_slice,
+                                                const int* __restrict__ tiles,
+                                                double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) double L[2][HG_ROWS * HG_LD];
+    const int t = (int)(blockIdx.x % (unsigned)ntiles), ks = (int)(blockIdx.x / (unsigned)ntiles);
+    const int tp = tiles[2 * t], tq = tiles[2 * t + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long n8 = h_half_rows(n), R = 2 * n8;
+    const long r0 = (long)ks * rows_per_slice;
+    const long r1 = r0 + rows_per_slice < R ? r0 + rows_per_slice : R;
+    const int nst = r0 < r1 ? (int)((r1 - r0) / HG_ROWS) : 0;
+    // this thread's 6 pieces of a stage: item = tid + 512 m -> row of the stage,
+    // panel (0: p columns of U, 1: q columns of U, 2: q columns of V's row) and
+    // 2 doubles; their LDS offsets
+    int prow[6], ppan[6], loff[6], vsel[6];
+    long pcol[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int it = tid + 512 * m, pr = it >> 6, e = it & 63;
+        prow[m] = pr / 3;
+        ppan[m] = pr - 3 * prow[m];
+        pcol[m] = (ppan[m] == 0 ? (long)tp : (long)tq) * HG_TILE + 2 * e;
+        loff[m] = prow[m] * HG_LD + ppan[m] * HG_TILE + 2 * e;
+        vsel[m] = ppan[m] == 2 ? 1 : 0;
+    }
+    v4d accA[2][4], accB[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            accA[a][b] = v4d{0, 0, 0, 0};
+            accB[a][b] = v4d{0, 0, 0, 0};
+        }
+    const int pc = (wave >> 1) * 32 + lr, qc = (wave & 1) * 64 + lr;
+    // U's row of piece m of stage st (V's panel: the row in the other half)
+#define HG_SRC(m, st)                                                                   \
+    (U + (r0 + (long)(st) * HG_ROWS + prow[m] +                                         \
+          (long)vsel[m] * (r0 + (long)(st) * HG_ROWS + prow[m] < n8 ? n8 : -n8)) * ld +  \
+     pcol[m])
+    double2 g0, g1, g2, g3, g4, g5;
+    if (nst > 0) {
+        g0 = *(const double2*)HG_SRC(0, 0);
+        g1 = *(const double2*)HG_SRC(1, 0);
+        g2 = *(const double2*)HG_SRC(2, 0);
+        g3 = *(const double2*)HG_SRC(3, 0);
+        g4 = *(const double2*)HG_SRC(4, 0);
+        g5 = *(const double2*)HG_SRC(5, 0);
+        *(double2*)(&L[0][loff[0]]) = g0;
+        *(double2*)(&L[0][loff[1]]) = g1;
+        *(double2*)(&L[0][loff[2]]) = g2;
+        *(double2*)(&L[0][loff[3]]) = g3;
+        *(double2*)(&L[0][loff[4]]) = g4;
+        *(double2*)(&L[0][loff[5]]) = g5;
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int nx = st + 1 < nst ? st + 1 : st;  // (the last stage reloads itself, unused)
+        g0 = *(const double2*)HG_SRC(0, nx);
+        g1 = *(const double2*)HG_SRC(1, nx);
+        g2 = *(const double2*)HG_SRC(2, nx);
+        g3 = *(const double2*)HG_SRC(3, nx);
+        g4 = *(const double2*)HG_SRC(4, nx);
+        g5 = *(const double2*)HG_SRC(5, nx);
+        const double* Lb = L[st & 1];
+#pragma unroll
+        for (int j = 0; j < HG_ROWS / 4; ++j) {
+            const long gr = r0 + (long)st * HG_ROWS + 4 * j;
+            const double sg = gr < n8 ? 1.0 : -1.0;
+            const double* lrow = Lb + (4 * j + lk) * HG_LD;
+            double fa[2], fb[4], fv[4];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = lrow[pc + a * 16];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                fb[b] = lrow[HG_TILE + qc + b * 16];
+                fv[b] = sg * lrow[2 * HG_TILE + qc + b * 16];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    accA[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], accA[a][b], 0, 0, 0);
+                    accB[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fv[b], accB[a][b], 0, 0, 0);
+                }
+        }
+        double* Ln = L[(st + 1) & 1];
+        *(double2*)(&Ln[loff[0]]) = g0;
+        *(double2*)(&Ln[loff[1]]) = g1;
+        *(double2*)(&Ln[loff[2]]) = g2;
+        *(double2*)(&Ln[loff[3]]) = g3;
+        *(double2*)(&Ln[loff[4]]) = g4;
+        *(double2*)(&Ln[loff[5]]) = g5;
+        __syncthreads();
+    }
+#undef HG_SRC
+    double* pa_out = part + (size_t)blockIdx.x * 2 * HG_TILE * HG_TILE;
+    double* pb_out = pa_out + HG_TILE * HG_TILE;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pr = (wave >> 1) * 32 + a * 16 + acc_row<double>(lk, i);
+                const int qo = (wave & 1) * 64 + b * 16 + lr;
+                pa_out[pr * HG_TILE + qo] = accA[a][b][i];
+                pb_out[pr * HG_TILE + qo] = accB[a][b][i];
+            }
+}
+
+// Sum of the slice partials (in slice order) into A [P][ld] and B [P][ld],
+// with the lower triangles mirrored (A symmetric, B antisymmetric, B's diagonal
+// zero).  One block per 32 x 32 sub-block of a tile; the mirrored writes go
+// through LDS so that both are coalesced.  In a diagonal tile only entries on
+// or above the diagonal are taken.
+__global__ __launch_bounds__(256) void k_h_gram_fin(const double* __restrict__ part, int ntiles,
+                                                    int slices, const int* __restrict__ tiles,
+                                                    int P, long ld, double* __restrict__ A,
+                                                    double* __restrict__ B) {
+    __shared__ double sa[32][33], sb[32][33];
+    const int t = blockIdx.x >> 4, sub = blockIdx.x & 15;
+    const int tp = tiles[2 * t], tq = tiles[2 * t + 1];
+    const int i0 = (sub >> 2) * 32, j0 = (sub & 3) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const long P0 = (long)tp * HG_TILE, Q0 = (long)tq * HG_TILE;
+    const bool diag = tp == tq;
+    const size_t tile_sz = 2 * HG_TILE * HG_TILE;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int ii = ty + 8 * m, jj = tx;
+        const size_t e = (size_t)(i0 + ii) * HG_TILE + (j0 + jj);
+        double a = 0.0, b = 0.0;
+        for (int ks = 0; ks < slices; ++ks) {
+            const double* pt = part + ((size_t)ks * ntiles + t) * tile_sz;
+            a += pt[e];
+            b += pt[HG_TILE * HG_TILE + e];
+        }
+        if (diag && i0 + ii == j0 + jj) b = 0.0;
+        sa[ii][jj] = a;
+        sb[ii][jj] = b;
+        const long p = P0 + i0 + ii, q = Q0 + j0 + jj;
+        if ((!diag || i0 + ii <= j0 + jj) && p < P && q < P) {
+            A[p * ld + q] = a;
+            B[p * ld + q] = b;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int jj = ty + 8 * m, ii = tx;  // source element (ii, jj), written at (q, p)
+        const long p = P0 + i0 + ii, q = Q0 + j0 + jj;
+        if ((!diag || i0 + ii < j0 + jj) && p < P && q < P) {
+            A[q * ld + p] = sa[ii][jj];
+            B[q * ld + p] = -sb[ii][jj];
+        }
+    }
+}
+
+// (G + shift I) v for the real system [[A, -B], [B, A]], v = [v_r | v_i] (2P):
+// one wave per H_MV_RW rows p of A and B, each row read once for both halves of
+// the output; the products' dot v.(G + shift I) v is summed per block into
+// dpart (in a fixed order) for the CG step.
+constexpr int H_MV_RW = 4;
+int h_matvec_blocks(int P) { return (P + 4 * H_MV_RW - 1) / (4 * H_MV_RW); }
+
+__global__ __launch_bounds__(256) void k_h_matvec(const double* __restrict__ G, int P, long ld,
+                                                  const double* __restrict__ v, double shift,
+                                                  double* __restrict__ out,
+                                                  double* __restrict__ dpart,
+                                                  const CgScalars* __restrict__ sc) {
+    if (sc->done) return;
+    __shared__ double sh[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long p0 = ((long)blockIdx.x * 4 + wave) * H_MV_RW;
+    const double* A = G;
+    const double* B = G + (size_t)P * ld;
+    const double* vr = v;
+    const double* vi = v + P;
+    double ar[H_MV_RW], ai[H_MV_RW];
+#pragma unroll
+    for (int r = 0; r < H_MV_RW; ++r) ar[r] = ai[r] = 0.0;
+    for (long q = 4 * lane; q < P; q += 256) {
+        if (q + 4 <= P) {
+            const double x0 = vr[q], x1 = vr[q + 1], x2 = vr[q + 2], x3 = vr[q + 3];
+            const double y0 = vi[q], y1 = vi[q + 1], y2 = vi[q + 2], y3 = vi[q + 3];
+#pragma unroll
+            for (int r = 0; r < H_MV_RW; ++r) {
+                if (p0 + r >= P) break;
+                const double* ga = A + (p0 + r) * ld + q;
+                const double* gb = B + (p0 + r) * ld + q;
+                const double2 a01 = *(const double2*)ga, a23 = *(const double2*)(ga + 2);
+                const double2 b01 = *(const double2*)gb, b23 = *(const double2*)(gb + 2);
+                ar[r] += ((a01.x * x0 - b01.x * y0) + (a01.y * x1 - b01.y * y1)) +
+                         ((a23.x * x2 - b23.x * y2) + (a23.y * x3 - b23.y * y3));
+                ai[r] += ((b01.x * x0 + a01.x * y0) + (b01.y * x1 + a01.y * y1)) +
+                         ((b23.x * x2 + a23.x * y2) + (b23.y * x3 + a23.y * y3));
+            }
+        } else {  // ragged end of the row
+            for (long qq = q; qq < P; ++qq)
+#pragma unroll
+                for (int r = 0; r < H_MV_RW; ++r)
+                    if (p0 + r < P) {
+                        const double a = A[(p0 + r) * ld + qq], b = B[(p0 + r) * ld + qq];
+                        ar[r] += a * vr[qq] - b * vi[qq];
+                        ai[r] += b * vr[qq] + a * vi[qq];
+                    }
+        }
+    }
+    double dot = 0.0;
+#pragma unroll
+    for (int r = 0; r < H_MV_RW; ++r) {
+        const double sr = wave_sum(ar[r]), si = wave_sum(ai[r]);
+        const long p = p0 + r;
+        if (p < P) {
+            const double orr = sr + shift * vr[p], oi = si + shift * vi[p];
+            if (lane == 0) {
+                out[p] = orr;
+                out[P + p] = oi;
+            }
+            dot += orr * vr[p] + oi * vi[p];
+        }
+    }
+    if (lane == 0) sh[wave] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) dpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // out[p] = in[p] + c x_p, x_p = x[p] + i x[P + p] (the embedding of a complex
@@ -488,11 +741,35 @@ void launch_h_jacobian(hipStream_t st, int N, int M, const int8_t* s, const doub
     if (n <= 0) return;
     k_h_jacobian<<<nbk(n * P, 256), 256, 0, st>>>(N, M, s, t, n, P, O);
 }
-void launch_h_force(hipStream_t st, const double* Y, long n, long ld, int P2, const double2* E,
+void launch_h_force(hipStream_t st, const double* U, long n, long ld, int P, const double2* E,
                     const double* stats, double* f, double* scratch) {
-    k_h_force<<<dim3(nbk(P2, 256), H_SLICES), 256, 0, st>>>(Y, n, ld, P2, E, stats, H_SLICES,
-                                                            scratch);
-    k_h_sum_slices<<<nbk(P2, 256), 256, 0, st>>>(scratch, P2, H_SLICES, f);
+    // (slices over samples)
+    k_h_force<<<dim3(nbk(P, 256), H_SLICES), 256, 0, st>>>(U, n, ld, P, E, stats, H_SLICES,
+                                                           scratch);
+    k_h_sum_slices<<<nbk(2 * P, 256), 256, 0, st>>>(scratch, 2 * P, H_SLICES, f);
+}
+// Row slices of the Gram: enough (tile, slice) blocks to give every compute
+// unit several, each slice at least 256 rows (a multiple of 4)
+int h_gram_slices(int ntiles, long n) {
+    int S = 1;
+    while (S < 16 && (long)ntiles * S < 2048 && 2 * n / (2 * S) >= 256) S *= 2;
+    return S;
+}
+size_t h_gram_part_bytes(int ntiles, int slices) {
+    return (size_t)ntiles * slices * 2 * HG_TILE * HG_TILE * 8;
+}
+void launch_h_gram(hipStream_t st, const double* U, long n, long ld, int P, const int* tiles,
+                   int ntiles, int slices, double* part, double* G) {
+    const long R = 2 * h_half_rows(n);  // rows of U (a multiple of 16)
+    long rps = (R + slices - 1) / slices;
+    rps = (rps + HG_ROWS - 1) / HG_ROWS * HG_ROWS;
+    k_h_gram<<<(unsigned)(ntiles * slices), 512, 0, st>>>(U, n, ld, ntiles, rps, tiles, part);
+    k_h_gram_fin<<<(unsigned)(ntiles * 16), 256, 0, st>>>(part, ntiles, slices, tiles, P, ld, G,
+                                                          G + (size_t)P * ld);
+}
+void launch_h_matvec(hipStream_t st, const double* G, int P, long ld, const double* v,
+                     double shift, double* out, double* dpart, CgScalars* sc) {
+    k_h_matvec<<<h_matvec_blocks(P), 256, 0, st>>>(G, P, ld, v, shift, out, dpart, sc);
 }
 void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
                    double c2r, double c2i, const double* x2, double2* out) {

@@ -203,12 +203,25 @@ void launch_h_stats(hipStream_t st, const double2* E, long n, double* out);
 size_t h_slice_bytes(int P);
 void launch_h_jacobian(hipStream_t st, int N, int M, const int8_t* s, const double2* t, long n,
                        int P, double2* O);
-// Y [2n][ld] = the real embedding of (O - mean O) / sqrt(n); mean: complex [P]
+// U [2 n8][ld] = [Re; Im] of (O - mean O) / sqrt(n), stacked, each half
+// n8 = h_half_rows(n) rows (rows past n zero); mean: complex [P]
+__host__ __device__ inline long h_half_rows(long n) { return (n + 7) / 8 * 8; }
 void launch_h_jacobian_emb(hipStream_t st, int N, int M, const int8_t* s, const double2* t,
-                           long n, int P, long ld, double* Y, double2* mean, double* scratch);
-// f [2P] = Y^T [Re dE; Im dE] / sqrt(n) (the embedded force)
-void launch_h_force(hipStream_t st, const double* Y, long n, long ld, int P2, const double2* E,
+                           long n, int P, long ld, double* U, double2* mean, double* scratch);
+// f [2P] = [Re | Im] of dJ^H (E - mean E) / sqrt(n), from U
+void launch_h_force(hipStream_t st, const double* U, long n, long ld, int P, const double2* E,
                     const double* stats, double* f, double* scratch);
+// A = Re G (G [P][ld]) and B = Im G (G + P ld) from U; tiles from fill_gram_tiles(P);
+// part: h_gram_part_bytes(ntiles, slices) of scratch
+int h_gram_slices(int ntiles, long n);
+size_t h_gram_part_bytes(int ntiles, int slices);
+void launch_h_gram(hipStream_t st, const double* U, long n, long ld, int P, const int* tiles,
+                   int ntiles, int slices, double* part, double* G);
+// (G + shift I) v for [[A, -B], [B, A]] (v, out: [re | im], 2P) and the block
+// partials of v.(G + shift I) v (h_matvec_blocks(P) of them)
+int h_matvec_blocks(int P);
+void launch_h_matvec(hipStream_t st, const double* G, int P, long ld, const double* v,
+                     double shift, double* out, double* dpart, CgScalars* sc);
 // out = in + c x (+ c2 x2), x and x2 embedded [re | im], c complex
 void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
                    double c2r, double c2i, const double* x2, double2* out);
