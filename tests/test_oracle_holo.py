@@ -255,3 +255,42 @@ def test_exact_tdvp_follows_exact_evolution():
     assert fid > 1 - 1e-5, fid
     X = sum(exact.site_op(exact._X, i, N) for i in range(N)).toarray()
     assert abs(np.vdot(psi, X @ psi).real - np.vdot(ref, X @ ref).real) < 1e-3
+
+
+def test_exact_tdvp_quench_tracks_exact_dynamics():
+    """The real-time example's quench at L = 8: the complex RBM (alpha = 1) is
+    brought to the h = 1/2 ground state by imaginary-time TDVP (exact
+    expectations), then evolved in real time with h = 1 by Heun steps of
+    dt = 0.01.  Against exp(-i H1 t)|psi_0> (sparse matrix exponential of the
+    exact Hamiltonian applied to the same initial state): fidelity above
+    0.999, <sum sigma^x> within 0.01 and the energy conserved to 5e-4
+    relative up to t = 0.6."""
+    import scipy.sparse.linalg as spla
+    N, M = 8, 8
+    rng = np.random.default_rng(3)
+    P = N + M + M * N
+    r = holo.RbmC(N, M, 0.05 * (rng.normal(size=P) + 1j * rng.normal(size=P)))
+    h0 = core.Hamiltonian.tfim(N, _chain(N), 1.0, 0.5)
+    h1 = core.Hamiltonian.tfim(N, _chain(N), 1.0, 1.0)
+    for _ in range(60):
+        r = holo.exact_tdvp_step(r, h0, 0.2, -1.0, "euler", diag_shift=1e-4)
+    e0 = spla.eigsh(exact.hamiltonian_matrix(h0), k=1, which="SA")[0][0]
+    assert abs(holo.ExactStateC(r, h0).energy() - e0) < 1e-4 * abs(e0)
+    H1 = exact.hamiltonian_matrix(h1)
+    X = sum(exact.site_op(exact._X, i, N) for i in range(N))
+    cfg = exact.all_configs(N)
+
+    def state(q):
+        v = np.exp(holo.log_psi(q, cfg))
+        return v / np.linalg.norm(v)
+
+    psi0 = state(r)
+    E0 = np.vdot(psi0, H1 @ psi0).real
+    for k in range(1, 61):
+        r = holo.exact_tdvp_step(r, h1, 0.01, -1j, "heun", diag_shift=1e-5)
+        if k % 20 == 0:
+            ref = spla.expm_multiply(-1j * H1 * (0.01 * k), psi0)
+            v = state(r)
+            assert abs(np.vdot(ref, v)) ** 2 > 0.999, k
+            assert abs(np.vdot(v, X @ v).real - np.vdot(ref, X @ ref).real) < 0.01, k
+            assert abs(np.vdot(v, H1 @ v).real - E0) < 5e-4 * abs(E0), k
