@@ -498,6 +498,73 @@ def paper_workload_measure(torch, steps=5, warmup=2):
                                    s_per_step_cg_2gpu=1.7))
 
 
+def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e-3,
+                        observe_every=10):
+    """The real-time example: TFIM chain L = 20 (J = 1), complex RBM alpha = 1,
+    4096 samples.  The initial state is the h = 1/2 ground state found by SR
+    (the example's 300 steps, learning rate 0.01, shift 0.01); the field is then
+    quenched to h = 1 and the state evolved by TDVP Heun steps of dt up to
+    t = steps dt with the dense holomorphic QGT and CG.  Reports the time per
+    TDVP step (two evaluations of the equation of motion: sampling, local
+    energies, Jacobian, force, Gram, CG) and the trace of the energy (conserved
+    by the exact dynamics) and of sum_i <sigma^x_i> (local estimator
+    sum_i psi(s^i)/psi(s) = (J sum_<ab> s_a s_b - E_loc(s)) / h, from a batch
+    drawn after the step, outside the timed calls)."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.WORKLOADS["tfim1d_n20_quench"]
+    b = w.bonds()
+    prep = VMCState.from_workload(w.replace(h=0.5))
+    prep.thermalize(w.thermalize_segments)
+    for _ in range(prep_steps):
+        rep = prep.vmc_step(qgt="jacobian_dense", diag_shift=0.01, lr=0.01, tol=1e-6)
+    e_prep = rep.energy["mean"]
+    st = VMCState.from_workload(w, params=prep.get_params())
+    st.set_chains(prep.get_chains())
+    prep.close()
+
+    def observe(t):
+        smp, _, _ = st.sample()
+        s = smp.reshape(-1, w.n_sites)
+        E = st.local_energy(s).cpu().numpy()
+        sc = s.cpu().numpy().astype(np.float64)
+        zz = (sc[:, b[:, 0]] * sc[:, b[:, 1]]).sum(axis=1)
+        sx = (w.J * zz - E.real) / w.h
+        n = sx.size
+        return dict(t=t, energy=float(E.real.mean()), energy_err=float(E.real.std() / np.sqrt(n)),
+                    sx=float(sx.mean()), sx_err=float(sx.std() / np.sqrt(n)))
+
+    trace = [observe(0.0)]
+    lat, iters = [], []
+    for k in range(1, steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stages = st.tdvp_step(dt, gamma=-1j, scheme="heun", diag_shift=diag_shift, tol=1e-6)
+        lat.append(time.perf_counter() - t0)  # (the step reads its scalars back: synchronous)
+        iters.append(np.mean([g["solve"].iterations for g in stages]))
+        if k % observe_every == 0:
+            trace.append(observe(k * dt))
+    st.close()
+    lat_ms = np.array(lat) * 1e3
+    e = np.array([r["energy"] for r in trace])
+    print(f"[bench] TDVP quench: {np.median(lat_ms):.2f} ms per Heun step", file=sys.stderr,
+          flush=True)
+    return dict(metric="milliseconds per TDVP (Heun) step, quench of the TFIM chain",
+                value=float(np.mean(lat_ms)), unit="ms/step", higher_is_better=False,
+                p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
+                steps=steps, dt=dt, dtype="c128", data="synthetic",
+                config=dict(workload="tfim1d_n20_quench: 1D TFIM L=20 periodic J=1, h 0.5 -> 1, "
+                                     "complex RBM alpha=1 (440 complex parameters), 256 chains "
+                                     "x 16 samples, 20 proposals per sample, Heun dt "
+                                     f"{dt}, dense holomorphic QGT + CG tol 1e-6 shift "
+                                     f"{diag_shift}",
+                            n_samples=w.n_samples, n_params=w.n_params),
+                prep=dict(sr_steps=prep_steps, energy_h05=e_prep),
+                cg_iters_mean=float(np.mean(iters)),
+                energy_drift=float(e.max() - e.min()),
+                energy_err_mean=float(np.mean([r["energy_err"] for r in trace])),
+                trace=trace)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -563,6 +630,8 @@ def main():
                     help="SR steps on the N=10 TFIM chain: time and energy against the exact one")
     ap.add_argument("--paper-workload", action="store_true",
                     help="time full SR steps on the paper's timed workload (complex RBM)")
+    ap.add_argument("--tdvp-quench", action="store_true",
+                    help="time TDVP Heun steps of the L=20 TFIM quench (complex RBM)")
     ap.add_argument("--serve", action="store_true",
                     help="measure the continuous-batching server on a Poisson stream of runs")
     ap.add_argument("--serve-runs", type=int, default=256)
@@ -590,6 +659,9 @@ def main():
         return
     if args.paper_workload:
         print(json.dumps(paper_workload_measure(torch)), flush=True)
+        return
+    if args.tdvp_quench:
+        print(json.dumps(tdvp_quench_measure(torch)), flush=True)
         return
     if args.plain:
         print(json.dumps(plain_measure(torch)), flush=True)

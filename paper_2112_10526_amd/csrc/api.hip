@@ -106,6 +106,7 @@ struct nqs_ctx {
     // a full batch of on-the-fly CG iterations captured as a HIP graph
     bool graphs = true;
     hipGraphExec_t cg_graph = nullptr;
+    hipGraphExec_t cg_graph_dense = nullptr;  // a batch of dense-form iterations
     hipStream_t cap_stream = nullptr;
     // a step issued by nqs_step_begin: 0 none, 1 in CG, 2 update issued, results
     // on their way to the host (step_ev marks their arrival)
@@ -563,7 +564,7 @@ int read_acceptance(nqs_ctx* c) {
 }
 
 // dense Jacobian form: build G once for this batch and set up CG in packed space
-void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
+void issue_dense_setup(nqs_ctx* c, double tol, int maxiter, double shift) {
     const int P = (int)c->P;
     {
         PROF(NQS_PROF_JACOBIAN);
@@ -578,7 +579,7 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter) {
     }
     launch_pack(c->stream, c->d, c->b.grad, c->b.fp, P);
     launch_cg_init(c->stream, P, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
-                   maxiter);
+                   maxiter, shift);
 }
 
 void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
@@ -594,7 +595,8 @@ void issue_cg_init(nqs_ctx* c, double tol, int maxiter, double shift) {
 // w = J r + beta w; the chunk partials of J^T z; the update, which forms
 // p_new = r + beta p_old (the direction alternates between two buffers, the
 // head partials too) and updates x and r.
-// With host_flag, the last on-the-fly iteration stores the stop flag there.
+// Dense form: product, update, direction (the shift is in the scalars).
+// With host_flag, the last iteration stores the stop flag there.
 void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host_flag = nullptr) {
     const Dims& d = c->d;
     const int nbv = qgt_nbv(d, c->prec);
@@ -627,16 +629,16 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host
                 PROF(NQS_PROF_DENSE_MV);
                 if (c->cplx)
                     launch_h_matvec(c->stream, (const double*)c->b.G, (int)c->P, c->Plc, c->b.pp,
-                                    shift, c->b.App, c->b.dpart, c->b.sc);
+                                    c->b.App, c->b.dpart, c->b.sc);
                 else
-                    launch_dense_matvec(c->stream, c->prec, c->b.G, c->Pd, c->Pld, c->b.pp, shift,
+                    launch_dense_matvec(c->stream, c->prec, c->b.G, c->Pd, c->Pld, c->b.pp,
                                         c->b.App, c->b.dpart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_CGVEC);
                 launch_cg_update(c->stream, c->Pd, c->b.xp, c->b.rp, c->b.pp, c->b.App, c->b.dpart,
                                  c->cplx ? h_matvec_blocks((int)c->P) : dense_matvec_blocks(c->Pd),
-                                 c->b.sc);
+                                 c->b.sc, it + 1 == iters ? host_flag : nullptr);
             }
         }
     }
@@ -673,11 +675,13 @@ int sr_status(nqs_ctx* c, nqs_sr_info* info) {
 void drop_graphs(nqs_ctx* c) {
     if (c->cg_graph) hipGraphExecDestroy(c->cg_graph);
     c->cg_graph = nullptr;
+    if (c->cg_graph_dense) hipGraphExecDestroy(c->cg_graph_dense);
+    c->cg_graph_dense = nullptr;
 }
 
 // Records one batch of `every` on-the-fly iterations (starting at an even
 // iteration, so the alternating buffers line up) as a graph.
-int capture_batch(nqs_ctx* c, double shift, int every) {
+int capture_batch(nqs_ctx* c, int kind, double shift, int every) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t run = c->stream;
     const long it0 = c->cg_iter;
@@ -685,15 +689,16 @@ int capture_batch(nqs_ctx* c, double shift, int every) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        issue_cg_iters(c, NQS_QGT_ONTHEFLY, shift, every, &c->h_flag[0]);
+        issue_cg_iters(c, kind, shift, every, &c->h_flag[0]);
         e = hipStreamEndCapture(c->cap_stream, &graph);
     }
     c->stream = run;
     c->cg_iter = it0;
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->cg_graph, graph, nullptr, nullptr, 0);
+    hipGraphExec_t& g = kind == NQS_QGT_ONTHEFLY ? c->cg_graph : c->cg_graph_dense;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
     if (graph) hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        c->cg_graph = nullptr;
+        g = nullptr;
         return fail(c, NQS_EDEVICE, std::string("CG graph capture: ") + hipGetErrorString(e));
     }
     return NQS_OK;
@@ -701,13 +706,15 @@ int capture_batch(nqs_ctx* c, double shift, int every) {
 
 // kernel classes of the on-the-fly CG iterations
 constexpr uint32_t CG_CLASSES = (1u << NQS_PROF_QGT_W) | (1u << NQS_PROF_OUTER) |
-                                (1u << NQS_PROF_REDUCE) | (1u << NQS_PROF_CGVEC);
+                                (1u << NQS_PROF_REDUCE) | (1u << NQS_PROF_CGVEC) |
+                                (1u << NQS_PROF_DENSE_MV);
 
 // Issues CG iterations in batches and reads the stop flag of each batch while
 // the next batch is already queued, so the device never waits for the host.
 // Iterations issued after the stop return at once (every CG kernel tests the
-// flag first).  Full on-the-fly batches are replayed from one captured graph
-// (the iteration kernels take their scalars from the device) unless CG kernel
+// flag first).  Full batches are replayed from one captured graph per form
+// (the iteration kernels take their scalars from the device; the last one of
+// a batch stores the stop flag in pinned host memory) unless CG kernel
 // classes are being timed, which needs one event pair per launch and batches
 // of one iteration.  One CgRun drives one context; the batched step drives
 // several side by side.
@@ -729,26 +736,23 @@ struct CgRun {
         every = (c->prof_mask & CG_CLASSES) ? 1 : cg_check_interval();
         // the on-the-fly form tests convergence at the start of an iteration
         limit = kind == NQS_QGT_ONTHEFLY ? maxiter + 1 : maxiter;
-        use_graphs = c->graphs && kind == NQS_QGT_ONTHEFLY && every % 2 == 0 &&
-                     !(c->prof_mask & CG_CLASSES);
+        use_graphs = c->graphs && every % 2 == 0 && !(c->prof_mask & CG_CLASSES);
     }
     bool finished() const { return stop || (checked >= issued && launched >= limit); }
     int issue_batch() {
         const int k = (limit - launched) < every ? (limit - launched) : every;
         const int slot = issued & 1;
-        if (use_graphs && k == every && c->cg_iter % 2 == 0) {
-            if (!c->cg_graph) {
-                const int st = capture_batch(c, shift, every);
+        // (the on-the-fly form alternates buffers: its graph starts on an even iteration)
+        if (use_graphs && k == every && (kind != NQS_QGT_ONTHEFLY || c->cg_iter % 2 == 0)) {
+            hipGraphExec_t& g = kind == NQS_QGT_ONTHEFLY ? c->cg_graph : c->cg_graph_dense;
+            if (!g) {
+                const int st = capture_batch(c, kind, shift, every);
                 if (st) return st;
             }
-            HIPCHK(c, hipGraphLaunch(c->cg_graph, c->stream));
+            HIPCHK(c, hipGraphLaunch(g, c->stream));
             c->cg_iter += every;
-        } else if (kind == NQS_QGT_ONTHEFLY) {
-            issue_cg_iters(c, kind, shift, k, &c->h_flag[0]);
         } else {
-            issue_cg_iters(c, kind, shift, k);
-            HIPCHK(c, hipMemcpyAsync(&c->h_flag[slot], &c->b.sc->done, sizeof(int32_t),
-                                     hipMemcpyDeviceToHost, c->stream));
+            issue_cg_iters(c, kind, shift, k, &c->h_flag[0]);
         }
         launched += k;
         HIPCHK(c, hipEventRecord(c->flag_ev[slot], c->stream));
@@ -778,9 +782,10 @@ struct CgRun {
             if (e == hipErrorNotReady) return NQS_OK;
             HIPCHK(c, e);
         }
-        // on-the-fly: the batch's last update stored the flag in word 0 (a later
-        // batch may already have overwritten it with a value just as valid)
-        stop = c->h_flag[kind == NQS_QGT_ONTHEFLY ? 0 : slot] != 0;
+        // the batch's last iteration stored the flag in word 0 (a later batch may
+        // already have overwritten it with a value just as valid: the flag only
+        // goes from 0 to 1 within a solve)
+        stop = c->h_flag[0] != 0;
         ++checked;
         progress = true;
         return NQS_OK;
@@ -910,7 +915,7 @@ int h_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
                       c->ntiles, c->hS, c->b.hgp, (double*)c->b.G);
     }
     launch_cg_init(c->stream, c->Pd, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
-                   mi);
+                   mi, diag_shift);
     return run_cg(c, NQS_QGT_JACOBIAN_DENSE, diag_shift, mi);
 }
 
@@ -1530,7 +1535,7 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
         return last_launch(c);
     }
     const int mi = default_maxiter(c, maxiter);
-    if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi);
+    if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi, diag_shift);
     else issue_cg_init(c, tol, mi, diag_shift);
     st = run_cg(c, kind, diag_shift, mi);
     if (st) return st;
@@ -1657,7 +1662,8 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         issue_sample(c, 0, nullptr);
         issue_energy_grad(c);
         mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
-        if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfgs[k].cg_tol, mi[k]);
+        if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE)
+            issue_dense_setup(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
         else issue_cg_init(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
         st[k] = last_launch(c);
     }
@@ -1785,7 +1791,7 @@ int nqs_step_begin(nqs_ctx* c, const nqs_step_cfg* cfg) {
     if (!st) st = sr_check(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol);
     if (st) return st;
     const int mi = default_maxiter(c, cfg->cg_maxiter);
-    if (cfg->qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfg->cg_tol, mi);
+    if (cfg->qgt == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, cfg->cg_tol, mi, cfg->diag_shift);
     else issue_cg_init(c, cfg->cg_tol, mi, cfg->diag_shift);
     st = last_launch(c);
     if (st) return st;

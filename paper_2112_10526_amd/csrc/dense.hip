@@ -404,12 +404,13 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 constexpr int DMV_RW = 4;
 template <typename R>
 __global__ __launch_bounds__(256) void k_dense_matvec(const R* __restrict__ G, int P, long ld,
-                                                      const double* __restrict__ v, double shift,
+                                                      const double* __restrict__ v,
                                                       double* __restrict__ out,
                                                       double* __restrict__ dpart,
                                                       const CgScalars* __restrict__ sc) {
     if (sc->done) return;
     __shared__ double sh[4];
+    const double shift = sc->shift;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long p0 = ((long)blockIdx.x * 4 + wave) * DMV_RW;
     double acc[DMV_RW];
@@ -576,12 +577,12 @@ void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P
         k_gram_split<<<ntiles, 256, 0, st>>>((const uint32_t*)A, n, ld, P, (float*)G, tiles);
 }
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
-                         double shift, double* out, double* dpart, CgScalars* sc) {
+                         double* out, double* dpart, CgScalars* sc) {
     const int nb = dense_matvec_blocks(P);
     if (prec == 0)
-        k_dense_matvec<double><<<nb, 256, 0, st>>>((const double*)G, P, ld, v, shift, out, dpart, sc);
+        k_dense_matvec<double><<<nb, 256, 0, st>>>((const double*)G, P, ld, v, out, dpart, sc);
     else
-        k_dense_matvec<float><<<nb, 256, 0, st>>>((const float*)G, P, ld, v, shift, out, dpart, sc);
+        k_dense_matvec<float><<<nb, 256, 0, st>>>((const float*)G, P, ld, v, out, dpart, sc);
 }
 
 }  // namespace nqs

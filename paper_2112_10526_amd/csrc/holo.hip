@@ -579,7 +579,8 @@ __global__ __launch_bounds__(256) void k_h_gram_fin(const double* __restrict__ p
     }
 }
 
-// (G + shift I) v for the real system [[A, -B], [B, A]], v = [v_r | v_i] (2P):
+// (G + shift I) v for the real system [[A, -B], [B, A]], v = [v_r | v_i] (2P),
+// the shift taken from the CG scalars:
 // one wave per H_MV_RW rows p of A and B, each row read once for both halves of
 // the output; the products' dot v.(G + shift I) v is summed per block into
 // dpart (in a fixed order) for the CG step.
@@ -587,12 +588,13 @@ constexpr int H_MV_RW = 4;
 int h_matvec_blocks(int P) { return (P + 4 * H_MV_RW - 1) / (4 * H_MV_RW); }
 
 __global__ __launch_bounds__(256) void k_h_matvec(const double* __restrict__ G, int P, long ld,
-                                                  const double* __restrict__ v, double shift,
+                                                  const double* __restrict__ v,
                                                   double* __restrict__ out,
                                                   double* __restrict__ dpart,
                                                   const CgScalars* __restrict__ sc) {
     if (sc->done) return;
     __shared__ double sh[4];
+    const double shift = sc->shift;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long p0 = ((long)blockIdx.x * 4 + wave) * H_MV_RW;
     const double* A = G;
@@ -768,8 +770,8 @@ void launch_h_gram(hipStream_t st, const double* U, long n, long ld, int P, cons
                                                           G + (size_t)P * ld);
 }
 void launch_h_matvec(hipStream_t st, const double* G, int P, long ld, const double* v,
-                     double shift, double* out, double* dpart, CgScalars* sc) {
-    k_h_matvec<<<h_matvec_blocks(P), 256, 0, st>>>(G, P, ld, v, shift, out, dpart, sc);
+                     double* out, double* dpart, CgScalars* sc) {
+    k_h_matvec<<<h_matvec_blocks(P), 256, 0, st>>>(G, P, ld, v, out, dpart, sc);
 }
 void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
                    double c2r, double c2i, const double* x2, double2* out) {

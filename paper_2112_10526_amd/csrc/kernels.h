@@ -112,11 +112,13 @@ void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* pa
                          const double* p, double shift, double* out, double* dpart,
                          CgScalars* sc, int mode);
 void launch_cg_init(hipStream_t st, int total, const double* f, double* x, double* r, double* p,
-                    double* dpart, CgScalars* sc, double tol, int maxiter);
+                    double* dpart, CgScalars* sc, double tol, int maxiter, double shift);
 // dense-form CG iteration after the product: dpart holds the product's npap
-// partials of p.Ap, followed by room for the update's partials of r.r
+// partials of p.Ap, followed by room for the update's partials of r.r; with
+// host_flag (pinned), the stop flag is also stored there
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, int npap, CgScalars* sc);
+                      const double* Ap, double* dpart, int npap, CgScalars* sc,
+                      int32_t* host_flag = nullptr);
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc);
 
@@ -183,8 +185,9 @@ void fill_gram_tiles(int P, int* host_tiles);
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
                  const int* tiles, int ntiles);
 int dense_matvec_blocks(int P);  // blocks (and p.Ap partials) of one dense product
+// (G + shift I) v, the shift taken from sc
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
-                         double shift, double* out, double* dpart, CgScalars* sc);
+                         double* out, double* dpart, CgScalars* sc);
 
 // holo.hip: complex-parameter (holomorphic) RBM, complex FP64 (double2)
 int h_max_hidden();
@@ -217,11 +220,11 @@ int h_gram_slices(int ntiles, long n);
 size_t h_gram_part_bytes(int ntiles, int slices);
 void launch_h_gram(hipStream_t st, const double* U, long n, long ld, int P, const int* tiles,
                    int ntiles, int slices, double* part, double* G);
-// (G + shift I) v for [[A, -B], [B, A]] (v, out: [re | im], 2P) and the block
+// (G + shift I) v for [[A, -B], [B, A]] (v, out: [re | im], 2P; shift from sc) and the block
 // partials of v.(G + shift I) v (h_matvec_blocks(P) of them)
 int h_matvec_blocks(int P);
 void launch_h_matvec(hipStream_t st, const double* G, int P, long ld, const double* v,
-                     double shift, double* out, double* dpart, CgScalars* sc);
+                     double* out, double* dpart, CgScalars* sc);
 // out = in + c x (+ c2 x2), x and x2 embedded [re | im], c complex
 void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
                    double c2r, double c2i, const double* x2, double2* out);

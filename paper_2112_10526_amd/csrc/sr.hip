@@ -261,7 +261,10 @@ __global__ __launch_bounds__(256) void k_reduce_outer(Dims d, const R* __restric
 //   update:    p.Ap from the product's partials, alpha = r.r / p.Ap,
 //              x += alpha p, r -= alpha Ap, block partials of the new r.r;
 //   direction: r.r from the update's partials, beta = r.r / r.r_prev,
-//              p = r + beta p; block 0 advances the iteration and the stop flag.
+//              p = r + beta p; block 0 advances the iteration and the stop flag
+//              (also stored to a pinned host word when asked: the last
+//              iteration of a batch, so a batch can be replayed from a graph).
+// The diagonal shift is taken from the scalars (set by k_cg_init).
 // Every scalar is written by a different kernel from the one that reads it.
 __device__ __forceinline__ double sum_partials(const double* part, int np, double* sh) {
     double a = 0.0;
@@ -306,8 +309,12 @@ __global__ __launch_bounds__(256) void k_cg_update(int total, double* __restrict
 __global__ __launch_bounds__(256) void k_cg_p(int total, const double* __restrict__ r,
                                               double* __restrict__ p,
                                               const double* __restrict__ rr_part, int nrr,
-                                              CgScalars* sc) {
-    if (sc->done) return;
+                                              CgScalars* sc, volatile int32_t* host_flag) {
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (sc->done) {
+        if (host_flag && lead) *host_flag = 1;
+        return;
+    }
     __shared__ double sh[4];
     const double rr = sum_partials(rr_part, nrr, sh);
     const double beta = rr / sc->rr_prev;
@@ -322,6 +329,7 @@ __global__ __launch_bounds__(256) void k_cg_p(int total, const double* __restric
             sc->done = 1;
         }
         if (rr <= sc->tol2 || sc->iters >= sc->maxiter) sc->done = 1;
+        if (host_flag) *host_flag = sc->done;
     }
 }
 
@@ -329,7 +337,8 @@ __global__ __launch_bounds__(256) void k_cg_p(int total, const double* __restric
 __global__ __launch_bounds__(256) void k_cg_init(int total, const double* __restrict__ f,
                                                  double* __restrict__ x, double* __restrict__ r,
                                                  double* __restrict__ p, double* __restrict__ dpart,
-                                                 CgScalars* sc, double tol, int maxiter) {
+                                                 CgScalars* sc, double tol, int maxiter,
+                                                 double shift) {
     __shared__ double sh[4];
     const int e = blockIdx.x * 256 + threadIdx.x;
     double ff = 0.0;
@@ -351,6 +360,7 @@ __global__ __launch_bounds__(256) void k_cg_init(int total, const double* __rest
             sc->tol2 = tol * tol * s;
             sc->iters = 0;
             sc->maxiter = maxiter;
+            sc->shift = shift;
             sc->bad = isfinite(s) ? 0 : 1;
             sc->done = (s <= sc->tol2 || maxiter <= 0 || !isfinite(s)) ? 1 : 0;
             sc->counter[2] = 0;
@@ -431,15 +441,16 @@ void launch_reduce_outer(hipStream_t st, const Dims& d, int prec, const void* pa
                                                   dpart, sc, mode);
 }
 void launch_cg_init(hipStream_t st, int total, const double* f, double* x, double* r, double* p,
-                    double* dpart, CgScalars* sc, double tol, int maxiter) {
-    k_cg_init<<<nblk(total, 256), 256, 0, st>>>(total, f, x, r, p, dpart, sc, tol, maxiter);
+                    double* dpart, CgScalars* sc, double tol, int maxiter, double shift) {
+    k_cg_init<<<nblk(total, 256), 256, 0, st>>>(total, f, x, r, p, dpart, sc, tol, maxiter, shift);
 }
 void launch_cg_update(hipStream_t st, int total, double* x, double* r, double* p,
-                      const double* Ap, double* dpart, int npap, CgScalars* sc) {
+                      const double* Ap, double* dpart, int npap, CgScalars* sc,
+                      int32_t* host_flag) {
     const int nb = nblk(total, 256);
     double* rr_part = dpart + npap;  // after the product's partials
     k_cg_update<<<nb, 256, 0, st>>>(total, x, r, p, Ap, dpart, npap, rr_part, sc);
-    k_cg_p<<<nb, 256, 0, st>>>(total, r, p, rr_part, nb, sc);
+    k_cg_p<<<nb, 256, 0, st>>>(total, r, p, rr_part, nb, sc, host_flag);
 }
 void launch_axpy_update(hipStream_t st, int total, double* x, const double* delta, double lr,
                         CgScalars* sc) {
