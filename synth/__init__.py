@@ -24,7 +24,8 @@ import numpy as np
 
 __all__ = [
     "chain_bonds", "square_bonds", "chain_sublattice", "square_sublattice",
-    "n_params", "rbm_params", "rbm_params_c", "random_configs", "sz0_configs", "Workload",
+    "n_params", "rbm_params", "rbm_params_c", "random_configs", "chain_translations",
+    "square_translations", "symm_params", "sz0_configs", "Workload",
     "WORKLOADS",
 ]
 
@@ -60,6 +61,30 @@ def square_sublattice(L: int) -> np.ndarray:
     x = np.arange(L * L) % L
     y = np.arange(L * L) // L
     return ((x + y) % 2).astype(np.int8)
+
+
+def chain_translations(n: int) -> np.ndarray:
+    """Translations of the periodic chain as site permutations: row g maps site k
+    to k + g mod n (row 0 the identity); int32 [n, n]."""
+    k = np.arange(n)
+    return np.stack([(k + g) % n for g in range(n)]).astype(np.int32)
+
+
+def square_translations(L: int) -> np.ndarray:
+    """Translations of the periodic L x L square lattice (site = x + L*y): row
+    g = dx + L*dy maps (x, y) to (x+dx, y+dy) mod L; int32 [L*L, L*L]."""
+    x = np.arange(L * L) % L
+    y = np.arange(L * L) // L
+    rows = [((x + dx) % L) + L * ((y + dy) % L) for dy in range(L) for dx in range(L)]
+    return np.stack(rows).astype(np.int32)
+
+
+def symm_params(n_sites: int, alpha: int, seed: int, sigma: float = 0.01,
+                visible_bias: bool = True, hidden_bias: bool = True) -> np.ndarray:
+    """Initial parameters of a symmetric RBM, packed [a (1) | b (alpha) | W
+    (alpha x n_sites)], drawn i.i.d. normal(0, sigma)."""
+    P = (1 if visible_bias else 0) + (alpha if hidden_bias else 0) + alpha * n_sites
+    return np.random.default_rng(seed).normal(0.0, sigma, size=P).astype(np.float64)
 
 
 def n_params(n_sites: int, n_hidden: int, visible_bias: bool = True,
