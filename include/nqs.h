@@ -187,6 +187,26 @@ int nqs_set_heisenberg(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bo
 int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,
                 nqs_precision prec);
 
+/* Symmetric RBM (paper: table of models, RBMSymm; symmetric NQS section,
+ * symmetric-RBM equation): alpha features over a group G of site permutations,
+ *   ln psi(s) = a sum_k s_k + sum_{i < alpha, g} ln cosh(b_i + sum_k W_i[k] s[perm_g[k]]).
+ * perms: host int32 [n_perms][n_sites], copied; row g is perm_g, row 0 must be
+ * the identity and the rows must form a group (closed under composition).
+ * Parameters (nqs_set_params / nqs_get_params, nqs_num_params of them), packed
+ * [a (1, if visible_bias) | b (alpha, if hidden_bias) | W (alpha x n_sites,
+ * row-major)]; gradients, SR directions and Jacobian columns use the same order.
+ * The model runs as the equal plain RBM with alpha * n_perms hidden units
+ * (sampler, local energies and ln psi as for nqs_set_rbm, in the chosen
+ * precision: NQS_FP64, NQS_FP32 or NQS_BF16); its Jacobian (nqs_jacobian, FP64
+ * [n][P] whatever the precision), force and dense QGT are over the symmetric
+ * parameters (sums over G of the plain ones).  Sets the dense QGT
+ * (NQS_QGT_JACOBIAN_DENSE; the SR solve takes at most 65535 samples).
+ * nqs_log_psi_vjp, nqs_batch_step and nqs_step_begin return NQS_EINVAL for it.
+ * Errors: NQS_EINVAL (not a group, alpha * n_perms > 2048, NQS_C128),
+ * NQS_ESTATE (no Hamiltonian yet). */
+int nqs_set_rbm_symm(nqs_ctx* ctx, int n_perms, const int32_t* perms, int alpha,
+                     int visible_bias, int hidden_bias, nqs_precision prec);
+
 /* Number P of packed parameters. 0 before nqs_set_rbm. */
 size_t nqs_num_params(const nqs_ctx* ctx);
 

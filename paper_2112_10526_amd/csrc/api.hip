@@ -6,6 +6,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <set>
 #include <vector>
 
 #include "../../include/nqs.h"
@@ -44,6 +45,8 @@ struct Buffers {
     // batch, local energies, Jacobian column means, the TDVP's first slope
     double2 *hp, *hp0, *hT, *hK, *htch, *htsm, *htx, *heloc, *hmean;
     double* hk1;
+    double* psym;     // symmetric model: its parameters
+    int32_t* perms;   // symmetric model: the group, [G][N]
     double* hgp;  // complex: Gram slice partials
 };
 
@@ -68,7 +71,12 @@ struct nqs_ctx {
     bool cplx = false;  // complex parameters (NQS_C128)
     long Plc = 0;       // complex: row stride of the stacked Jacobian U and of Re G, Im G
     int hS = 1;         // complex: row slices of the Gram
-    int Pd = 0;         // size of the dense SR system: P, or 2 P (real embedding)
+    int Pd = 0;         // size of the dense SR system: P, 2 P (real embedding) or P_sym
+    // symmetric model (nqs_set_rbm_symm): M = alpha |G| hidden units of the plain
+    // RBM it expands to; P stays that RBM's count, Psym the model's own
+    bool symm = false;
+    int alpha = 0, G = 0, Psym = 0;
+    std::vector<int32_t> perms;
     Dims d{};
     size_t P = 0;
     // sampler
@@ -229,9 +237,18 @@ size_t layout(nqs_ctx* c, char* base) {
         const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
         b.part = take(es * ks * PV);
     }
+    if (c->symm) {
+        b.psym = (double*)take(8 * (size_t)c->Psym);
+        b.perms = (int32_t*)take(4 * c->perms.size());
+    } else {
+        b.psym = nullptr;
+        b.perms = nullptr;
+    }
     if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
-        b.O = take(es * (size_t)c->Ns * c->Pld);
-        b.G = take(es * (size_t)c->P * c->Pld);
+        // (a symmetric model's Jacobian and Gram are FP64, P_sym columns)
+        const size_t des = c->symm ? 8 : es;
+        b.O = take(des * (size_t)c->Ns * c->Pld);
+        b.G = take(des * (size_t)c->Pd * c->Pld);
         b.colsum = (double*)take(8 * (size_t)c->Pld);
         b.fp = (double*)take(8 * (size_t)c->Pld);
         b.xp = (double*)take(8 * (size_t)c->Pld);
@@ -317,7 +334,8 @@ void derive(nqs_ctx* c) {
     d.hb = c->hb;
     c->P = (size_t)(c->vb ? c->N : 0) + (c->hb ? c->M : 0) + (size_t)c->M * c->N;
     c->cplx = c->prec == NQS_C128;
-    c->Pd = (int)(c->cplx ? 2 * c->P : c->P);
+    if (c->symm) c->Psym = symm_num_params(c->N, c->alpha, c->vb, c->hb);
+    c->Pd = (int)(c->cplx ? 2 * c->P : c->symm ? (size_t)c->Psym : c->P);
     if (c->has_sampler) {
         c->Ns = (long)c->C * c->S;
         c->Bx = c->Ns > 1024 ? c->Ns : 1024;
@@ -631,8 +649,8 @@ void issue_cg_iters(nqs_ctx* c, int kind, double shift, int iters, int32_t* host
                     launch_h_matvec(c->stream, (const double*)c->b.G, (int)c->P, c->Plc, c->b.pp,
                                     c->b.App, c->b.dpart, c->b.sc);
                 else
-                    launch_dense_matvec(c->stream, c->prec, c->b.G, c->Pd, c->Pld, c->b.pp,
-                                        c->b.App, c->b.dpart, c->b.sc);
+                    launch_dense_matvec(c->stream, c->symm ? 0 : c->prec, c->b.G, c->Pd, c->Pld,
+                                        c->b.pp, c->b.App, c->b.dpart, c->b.sc);
             }
             {
                 PROF(NQS_PROF_CGVEC);
@@ -816,7 +834,9 @@ int default_maxiter(const nqs_ctx* c, int maxiter) {
 }
 
 // ---- the complex (holomorphic) model ----------------------------------------
-size_t param_doubles(const nqs_ctx* c) { return c->cplx ? 2 * c->P : c->P; }
+size_t param_doubles(const nqs_ctx* c) {
+    return c->cplx ? 2 * c->P : c->symm ? (size_t)c->Psym : c->P;
+}
 
 int h_check(nqs_ctx* c) {
     if (c->ham_kind != 0) return fail(c, NQS_EINVAL, "complex models take the TFIM");
@@ -926,6 +946,41 @@ void h_params_changed(nqs_ctx* c) {
     c->chains_dirty = true;
     c->have_grad = false;
     c->have_samples = false;
+}
+
+// ---- the symmetric model ------------------------------------------------------
+// new symmetric parameters: the plain RBM they expand to, its tables; chain
+// activations and the held batch belong to the old ones
+void s_params_changed(nqs_ctx* c) {
+    launch_symm_expand(c->stream, c->N, c->G, c->alpha, c->vb, c->hb, c->b.perms, c->b.psym,
+                       c->b.tmpv);
+    launch_unpack(c->stream, c->d, c->b.tmpv, c->b.Pm, (int)c->P);
+    launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
+    c->chains_dirty = true;
+    c->have_grad = false;
+    c->have_samples = false;
+}
+
+// the tied Jacobian of the held batch (centred, scaled), its Gram matrix and the
+// CG solve of (S + eps I) x = f (x in xp; f in fp from the tied force)
+int s_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
+    if (c->Ns > 65535)
+        return fail(c, NQS_EINVAL, "the symmetric model's dense QGT takes at most 65535 samples");
+    const int mi = default_maxiter(c, maxiter);
+    {
+        PROF(NQS_PROF_JACOBIAN);
+        launch_symm_jacobian(c->stream, c->prec, c->N, c->G, c->alpha, c->vb, c->hb, c->d.Mw,
+                             c->b.perms, c->b.samples, c->b.tsm, c->Ns, c->Pld, (double*)c->b.O);
+        launch_center_cols(c->stream, 0, c->b.O, c->Ns, c->Pld, c->Psym, c->b.colsum,
+                           (double*)c->b.G, 8 * (size_t)c->Pd * c->Pld, false);
+    }
+    {
+        PROF(NQS_PROF_GRAM);
+        launch_gram(c->stream, 0, c->b.O, c->Ns, c->Pld, c->Psym, c->b.G, c->b.tiles, c->ntiles);
+    }
+    launch_cg_init(c->stream, c->Psym, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
+                   mi, diag_shift);
+    return run_cg(c, NQS_QGT_JACOBIAN_DENSE, diag_shift, mi);
 }
 
 __global__ void k_f32_to_f64(const float* a, double* b, long n) {
@@ -1062,6 +1117,8 @@ int nqs_set_rbm(nqs_ctx* c, int n_hidden, int visible_bias, int hidden_bias, nqs
     c->vb = visible_bias ? 1 : 0;
     c->hb = hidden_bias ? 1 : 0;
     c->prec = (int)prec;
+    c->symm = false;
+    c->perms.clear();
     c->has_model = true;
     c->params_set = false;
     derive(c);
@@ -1069,7 +1126,55 @@ int nqs_set_rbm(nqs_ctx* c, int n_hidden, int visible_bias, int hidden_bias, nqs
     return NQS_OK;
 }
 
-size_t nqs_num_params(const nqs_ctx* c) { return (c && c->has_model) ? c->P : 0; }
+int nqs_set_rbm_symm(nqs_ctx* c, int n_perms, const int32_t* perms, int alpha, int visible_bias,
+                     int hidden_bias, nqs_precision prec) {
+    if (!c) return NQS_EINVAL;
+    if (c->ham_kind < 0) return fail(c, NQS_ESTATE, "set a Hamiltonian first");
+    if (prec < NQS_FP64 || prec > NQS_BF16)
+        return fail(c, NQS_EINVAL, "symmetric models take FP64, FP32 or BF16");
+    if (n_perms < 1 || !perms || alpha < 1) return fail(c, NQS_EINVAL, "bad group or alpha");
+    if ((long)alpha * n_perms > 2048)
+        return fail(c, NQS_EINVAL, "alpha |G| (the hidden units) must be at most 2048");
+    if (c->N > 4096) return fail(c, NQS_EINVAL, "at most 4096 sites");
+    const int N = c->N;
+    std::vector<int32_t> P(perms, perms + (size_t)n_perms * N);
+    std::set<std::vector<int32_t>> rows;
+    for (int g = 0; g < n_perms; ++g) {
+        std::vector<int32_t> r(P.begin() + (size_t)g * N, P.begin() + (size_t)(g + 1) * N);
+        std::vector<char> seen(N, 0);
+        for (int k = 0; k < N; ++k) {
+            if (r[k] < 0 || r[k] >= N || seen[r[k]])
+                return fail(c, NQS_EINVAL, "row " + std::to_string(g) + " is not a permutation");
+            seen[r[k]] = 1;
+            if (g == 0 && r[k] != k) return fail(c, NQS_EINVAL, "row 0 must be the identity");
+        }
+        if (!rows.insert(r).second) return fail(c, NQS_EINVAL, "repeated permutation");
+    }
+    std::vector<int32_t> comp(N);
+    for (int g = 0; g < n_perms; ++g)
+        for (int h = 0; h < n_perms; ++h) {
+            for (int k = 0; k < N; ++k) comp[k] = P[(size_t)g * N + P[(size_t)h * N + k]];
+            if (!rows.count(comp)) return fail(c, NQS_EINVAL, "the permutations do not form a group");
+        }
+    c->perms.swap(P);
+    c->G = n_perms;
+    c->alpha = alpha;
+    c->symm = true;
+    c->M = alpha * n_perms;
+    c->vb = visible_bias ? 1 : 0;
+    c->hb = hidden_bias ? 1 : 0;
+    c->prec = (int)prec;
+    c->qgt = NQS_QGT_JACOBIAN_DENSE;
+    c->has_model = true;
+    c->params_set = false;
+    derive(c);
+    invalidate_binding(c);
+    return NQS_OK;
+}
+
+size_t nqs_num_params(const nqs_ctx* c) {
+    return (c && c->has_model) ? (c->symm ? (size_t)c->Psym : c->P) : 0;
+}
 
 int nqs_set_sampler(nqs_ctx* c, nqs_rule rule, int n_chains, int samples_per_chain,
                     int sweep_size, uint64_t seed, int total_sz_zero) {
@@ -1104,6 +1209,8 @@ int nqs_set_qgt(nqs_ctx* c, nqs_qgt kind) {
         return fail(c, NQS_EINVAL, "bad QGT kind");
     if (c->cplx && kind != NQS_QGT_JACOBIAN_DENSE)
         return fail(c, NQS_EINVAL, "complex models use the dense holomorphic QGT");
+    if (c->symm && kind != NQS_QGT_JACOBIAN_DENSE)
+        return fail(c, NQS_EINVAL, "symmetric models use the dense QGT");
     if (c->qgt != (int)kind) {
         c->qgt = (int)kind;
         invalidate_binding(c);
@@ -1143,6 +1250,9 @@ int nqs_bind_workspace(nqs_ctx* c, void* dev_ptr, size_t bytes) {
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(c->b.sub, c->sub.data(), c->sub.size(), hipMemcpyHostToDevice,
                              c->stream));
+    if (c->symm)
+        HIPCHK(c, hipMemcpyAsync(c->b.perms, c->perms.data(), 4 * c->perms.size(),
+                                 hipMemcpyHostToDevice, c->stream));
     if (c->qgt == NQS_QGT_JACOBIAN_DENSE) {
         std::vector<int> t(2 * (size_t)c->ntiles);
         fill_gram_tiles(c->cplx ? (int)c->P : c->Pd, t.data());
@@ -1189,7 +1299,13 @@ int nqs_set_params(nqs_ctx* c, const double* p, int on_device) {
         c->params_set = true;
         return last_launch(c);
     }
-    HIPCHK(c, hipMemcpyAsync(c->b.tmpv, h.data(), 8 * c->P, hipMemcpyHostToDevice, c->stream));
+    if (c->symm) {  // the symmetric parameters, expanded to the plain RBM's
+        HIPCHK(c, hipMemcpyAsync(c->b.psym, h.data(), 8 * np, hipMemcpyHostToDevice, c->stream));
+        launch_symm_expand(c->stream, c->N, c->G, c->alpha, c->vb, c->hb, c->b.perms, c->b.psym,
+                           c->b.tmpv);
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->b.tmpv, h.data(), 8 * c->P, hipMemcpyHostToDevice, c->stream));
+    }
     launch_unpack(c->stream, c->d, c->b.tmpv, c->b.Pm, (int)c->P);
     launch_tables(c->stream, c->d, c->prec, c->b.Pm, c->b.tab);
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1208,6 +1324,13 @@ int nqs_get_params(nqs_ctx* c, double* p, int on_device) {
     if (!p) return fail(c, NQS_EINVAL, "null output");
     if (c->cplx) {
         HIPCHK(c, hipMemcpyAsync(p, c->b.hp, 16 * c->P,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return last_launch(c);
+    }
+    if (c->symm) {
+        HIPCHK(c, hipMemcpyAsync(p, c->b.psym, 8 * (size_t)c->Psym,
                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1425,7 +1548,8 @@ int nqs_log_psi_vjp(nqs_ctx* c, const int8_t* s, int64_t n, const void* g, void*
     int st = need_bound(c);
     if (st) return st;
     if (n < 0 || (n > 0 && (!s || !g)) || !grad_out) return fail(c, NQS_EINVAL, "bad batch");
-    if (c->cplx) return fail(c, NQS_EINVAL, "complex models are not supported here");
+    if (c->cplx || c->symm)
+        return fail(c, NQS_EINVAL, "complex and symmetric models are not supported here");
     const int PV = c->d.Ma * c->d.Na;
     launch_zero(c->stream, c->b.gacc, 8 * (size_t)PV);
     for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
@@ -1470,6 +1594,22 @@ int nqs_jacobian(nqs_ctx* c, const int8_t* s, int64_t n, void* O_out, int center
         }
         return last_launch(c);
     }
+    if (c->symm) {  // FP64 O [n][P_sym]
+        for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
+            const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
+            const int8_t* sk = s + (size_t)k0 * c->N;
+            launch_theta(c->stream, c->d, c->prec, c->b.tab, sk, (int)m, c->b.tx, nullptr, 0);
+            launch_symm_jacobian(c->stream, c->prec, c->N, c->G, c->alpha, c->vb, c->hb, c->d.Mw,
+                                 c->b.perms, sk, c->b.tx, m, c->Psym,
+                                 (double*)O_out + (size_t)k0 * c->Psym);
+        }
+        if (center) {
+            if (n > 65535) return fail(c, NQS_EINVAL, "centring supports at most 65535 rows");
+            launch_center_cols(c->stream, 0, O_out, n, c->Psym, c->Psym, c->b.tmpv, nullptr, 0,
+                               false);
+        }
+        return last_launch(c);
+    }
     const size_t es = esize(c->prec);
     for (int64_t k0 = 0; k0 < n; k0 += c->Bx) {
         const long m = (long)((n - k0) < c->Bx ? (n - k0) : c->Bx);
@@ -1497,7 +1637,15 @@ int nqs_expect_and_grad(nqs_ctx* c, nqs_stats* E, double* grad) {
         if (grad) launch_h_join(c->stream, (int)c->P, c->b.fp, (double2*)grad);
     } else {
         issue_energy_grad(c);
-        if (grad) launch_pack(c->stream, c->d, c->b.grad, grad, (int)c->P);
+        if (c->symm) {  // the plain force, summed over the group
+            launch_symm_tie(c->stream, c->N, c->G, c->alpha, c->vb, c->hb, c->d.Na, c->b.perms,
+                            c->b.grad, c->b.fp);
+            if (grad)
+                HIPCHK(c, hipMemcpyAsync(grad, c->b.fp, 8 * (size_t)c->Psym,
+                                         hipMemcpyDeviceToDevice, c->stream));
+        } else if (grad) {
+            launch_pack(c->stream, c->d, c->b.grad, grad, (int)c->P);
+        }
     }
     st = last_launch(c);
     if (st) return st;
@@ -1512,6 +1660,8 @@ static int sr_check(nqs_ctx* c, nqs_qgt kind, double diag_shift, double lr, doub
     if (!c->have_grad) return fail(c, NQS_ESTATE, "no gradient: call nqs_expect_and_grad first");
     if (kind == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
         return fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace (nqs_set_qgt)");
+    if (c->symm && kind != NQS_QGT_JACOBIAN_DENSE)
+        return fail(c, NQS_EINVAL, "symmetric models take the dense QGT");
     if (!(diag_shift >= 0) || !std::isfinite(lr) || !(tol >= 0))
         return fail(c, NQS_EINVAL, "bad solver settings");
     return set_device(c);
@@ -1531,6 +1681,19 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
             launch_h_axpy(c->stream, (int)c->P, c->b.hp, -lr, 0.0, c->b.xp, 0.0, 0.0, nullptr,
                           c->b.hp);
             h_params_changed(c);
+        }
+        return last_launch(c);
+    }
+    if (c->symm) {  // (S + eps I) delta = f over the symmetric parameters
+        st = s_issue_solve(c, diag_shift, tol, maxiter);
+        if (st) return st;
+        if (delta_out)
+            HIPCHK(c, hipMemcpyAsync(delta_out, c->b.xp, 8 * (size_t)c->Psym,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        {
+            PROF(NQS_PROF_UPDATE);
+            launch_axpy_update(c->stream, c->Psym, c->b.psym, c->b.xp, lr, c->b.sc);
+            s_params_changed(c);
         }
         return last_launch(c);
     }
@@ -1652,7 +1815,8 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
             st[k] = fail(c, NQS_ESTATE, "a step begun by nqs_step_begin is in flight");
         if (!st[k] && cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE && c->qgt != NQS_QGT_JACOBIAN_DENSE)
             st[k] = fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace");
-        if (!st[k] && c->cplx) st[k] = fail(c, NQS_EINVAL, "complex models step one at a time");
+        if (!st[k] && (c->cplx || c->symm))
+            st[k] = fail(c, NQS_EINVAL, "complex and symmetric models step one at a time");
         if (!st[k]) st[k] = set_device(c);
     }
     // sampling, energies and gradients for every context, then CG init
@@ -1785,7 +1949,8 @@ int nqs_step_begin(nqs_ctx* c, const nqs_step_cfg* cfg) {
     if (!c) return NQS_EINVAL;
     if (!cfg) return fail(c, NQS_EINVAL, "null settings");
     if (c->step_phase) return fail(c, NQS_ESTATE, "a step is already in flight");
-    if (c->cplx) return fail(c, NQS_EINVAL, "complex models step one at a time");
+    if (c->cplx || c->symm)
+        return fail(c, NQS_EINVAL, "complex and symmetric models step one at a time");
     int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
     if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
     if (!st) st = sr_check(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol);

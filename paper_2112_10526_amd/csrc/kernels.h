@@ -231,4 +231,19 @@ void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double c
 void launch_h_split(hipStream_t st, int P, const double2* z, double* emb);
 void launch_h_join(hipStream_t st, int P, const double* emb, double2* z);
 
+// symm.hip: symmetric RBM (alpha features over a site-permutation group G,
+// expanded to the plain RBM with alpha |G| hidden units, hidden unit i |G| + g)
+int symm_num_params(int N, int alpha, int vb, int hb);
+// psym -> the plain RBM's packed parameters (out: N + M + M N doubles, biases as flagged)
+void launch_symm_expand(hipStream_t st, int N, int G, int alpha, int vb, int hb,
+                        const int32_t* perms, const double* psym, double* out);
+// the plain force in the augmented [Ma][Na] layout -> the symmetric one (sums over G)
+void launch_symm_tie(hipStream_t st, int N, int G, int alpha, int vb, int hb, int Na,
+                     const int32_t* perms, const double* grad, double* out);
+// O [n][ld] FP64 = d ln psi / d psym for n configurations s with activations t
+// ([n][Mw], FP64 for prec 0, FP32 otherwise); columns past P_sym zero
+void launch_symm_jacobian(hipStream_t st, int prec, int N, int G, int alpha, int vb, int hb,
+                          int Mw, const int32_t* perms, const int8_t* s, const void* t, long n,
+                          long ld, double* O);
+
 }  // namespace nqs

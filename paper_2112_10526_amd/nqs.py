@@ -53,7 +53,12 @@ class VMCState:
                  hidden_bias: bool = True, precision: str = "fp64", rule: str = "local",
                  n_chains: int, samples_per_chain: int, sweep_size: int, seed: int,
                  total_sz_zero: bool = False, qgt: str = "onthefly", device: int = 0,
-                 stream: Optional[torch.cuda.Stream] = None, params=None, allocate: bool = True):
+                 stream: Optional[torch.cuda.Stream] = None, params=None, allocate: bool = True,
+                 symmetries=None, alpha: Optional[int] = None):
+        """symmetries (int [G][n_sites] site permutations, row 0 the identity) with
+        alpha: the symmetric RBM (alpha features over the group; n_hidden is then
+        alpha * G, the plain RBM it runs as); its Jacobian is FP64 over the
+        symmetric parameters and its QGT the dense one."""
         if not torch.cuda.is_available():
             raise RuntimeError("libnqs needs a HIP device; none is visible")
         self.lib = _lib.load()
@@ -63,10 +68,18 @@ class VMCState:
         self.n_sites, self.n_hidden = n_sites, n_hidden
         self.n_chains, self.samples_per_chain, self.sweep_size = n_chains, samples_per_chain, sweep_size
         self.complex = precision == "c128"
+        self.symmetric = symmetries is not None
         self.rdtype = (torch.complex128 if self.complex else
                        torch.float64 if precision == "fp64" else torch.float32)
-        if self.complex:
+        self.jdtype = torch.float64 if self.symmetric else self.rdtype  # Jacobian entries
+        if self.complex or self.symmetric:
             qgt = "jacobian_dense"
+        if self.symmetric:
+            self._perms = np.ascontiguousarray(symmetries, dtype=np.int32)
+            if alpha is None:
+                raise ValueError("a symmetric RBM needs alpha")
+            n_hidden = alpha * self._perms.shape[0]
+        self.alpha = alpha
         h_ctx = ctypes.c_void_p()
         st = self.lib.nqs_create(ctypes.byref(h_ctx), device, ctypes.c_void_p(self.stream.cuda_stream))
         if st:
@@ -84,8 +97,15 @@ class VMCState:
                 None if sub is None else sub.ctypes.data_as(ctypes.c_void_p)))
         else:
             raise ValueError(f"unknown model {model!r}")
-        self._check(self.lib.nqs_set_rbm(self.ctx, n_hidden, int(visible_bias), int(hidden_bias),
-                                         _lib.PRECISIONS[precision]))
+        if self.symmetric:
+            if self._perms.ndim != 2 or self._perms.shape[1] != n_sites:
+                raise ValueError("symmetries must be [G][n_sites]")
+            self._check(self.lib.nqs_set_rbm_symm(
+                self.ctx, self._perms.shape[0], self._perms.ctypes.data_as(ctypes.c_void_p), alpha,
+                int(visible_bias), int(hidden_bias), _lib.PRECISIONS[precision]))
+        else:
+            self._check(self.lib.nqs_set_rbm(self.ctx, n_hidden, int(visible_bias),
+                                             int(hidden_bias), _lib.PRECISIONS[precision]))
         self._check(self.lib.nqs_set_sampler(self.ctx, _lib.RULES[rule], n_chains,
                                              samples_per_chain, sweep_size, seed,
                                              int(total_sz_zero)))
@@ -267,7 +287,7 @@ class VMCState:
 
     def jacobian(self, s: torch.Tensor, center: bool = False) -> torch.Tensor:
         s = self._dev(s.reshape(-1, self.n_sites), torch.int8)
-        out = torch.empty((s.shape[0], self.n_params), dtype=self.rdtype, device=self.device)
+        out = torch.empty((s.shape[0], self.n_params), dtype=self.jdtype, device=self.device)
         self._check(self.lib.nqs_jacobian(self.ctx, _ptr(s), s.shape[0], _ptr(out), int(center)))
         return out
 
@@ -282,7 +302,7 @@ class VMCState:
                   tol: float = 1e-6, maxiter: int = 0, want_delta: bool = True,
                   allow_notconv: bool = False):
         info = NqsSrInfo()
-        if self.complex:
+        if self.complex or self.symmetric:
             qgt = "jacobian_dense"
         dt = torch.complex128 if self.complex else torch.float64
         d = torch.empty(self.n_params, dtype=dt, device=self.device) if want_delta else None
@@ -294,7 +314,7 @@ class VMCState:
 
     def vmc_step(self, qgt: str = "onthefly", diag_shift: float = 0.01, lr: float = 0.01,
                  tol: float = 1e-6, maxiter: int = 0) -> StepReport:
-        if self.complex:
+        if self.complex or self.symmetric:
             qgt = "jacobian_dense"
         cfg = NqsStepCfg(_lib.QGTS[qgt], diag_shift, lr, tol, maxiter)
         rep = NqsStepReport()
