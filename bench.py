@@ -565,6 +565,51 @@ def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e
                 trace=trace)
 
 
+def symm_measure(torch, steps=20, warmup=3):
+    """Full SR steps of the translation-symmetric RBM on the 10x10 TFIM workload
+    (alpha = 2 features over the 100 translations: the same 200 hidden units as
+    the plain alpha = 2 RBM, but 203 parameters instead of 20,300), dense QGT +
+    CG over the symmetric parameters, FP64 path and BF16 form."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.WORKLOADS["tfim2d_l10"]
+    perms = synth.square_translations(w.L)
+    runs = {}
+    for prec in ("fp64", "bf16"):
+        st = VMCState(model="tfim", n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
+                      n_hidden=0, precision=prec, rule="local", n_chains=w.n_chains,
+                      samples_per_chain=w.samples_per_chain, sweep_size=w.sweep_size,
+                      seed=w.chain_seed, params=synth.symm_params(w.n_sites, 2, w.param_seed),
+                      symmetries=perms, alpha=2)
+        st.thermalize(w.thermalize_segments)
+        st.profile_enable(None)
+        for _ in range(warmup):
+            st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+        prof = st.profile_read()
+        st.profile_enable([])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, energies = [], []
+        for _ in range(steps):
+            rep = st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+            iters.append(rep.sr.iterations)
+            energies.append(rep.energy["mean"])
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        runs[prec] = dict(ms_per_step=el * 1e3, local_energies_per_s=w.n_samples / el,
+                          cg_iters_mean=float(np.mean(iters)), energy_first=energies[0],
+                          energy_last=energies[-1],
+                          warmup_profile_ms={k: round(v["ms"] / warmup, 4)
+                                             for k, v in prof.items() if v["launches"]})
+        st.close()
+        print(f"[bench] symmetric RBM {prec}: {el * 1e3:.2f} ms/step", file=sys.stderr,
+              flush=True)
+    return dict(metric="SR steps of the translation-symmetric RBM", unit="ms/step",
+                workload="tfim2d_l10 with RBMSymm: 2D TFIM 10x10 periodic J=1 h=3.044, alpha=2 "
+                         "over 100 translations (203 parameters), 4096 chains x 4 samples, 100 "
+                         "proposals per sample, dense QGT + CG tol 1e-6 shift 0.01 lr 0.01",
+                steps=steps, warmup=warmup, runs=runs, data="synthetic")
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -632,6 +677,8 @@ def main():
                     help="time full SR steps on the paper's timed workload (complex RBM)")
     ap.add_argument("--tdvp-quench", action="store_true",
                     help="time TDVP Heun steps of the L=20 TFIM quench (complex RBM)")
+    ap.add_argument("--symm", action="store_true",
+                    help="time SR steps of the translation-symmetric RBM (10x10 TFIM)")
     ap.add_argument("--serve", action="store_true",
                     help="measure the continuous-batching server on a Poisson stream of runs")
     ap.add_argument("--serve-runs", type=int, default=256)
@@ -659,6 +706,9 @@ def main():
         return
     if args.paper_workload:
         print(json.dumps(paper_workload_measure(torch)), flush=True)
+        return
+    if args.symm:
+        print(json.dumps(symm_measure(torch)), flush=True)
         return
     if args.tdvp_quench:
         print(json.dumps(tdvp_quench_measure(torch)), flush=True)

@@ -46,6 +46,7 @@ struct Buffers {
     double2 *hp, *hp0, *hT, *hK, *htch, *htsm, *htx, *heloc, *hmean;
     double* hk1;
     double* psym;     // symmetric model: its parameters
+    double* gpart;    // FP64 dense Gram: slice partials (when sliced)
     int32_t* perms;   // symmetric model: the group, [G][N]
     double* hgp;  // complex: Gram slice partials
 };
@@ -71,6 +72,7 @@ struct nqs_ctx {
     bool cplx = false;  // complex parameters (NQS_C128)
     long Plc = 0;       // complex: row stride of the stacked Jacobian U and of Re G, Im G
     int hS = 1;         // complex: row slices of the Gram
+    int gS = 1;         // FP64 dense Gram (real, symmetric): row slices
     int Pd = 0;         // size of the dense SR system: P, 2 P (real embedding) or P_sym
     // symmetric model (nqs_set_rbm_symm): M = alpha |G| hidden units of the plain
     // RBM it expands to; P stays that RBM's count, Psym the model's own
@@ -250,6 +252,7 @@ size_t layout(nqs_ctx* c, char* base) {
         b.O = take(des * (size_t)c->Ns * c->Pld);
         b.G = take(des * (size_t)c->Pd * c->Pld);
         b.colsum = (double*)take(8 * (size_t)c->Pld);
+        b.gpart = c->gS > 1 ? (double*)take(gram_part_bytes(c->ntiles, c->gS)) : nullptr;
         b.fp = (double*)take(8 * (size_t)c->Pld);
         b.xp = (double*)take(8 * (size_t)c->Pld);
         b.rp = (double*)take(8 * (size_t)c->Pld);
@@ -348,6 +351,7 @@ void derive(nqs_ctx* c) {
             c->ntiles = gram_tiles((int)c->P);
             c->hS = h_gram_slices(c->ntiles, c->Ns);
         }
+        c->gS = (!c->cplx && (c->symm || c->prec == 0)) ? gram_slices(c->ntiles, c->Ns) : 1;
         long nd = (long)d.Ma * d.Na / 256 + 2;
         const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->Pd / 4 + 2;
         if (nd2 > nd) nd = nd2;
@@ -593,7 +597,12 @@ void issue_dense_setup(nqs_ctx* c, double tol, int maxiter, double shift) {
     }
     {
         PROF(NQS_PROF_GRAM);
-        launch_gram(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.G, c->b.tiles, c->ntiles);
+        if (c->prec == 0)
+            launch_gram_sliced(c->stream, (const double*)c->b.O, c->Ns, c->Pld, P,
+                               (double*)c->b.G, c->b.tiles, c->ntiles, c->gS, c->b.gpart);
+        else
+            launch_gram(c->stream, c->prec, c->b.O, c->Ns, c->Pld, P, c->b.G, c->b.tiles,
+                        c->ntiles);
     }
     launch_pack(c->stream, c->d, c->b.grad, c->b.fp, P);
     launch_cg_init(c->stream, P, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
@@ -976,7 +985,8 @@ int s_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
     }
     {
         PROF(NQS_PROF_GRAM);
-        launch_gram(c->stream, 0, c->b.O, c->Ns, c->Pld, c->Psym, c->b.G, c->b.tiles, c->ntiles);
+        launch_gram_sliced(c->stream, (const double*)c->b.O, c->Ns, c->Pld, c->Psym,
+                           (double*)c->b.G, c->b.tiles, c->ntiles, c->gS, c->b.gpart);
     }
     launch_cg_init(c->stream, c->Psym, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
                    mi, diag_shift);

@@ -286,6 +286,85 @@ __global__ __launch_bounds__(256) void k_gram(const R* __restrict__ A, long n, l
             }
 }
 
+// FP64 Gram over row slices, for matrices with few tiles (a small P leaves most
+// compute units idle when each tile walks all n rows): block = (tile, slice of
+// rows), the tile's partial written in tile order [128][128]; k_gram_fin sums
+// the slices in order (deterministic) and writes G with the lower triangle
+// mirrored (within a diagonal tile only entries on or above the diagonal are
+// taken, so G is exactly symmetric).
+__global__ __launch_bounds__(256) void k_gram_slices(const double* __restrict__ A, long n, long ld,
+                                                     int ntiles, long rows_per_slice,
+                                                     const int* __restrict__ tiles,
+                                                     double* __restrict__ part) {
+    const int t = (int)(blockIdx.x % (unsigned)ntiles), ks = (int)(blockIdx.x / (unsigned)ntiles);
+    const int tp = tiles[2 * t], tq = tiles[2 * t + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long p0 = (long)tp * 128 + (wave >> 1) * 64;
+    const long q0 = (long)tq * 128 + (wave & 1) * 64;
+    const long r0 = (long)ks * rows_per_slice;
+    const long r1 = r0 + rows_per_slice < n ? r0 + rows_per_slice : n;
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    for (long k0 = r0; k0 < r1; k0 += 4) {
+        const long k = k0 + lk;
+        double fa[4], fb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            fa[a] = k < r1 ? A[k * ld + p0 + a * 16 + lr] : 0.0;
+            fb[a] = k < r1 ? A[k * ld + q0 + a * 16 + lr] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    double* pt = part + (size_t)blockIdx.x * 128 * 128;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pr = (wave >> 1) * 64 + a * 16 + acc_row<double>(lk, i);
+                const int qc = (wave & 1) * 64 + b * 16 + lr;
+                pt[pr * 128 + qc] = acc[a][b][i];
+            }
+}
+
+__global__ __launch_bounds__(256) void k_gram_fin(const double* __restrict__ part, int ntiles,
+                                                  int slices, const int* __restrict__ tiles, int P,
+                                                  long ld, double* __restrict__ G) {
+    __shared__ double sg[32][33];
+    const int t = blockIdx.x >> 4, sub = blockIdx.x & 15;
+    const int tp = tiles[2 * t], tq = tiles[2 * t + 1];
+    const int i0 = (sub >> 2) * 32, j0 = (sub & 3) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const long P0 = (long)tp * 128, Q0 = (long)tq * 128;
+    const bool diag = tp == tq;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int ii = ty + 8 * m, jj = tx;
+        const size_t e = (size_t)(i0 + ii) * 128 + (j0 + jj);
+        double a = 0.0;
+        for (int ks = 0; ks < slices; ++ks) a += part[((size_t)ks * ntiles + t) * 128 * 128 + e];
+        sg[ii][jj] = a;
+        const long p = P0 + i0 + ii, q = Q0 + j0 + jj;
+        if ((!diag || i0 + ii <= j0 + jj) && p < P && q < P) G[p * ld + q] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int jj = ty + 8 * m, ii = tx;  // element (ii, jj) written at (q, p)
+        const long p = P0 + i0 + ii, q = Q0 + j0 + jj;
+        if ((!diag || i0 + ii < j0 + jj) && p < P && q < P) G[q * ld + p] = sg[ii][jj];
+    }
+}
+
 // BF16 form: the same Gram on the BF16 matrix cores.  The centring kernel has
 // stored every entry x as the BF16 pair (hi << 16) | lo with x ~= hi + lo;
 // three products (hi hi + hi lo + lo hi) are accumulated in FP32: about 2^-16
@@ -566,6 +645,27 @@ void fill_gram_tiles(int P, int* host_tiles) {
         pos[src] += 2;
         ++e;
     }
+}
+// Row slices for the FP64 Gram: enough (tile, slice) blocks for two per compute
+// unit, each slice at least 128 rows; 1 = the unsliced kernel.
+int gram_slices(int ntiles, long n) {
+    int S = 1;
+    while (S < 256 && (long)ntiles * S < 512 && n / (2 * S) >= 128) S *= 2;
+    return S;
+}
+size_t gram_part_bytes(int ntiles, int slices) {
+    return slices > 1 ? (size_t)ntiles * slices * 128 * 128 * 8 : 0;
+}
+void launch_gram_sliced(hipStream_t st, const double* A, long n, long ld, int P, double* G,
+                        const int* tiles, int ntiles, int slices, double* part) {
+    if (slices <= 1 || !part) {
+        k_gram<double><<<ntiles, 256, 0, st>>>(A, n, ld, P, G, tiles);
+        return;
+    }
+    long rps = (n + slices - 1) / slices;
+    rps = (rps + 3) / 4 * 4;
+    k_gram_slices<<<(unsigned)(ntiles * slices), 256, 0, st>>>(A, n, ld, ntiles, rps, tiles, part);
+    k_gram_fin<<<(unsigned)(ntiles * 16), 256, 0, st>>>(part, ntiles, slices, tiles, P, ld, G);
 }
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
                  const int* tiles, int ntiles) {

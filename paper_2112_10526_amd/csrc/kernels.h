@@ -184,6 +184,12 @@ int gram_tiles(int P);
 void fill_gram_tiles(int P, int* host_tiles);
 void launch_gram(hipStream_t st, int prec, const void* A, long n, long ld, int P, void* G,
                  const int* tiles, int ntiles);
+// FP64 Gram over row slices (deterministic slice sum); slices from gram_slices,
+// part: gram_part_bytes(ntiles, slices) of scratch (slices == 1: the plain kernel)
+int gram_slices(int ntiles, long n);
+size_t gram_part_bytes(int ntiles, int slices);
+void launch_gram_sliced(hipStream_t st, const double* A, long n, long ld, int P, double* G,
+                        const int* tiles, int ntiles, int slices, double* part);
 int dense_matvec_blocks(int P);  // blocks (and p.Ap partials) of one dense product
 // (G + shift I) v, the shift taken from sc
 void launch_dense_matvec(hipStream_t st, int prec, const void* G, int P, long ld, const double* v,
