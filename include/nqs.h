@@ -187,6 +187,20 @@ int nqs_set_heisenberg(nqs_ctx* ctx, int n_sites, int n_bonds, const int32_t* bo
 int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,
                 nqs_precision prec);
 
+/* How the dense QGT system (S + eps I) x = f is solved (paper: solving linear
+ * systems in the QGT section; the dense-solver and CG rows of the jVMC
+ * comparison): conjugate gradients (default), or a direct solve by an in-place
+ * blocked Cholesky factorisation of the FP64 S + eps I (the Gram matrix is
+ * overwritten), reporting 0 iterations and a zero residual.  The Cholesky solve
+ * needs S + eps I positive definite (eps > 0 unless S is), else the SR call
+ * returns NQS_ENUMERIC; it takes the FP64 dense QGT (NQS_FP64 plain models,
+ * symmetric models, complex models through the real embedding of G, 2P <=
+ * 32768, which adds a [2P][2P] FP64 buffer to the workspace).  Set it before
+ * nqs_bind_workspace (a complex model's workspace changes with it).
+ * nqs_batch_step and nqs_step_begin do not take it (NQS_EINVAL). */
+typedef enum { NQS_SOLVER_CG = 0, NQS_SOLVER_CHOLESKY = 1 } nqs_dense_solver;
+int nqs_set_dense_solver(nqs_ctx* ctx, nqs_dense_solver solver);
+
 /* Symmetric RBM (paper: table of models, RBMSymm; symmetric NQS section,
  * symmetric-RBM equation): alpha features over a group G of site permutations,
  *   ln psi(s) = a sum_k s_k + sum_{i < alpha, g} ln cosh(b_i + sum_k W_i[k] s[perm_g[k]]).

@@ -47,6 +47,8 @@ struct Buffers {
     double* hk1;
     double* psym;     // symmetric model: its parameters
     double* gpart;    // FP64 dense Gram: slice partials (when sliced)
+    int32_t* cbad;    // Cholesky: pivot-not-positive flag
+    double* hE;       // complex + Cholesky: the real embedding of G
     int32_t* perms;   // symmetric model: the group, [G][N]
     double* hgp;  // complex: Gram slice partials
 };
@@ -73,6 +75,8 @@ struct nqs_ctx {
     long Plc = 0;       // complex: row stride of the stacked Jacobian U and of Re G, Im G
     int hS = 1;         // complex: row slices of the Gram
     int gS = 1;         // FP64 dense Gram (real, symmetric): row slices
+    int dsolver = NQS_SOLVER_CG;  // how dense QGT systems are solved
+    long Ple = 0;       // complex + Cholesky: row stride of the real embedding E
     int Pd = 0;         // size of the dense SR system: P, 2 P (real embedding) or P_sym
     // symmetric model (nqs_set_rbm_symm): M = alpha |G| hidden units of the plain
     // RBM it expands to; P stays that RBM's count, Psym the model's own
@@ -222,6 +226,8 @@ size_t layout(nqs_ctx* c, char* base) {
     b.dpart = (double*)take(8 * (size_t)c->ndpart);
     b.acc_count = (uint32_t*)take(4 * (size_t)c->C);
     b.sc = (CgScalars*)take(sizeof(CgScalars));
+    b.cbad = (int32_t*)take(16);
+    b.hE = nullptr;
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
@@ -312,6 +318,8 @@ size_t layout_holo(nqs_ctx* c, char* base) {
     b.pp = (double*)take(8 * Pld);
     b.App = (double*)take(8 * Pld);
     b.hk1 = (double*)take(8 * Pld);
+    b.cbad = (int32_t*)take(16);
+    b.hE = c->dsolver == NQS_SOLVER_CHOLESKY ? (double*)take(8 * 2 * P * (size_t)c->Ple) : nullptr;
     b.tiles = (int*)take(8 * (size_t)c->ntiles);
     return (off + ALIGN - 1) / ALIGN * ALIGN;
 }
@@ -352,6 +360,7 @@ void derive(nqs_ctx* c) {
             c->hS = h_gram_slices(c->ntiles, c->Ns);
         }
         c->gS = (!c->cplx && (c->symm || c->prec == 0)) ? gram_slices(c->ntiles, c->Ns) : 1;
+        c->Ple = round_up(2 * (long)c->P, 128);
         long nd = (long)d.Ma * d.Na / 256 + 2;
         const long nd2 = c->Bx / 64 + 2, nd3 = (long)c->Pd / 4 + 2;
         if (nd2 > nd) nd = nd2;
@@ -943,6 +952,13 @@ int h_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
         launch_h_gram(c->stream, (const double*)c->b.O, c->Ns, c->Plc, (int)c->P, c->b.tiles,
                       c->ntiles, c->hS, c->b.hgp, (double*)c->b.G);
     }
+    if (c->dsolver == NQS_SOLVER_CHOLESKY) {  // on the real embedding, size 2P
+        PROF(NQS_PROF_CGVEC);
+        launch_h_embed(c->stream, (const double*)c->b.G, (int)c->P, c->Plc, c->b.hE, c->Ple);
+        launch_chol_solve(c->stream, c->b.hE, c->Pd, c->Ple, diag_shift, c->b.fp, c->b.xp,
+                          c->b.cbad, c->b.sc);
+        return NQS_OK;
+    }
     launch_cg_init(c->stream, c->Pd, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
                    mi, diag_shift);
     return run_cg(c, NQS_QGT_JACOBIAN_DENSE, diag_shift, mi);
@@ -987,6 +1003,12 @@ int s_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
         PROF(NQS_PROF_GRAM);
         launch_gram_sliced(c->stream, (const double*)c->b.O, c->Ns, c->Pld, c->Psym,
                            (double*)c->b.G, c->b.tiles, c->ntiles, c->gS, c->b.gpart);
+    }
+    if (c->dsolver == NQS_SOLVER_CHOLESKY) {
+        PROF(NQS_PROF_CGVEC);
+        launch_chol_solve(c->stream, (double*)c->b.G, c->Psym, c->Pld, diag_shift, c->b.fp, c->b.xp,
+                          c->b.cbad, c->b.sc);
+        return NQS_OK;
     }
     launch_cg_init(c->stream, c->Psym, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
                    mi, diag_shift);
@@ -1224,6 +1246,23 @@ int nqs_set_qgt(nqs_ctx* c, nqs_qgt kind) {
     if (c->qgt != (int)kind) {
         c->qgt = (int)kind;
         invalidate_binding(c);
+    }
+    return NQS_OK;
+}
+
+int nqs_set_dense_solver(nqs_ctx* c, nqs_dense_solver solver) {
+    if (!c) return NQS_EINVAL;
+    if (solver != NQS_SOLVER_CG && solver != NQS_SOLVER_CHOLESKY)
+        return fail(c, NQS_EINVAL, "bad solver");
+    if (solver == NQS_SOLVER_CHOLESKY && c->has_model) {
+        if (!c->cplx && !c->symm && c->prec != 0)
+            return fail(c, NQS_EINVAL, "the Cholesky solve takes the FP64 dense QGT");
+        if (c->cplx && 2 * c->P > 32768)
+            return fail(c, NQS_EINVAL, "the Cholesky solve of a complex model takes P <= 16384");
+    }
+    if (c->dsolver != (int)solver) {
+        c->dsolver = (int)solver;
+        if (c->cplx) invalidate_binding(c);  // the embedding's buffer
     }
     return NQS_OK;
 }
@@ -1710,7 +1749,15 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
     const int mi = default_maxiter(c, maxiter);
     if (kind == NQS_QGT_JACOBIAN_DENSE) issue_dense_setup(c, tol, mi, diag_shift);
     else issue_cg_init(c, tol, mi, diag_shift);
-    st = run_cg(c, kind, diag_shift, mi);
+    if (kind == NQS_QGT_JACOBIAN_DENSE && c->dsolver == NQS_SOLVER_CHOLESKY) {
+        if (c->prec != 0) return fail(c, NQS_EINVAL, "the Cholesky solve takes the FP64 dense QGT");
+        PROF(NQS_PROF_CGVEC);
+        launch_chol_solve(c->stream, (double*)c->b.G, (int)c->P, c->Pld, diag_shift, c->b.fp,
+                          c->b.xp, c->b.cbad, c->b.sc);
+        st = NQS_OK;
+    } else {
+        st = run_cg(c, kind, diag_shift, mi);
+    }
     if (st) return st;
     issue_finish_solve(c, kind);
     if (delta_out) launch_pack(c->stream, c->d, c->b.x, delta_out, (int)c->P);
@@ -1827,6 +1874,8 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
             st[k] = fail(c, NQS_ESTATE, "dense QGT buffers not in the workspace");
         if (!st[k] && (c->cplx || c->symm))
             st[k] = fail(c, NQS_EINVAL, "complex and symmetric models step one at a time");
+        if (!st[k] && cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE && c->dsolver == NQS_SOLVER_CHOLESKY)
+            st[k] = fail(c, NQS_EINVAL, "the Cholesky solve steps one at a time");
         if (!st[k]) st[k] = set_device(c);
     }
     // sampling, energies and gradients for every context, then CG init
@@ -1961,6 +2010,8 @@ int nqs_step_begin(nqs_ctx* c, const nqs_step_cfg* cfg) {
     if (c->step_phase) return fail(c, NQS_ESTATE, "a step is already in flight");
     if (c->cplx || c->symm)
         return fail(c, NQS_EINVAL, "complex and symmetric models step one at a time");
+    if (cfg->qgt == NQS_QGT_JACOBIAN_DENSE && c->dsolver == NQS_SOLVER_CHOLESKY)
+        return fail(c, NQS_EINVAL, "the Cholesky solve steps one at a time");
     int st = nqs_sample(c, 0, nullptr, nullptr, nullptr);
     if (!st) st = nqs_expect_and_grad(c, nullptr, nullptr);
     if (!st) st = sr_check(c, cfg->qgt, cfg->diag_shift, cfg->lr, cfg->cg_tol);

@@ -668,6 +668,18 @@ __global__ void k_h_axpy(int P, const double2* __restrict__ in, double cr, doubl
     out[p] = r;
 }
 
+// lower triangle of the real embedding E = [[A, -B], [B, A]] of G = A + i B
+__global__ void k_h_embed(const double* __restrict__ A, const double* __restrict__ B, int P,
+                          long ld, double* __restrict__ E, long lde) {
+    const long j = (long)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (j > i || j >= 2L * P) return;
+    const long ia = i < P ? i : i - P, ja = j < P ? j : j - P;
+    double v;
+    if ((i < P) == (j < P)) v = A[ia * ld + ja];
+    else v = B[ia * ld + ja];  // (i >= P > j: the lower-left block, + Im G)
+    E[i * lde + j] = v;
+}
+
 // interleaved complex vector <-> embedding [re..., im...]
 __global__ void k_h_split(int P, const double2* __restrict__ z, double* __restrict__ emb) {
     const int p = blockIdx.x * 256 + threadIdx.x;
@@ -776,6 +788,10 @@ void launch_h_matvec(hipStream_t st, const double* G, int P, long ld, const doub
 void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double ci, const double* x,
                    double c2r, double c2i, const double* x2, double2* out) {
     k_h_axpy<<<nbk(P, 256), 256, 0, st>>>(P, in, cr, ci, x, c2r, c2i, x2, out);
+}
+void launch_h_embed(hipStream_t st, const double* G, int P, long ld, double* E, long lde) {
+    k_h_embed<<<dim3(nbk(2L * P, 256), (unsigned)(2 * P)), 256, 0, st>>>(G, G + (size_t)P * ld, P,
+                                                                         ld, E, lde);
 }
 void launch_h_split(hipStream_t st, int P, const double2* z, double* emb) {
     k_h_split<<<nbk(P, 256), 256, 0, st>>>(P, z, emb);

@@ -237,6 +237,16 @@ void launch_h_axpy(hipStream_t st, int P, const double2* in, double cr, double c
 void launch_h_split(hipStream_t st, int P, const double2* z, double* emb);
 void launch_h_join(hipStream_t st, int P, const double* emb, double2* z);
 
+// chol.hip: (A + shift I) x = f by an in-place blocked Cholesky of the FP64
+// symmetric A [n][ld] (lower triangle read and overwritten by L), then the two
+// triangular solves; bad (device int) set when a pivot is not positive; the CG
+// scalars sc are set to those of a converged solve (no iterations) or bad
+void launch_chol_solve(hipStream_t st, double* A, int n, long ld, double shift, const double* f,
+                       double* x, int32_t* bad, CgScalars* sc);
+// holo.hip: the lower triangle of E = [[Re G, -Im G], [Im G, Re G]] ([2P][lde]) from
+// Re G = G and Im G = G + P ld
+void launch_h_embed(hipStream_t st, const double* G, int P, long ld, double* E, long lde);
+
 // symm.hip: symmetric RBM (alpha features over a site-permutation group G,
 // expanded to the plain RBM with alpha |G| hidden units, hidden unit i |G| + g)
 int symm_num_params(int N, int alpha, int vb, int hb);

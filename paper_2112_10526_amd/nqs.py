@@ -54,11 +54,12 @@ class VMCState:
                  n_chains: int, samples_per_chain: int, sweep_size: int, seed: int,
                  total_sz_zero: bool = False, qgt: str = "onthefly", device: int = 0,
                  stream: Optional[torch.cuda.Stream] = None, params=None, allocate: bool = True,
-                 symmetries=None, alpha: Optional[int] = None):
+                 symmetries=None, alpha: Optional[int] = None, dense_solver: str = "cg"):
         """symmetries (int [G][n_sites] site permutations, row 0 the identity) with
         alpha: the symmetric RBM (alpha features over the group; n_hidden is then
         alpha * G, the plain RBM it runs as); its Jacobian is FP64 over the
-        symmetric parameters and its QGT the dense one."""
+        symmetric parameters and its QGT the dense one.  dense_solver ("cg" or
+        "cholesky"): how dense QGT systems are solved."""
         if not torch.cuda.is_available():
             raise RuntimeError("libnqs needs a HIP device; none is visible")
         self.lib = _lib.load()
@@ -110,6 +111,7 @@ class VMCState:
                                              samples_per_chain, sweep_size, seed,
                                              int(total_sz_zero)))
         self._check(self.lib.nqs_set_qgt(self.ctx, _lib.QGTS[qgt]))
+        self._check(self.lib.nqs_set_dense_solver(self.ctx, _lib.DENSE_SOLVERS[dense_solver]))
         self.n_params = int(self.lib.nqs_num_params(self.ctx))
         self.workspace_bytes = int(self.lib.nqs_workspace_bytes(self.ctx))
         self.workspace = None
