@@ -455,6 +455,7 @@ def paper_workload_measure(torch, steps=5, warmup=2):
     4 N_s P^2 real flops of the Hermitian product dJ^H dJ (its upper triangle)."""
     from paper_2112_10526_amd.nqs import VMCState
     w = synth.WORKLOADS["tfim1d_n64_c"]
+    direct = paper_workload_direct(torch, w, steps, warmup)
     st = VMCState.from_workload(w)
     st.thermalize(w.thermalize_segments)
     st.profile_enable(None)
@@ -493,13 +494,43 @@ def paper_workload_measure(torch, steps=5, warmup=2):
                 gram=dict(bound="mfma", avg_launch_us=gram_us, algorithmic_flops=gram_flops,
                           achieved=gram_flops / (gram_us * 1e-6) / 1e12, peak=78.6,
                           unit="TFLOP/s", frac=gram_flops / (gram_us * 1e-6) / 78.6e12),
+                direct_solve=direct,
                 paper_context=dict(hardware="1x NVIDIA RTX 3090 (paper's table)",
                                    s_per_step_cg=3.9, s_per_step_svd=24.0,
                                    s_per_step_cg_2gpu=1.7))
 
 
+def paper_workload_direct(torch, w, steps, warmup):
+    """The same SR steps with the dense system solved directly (Cholesky of the
+    real embedding, size 2P = 8448) instead of by CG: the counterpart of the
+    paper's dense-solver row."""
+    from paper_2112_10526_amd.nqs import VMCState
+    st = VMCState(model=w.model, n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
+                  n_hidden=w.n_hidden, precision=w.precision, rule=w.rule,
+                  n_chains=w.n_chains, samples_per_chain=w.samples_per_chain,
+                  sweep_size=w.sweep_size, seed=w.chain_seed, params=w.params(),
+                  dense_solver="cholesky")
+    st.thermalize(w.thermalize_segments)
+    st.profile_enable(None)
+    for _ in range(warmup):
+        st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    prof = st.profile_read()
+    st.profile_enable([])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.vmc_step(diag_shift=w.diag_shift, lr=w.lr, tol=w.cg_tol)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st.close()
+    print(f"[bench] paper workload (complex, Cholesky): {el * 1e3:.2f} ms/step", file=sys.stderr,
+          flush=True)
+    return dict(s_per_step=el, warmup_profile_ms={k: round(v["ms"] / warmup, 4)
+                                                  for k, v in prof.items() if v["launches"]})
+
+
 def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e-3,
-                        observe_every=10):
+                        observe_every=10, solver="cholesky"):
     """The real-time example: TFIM chain L = 20 (J = 1), complex RBM alpha = 1,
     4096 samples.  The initial state is the h = 1/2 ground state found by SR
     (the example's 300 steps, learning rate 0.01, shift 0.01); the field is then
@@ -518,7 +549,10 @@ def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e
     for _ in range(prep_steps):
         rep = prep.vmc_step(qgt="jacobian_dense", diag_shift=0.01, lr=0.01, tol=1e-6)
     e_prep = rep.energy["mean"]
-    st = VMCState.from_workload(w, params=prep.get_params())
+    st = VMCState(model=w.model, n_sites=w.n_sites, bonds=b, J=w.J, h=w.h, n_hidden=w.n_hidden,
+                  precision=w.precision, rule=w.rule, n_chains=w.n_chains,
+                  samples_per_chain=w.samples_per_chain, sweep_size=w.sweep_size,
+                  seed=w.chain_seed, params=prep.get_params(), dense_solver=solver)
     st.set_chains(prep.get_chains())
     prep.close()
 
@@ -546,8 +580,8 @@ def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e
     st.close()
     lat_ms = np.array(lat) * 1e3
     e = np.array([r["energy"] for r in trace])
-    print(f"[bench] TDVP quench: {np.median(lat_ms):.2f} ms per Heun step", file=sys.stderr,
-          flush=True)
+    print(f"[bench] TDVP quench ({solver}): {np.median(lat_ms):.2f} ms per Heun step",
+          file=sys.stderr, flush=True)
     return dict(metric="milliseconds per TDVP (Heun) step, quench of the TFIM chain",
                 value=float(np.mean(lat_ms)), unit="ms/step", higher_is_better=False,
                 p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
@@ -555,8 +589,8 @@ def tdvp_quench_measure(torch, steps=100, dt=0.01, prep_steps=300, diag_shift=1e
                 config=dict(workload="tfim1d_n20_quench: 1D TFIM L=20 periodic J=1, h 0.5 -> 1, "
                                      "complex RBM alpha=1 (440 complex parameters), 256 chains "
                                      "x 16 samples, 20 proposals per sample, Heun dt "
-                                     f"{dt}, dense holomorphic QGT + CG tol 1e-6 shift "
-                                     f"{diag_shift}",
+                                     f"{dt}, dense holomorphic QGT solved by {solver} "
+                                     f"(CG tol 1e-6), shift {diag_shift}",
                             n_samples=w.n_samples, n_params=w.n_params),
                 prep=dict(sr_steps=prep_steps, energy_h05=e_prep),
                 cg_iters_mean=float(np.mean(iters)),
@@ -574,12 +608,13 @@ def symm_measure(torch, steps=20, warmup=3):
     w = synth.WORKLOADS["tfim2d_l10"]
     perms = synth.square_translations(w.L)
     runs = {}
-    for prec in ("fp64", "bf16"):
+    for prec, solver in (("fp64", "cg"), ("bf16", "cg"), ("fp64", "cholesky"),
+                         ("bf16", "cholesky")):
         st = VMCState(model="tfim", n_sites=w.n_sites, bonds=w.bonds(), J=w.J, h=w.h,
                       n_hidden=0, precision=prec, rule="local", n_chains=w.n_chains,
                       samples_per_chain=w.samples_per_chain, sweep_size=w.sweep_size,
                       seed=w.chain_seed, params=synth.symm_params(w.n_sites, 2, w.param_seed),
-                      symmetries=perms, alpha=2)
+                      symmetries=perms, alpha=2, dense_solver=solver)
         st.thermalize(w.thermalize_segments)
         st.profile_enable(None)
         for _ in range(warmup):
@@ -595,18 +630,19 @@ def symm_measure(torch, steps=20, warmup=3):
             energies.append(rep.energy["mean"])
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / steps
-        runs[prec] = dict(ms_per_step=el * 1e3, local_energies_per_s=w.n_samples / el,
+        runs[f"{prec}_{solver}"] = dict(ms_per_step=el * 1e3, local_energies_per_s=w.n_samples / el,
                           cg_iters_mean=float(np.mean(iters)), energy_first=energies[0],
                           energy_last=energies[-1],
                           warmup_profile_ms={k: round(v["ms"] / warmup, 4)
                                              for k, v in prof.items() if v["launches"]})
         st.close()
-        print(f"[bench] symmetric RBM {prec}: {el * 1e3:.2f} ms/step", file=sys.stderr,
+        print(f"[bench] symmetric RBM {prec} {solver}: {el * 1e3:.2f} ms/step", file=sys.stderr,
               flush=True)
     return dict(metric="SR steps of the translation-symmetric RBM", unit="ms/step",
                 workload="tfim2d_l10 with RBMSymm: 2D TFIM 10x10 periodic J=1 h=3.044, alpha=2 "
                          "over 100 translations (203 parameters), 4096 chains x 4 samples, 100 "
-                         "proposals per sample, dense QGT + CG tol 1e-6 shift 0.01 lr 0.01",
+                         "proposals per sample, dense QGT solved by CG (tol 1e-6) or Cholesky, "
+                         "shift 0.01 lr 0.01",
                 steps=steps, warmup=warmup, runs=runs, data="synthetic")
 
 
@@ -711,7 +747,10 @@ def main():
         print(json.dumps(symm_measure(torch)), flush=True)
         return
     if args.tdvp_quench:
-        print(json.dumps(tdvp_quench_measure(torch)), flush=True)
+        out = tdvp_quench_measure(torch, solver="cholesky")
+        out["cg_run"] = {k: v for k, v in tdvp_quench_measure(torch, solver="cg").items()
+                         if k in ("value", "p50_ms", "cg_iters_mean", "energy_drift")}
+        print(json.dumps(out), flush=True)
         return
     if args.plain:
         print(json.dumps(plain_measure(torch)), flush=True)

@@ -195,8 +195,9 @@ int nqs_set_rbm(nqs_ctx* ctx, int n_hidden, int visible_bias, int hidden_bias,
  * needs S + eps I positive definite (eps > 0 unless S is), else the SR call
  * returns NQS_ENUMERIC; it takes the FP64 dense QGT (NQS_FP64 plain models,
  * symmetric models, complex models through the real embedding of G, 2P <=
- * 32768, which adds a [2P][2P] FP64 buffer to the workspace).  Set it before
- * nqs_bind_workspace (a complex model's workspace changes with it).
+ * 32768, which adds a [2P][2P] FP64 buffer to the workspace; every model adds the
+ * inverses of the 32 x 32 diagonal blocks).  Set it before
+ * nqs_bind_workspace (the workspace changes with it; changing it unbinds).
  * nqs_batch_step and nqs_step_begin do not take it (NQS_EINVAL). */
 typedef enum { NQS_SOLVER_CG = 0, NQS_SOLVER_CHOLESKY = 1 } nqs_dense_solver;
 int nqs_set_dense_solver(nqs_ctx* ctx, nqs_dense_solver solver);

@@ -48,6 +48,7 @@ struct Buffers {
     double* psym;     // symmetric model: its parameters
     double* gpart;    // FP64 dense Gram: slice partials (when sliced)
     int32_t* cbad;    // Cholesky: pivot-not-positive flag
+    double* cinv;     // Cholesky: inverses of the 32 x 32 diagonal blocks
     double* hE;       // complex + Cholesky: the real embedding of G
     int32_t* perms;   // symmetric model: the group, [G][N]
     double* hgp;  // complex: Gram slice partials
@@ -228,6 +229,7 @@ size_t layout(nqs_ctx* c, char* base) {
     b.sc = (CgScalars*)take(sizeof(CgScalars));
     b.cbad = (int32_t*)take(16);
     b.hE = nullptr;
+    b.cinv = c->dsolver == NQS_SOLVER_CHOLESKY ? (double*)take(chol_side_bytes(c->Pd)) : nullptr;
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
@@ -320,6 +322,7 @@ size_t layout_holo(nqs_ctx* c, char* base) {
     b.hk1 = (double*)take(8 * Pld);
     b.cbad = (int32_t*)take(16);
     b.hE = c->dsolver == NQS_SOLVER_CHOLESKY ? (double*)take(8 * 2 * P * (size_t)c->Ple) : nullptr;
+    b.cinv = c->dsolver == NQS_SOLVER_CHOLESKY ? (double*)take(chol_side_bytes(c->Pd)) : nullptr;
     b.tiles = (int*)take(8 * (size_t)c->ntiles);
     return (off + ALIGN - 1) / ALIGN * ALIGN;
 }
@@ -956,7 +959,7 @@ int h_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
         PROF(NQS_PROF_CGVEC);
         launch_h_embed(c->stream, (const double*)c->b.G, (int)c->P, c->Plc, c->b.hE, c->Ple);
         launch_chol_solve(c->stream, c->b.hE, c->Pd, c->Ple, diag_shift, c->b.fp, c->b.xp,
-                          c->b.cbad, c->b.sc);
+                          c->b.cbad, c->b.cinv, c->b.rp, c->b.sc);
         return NQS_OK;
     }
     launch_cg_init(c->stream, c->Pd, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
@@ -1007,7 +1010,7 @@ int s_issue_solve(nqs_ctx* c, double diag_shift, double tol, int maxiter) {
     if (c->dsolver == NQS_SOLVER_CHOLESKY) {
         PROF(NQS_PROF_CGVEC);
         launch_chol_solve(c->stream, (double*)c->b.G, c->Psym, c->Pld, diag_shift, c->b.fp, c->b.xp,
-                          c->b.cbad, c->b.sc);
+                          c->b.cbad, c->b.cinv, c->b.rp, c->b.sc);
         return NQS_OK;
     }
     launch_cg_init(c->stream, c->Psym, c->b.fp, c->b.xp, c->b.rp, c->b.pp, c->b.dpart, c->b.sc, tol,
@@ -1262,7 +1265,7 @@ int nqs_set_dense_solver(nqs_ctx* c, nqs_dense_solver solver) {
     }
     if (c->dsolver != (int)solver) {
         c->dsolver = (int)solver;
-        if (c->cplx) invalidate_binding(c);  // the embedding's buffer
+        invalidate_binding(c);  // the solver's buffers (and a complex model's embedding)
     }
     return NQS_OK;
 }
@@ -1753,7 +1756,7 @@ static int sr_update_issue(nqs_ctx* c, nqs_qgt kind, double diag_shift, double l
         if (c->prec != 0) return fail(c, NQS_EINVAL, "the Cholesky solve takes the FP64 dense QGT");
         PROF(NQS_PROF_CGVEC);
         launch_chol_solve(c->stream, (double*)c->b.G, (int)c->P, c->Pld, diag_shift, c->b.fp,
-                          c->b.xp, c->b.cbad, c->b.sc);
+                          c->b.xp, c->b.cbad, c->b.cinv, c->b.rp, c->b.sc);
         st = NQS_OK;
     } else {
         st = run_cg(c, kind, diag_shift, mi);

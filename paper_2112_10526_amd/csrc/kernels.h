@@ -241,8 +241,11 @@ void launch_h_join(hipStream_t st, int P, const double* emb, double2* z);
 // symmetric A [n][ld] (lower triangle read and overwritten by L), then the two
 // triangular solves; bad (device int) set when a pivot is not positive; the CG
 // scalars sc are set to those of a converged solve (no iterations) or bad
+// (Yinv: chol_side_bytes(n) of scratch for the diagonal blocks' inverses)
+size_t chol_side_bytes(int n);
+// (y: n doubles of scratch; x must not alias f)
 void launch_chol_solve(hipStream_t st, double* A, int n, long ld, double shift, const double* f,
-                       double* x, int32_t* bad, CgScalars* sc);
+                       double* x, int32_t* bad, double* Yinv, double* y, CgScalars* sc);
 // holo.hip: the lower triangle of E = [[Re G, -Im G], [Im G, Re G]] ([2P][lde]) from
 // Re G = G and Im G = G + P ld
 void launch_h_embed(hipStream_t st, const double* G, int P, long ld, double* E, long lde);
