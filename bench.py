@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import ctypes
 import json
 import os
 import sys
@@ -39,6 +40,41 @@ PEAK = {  # MI355X dense peaks
     "mfma_fp64": 78.6e12, "mfma_fp32": 157.3e12, "mfma_bf16": 2.5e15,
     "valu_fp64": 78.6e12, "valu_fp32": 157.3e12, "hbm": 8.0e12,
 }
+
+
+MEASURED = {}  # rates measured on the device by nqs_probe_rate (filled by measured_peaks)
+
+
+def measured_peaks(torch) -> dict:
+    """Rates of the instruction kinds the stages are bound by, measured on this
+    device (nqs_probe_rate): flops/s for FMA and MFMA, exponentials/s for exp."""
+    from paper_2112_10526_amd import _lib
+    L = _lib.load()
+    ctx = ctypes.c_void_p()
+    if L.nqs_create(ctypes.byref(ctx), 0,
+                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)):
+        return {}
+    out = {}
+    for name, kind in _lib.PROBES.items():
+        v = ctypes.c_double(0.0)
+        if L.nqs_probe_rate(ctx, kind, ctypes.byref(v)) == 0:
+            out[name] = v.value
+    L.nqs_destroy(ctx)
+    MEASURED.update(out)
+    return out
+
+
+def measured_peak(bound: str, cls: str, precision: str):
+    """The measured counterpart of a roof (None where no probe covers it)."""
+    if bound == "hbm":
+        return MEASURED.get("copy_Bps")
+    if bound == "mfma":
+        if precision == "fp64":
+            return MEASURED.get("fp64_mfma")
+        return MEASURED.get("bf16_mfma") if (cls == "theta" and precision == "bf16") else None
+    if bound == "alu":
+        return MEASURED.get("fp64_fma" if precision == "fp64" else "fp32_fma")
+    return None
 
 
 def kernel_work(cls: str, w, precision: str):
@@ -116,8 +152,11 @@ def stage_rooflines(w, precision, prof):
         us = p["ms"] * 1e3 / p["launches"]
         per_s = work / (us * 1e-6)
         scale = 1e12 if unit == "TFLOP/s" else 1e9
+        mp = measured_peak(bound, cls, precision)
         out[cls] = dict(bound=bound, achieved=per_s / scale, peak=peak / scale, unit=unit,
-                        frac=per_s / peak, avg_launch_us=us, launches=p["launches"])
+                        frac=per_s / peak, avg_launch_us=us, launches=p["launches"],
+                        measured_peak=None if mp is None else mp / scale,
+                        frac_of_measured=None if mp is None else per_s / mp)
     return out
 
 
@@ -764,6 +803,11 @@ def main():
             torch.mul(src, 1.0, out=dst)  # one read + one write of the buffer
         torch.cuda.synchronize()
         del src, dst
+    # the device's own ceilings (copy rate and instruction-kind probes), taken
+    # before the runs so that every stage roofline can be set against them
+    copy_gbps = copy_rate_gbps(torch)
+    MEASURED["copy_Bps"] = copy_gbps * 1e9
+    probes = measured_peaks(torch)
     main_run = run_precision(w, args.precision, args.steps, args.warmup, torch,
                              step_log=args.step_log or None)
     print(f"[bench] {args.precision}: {main_run['value']:.4g} local energies/s", file=sys.stderr,
@@ -782,7 +826,10 @@ def main():
                     peak=peak / scale, unit=unit, frac=achieved / peak,
                     avg_launch_us=avg_s * 1e6, work_per_launch=work,
                     traffic=read_traffic(dom["kernel_class"], args.precision),
-                    measured_copy_GBps=copy_rate_gbps(torch))
+                    measured_copy_GBps=copy_gbps)
+    mp = measured_peak(bound, dom["kernel_class"], args.precision)
+    roofline.update(measured_peak=None if mp is None else mp / scale,
+                    frac_of_measured=None if mp is None else achieved / mp)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = dict(
         metric=METRIC, value=main_run["value"], unit="local energies/s", n_gpus=1,
@@ -799,6 +846,10 @@ def main():
         cg_iters_mean=main_run["cg_iters_mean"], acceptance=main_run["acceptance_mean"],
         trajectory=main_run["trajectory"],
         roofline=roofline, stage_roofline=main_run["stages"], cpu_baseline=cpu,
+        measured_peaks=dict(copy_GBps=copy_gbps,
+                            **{k + ("_Gexp_per_s" if k.endswith("exp") else "_TFLOPs"):
+                               v / (1e9 if k.endswith("exp") else 1e12)
+                               for k, v in probes.items()}),
         compare=cmp_run, detail=main_run,
     )
     print(json.dumps(line))

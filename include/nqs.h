@@ -459,6 +459,24 @@ int nqs_profile_enable(nqs_ctx* ctx, uint32_t class_mask);
  * Synchronises the stream. */
 int nqs_profile_read(nqs_ctx* ctx, double* ms, int64_t* launches, int n);
 
+/* Throughput probes: the rate one instruction kind reaches on this device when
+ * every lane of 8 waves per SIMD issues independent chains of it (the ceiling
+ * the kernels are measured against; the datasheet's FP32 figure counts packed
+ * FP32, which this library does not use).  per_second: flops per second
+ * (FMA: 2 per instruction and lane; MFMA: 2 M N K per instruction), or
+ * exponentials per second for NQS_PROBE_FP32_EXP.  Runs on the context's
+ * device and stream (a context need not be configured), one warm-up launch
+ * then three timed ones; its throwaway results go to the library's static
+ * scratch (as nqs_local_energy_noalloc: calls overlapping on one GPU race). */
+typedef enum {
+    NQS_PROBE_FP32_FMA = 0,
+    NQS_PROBE_FP64_FMA = 1,
+    NQS_PROBE_FP32_EXP = 2,
+    NQS_PROBE_FP64_MFMA = 3, /* v_mfma_f64_16x16x4f64 */
+    NQS_PROBE_BF16_MFMA = 4  /* v_mfma_f32_16x16x32_bf16 */
+} nqs_probe;
+int nqs_probe_rate(nqs_ctx* ctx, nqs_probe kind, double* per_second);
+
 /* On-the-fly CG (section "Solving linear systems"): with enable != 0 (the
  * default) a full batch of iterations is captured once as a HIP graph and
  * replayed, which removes most of the per-kernel launch cost; with 0 every

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "NQS_OK", 1: "NQS_EINVAL", 2: "NQS_ENOMEM", 3: "NQS_EDEVICE",
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "c128": 3}
 RK_SCHEMES = {"euler": 0, "heun": 1}
 DENSE_SOLVERS = {"cg": 0, "cholesky": 1}
+PROBES = {"fp32_fma": 0, "fp64_fma": 1, "fp32_exp": 2, "fp64_mfma": 3, "bf16_mfma": 4}
 RULES = {"local": 0, "exchange": 1}
 QGTS = {"onthefly": 0, "jacobian_dense": 1}
 
@@ -21,6 +22,7 @@ QGTS = {"onthefly": 0, "jacobian_dense": 1}
 EXPORTS = [
     "nqs_create", "nqs_destroy", "nqs_last_error", "nqs_set_stream", "nqs_set_tfim",
     "nqs_set_heisenberg", "nqs_set_rbm", "nqs_set_rbm_symm", "nqs_set_dense_solver",
+    "nqs_probe_rate",
     "nqs_num_params", "nqs_set_sampler", "nqs_set_qgt",
     "nqs_workspace_bytes", "nqs_bind_workspace", "nqs_set_params", "nqs_get_params",
     "nqs_reset_chains", "nqs_get_chains", "nqs_set_chains", "nqs_proposal_count",
@@ -90,6 +92,7 @@ def load(path: str = LIB_PATH):
         "nqs_set_rbm": (I, [V, I, I, I, I]),
         "nqs_set_rbm_symm": (I, [V, I, V, I, I, I, I]),
         "nqs_set_dense_solver": (I, [V, I]),
+        "nqs_probe_rate": (I, [V, I, ctypes.POINTER(ctypes.c_double)]),
         "nqs_num_params": (SZ, [V]),
         "nqs_set_sampler": (I, [V, I, I, I, I, U64, I]),
         "nqs_set_qgt": (I, [V, I]),

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnqs.so")
 SOURCES = ["tables.hip", "theta.hip", "sampler.hip", "eloc.hip", "sr.hip", "qgt.hip", "dense.hip",
-           "holo.hip", "symm.hip", "chol.hip", "api.hip"]
+           "holo.hip", "symm.hip", "chol.hip", "probe.hip", "api.hip"]
 ARCH = os.environ.get("NQS_ARCH", "gfx950")
 # Packed FP32 VALU forms are switched off: the compiler must not emit them.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",

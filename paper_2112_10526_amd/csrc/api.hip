@@ -2086,6 +2086,32 @@ int nqs_step_poll(nqs_ctx* const* ctxs, int n, int wait, nqs_step_report* reps,
     return first;
 }
 
+int nqs_probe_rate(nqs_ctx* c, nqs_probe kind, double* per_second) {
+    if (!c || !per_second) return NQS_EINVAL;
+    if (kind < NQS_PROBE_FP32_FMA || kind > NQS_PROBE_BF16_MFMA) return fail(c, NQS_EINVAL, "bad probe");
+    int st = set_device(c);
+    if (st) return st;
+    if (!c->scratch_dev || probe_sink_bytes() > kNoallocScratchBytes)
+        return fail(c, NQS_EDEVICE, "no static scratch on this device");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    launch_probe(c->stream, (int)kind, c->scratch_dev);  // warm-up
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    double work = 0.0;
+    for (int r = 0; r < 3; ++r) work += launch_probe(c->stream, (int)kind, c->scratch_dev);
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    st = last_launch(c);
+    if (st) return st;
+    *per_second = ms > 0.f ? work / (1e-3 * (double)ms) : 0.0;
+    return NQS_OK;
+}
+
 int nqs_profile_enable(nqs_ctx* c, uint32_t class_mask) {
     if (!c) return NQS_EINVAL;
     int st = set_device(c);

@@ -250,6 +250,12 @@ void launch_chol_solve(hipStream_t st, double* A, int n, long ld, double shift, 
 // Re G = G and Im G = G + P ld
 void launch_h_embed(hipStream_t st, const double* G, int P, long ld, double* E, long lde);
 
+// probe.hip: throughput probes (kind 0 FP32 FMA, 1 FP64 FMA, 2 FP32 exp, 3 FP64
+// MFMA, 4 BF16 MFMA); launch_probe returns the work one launch does (flops, or
+// exponentials for kind 2); sink: probe_sink_bytes() of device memory
+size_t probe_sink_bytes();
+double launch_probe(hipStream_t st, int kind, void* sink);
+
 // symm.hip: symmetric RBM (alpha features over a site-permutation group G,
 // expanded to the plain RBM with alpha |G| hidden units, hidden unit i |G| + g)
 int symm_num_params(int N, int alpha, int vb, int hb);

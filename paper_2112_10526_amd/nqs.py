@@ -410,6 +410,16 @@ def _set_cg_graphs(self, enable: bool = True) -> None:
     self._check(self.lib.nqs_set_cg_graphs(self.ctx, 1 if enable else 0))
 
 
+def _probe_rate(self, kind: str) -> float:
+    """Measured rate of one instruction kind on this device (see nqs_probe_rate):
+    flops/s for "fp32_fma", "fp64_fma", "fp64_mfma", "bf16_mfma"; exponentials/s
+    for "fp32_exp"."""
+    v = ctypes.c_double(0.0)
+    self._check(self.lib.nqs_probe_rate(self.ctx, _lib.PROBES[kind], ctypes.byref(v)))
+    return v.value
+
+
+VMCState.probe_rate = _probe_rate
 VMCState.profile_enable = _profile_enable
 VMCState.profile_read = _profile_read
 VMCState.set_cg_graphs = _set_cg_graphs
