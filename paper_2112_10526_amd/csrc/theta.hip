@@ -130,34 +130,87 @@ __device__ __forceinline__ v8bf spins_bf16(const int8_t* __restrict__ s, int N, 
     return __builtin_bit_cast(v8bf, v);
 }
 
+constexpr int TB_KC = 64;            // k per LDS chunk (two k-steps of 32)
+constexpr int TB_LD = TB_KC + 8;     // LDS row of one column (+8: spreads the banks)
+
 __global__ __launch_bounds__(256) void k_theta_bf16(Dims d, const int8_t* __restrict__ s, int rows,
                                                     const uint16_t* __restrict__ Whi,
                                                     const uint16_t* __restrict__ Wlo,
                                                     float* __restrict__ dst1, float* __restrict__ dst2,
                                                     long dst2_stride) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // block = 64 rows x 64 columns, wave = 16 rows x the 64 columns (four MFMA
+    // tiles sharing the spin fragment).  The block's W panel moves through LDS
+    // in chunks of 64 k (two coalesced 16-byte loads per thread and plane, read
+    // by all four waves); the next chunk's W and spins are in flight while the
+    // current chunk is multiplied.  Per element the accumulation order is that
+    // of one k-step at a time: + a W_hi, then + a W_lo.
+    __shared__ __attribute__((aligned(16))) uint16_t Sh[2][64 * TB_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Sl[2][64 * TB_LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
     const int row0 = blockIdx.x * 64 + wave * 16;
     const int col0 = blockIdx.y * 64;
-    const int lr = lane & 15, lk = lane >> 4;
+    const int nch = (d.Kb + TB_KC - 1) / TB_KC;
+    // staging items of this thread: columns sc and sc + 32 of the panel, k
+    // offset sk of the chunk (8 entries each)
+    const int sc = tid >> 3, sk = (tid & 7) * 8;
+    const bool scin0 = col0 + sc < d.Mw, scin1 = col0 + sc + 32 < d.Mw;
+    const uint16_t* gh = Whi + (size_t)(col0 + sc) * d.Kb + sk;
+    const uint16_t* gl = Wlo + (size_t)(col0 + sc) * d.Kb + sk;
+    const size_t g32 = (size_t)32 * d.Kb;  // 32 columns further
+    const v8s z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     v4f acc[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = v4f{0, 0, 0, 0};
-    for (int k0 = 0; k0 < d.Kb; k0 += 32) {
-        const int kk = k0 + 8 * lk;
-        const v8bf a = spins_bf16(s, d.N, row0 + lr, rows, kk);
+    v8s nh, nl, nh1, nl1;
+    v8bf na[2];
+    auto fetch = [&](int ch) {  // W pieces of chunk ch, and this lane's spins for it
+        const int k = ch * TB_KC + sk;
+        const bool kin = k < d.Kb;
+        nh = (scin0 && kin) ? *(const v8s*)(gh + ch * TB_KC) : z8;
+        nl = (scin0 && kin) ? *(const v8s*)(gl + ch * TB_KC) : z8;
+        nh1 = (scin1 && kin) ? *(const v8s*)(gh + g32 + ch * TB_KC) : z8;
+        nl1 = (scin1 && kin) ? *(const v8s*)(gl + g32 + ch * TB_KC) : z8;
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const int col = col0 + ct * 16 + lr;
-            v8s bh = {0, 0, 0, 0, 0, 0, 0, 0}, bl = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (col < d.Mw) {
-                bh = *(const v8s*)(Whi + (size_t)col * d.Kb + kk);
-                bl = *(const v8s*)(Wlo + (size_t)col * d.Kb + kk);
-            }
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh),
-                                                              acc[ct], 0, 0, 0);
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl),
-                                                              acc[ct], 0, 0, 0);
+        for (int u = 0; u < 2; ++u) {
+            const int kk = ch * TB_KC + 32 * u + 8 * lk;
+            na[u] = kk < d.Kb ? spins_bf16(s, d.N, row0 + lr, rows, kk)
+                              : __builtin_bit_cast(v8bf, z8);
         }
+    };
+    fetch(0);
+    *(v8s*)&Sh[0][sc * TB_LD + sk] = nh;
+    *(v8s*)&Sl[0][sc * TB_LD + sk] = nl;
+    *(v8s*)&Sh[0][(sc + 32) * TB_LD + sk] = nh1;
+    *(v8s*)&Sl[0][(sc + 32) * TB_LD + sk] = nl1;
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const v8bf a0 = na[0], a1 = na[1];
+        if (ch + 1 < nch) fetch(ch + 1);
+        const uint16_t* ph = Sh[ch & 1];
+        const uint16_t* pl = Sl[ch & 1];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const v8bf a = u == 0 ? a0 : a1;
+            if (ch * TB_KC + 32 * u < d.Kb) {
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int o = (ct * 16 + lr) * TB_LD + 32 * u + 8 * lk;
+                    const v8s bh = *(const v8s*)&ph[o], bl = *(const v8s*)&pl[o];
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bh),
+                                                                      acc[ct], 0, 0, 0);
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(v8bf, bl),
+                                                                      acc[ct], 0, 0, 0);
+                }
+            }
+        }
+        if (ch + 1 < nch) {
+            *(v8s*)&Sh[(ch + 1) & 1][sc * TB_LD + sk] = nh;
+            *(v8s*)&Sl[(ch + 1) & 1][sc * TB_LD + sk] = nl;
+            *(v8s*)&Sh[(ch + 1) & 1][(sc + 32) * TB_LD + sk] = nh1;
+            *(v8s*)&Sl[(ch + 1) & 1][(sc + 32) * TB_LD + sk] = nl1;
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
