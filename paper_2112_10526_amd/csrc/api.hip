@@ -100,6 +100,7 @@ struct nqs_ctx {
     long Ns = 0, Bx = 0;
     int ksplit = 1, chunk = 256, ndpart = 1, Pld = 0, ntiles = 0;
     size_t lds_limit = 65536;
+    int ncu = 256;  // compute units of the device
     long cg_iter = 0;
     double cg_tol = 1e-6;
     int cg_maxiter = 0;
@@ -233,7 +234,7 @@ size_t layout(nqs_ctx* c, char* base) {
     {
         const long Nsp = qgt_padded_samples(c->Ns);
         b.q.Nsp = Nsp;
-        b.q.kc = qgt_chunk(c->prec);
+        qgt_split(b.q, d, c->prec, c->Ns, c->ncu);
         // FP64: int8 spins; BF16 forms: one FP4 code per spin
         b.q.Sp = take(qgt_spin_bytes(d, c->prec, Nsp));
         b.q.St = (int8_t*)take(qgt_spin_bytes(d, c->prec, Nsp));
@@ -244,7 +245,7 @@ size_t layout(nqs_ctx* c, char* base) {
         b.rrp = (double*)take(8 * 2 * 3 * (size_t)qgt_nbr(d));
         b.pap = (double*)take(8 * (size_t)qgt_nbo(d, b.q));   // p.G p partials
         b.Pop = take(qgt_pop_bytes(d, c->prec));               // r, contraction-1 layout
-        const size_t ks = (size_t)(c->ksplit > Nsp / 256 ? c->ksplit : Nsp / 256);
+        const size_t ks = (size_t)(c->ksplit > b.q.ks ? c->ksplit : b.q.ks);
         b.part = take(es * ks * PV);
     }
     if (c->symm) {
@@ -1081,6 +1082,10 @@ int nqs_create(nqs_ctx** out, int device, void* hip_stream) {
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
         lds > 0)
         c->lds_limit = (size_t)lds;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        c->ncu = ncu;
     if (hipSetDevice(device) != hipSuccess ||
         hipHostMalloc((void**)&c->h_sc, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||

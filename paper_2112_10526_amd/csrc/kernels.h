@@ -129,7 +129,8 @@ struct QgtBatch {
     void* Th;        // [Ma][Nsp] t~ hidden-major: double (FP64 path) or float
     float* Tf;       // BF16 forms: t~ in contraction-1 fragment order (Nsp * Ma floats)
     long Nsp;        // samples padded to a multiple of 512
-    int kc;          // samples per contraction-2 chunk (qgt_chunk)
+    int kc;          // BF16 forms: samples per contraction-2 chunk (0 on the FP64 path)
+    int ks;          // contraction-2 partial slots: chunks (BF16) or sample ranges (FP64)
     double* wpart;   // [qgt_nbw(n, prec)] block partials of sum w
 };
 long qgt_padded_samples(long n);
@@ -142,8 +143,9 @@ int qgt_nbr(const Dims& d);   // 64-entry blocks of a CG vector (the largest par
 int qgt_nbv(const Dims& d, int prec);  // CG update blocks = head partials per array
 size_t qgt_spin_bytes(const Dims& d, int prec, long Nsp);  // bytes of Sp (and of St)
 int qgt_ksplit(const QgtBatch& q);
-int qgt_chunk(int prec);
-int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per chunk)
+// sets q.kc and q.ks for n samples (q.Nsp set) on a device with ncu CUs
+void qgt_split(QgtBatch& q, const Dims& d, int prec, long n, int ncu);
+int qgt_nbo(const Dims& d, const QgtBatch& q);  // p.G p partials (one per slot)
 void launch_qgt_prepare(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                         const void* tact, long n, const QgtBatch& q);
 // bytes of a vector in the contraction-1 operand layout
@@ -151,11 +153,11 @@ size_t qgt_pop_bytes(const Dims& d, int prec);
 // CG iteration, kernel 1: head (stop test, beta, p.p) + w = J r + beta w (in place)
 void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, const void* tact,
                   long n, const void* Rop, double* w, const double* aux, CgScalars* sc);
-// kernel 2 (and the force with v_mode 1): chunk partials of J^T z
+// kernel 2 (and the force with v_mode 1): slot partials of J^T z
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
                       const double* v, int v_mode, void* part, double* papart,
                       const CgScalars* sc);
-// force: sum of the chunk partials
+// force: sum of the slot partials
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
                        const double* p, double shift, double* out, double* pap,
                        const CgScalars* sc, int cg);

@@ -341,16 +341,115 @@ static inline void wave_split(int tiles, int maxw, int& waves, int& per_wave) {
 // contraction 1: w_k = t~_k . (P s~_k) for the 16 RT samples of a block.
 // Wave w computes hidden tiles w, w + nw, ... (16 x 16 blocks of S P^T for
 // each of the RT sample tiles, so each P fragment serves RT tiles) and
-// weights them with tanh(theta).  Sites run in whole groups (128 BF16 / 32
-// FP64) over the zero-padded extent Kq, so a group's loads are unconditional
-// and issued together.  Rows past n have zero spins (k_prep_spins), so their
-// products vanish; their activation rows (the activation buffer holds whole
-// blocks of rows) are read but only ever multiply those zeros.
+// weights them with tanh(theta).  Rows past n have zero spins (k_prep_spins),
+// so their products vanish; their activation rows (the activation buffer
+// holds whole blocks of rows) are read but only ever multiply those zeros.
 // ---------------------------------------------------------------------------
 constexpr int W5_RT = 2;        // FP64: sample tiles per block (32 samples)
 constexpr int W_ROWS_MAX = 64;  // samples per contraction-1 block, largest form
 
-// FP64 path: at most 8 waves per block (the FP64 fragments need the registers)
+// A load at a uniform base plus a 32-bit lane byte offset (the base stays in
+// scalar registers, the lane part in one vector register).
+template <typename T>
+__device__ __forceinline__ T ld_at(const void* base, unsigned bytes) {
+    return *(const T*)((const char*)base + bytes);
+}
+
+// FP64 operands of one 16-site group (sites g .. g + 15) of hidden tile ct:
+// the residual rows g + 4 lk + e (e < 4) at column lr of the tile (global
+// memory), and each sample tile's four spins at sites g + 4 lk .. + 3 (one
+// 32-bit word of the block's spins, staged in LDS)
+struct W5Src {
+    const double* Pt;
+    const double* Tb;      // the block's first activation row
+    const uint32_t* Ls;    // the block's spins in LDS, LW words per sample row
+    int Ma, Mw, LW;
+    unsigned po, to, lo;   // lane offsets: residual and activations (bytes), spins (words)
+};
+template <int RT>
+__device__ __forceinline__ void w5_group(const W5Src& c, int ct, int g, double (&b)[4],
+                                         uint32_t (&s)[RT]) {
+    const double* Pg = c.Pt + (size_t)g * c.Ma + 16 * ct;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b[e] = ld_at<double>(Pg + (size_t)e * c.Ma, c.po);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) s[rt] = c.Ls[c.lo + 16 * rt * c.LW + g / 4];
+}
+// the activations of hidden tile ct at the lane's accumulator rows (sample
+// 16 rt + 4 q + lk of the block, hidden unit 16 ct + lr)
+template <int RT>
+__device__ __forceinline__ void w5_act(const W5Src& c, int ct, double (&t)[RT][4]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            t[rt][q] = ld_at<double>(c.Tb + (size_t)(16 * rt + 4 * q) * c.Mw + 16 * ct, c.to);
+}
+template <int RT>
+__device__ __forceinline__ void w5_mfma(const double (&b)[4], const uint32_t (&s)[RT],
+                                        v4d (&acc)[RT]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const double a = (double)(int8_t)(s[rt] >> (8 * e));
+            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[e], acc[rt], 0, 0, 0);
+        }
+}
+// the second group of a pair: its MFMAs, or, for the zero padding group past
+// the last one (an odd number of groups), only a use of its operands, so that
+// their loads stay where they were issued
+__device__ __forceinline__ void w5_second(bool real, const double (&bq)[4],
+                                          const uint32_t (&sq)[2], v4d (&acc)[2]) {
+    if (real)
+        w5_mfma<2>(bq, sq, acc);
+    else
+        asm volatile("" ::"v"(bq[0]), "v"(bq[1]), "v"(bq[2]), "v"(bq[3]), "v"(sq[0]), "v"(sq[1]));
+}
+
+// One hidden tile ct of a wave, its groups in pairs: the pair's second
+// group loads (into bq) while the first group's MFMAs run, and the next
+// pair's first group (into a; after the tile's last pair the first group of
+// tile cn: the wave's next tile, or ct itself when there is none, so that
+// every load is unconditional) while the second group's run.  The tile's
+// activations are loaded with its first pair, ahead of its second group, and
+// weight its 16 x 16 blocks into rs at the end.  Every wait then covers
+// operands issued one group earlier.  ng groups in np = ceil(ng / 2) pairs.
+template <int RT>
+__device__ __forceinline__ void w5_tile(const W5Src& c, int ct, int cn, int ng, int np,
+                                        double (&a)[4], uint32_t (&sa)[RT], double (&rs)[RT][4]) {
+    v4d acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt] = v4d{0, 0, 0, 0};
+    double tv[RT][4], bq[4];
+    uint32_t sq[RT];
+    w5_act<RT>(c, ct, tv);
+    w5_group<RT>(c, ct, 16, bq, sq);
+    __builtin_amdgcn_sched_barrier(0);  // loads ahead of the MFMAs that hide them
+    w5_mfma<RT>(a, sa, acc);
+    w5_group<RT>(c, np > 1 ? ct : cn, np > 1 ? 32 : 0, a, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    w5_second(1 < ng, bq, sq, acc);
+    for (int gp = 1; gp < np; ++gp) {
+        w5_group<RT>(c, ct, 32 * gp + 16, bq, sq);
+        __builtin_amdgcn_sched_barrier(0);
+        w5_mfma<RT>(a, sa, acc);
+        const bool more = gp + 1 < np;
+        w5_group<RT>(c, more ? ct : cn, more ? 32 * (gp + 1) : 0, a, sa);
+        __builtin_amdgcn_sched_barrier(0);
+        w5_second(2 * gp + 1 < ng, bq, sq, acc);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rs[rt][q] += tv[rt][q] * acc[rt][q];
+}
+
+// FP64 path: at most 8 waves per block.  Sites run over the Na columns of the
+// augmented layout (16 per group; the residual and Sp are zero past them,
+// and a padding group completing the last pair only loads).  The block's
+// spins (16 RT rows of Kb sites) are staged in LDS at the start, rows
+// Kb + 8 bytes apart (lane quads of one row then fall in distinct banks).
 __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ Sp,
                                             const double* __restrict__ tact, long n,
                                             const double* __restrict__ Pt,
@@ -358,90 +457,80 @@ __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ S
                                             const double* __restrict__ aux, int nbv,
                                             CgScalars* sc) {
     constexpr int RT = W5_RT;
+    static_assert(RT == 2, "the keep-alives name two sample tiles");
     // the stop flag and the head's scalars; the flag is tested once the
     // first tile's loads are in flight
     const int done = sc->done;
     const HeadIn hin = head_in(sc);
+    extern __shared__ uint32_t w5_spins[];
     __shared__ double wsh[16][16 * RT];
+    __shared__ double wo[16 * RT];
     __shared__ double s3[3][16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, nth = blockDim.x, nw = nth >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // tiles and their tests: scalar
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blockIdx.x * (16 * RT);
     // CG head inputs and the previous w, issued before the contraction
     const double xa = pload1(aux, nbv), xb = pload1(aux + nbv, nbv), xc = pload1(aux + 2 * nbv, nbv);
     const double wold = w[min(r0 + (lane & (16 * RT - 1)), n - 1)];
-    const int Kq = d.Kq, Ma = d.Ma, Mw = d.Mw, nct = d.Ma / 16;
-    const int8_t* Sbase = Sp + (r0 + lr) * Kq;  // sample tile rt: + 16 rt Kq
-    double rs[RT][4];
+    // the block's spins: 16-byte pieces, the first two per thread issued now
+    const int Kb = d.Kb, pr = Kb / 16, npc = 16 * RT * pr;
+    uint4 sv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = min(tid + u * nth, npc - 1);
+        sv[u] = *(const uint4*)(Sp + (r0 + e / pr) * d.Kq + 16 * (e % pr));
+    }
+    const int nct = d.Ma / 16, ng = d.Na / 16, np = (ng + 1) / 2;
+    W5Src c;
+    c.Pt = Pt;
+    c.Tb = tact + r0 * d.Mw;
+    c.Ls = w5_spins;
+    c.Ma = d.Ma;
+    c.Mw = d.Mw;
+    c.LW = (Kb + 8) / 4;
+    c.po = 8u * (unsigned)(4 * lk * d.Ma + lr);
+    c.to = 8u * (unsigned)(lk * d.Mw + lr);
+    c.lo = (unsigned)(lr * c.LW + lk);
+    double rs[RT][4], b[4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) rs[rt][q] = 0.0;
-    for (int ct = wave; ct < nct; ct += nw) {
-        const int j = ct * 16 + lr;
-        double tv[RT][4];
+    // the first group's residual (every wave has at least one tile: wave_split)
+    {
+        const double* Pg = Pt + 16 * wave;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                tv[rt][q] = tact[(size_t)(r0 + 16 * rt + acc_row<double>(lk, q)) * Mw + j];
-        // two accumulation chains per sample tile (even / odd k-steps of
-        // 16 sites), added at the end; the next group's operands are
-        // loaded while the current group's MFMAs run
-        v4d acc[RT][2];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][0] = acc[rt][1] = v4d{0, 0, 0, 0};
-        const double* Pc = Pt + (size_t)(4 * lk) * Ma + j;
-        double b[2][4];
-        uint32_t sb[RT][2];
-        auto load_group = [&](int g) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) b[u][e] = Pc[(size_t)(g + 16 * u + e) * Ma];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    sb[rt][u] = *(const uint32_t*)(Sbase + (size_t)16 * rt * Kq + g + 16 * u + 4 * lk);
-        };
-        load_group(0);
-        if (ct == wave) {
-            asm volatile("" ::: "memory");  // the loads above go out before the stop test
-            if (done) return;               // (uniform over the block, before any barrier)
-        }
-        for (int g = 0; g < Kq; g += 32) {
-            double bc[2][4];
-            uint32_t sc2[RT][2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) bc[u][e] = b[u][e];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) sc2[rt][u] = sb[rt][u];
-            if (g + 32 < Kq) load_group(g + 32);
-            __builtin_amdgcn_sched_barrier(0);  // next group's loads ahead of the MFMAs
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int rt = 0; rt < RT; ++rt) {
-                        const double a = (double)(int8_t)(sc2[rt][u] >> (8 * e));
-                        acc[rt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc[u][e], acc[rt][u], 0, 0, 0);
-                    }
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                rs[rt][q] += tv[rt][q] * (acc[rt][0][q] + acc[rt][1][q]);
+        for (int e = 0; e < 4; ++e) b[e] = ld_at<double>(Pg + (size_t)e * d.Ma, c.po);
     }
-    // CG head partials and the sums over the 16 columns of the wave's tiles,
-    // parked in LDS behind one barrier
-    head_park(aux, nbv, blockDim.x, xa, xb, xc, s3);
+    asm volatile("" ::: "memory");  // the loads above go out before the stop test
+    if (done) return;               // (uniform over the block, before any barrier)
+    // the head's partials and the previous w go to LDS now (their loads were
+    // issued first), so that they hold no registers through the contraction
+    head_park(aux, nbv, nth, xa, xb, xc, s3);
+    if (wave == 0 && lane < 16 * RT) wo[lane] = wold;
+    auto put = [&](int e, const uint4& v) {
+        uint2* q = (uint2*)(w5_spins + (e / pr) * c.LW + 4 * (e % pr));
+        q[0] = make_uint2(v.x, v.y);
+        q[1] = make_uint2(v.z, v.w);
+    };
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (tid + u * nth < npc) put(tid + u * nth, sv[u]);
+    for (int e = tid + 2 * nth; e < npc; e += nth)  // wide rows only
+        put(e, *(const uint4*)(Sp + (r0 + e / pr) * d.Kq + 16 * (e % pr)));
+    __syncthreads();
+    uint32_t s[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) s[rt] = c.Ls[c.lo + 16 * rt * c.LW];
+    for (int ct = wave; ct < nct; ct += nw)
+        w5_tile<RT>(c, ct, ct + nw < nct ? ct + nw : ct, ng, np, b, s, rs);
+    // the repeat loads issued with the last tile are used here, so that the
+    // compiler keeps them ahead of that tile's matrix-core work (on the loop's
+    // exit they would otherwise be dead and moved past it)
+    asm volatile("" : "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]), "+v"(s[0]), "+v"(s[1]));
+    // the sums over the 16 columns of the wave's tiles, parked in LDS behind
+    // one barrier (shared with the head's)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -459,7 +548,7 @@ __global__ __launch_bounds__(512) void k_w5(Dims d, const int8_t* __restrict__ S
 #pragma unroll
             for (int q = 0; q < 16; ++q)
                 if (q < nw) v += wsh[q][lane];
-            v += beta * wold;  // J p = J r + beta J p_old
+            v += beta * wo[lane];  // J p = J r + beta J p_old
             if (k < n) w[k] = v;
         }
         const double t = wave_sum(lane < 16 * RT && k < n ? v : 0.0);
@@ -628,23 +717,17 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// contraction 2: part[kc][j][i] = sum_{k in chunk kc} t~_kj z_k s~_ki
+// contraction 2: part[q][j][i] = sum_{k in range q} t~_kj z_k s~_ki
 // v_mode 0: z_k = (w_k - mean w) / n with mean w from the contraction-1
-// partials, and the blocks of hidden tile 0 write their chunk's partial of
+// partials, and the blocks of hidden tile 0 write their range's partial of
 // p . G p without the shift (sum_k z_k (w_k - mean w)); v_mode 1: z_k = v_k.
-// One block per (hidden tile jt, chunk kc); the tile's t~ rows are staged in
-// LDS and wave w computes site tile w, holding its spins in registers.  All
-// global loads of a block are issued before any of them is consumed (clamped
-// indices, so they are unconditional).
 // Block order: the hardware deals consecutive blocks to the 8 XCDs in turn;
-// the blocks of one chunk are placed on one XCD, so that chunk's spins are
-// brought into a single L2.
+// the blocks of one sample range (or chunk) are placed on one XCD where the
+// grid allows, so that its spins are brought into a single L2.
 // ---------------------------------------------------------------------------
 constexpr int NXCD = 8;
-// FP64 path: 256 samples per chunk (limited by the LDS tile); rows of the
-// staged tile 257 doubles apart, so that the 16 rows fall in distinct banks
-constexpr int O64_KC = 256, O64_KD = O64_KC + 1;
-// BF16 forms: 512 samples per chunk; BF16 rows 520 halves apart
+// BF16 forms: one block per (hidden tile, chunk of 512 samples); BF16 rows
+// 520 halves apart
 constexpr int O16_KC = 512, O16_KP = O16_KC + 8;
 
 // block -> (hidden tile, chunk), chunks grouped by XCD
@@ -654,129 +737,220 @@ __device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
     kc = x + NXCD * (m / nj);
 }
 
-// FP64 path: the t~ tile (FP64, [Ma][Nsp]) is staged in LDS as a = t~ z (z
-// computed first, into LDS); the FP64 MFMA takes A = a and B = the int8 spins
-// as +1 / -1 (0 on padding sites).
-__global__ __launch_bounds__(1024) void k_outer6(Dims d, const int8_t* __restrict__ St,
-                                                 const double* __restrict__ Th, long Nsp, long n,
-                                                 const double* __restrict__ v, int v_mode,
-                                                 const double* __restrict__ wpart, int nbw,
-                                                 double* __restrict__ part, int ksplit,
-                                                 double* __restrict__ papart,
-                                                 const CgScalars* __restrict__ sc) {
+// FP64 path.  Block (pass, jt, q): hidden tile jt, the site tiles of the
+// pass, and the q-th of ks near-equal ranges of 16-sample units (ks chosen so
+// that the blocks fill every CU twice in one round, all with the same work).
+// The range streams through LDS in sub-chunks of 128 samples: while the
+// matrix cores take a = t~ z of the current sub-chunk from LDS, the next
+// sub-chunk's t~ and z source and the spins are loaded; every wave keeps the
+// sums of its site tiles in registers over the whole range.  The FP64 MFMA
+// takes A = a and B = the int8 spins as +1 / -1 (0 on padding sites); within
+// 16 samples, k-step e of lane quad lk takes sample 4 lk + e.
+constexpr int O9_SC = 128;           // samples per sub-chunk
+constexpr int O9_LD = O9_SC + 1;     // doubles between staged rows (odd)
+constexpr int O9_NU = O9_SC / 16;    // 16-sample units per sub-chunk
+constexpr int O9_THREADS = 512;
+constexpr int O9_UNITS = 16 * O9_SC / 2 / O9_THREADS;  // 16-byte staging units per thread
+
+struct O9Range {
+    long k0, k1;  // the block's samples [k0, k1)
+    int nsc;      // sub-chunks
+};
+
+// t~ and the z source of sub-chunk c (16-byte units: thread unit e is row e / 64,
+// samples 2 (e % 64) + {0, 1}), clamped into the block's range
+__device__ __forceinline__ void o9_load(const double* __restrict__ Tj, const double* __restrict__ v,
+                                        long Nsp, const O9Range& R, int c, double2 (&ta)[O9_UNITS],
+                                        double2 (&va)[O9_UNITS]) {
+#pragma unroll
+    for (int i = 0; i < O9_UNITS; ++i) {
+        const int e = threadIdx.x + O9_THREADS * i;
+        const long k = min(R.k0 + (long)c * O9_SC + 2 * (e & 63), R.k1 - 2);
+        ta[i] = *(const double2*)(Tj + (size_t)(e >> 6) * Nsp + k);
+        va[i] = *(const double2*)(v + k);
+    }
+}
+// a = t~ z of sub-chunk c into LDS (zero past the range and past n); the
+// threads holding row 0 add up z_k (v_k - shift) (the p . G p partial)
+__device__ __forceinline__ void o9_stage(double* __restrict__ A, const O9Range& R, int c, long n,
+                                         double shift, double scale, const double2 (&ta)[O9_UNITS],
+                                         const double2 (&va)[O9_UNITS], double& zw) {
+#pragma unroll
+    for (int i = 0; i < O9_UNITS; ++i) {
+        const int e = threadIdx.x + O9_THREADS * i;
+        const int r = e >> 6, c2 = 2 * (e & 63);
+        const long k = R.k0 + (long)c * O9_SC + c2;
+        const bool ok0 = k < R.k1 && k < n, ok1 = k + 1 < R.k1 && k + 1 < n;
+        const double z0 = ok0 ? (va[i].x - shift) * scale : 0.0;
+        const double z1 = ok1 ? (va[i].y - shift) * scale : 0.0;
+        A[r * O9_LD + c2] = ta[i].x * z0;
+        A[r * O9_LD + c2 + 1] = ta[i].y * z1;
+        if (r == 0) zw += z0 * (va[i].x - shift) + z1 * (va[i].y - shift);
+    }
+}
+// the spins of site tile it for sub-chunk c: one word (4 samples) per unit
+template <int PT>
+__device__ __forceinline__ void o9_spins(const int8_t* __restrict__ St, long Nsp, const O9Range& R,
+                                         int c, const int (&its)[PT], int lr, int lk,
+                                         uint32_t (&sb)[PT][O9_NU]) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int u = 0; u < O9_NU; ++u) {
+            const long k = min(R.k0 + (long)c * O9_SC + 16 * u, R.k1 - 16) + 4 * lk;
+            sb[p][u] = *(const uint32_t*)(St + (size_t)(its[p] * 16 + lr) * Nsp + k);
+        }
+}
+
+// the MFMAs of one sub-chunk for the wave's first NT site tiles: units of 16
+// samples (those past the range: none), the LDS operands of unit u + 1 read
+// while unit u's MFMAs run
+template <int NT, int PT, int CH>
+__device__ __forceinline__ void o9_units(const double* __restrict__ A, int nu,
+                                         const uint32_t (&sb)[PT][O9_NU], v4d (&acc)[PT][CH]) {
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = A[e];
+#pragma unroll
+    for (int u = 0; u < O9_NU; ++u) {
+        double an[4];
+        if (u + 1 < O9_NU) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) an[e] = A[16 * (u + 1) + e];
+        }
+        if (u < nu) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int p = 0; p < NT; ++p) {
+                    const double b = (double)(int8_t)(sb[p][u] >> (8 * e));
+                    acc[p][e % CH] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b, acc[p][e % CH], 0, 0, 0);
+                }
+        }
+        if (u + 1 < O9_NU) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[e] = an[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one unit's LDS operands in flight at a time
+    }
+}
+
+template <int PT>
+__global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __restrict__ St,
+                                                       const double* __restrict__ Th, long Nsp,
+                                                       long n, const double* __restrict__ v,
+                                                       int v_mode, const double* __restrict__ wpart,
+                                                       int nbw, double* __restrict__ part, int ks,
+                                                       int tpp, double* __restrict__ papart,
+                                                       const CgScalars* __restrict__ sc) {
     // stop flag of the CG product, tested once the block's loads are in flight
     const int done = v_mode == 0 ? sc->done : 0;
-    constexpr int KC = O64_KC, KD = O64_KD;
-    constexpr int UR = KC / 2;         // 16-byte units per row (2 doubles)
-    constexpr int UA = 16 * UR;        // units in the tile
-    constexpr int BA = 8;              // units per thread issued up front
-    constexpr int BW = 2;              // mean-w partials per thread issued up front
-    constexpr int KS = KC / 16;        // k-steps (4 samples per lane quad x 4 quads)
-    __shared__ __align__(16) double As[16 * KD + KC];  // a = t~ z tile, then z
+    constexpr int CH = PT == 1 ? 4 : 2;  // accumulation chains per site tile
+    constexpr int BW = 2;                // mean-w partials per thread issued up front
+    __shared__ double As[2][16 * O9_LD];
     __shared__ double sh[16];
-    const int nj = d.Ma / 16;
-    int jt, kc;
-    outer_block(nj, jt, kc);
-    if (kc >= ksplit) return;  // no chunk for this block
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nth = blockDim.x, nw = nth >> 6;
+    const int nj = d.Ma / 16, ni = d.Na / 16;
+    // work item (pass, q, jt), range-major, from the block index: XCD x (the
+    // blocks x, x + 8, ...) takes a contiguous run of items, so that the
+    // blocks of one range share one or two L2s
+    const int nit = (int)gridDim.x, L = blockIdx.x, x = L % NXCD;
+    const int before = x * (nit / NXCD) + min(x, nit % NXCD);  // items of XCDs 0 .. x - 1
+    const int item = before + L / NXCD;
+    const int pass = item / (nj * ks), i2 = item - pass * nj * ks;
+    const int q = i2 / nj, jt = i2 - q * nj;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
-    const long kbeg = (long)kc * KC;
-    const int nit = d.Na / 16;
-    const double* Ab = Th + (size_t)jt * 16 * Nsp + kbeg;
-    // ---- issue: mean-w partials, t~ tile, z source, this wave's first spins
+    const long U = (n + 15) / 16;
+    O9Range R;
+    R.k0 = 16 * ((long)q * U / ks);
+    R.k1 = 16 * (((long)q + 1) * U / ks);
+    R.nsc = (int)((R.k1 - R.k0 + O9_SC - 1) / O9_SC);
+    // this wave's site tiles (clamped to a valid one; act[p] says which count)
+    const int t0 = pass * tpp, t1 = min(ni, t0 + tpp);
+    int its[PT], nact = 0;
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+        const int it = t0 + wave + 8 * p;
+        nact += it < t1 ? 1 : 0;
+        its[p] = it < t1 ? it : t1 - 1;
+    }
+    const double* Tj = Th + (size_t)jt * 16 * Nsp;
+    // ---- issue: mean-w partials, the first sub-chunk and its spins
     double wp[BW];
 #pragma unroll
     for (int u = 0; u < BW; ++u) {
-        const int b = u * nth + tid;
+        const int b = u * O9_THREADS + tid;
         wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
     }
-    double2 ra[BA];
-#pragma unroll
-    for (int u = 0; u < BA; ++u) {
-        const int e = min(u * nth + tid, UA - 1);
-        ra[u] = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * (e % UR));
-    }
-    const double vz = v[min(kbeg + (tid & (KC - 1)), n - 1)];
-    uint32_t sb[KS];  // int8 spins of the lane's site row: 4 per k-step
-    auto load_spins = [&](int it) {
-        const int8_t* Sr = St + (size_t)(it * 16 + lr) * Nsp + kbeg;
-#pragma unroll
-        for (int u = 0; u < KS; ++u) sb[u] = *(const uint32_t*)(Sr + 16 * u + 4 * lk);
-    };
-    load_spins(wave);
+    double2 ta[O9_UNITS], va[O9_UNITS];
+    o9_load(Tj, v, Nsp, R, 0, ta, va);
+    uint32_t sb[PT][O9_NU];
+    o9_spins<PT>(St, Nsp, R, 0, its, lr, lk, sb);
     asm volatile("" ::: "memory");  // the loads above go out before the stop test
     if (done) return;               // (uniform over the block, before any barrier)
-    __builtin_amdgcn_sched_barrier(0);  // all of the above in flight before any use
-    // ---- consume
     double shift = 0.0, scale = 1.0;
     if (v_mode == 0) {
         double a = 0.0;
 #pragma unroll
         for (int u = 0; u < BW; ++u) a += wp[u];
-        for (int b = BW * nth + tid; b < nbw; b += nth) a += wpart[b];
-        shift = bsum_waves(a, sh, nw) / (double)n;
+        for (int b = BW * O9_THREADS + tid; b < nbw; b += O9_THREADS) a += wpart[b];
+        shift = bsum_waves(a, sh, O9_THREADS / 64) / (double)n;
         scale = 1.0 / (double)n;
     }
-    double* zs = As + 16 * KD;
-    double zw = 0.0;  // this thread's part of sum_k z_k (w_k - mean w) over the chunk
-    for (int t = tid; t < KC; t += nth) {
-        const long k = kbeg + t;
-        const double vk = t == (tid & (KC - 1)) ? vz : v[min(k, n - 1)];
-        const double z = k < n ? (vk - shift) * scale : 0.0;
-        zw += z * (vk - shift);
-        zs[t] = z;
-    }
-    // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
-    // chunk, from the blocks of hidden tile 0 (its barriers also publish z)
-    if (v_mode == 0 && jt == 0) {
-        const double t = bsum_waves(zw, sh, nw);
-        if (tid == 0) papart[kc] = t;
-    } else {
+    double zw = 0.0;
+    o9_stage(As[0], R, 0, n, shift, scale, ta, va, zw);
+    __syncthreads();
+    v4d acc[PT][CH];
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int h = 0; h < CH; ++h) acc[p][h] = v4d{0, 0, 0, 0};
+    for (int c = 0; c < R.nsc; ++c) {
+        // the next sub-chunk (this one again after the last: every load unconditional)
+        const int cn = c + 1 < R.nsc ? c + 1 : c;
+        o9_load(Tj, v, Nsp, R, cn, ta, va);
+        uint32_t sn[PT][O9_NU];
+        o9_spins<PT>(St, Nsp, R, cn, its, lr, lk, sn);
+        __builtin_amdgcn_sched_barrier(0);  // those loads ahead of the MFMAs that hide them
+        const double* A = As[c & 1] + lr * O9_LD + 4 * lk;
+        const int nu = (int)min((long)O9_NU, (R.k1 - R.k0) / 16 - (long)c * O9_NU);
+        if (nact == PT)
+            o9_units<PT, PT, CH>(A, nu, sb, acc);
+        else if (nact > 0)
+            o9_units<1, PT, CH>(A, nu, sb, acc);
+        static_assert(O9_UNITS == 2, "the keep-alive below names two units");
+        if (c + 1 < R.nsc)
+            o9_stage(As[(c + 1) & 1], R, c + 1, n, shift, scale, ta, va, zw);
+        else  // a use of the repeat loads, which keeps them where they were issued
+            asm volatile("" ::"v"(ta[0].x), "v"(ta[1].x), "v"(va[0].x), "v"(va[1].x));
+#pragma unroll
+        for (int p = 0; p < PT; ++p)
+#pragma unroll
+            for (int u = 0; u < O9_NU; ++u) sb[p][u] = sn[p][u];
         __syncthreads();
     }
-    // the tile as a = t~ z (rows KD (odd) doubles apart: 8-byte stores)
-#pragma unroll
-    for (int u = 0; u < BA; ++u) {
-        const int e = u * nth + tid;
-        if (e < UA) {
-            const int c = e % UR;
-            double* q = As + (e / UR) * KD + 2 * c;
-            q[0] = ra[u].x * zs[2 * c];
-            q[1] = ra[u].y * zs[2 * c + 1];
-        }
+    // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
+    // range, from the blocks of hidden tile 0
+    if (v_mode == 0 && jt == 0 && pass == 0) {
+        const double t = bsum_waves(zw, sh, O9_THREADS / 64);
+        if (tid == 0) papart[q] = t;
     }
-    for (int e = BA * nth + tid; e < UA; e += nth) {  // small blocks only
-        const int c = e % UR;
-        const double2 t2 = *(const double2*)(Ab + (size_t)(e / UR) * Nsp + 2 * c);
-        double* q = As + (e / UR) * KD + 2 * c;
-        q[0] = t2.x * zs[2 * c];
-        q[1] = t2.y * zs[2 * c + 1];
-    }
-    __syncthreads();
-    for (int it = wave; it < nit; it += nw) {
-        if (it != wave) load_spins(it);
-        // four independent accumulation chains (one per sample of a k-step's
-        // quad), added in a fixed order at the end
-        v4d acc[4];
+    double* out = part + (size_t)q * d.Ma * d.Na;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = v4d{0, 0, 0, 0};
+    for (int p = 0; p < PT; ++p)
+        if (p < nact) {
 #pragma unroll
-        for (int u = 0; u < KS; ++u) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kl = 16 * u + 4 * lk + e;
-                const double b = (double)(int8_t)(sb[u] >> (8 * e));  // spin +1 / -1 (0: padding)
-                acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[lr * KD + kl], b, acc[e], 0, 0, 0);
+            for (int r = 0; r < 4; ++r) {
+                double t;
+                if constexpr (CH == 4)
+                    t = (acc[p][0][r] + acc[p][1][r]) + (acc[p][2][r] + acc[p][3][r]);
+                else
+                    t = acc[p][0][r] + acc[p][1][r];
+                out[(size_t)(jt * 16 + acc_row<double>(lk, r)) * d.Na + its[p] * 16 + lr] = t;
             }
-            __builtin_amdgcn_sched_barrier(0);  // one k-step of LDS operands live at a time
         }
-        double* out = part + (size_t)kc * d.Ma * d.Na;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            out[(size_t)(jt * 16 + acc_row<double>(lk, q)) * d.Na + it * 16 + lr] =
-                (acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q]);
-    }
 }
 
 // BF16 forms: t~ (FP32, [Ma][Nsp]) is scaled by z while it is staged: the
@@ -1271,7 +1445,8 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
     wave_split(d.Ma / 16, prec == 0 ? 8 : 15, waves, per);
     const int nb = qgt_nbw(n, prec), nbv = qgt_nbv(d, prec);
     if (prec == 0) {
-        k_w5<<<nb, 64 * waves, 0, st>>>(d, (const int8_t*)q.Sp, (const double*)tact, n,
+        k_w5<<<nb, 64 * waves, (size_t)16 * W5_RT * (d.Kb + 8), st>>>(d, (const int8_t*)q.Sp,
+                                                                   (const double*)tact, n,
                                         (const double*)Rop, w, q.wpart, aux, nbv, sc);
     } else {  // one more wave for the CG head
         k_w7<<<nb, 64 * (waves + 1), 0, st>>>(d, (const uint8_t*)q.Sp, q.Tf, n,
@@ -1279,28 +1454,53 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
     }
 }
 
-int qgt_ksplit(const QgtBatch& q) { return (int)(q.Nsp / q.kc); }
-int qgt_chunk(int prec) { return prec == 0 ? O64_KC : O16_KC; }
+int qgt_ksplit(const QgtBatch& q) { return q.ks; }
 
-// waves of a contraction-2 block
-static int outer_waves(const Dims& d) {
-    int waves, per;
-    wave_split(d.Na / 16, 16, waves, per);
-    return waves;
+// FP64 contraction 2: site-tile passes (at most 16 site tiles per block) and
+// tiles per pass
+static void o9_passes(const Dims& d, int& passes, int& tpp) {
+    const int ni = d.Na / 16;
+    passes = (ni + 15) / 16;
+    tpp = (ni + passes - 1) / passes;
+}
+void qgt_split(QgtBatch& q, const Dims& d, int prec, long n, int ncu) {
+    if (prec != 0) {
+        q.kc = O16_KC;
+        q.ks = (int)(q.Nsp / q.kc);
+        return;
+    }
+    // ranges per hidden tile: two blocks per CU in all, each range at least
+    // one 16-sample unit
+    int passes, tpp;
+    o9_passes(d, passes, tpp);
+    const long U = (n + 15) / 16, nj = d.Ma / 16;
+    long ks = 2L * (ncu > 0 ? ncu : 1) / (nj * passes);
+    ks = ks < 1 ? 1 : (ks > U ? U : ks);
+    q.kc = 0;
+    q.ks = (int)ks;
 }
 
 void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, long n,
                       const double* v, int v_mode, void* part, double* papart,
                       const CgScalars* sc) {
-    const int ks = qgt_ksplit(q), nj = d.Ma / 16;
-    const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
-    const int nw = outer_waves(d), nbw = qgt_nbw(n, prec);
-    if (prec == 0)
-        k_outer6<<<nb, 64 * nw, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v, v_mode,
-                                         q.wpart, nbw, (double*)part, ks, papart, sc);
-    else
+    const int ks = qgt_ksplit(q), nj = d.Ma / 16, nbw = qgt_nbw(n, prec);
+    if (prec == 0) {
+        int passes, tpp;
+        o9_passes(d, passes, tpp);
+        const int nb = passes * nj * ks;  // one block per work item, all in one round
+        if (tpp <= 8)
+            k_outer9<1><<<nb, O9_THREADS, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v,
+                                                    v_mode, q.wpart, nbw, (double*)part, ks, tpp,
+                                                    papart, sc);
+        else
+            k_outer9<2><<<nb, O9_THREADS, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v,
+                                                    v_mode, q.wpart, nbw, (double*)part, ks, tpp,
+                                                    papart, sc);
+    } else {
+        const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
         k_outer8<<<nb, O8_THREADS, 0, st>>>(d, (const uint8_t*)q.St, (const float*)q.Th, q.Nsp, n,
                                             v, v_mode, q.wpart, nbw, (float*)part, ks, papart, sc);
+    }
 }
 
 void launch_qgt_reduce(hipStream_t st, const Dims& d, int prec, const void* part, int ksplit,
