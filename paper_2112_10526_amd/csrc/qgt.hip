@@ -738,8 +738,10 @@ __device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
 }
 
 // FP64 path.  Block (pass, jt, q): hidden tile jt, the site tiles of the
-// pass, and the q-th of ks near-equal ranges of 16-sample units (ks chosen so
-// that the blocks fill every CU twice in one round, all with the same work).
+// pass (up to 32; PT per active wave, the active waves taking tiles w,
+// w + nwa, ...), and the q-th of ks near-equal ranges of 16-sample units (ks
+// chosen so that the blocks fill the CUs in one round, all with the same
+// work: two 512-thread blocks or one 1024-thread block per CU).
 // The range streams through LDS in sub-chunks of 128 samples: while the
 // matrix cores take a = t~ z of the current sub-chunk from LDS, the next
 // sub-chunk's t~ and z source and the spins are loaded; every wave keeps the
@@ -749,8 +751,7 @@ __device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
 constexpr int O9_SC = 128;           // samples per sub-chunk
 constexpr int O9_LD = O9_SC + 1;     // doubles between staged rows (odd)
 constexpr int O9_NU = O9_SC / 16;    // 16-sample units per sub-chunk
-constexpr int O9_THREADS = 512;
-constexpr int O9_UNITS = 16 * O9_SC / 2 / O9_THREADS;  // 16-byte staging units per thread
+constexpr int O9_PIECES = 16 * O9_SC / 2;  // 16-byte staging units of a sub-chunk
 
 struct O9Range {
     long k0, k1;  // the block's samples [k0, k1)
@@ -759,12 +760,14 @@ struct O9Range {
 
 // t~ and the z source of sub-chunk c (16-byte units: thread unit e is row e / 64,
 // samples 2 (e % 64) + {0, 1}), clamped into the block's range
+template <int NTH>
 __device__ __forceinline__ void o9_load(const double* __restrict__ Tj, const double* __restrict__ v,
-                                        long Nsp, const O9Range& R, int c, double2 (&ta)[O9_UNITS],
-                                        double2 (&va)[O9_UNITS]) {
+                                        long Nsp, const O9Range& R, int c,
+                                        double2 (&ta)[O9_PIECES / NTH],
+                                        double2 (&va)[O9_PIECES / NTH]) {
 #pragma unroll
-    for (int i = 0; i < O9_UNITS; ++i) {
-        const int e = threadIdx.x + O9_THREADS * i;
+    for (int i = 0; i < O9_PIECES / NTH; ++i) {
+        const int e = threadIdx.x + NTH * i;
         const long k = min(R.k0 + (long)c * O9_SC + 2 * (e & 63), R.k1 - 2);
         ta[i] = *(const double2*)(Tj + (size_t)(e >> 6) * Nsp + k);
         va[i] = *(const double2*)(v + k);
@@ -772,12 +775,14 @@ __device__ __forceinline__ void o9_load(const double* __restrict__ Tj, const dou
 }
 // a = t~ z of sub-chunk c into LDS (zero past the range and past n); the
 // threads holding row 0 add up z_k (v_k - shift) (the p . G p partial)
+template <int NTH>
 __device__ __forceinline__ void o9_stage(double* __restrict__ A, const O9Range& R, int c, long n,
-                                         double shift, double scale, const double2 (&ta)[O9_UNITS],
-                                         const double2 (&va)[O9_UNITS], double& zw) {
+                                         double shift, double scale,
+                                         const double2 (&ta)[O9_PIECES / NTH],
+                                         const double2 (&va)[O9_PIECES / NTH], double& zw) {
 #pragma unroll
-    for (int i = 0; i < O9_UNITS; ++i) {
-        const int e = threadIdx.x + O9_THREADS * i;
+    for (int i = 0; i < O9_PIECES / NTH; ++i) {
+        const int e = threadIdx.x + NTH * i;
         const int r = e >> 6, c2 = 2 * (e & 63);
         const long k = R.k0 + (long)c * O9_SC + c2;
         const bool ok0 = k < R.k1 && k < n, ok1 = k + 1 < R.k1 && k + 1 < n;
@@ -836,17 +841,18 @@ __device__ __forceinline__ void o9_units(const double* __restrict__ A, int nu,
     }
 }
 
-template <int PT>
-__global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __restrict__ St,
-                                                       const double* __restrict__ Th, long Nsp,
-                                                       long n, const double* __restrict__ v,
-                                                       int v_mode, const double* __restrict__ wpart,
-                                                       int nbw, double* __restrict__ part, int ks,
-                                                       int tpp, double* __restrict__ papart,
-                                                       const CgScalars* __restrict__ sc) {
+template <int PT, int NTH>
+__global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict__ St,
+                                                const double* __restrict__ Th, long Nsp, long n,
+                                                const double* __restrict__ v, int v_mode,
+                                                const double* __restrict__ wpart, int nbw,
+                                                double* __restrict__ part, int ks, int tpp,
+                                                int nwa, double* __restrict__ papart,
+                                                const CgScalars* __restrict__ sc) {
+    constexpr int UT = O9_PIECES / NTH;  // staging units per thread
     // stop flag of the CG product, tested once the block's loads are in flight
     const int done = v_mode == 0 ? sc->done : 0;
-    constexpr int CH = PT == 1 ? 4 : 2;  // accumulation chains per site tile
+    constexpr int CH = PT == 1 ? 4 : 1;  // accumulation chains per site tile
     constexpr int BW = 2;                // mean-w partials per thread issued up front
     __shared__ double As[2][16 * O9_LD];
     __shared__ double sh[16];
@@ -867,12 +873,12 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
     R.k0 = 16 * ((long)q * U / ks);
     R.k1 = 16 * (((long)q + 1) * U / ks);
     R.nsc = (int)((R.k1 - R.k0 + O9_SC - 1) / O9_SC);
-    // this wave's site tiles (clamped to a valid one; act[p] says which count)
+    // this wave's site tiles (clamped to a valid one; nact of them count)
     const int t0 = pass * tpp, t1 = min(ni, t0 + tpp);
     int its[PT], nact = 0;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        const int it = t0 + wave + 8 * p;
+        const int it = wave < nwa ? t0 + wave + nwa * p : t1;
         nact += it < t1 ? 1 : 0;
         its[p] = it < t1 ? it : t1 - 1;
     }
@@ -881,11 +887,11 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
     double wp[BW];
 #pragma unroll
     for (int u = 0; u < BW; ++u) {
-        const int b = u * O9_THREADS + tid;
+        const int b = u * NTH + tid;
         wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
     }
-    double2 ta[O9_UNITS], va[O9_UNITS];
-    o9_load(Tj, v, Nsp, R, 0, ta, va);
+    double2 ta[UT], va[UT];
+    o9_load<NTH>(Tj, v, Nsp, R, 0, ta, va);
     uint32_t sb[PT][O9_NU];
     o9_spins<PT>(St, Nsp, R, 0, its, lr, lk, sb);
     asm volatile("" ::: "memory");  // the loads above go out before the stop test
@@ -895,12 +901,12 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
         double a = 0.0;
 #pragma unroll
         for (int u = 0; u < BW; ++u) a += wp[u];
-        for (int b = BW * O9_THREADS + tid; b < nbw; b += O9_THREADS) a += wpart[b];
-        shift = bsum_waves(a, sh, O9_THREADS / 64) / (double)n;
+        for (int b = BW * NTH + tid; b < nbw; b += NTH) a += wpart[b];
+        shift = bsum_waves(a, sh, NTH / 64) / (double)n;
         scale = 1.0 / (double)n;
     }
     double zw = 0.0;
-    o9_stage(As[0], R, 0, n, shift, scale, ta, va, zw);
+    o9_stage<NTH>(As[0], R, 0, n, shift, scale, ta, va, zw);
     __syncthreads();
     v4d acc[PT][CH];
 #pragma unroll
@@ -910,7 +916,7 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
     for (int c = 0; c < R.nsc; ++c) {
         // the next sub-chunk (this one again after the last: every load unconditional)
         const int cn = c + 1 < R.nsc ? c + 1 : c;
-        o9_load(Tj, v, Nsp, R, cn, ta, va);
+        o9_load<NTH>(Tj, v, Nsp, R, cn, ta, va);
         uint32_t sn[PT][O9_NU];
         o9_spins<PT>(St, Nsp, R, cn, its, lr, lk, sn);
         __builtin_amdgcn_sched_barrier(0);  // those loads ahead of the MFMAs that hide them
@@ -920,11 +926,12 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
             o9_units<PT, PT, CH>(A, nu, sb, acc);
         else if (nact > 0)
             o9_units<1, PT, CH>(A, nu, sb, acc);
-        static_assert(O9_UNITS == 2, "the keep-alive below names two units");
-        if (c + 1 < R.nsc)
-            o9_stage(As[(c + 1) & 1], R, c + 1, n, shift, scale, ta, va, zw);
-        else  // a use of the repeat loads, which keeps them where they were issued
-            asm volatile("" ::"v"(ta[0].x), "v"(ta[1].x), "v"(va[0].x), "v"(va[1].x));
+        if (c + 1 < R.nsc) {
+            o9_stage<NTH>(As[(c + 1) & 1], R, c + 1, n, shift, scale, ta, va, zw);
+        } else {  // a use of the repeat loads, which keeps them where they were issued
+#pragma unroll
+            for (int i = 0; i < UT; ++i) asm volatile("" ::"v"(ta[i].x), "v"(va[i].x));
+        }
 #pragma unroll
         for (int p = 0; p < PT; ++p)
 #pragma unroll
@@ -934,7 +941,7 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
     // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
     // range, from the blocks of hidden tile 0
     if (v_mode == 0 && jt == 0 && pass == 0) {
-        const double t = bsum_waves(zw, sh, O9_THREADS / 64);
+        const double t = bsum_waves(zw, sh, NTH / 64);
         if (tid == 0) papart[q] = t;
     }
     double* out = part + (size_t)q * d.Ma * d.Na;
@@ -947,7 +954,7 @@ __global__ __launch_bounds__(O9_THREADS) void k_outer9(Dims d, const int8_t* __r
                 if constexpr (CH == 4)
                     t = (acc[p][0][r] + acc[p][1][r]) + (acc[p][2][r] + acc[p][3][r]);
                 else
-                    t = acc[p][0][r] + acc[p][1][r];
+                    t = acc[p][0][r];
                 out[(size_t)(jt * 16 + acc_row<double>(lk, r)) * d.Na + its[p] * 16 + lr] = t;
             }
         }
@@ -1456,12 +1463,20 @@ void launch_qgt_w(hipStream_t st, const Dims& d, int prec, const QgtBatch& q, co
 
 int qgt_ksplit(const QgtBatch& q) { return q.ks; }
 
-// FP64 contraction 2: site-tile passes (at most 16 site tiles per block) and
-// tiles per pass
-static void o9_passes(const Dims& d, int& passes, int& tpp) {
+// FP64 contraction 2: site-tile passes of at most 32 tiles, tiles per pass,
+// tiles per active wave, active waves and the block size
+struct O9Shape {
+    int passes, tpp, pt, nwa, nth;
+};
+static O9Shape o9_shape(const Dims& d) {
     const int ni = d.Na / 16;
-    passes = (ni + 15) / 16;
-    tpp = (ni + passes - 1) / passes;
+    O9Shape s;
+    s.passes = (ni + 31) / 32;
+    s.tpp = (ni + s.passes - 1) / s.passes;
+    s.pt = s.tpp > 16 ? 2 : 1;
+    s.nwa = (s.tpp + s.pt - 1) / s.pt;
+    s.nth = s.nwa > 8 ? 1024 : 512;
+    return s;
 }
 void qgt_split(QgtBatch& q, const Dims& d, int prec, long n, int ncu) {
     if (prec != 0) {
@@ -1469,12 +1484,11 @@ void qgt_split(QgtBatch& q, const Dims& d, int prec, long n, int ncu) {
         q.ks = (int)(q.Nsp / q.kc);
         return;
     }
-    // ranges per hidden tile: two blocks per CU in all, each range at least
-    // one 16-sample unit
-    int passes, tpp;
-    o9_passes(d, passes, tpp);
+    // ranges per hidden tile: two 512-thread blocks or one 1024-thread block
+    // per CU in all, each range at least one 16-sample unit
+    const O9Shape sh = o9_shape(d);
     const long U = (n + 15) / 16, nj = d.Ma / 16;
-    long ks = 2L * (ncu > 0 ? ncu : 1) / (nj * passes);
+    long ks = (sh.nth == 512 ? 2L : 1L) * (ncu > 0 ? ncu : 1) / (nj * sh.passes);
     ks = ks < 1 ? 1 : (ks > U ? U : ks);
     q.kc = 0;
     q.ks = (int)ks;
@@ -1485,17 +1499,19 @@ void launch_qgt_outer(hipStream_t st, const Dims& d, int prec, const QgtBatch& q
                       const CgScalars* sc) {
     const int ks = qgt_ksplit(q), nj = d.Ma / 16, nbw = qgt_nbw(n, prec);
     if (prec == 0) {
-        int passes, tpp;
-        o9_passes(d, passes, tpp);
-        const int nb = passes * nj * ks;  // one block per work item, all in one round
-        if (tpp <= 8)
-            k_outer9<1><<<nb, O9_THREADS, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v,
-                                                    v_mode, q.wpart, nbw, (double*)part, ks, tpp,
-                                                    papart, sc);
+        const O9Shape s = o9_shape(d);
+        const int nb = s.passes * nj * ks;  // one block per work item, all in one round
+#define O9_LAUNCH(PT, NTH)                                                                      \
+    k_outer9<PT, NTH><<<nb, NTH, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v, v_mode,    \
+                                          q.wpart, nbw, (double*)part, ks, s.tpp, s.nwa, papart, \
+                                          sc)
+        if (s.nth == 512)
+            O9_LAUNCH(1, 512);
+        else if (s.pt == 1)
+            O9_LAUNCH(1, 1024);
         else
-            k_outer9<2><<<nb, O9_THREADS, 0, st>>>(d, q.St, (const double*)q.Th, q.Nsp, n, v,
-                                                    v_mode, q.wpart, nbw, (double*)part, ks, tpp,
-                                                    papart, sc);
+            O9_LAUNCH(2, 1024);
+#undef O9_LAUNCH
     } else {
         const int nb = NXCD * nj * ((ks + NXCD - 1) / NXCD);
         k_outer8<<<nb, O8_THREADS, 0, st>>>(d, (const uint8_t*)q.St, (const float*)q.Th, q.Nsp, n,

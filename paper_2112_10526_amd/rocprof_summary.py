@@ -149,7 +149,10 @@ def summarize_waves(counter_dir, cmd,
            "|---|---:|---:|---:|---:|---:|"]
     for name in ["nqs::k_w7", "nqs::k_outer8", "nqs::k_update5",
                  "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
-                 "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16"]:
+                 "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16",
+                 "nqs::k_w5", "nqs::k_outer9<1>", "nqs::k_outer9<2>", "nqs::k_update4",
+                 "nqs::k_sample<double, 4, 0, 2>", "nqs::k_sample<double, 16, 1, 1>",
+                 "nqs::k_eloc<double, 0>", "nqs::k_eloc<double, 1>", "nqs::k_theta<double>"]:
         if name not in agg:
             continue
         d = agg[name]

@@ -130,3 +130,29 @@ def test_precision_form_shape_sr_direction():
     d, g, _ = out["bf16"]
     assert np.abs(g - f).max() <= 2e-4 * np.abs(f).max()
     _check("bf16", O, f, g, d, shift, tol, 3e-5, gnorm)
+
+
+@pytest.mark.timeout(600)
+def test_onthefly_wide_site_tiles_fp64():
+    """A 150-site TFIM chain, alpha = 2 (ten 16-site tiles, nineteen 16-unit hidden
+    tiles): the contraction-2 blocks of the FP64 path then hold 1,024 threads with
+    one site tile per active wave, and the sample ranges split 256 samples over
+    13 blocks per hidden tile.  Force and SR direction against the oracle's
+    Jacobian on the same random batch (same property as above, FP64 e)."""
+    torch = _torch()
+    w = synth.WORKLOADS["tfim1d_n10"].replace(L=150, alpha=2, sweep_size=150, n_chains=64,
+                                              samples_per_chain=4, sigma=0.05)
+    tol, shift = 1e-9, 0.01
+    st = _state(w, precision="fp64")
+    s = synth.random_configs(w.n_samples, w.n_sites, 21)
+    st.load_samples(torch.from_numpy(s).cuda())
+    _, g = st.expect_and_grad()
+    d, info = st.sr_update(diag_shift=shift, lr=0.0, tol=tol, maxiter=4000)
+    assert info.converged, info
+    rbm = core.Rbm(w.n_sites, w.n_hidden, w.params())
+    ham = core.Hamiltonian.tfim(w.n_sites, w.bonds(), w.J, w.h)
+    O = core.jacobian(rbm, s)
+    f = core.force(O, core.local_energy(rbm, ham, s))
+    g = g.cpu().numpy()
+    assert np.abs(g - f).max() <= 1e-10 * np.abs(f).max()
+    _check("fp64 wide", O, f, g, d.cpu().numpy(), shift, tol, 1e-13, _spectral_norm(O, shift))
