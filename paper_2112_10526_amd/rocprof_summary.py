@@ -134,7 +134,7 @@ def summarize_traffic(fetch_dir, write_dir, cls, precision, copy_mib, cmds):
 def summarize_waves(counter_dir, cmd,
                     title="Wave-state counters of the hot-path kernels (10x10 TFIM workload, "
                           "BF16 form)"):
-    """Markdown table of the wave-state counters (SQ_*) of the BF16 hot-path kernels."""
+    """Markdown table of the wave-state counters (SQ_*) of the hot-path kernels."""
     rows = _counter_rows(counter_dir)
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
@@ -150,20 +150,26 @@ def summarize_waves(counter_dir, cmd,
     for name in ["nqs::k_w7", "nqs::k_outer8", "nqs::k_update5",
                  "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
                  "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16",
-                 "nqs::k_w5", "nqs::k_outer9<1>", "nqs::k_outer9<2>", "nqs::k_update4",
+                 "nqs::k_w5", "nqs::k_outer9<", "nqs::k_update4",
                  "nqs::k_sample<double, 4, 0, 2>", "nqs::k_sample<double, 16, 1, 1>",
                  "nqs::k_eloc<double, 0>", "nqs::k_eloc<double, 1>", "nqs::k_theta<double>"]:
-        if name not in agg:
-            continue
-        d = agg[name]
-        wc = np.array(d["SQ_WAVE_CYCLES"])
-        keep = wc >= 0.1 * wc.max()
-        med = {k: float(np.median(np.array(v)[keep])) for k, v in d.items() if len(v) == len(wc)}
-        w = med["SQ_WAVE_CYCLES"]
-        out.append(f"| `{name}` | {med['SQ_WAVES']:.0f} | {w / med['SQ_WAVES']:.0f} | "
-                   f"{100 * med['SQ_WAIT_ANY'] / w:.0f} | {100 * med['SQ_WAIT_INST_ANY'] / w:.0f} | "
-                   f"{100 * med['SQ_ACTIVE_INST_ANY'] / w:.0f} |")
+        # (a name ending in "<" stands for every instantiation of that template)
+        hits = [k for k in agg if k.startswith(name)] if name.endswith("<") else (
+            [name] if name in agg else [])
+        for name in sorted(hits):
+            _wave_row(out, name, agg[name])
     print("\n".join(out))
+
+
+def _wave_row(out, name, d):
+    """One row of the wave-state table: medians over the dispatches that did work."""
+    wc = np.array(d["SQ_WAVE_CYCLES"])
+    keep = wc >= 0.1 * wc.max()
+    med = {k: float(np.median(np.array(v)[keep])) for k, v in d.items() if len(v) == len(wc)}
+    w = med["SQ_WAVE_CYCLES"]
+    out.append(f"| `{name}` | {med['SQ_WAVES']:.0f} | {w / med['SQ_WAVES']:.0f} | "
+               f"{100 * med['SQ_WAIT_ANY'] / w:.0f} | {100 * med['SQ_WAIT_INST_ANY'] / w:.0f} | "
+               f"{100 * med['SQ_ACTIVE_INST_ANY'] / w:.0f} |")
 
 
 MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",

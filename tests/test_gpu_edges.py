@@ -103,3 +103,23 @@ def test_sr_direction_largest_sizes(precision, eps, lattice, L, n_hidden):
           f"iterations {info.iterations}")
     assert res <= bound
     assert bound < 0.2 * np.linalg.norm(f)
+
+
+def test_contraction_ranges_of_unequal_length_fp64():
+    """10-site chain, alpha = 3 (two hidden tiles, one site tile) on 34,816
+    samples: contraction 2 of the FP64 path splits them into 256 sample ranges of
+    8 or 9 16-sample units, so its blocks stream one or two 128-sample sub-chunks
+    (the second one partial).  SR direction against the oracle's Cholesky solve of
+    the same system (P = 340), within 1e-7 of its largest entry."""
+    torch = _torch()
+    st, rbm, ham, params, _ = _tfim_state(10, "chain", 30, "fp64", 34816, 10, 0.1)
+    s = synth.random_configs(34816, 10, 31)
+    st.load_samples(torch.from_numpy(s).cuda())
+    _, g = st.expect_and_grad()
+    d, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=1e-11, maxiter=4000)
+    assert info.converged, info
+    O = core.jacobian(rbm, s)
+    f = core.force(O, core.local_energy(rbm, ham, s))
+    assert np.abs(g.cpu().numpy() - f).max() <= 1e-10 * np.abs(f).max()
+    x = core.cholesky_solve(core.qgt_dense(O), f, 0.01)
+    assert np.abs(d.cpu().numpy() - x).max() <= 1e-7 * np.abs(x).max()
