@@ -11,8 +11,9 @@
 // Layout: a block of 4 waves handles 4 SB samples; lanes run over sites (TFIM)
 // or bonds (Heisenberg), up to ICH chunks of 64 per pass.  The hidden-major
 // table T = tanh(2W) is staged in LDS JC hidden units at a time and shared by
-// the block's samples; each sample's tanh(theta_j) is a wave-uniform (scalar)
-// operand.
+// the block's samples; each sample's tanh(theta_j) is a wave-uniform operand,
+// loaded for the whole chunk into the lanes (lane l: hidden unit j0 + l) and
+// read out with v_readlane.
 #include "kernels.h"
 
 namespace nqs {
@@ -92,6 +93,12 @@ __global__ __launch_bounds__(256) void k_eloc(Dims d, const R* __restrict__ Tj,
         }
         for (int j0 = 0; j0 < M; j0 += JC) {
             const int jn = min(JC, M - j0);
+            // the chunk's activations of the wave's samples, lane l holding hidden
+            // unit j0 + l (JC <= 64), loaded ahead of the staging; the loop takes
+            // each as a wave-uniform value with v_readlane
+            R tv[SB];
+#pragma unroll
+            for (int r = 0; r < SB; ++r) tv[r] = tact[kr[r] * Mw + j0 + min(lane, jn - 1)];
             __syncthreads();
             stage_rows<R>(Ts, Tj, j0, jn, Nw);
             __syncthreads();
@@ -99,7 +106,7 @@ __global__ __launch_bounds__(256) void k_eloc(Dims d, const R* __restrict__ Tj,
                 for (int jl = 0; jl < jn; ++jl) {
                     R tj[SB];
 #pragma unroll
-                    for (int r = 0; r < SB; ++r) tj[r] = tact[kr[r] * Mw + j0 + jl];
+                    for (int r = 0; r < SB; ++r) tj[r] = readlane(tv[r], jl);
                     const R* row = Ts + jl * Nw;
 #pragma unroll
                     for (int c = 0; c < ICH; ++c) {
