@@ -103,20 +103,40 @@ __global__ __launch_bounds__(256) void k_eloc(Dims d, const R* __restrict__ Tj,
             stage_rows<R>(Ts, Tj, j0, jn, Nw);
             __syncthreads();
             if (k0 < n) {
+                // the table entries of hidden unit jl + 1 are read while unit jl's
+                // products are formed (the last unit's again at the end: the reads
+                // stay unconditional)
+                R na[ICH], nb[ICH];
+#pragma unroll
+                for (int c = 0; c < ICH; ++c) {
+                    na[c] = Ts[ia[c]];
+                    nb[c] = KIND == 1 ? Ts[ib[c]] : (R)0;
+                }
                 for (int jl = 0; jl < jn; ++jl) {
                     R tj[SB];
 #pragma unroll
                     for (int r = 0; r < SB; ++r) tj[r] = readlane(tv[r], jl);
-                    const R* row = Ts + jl * Nw;
+                    R ca[ICH], cb[ICH];
+#pragma unroll
+                    for (int c = 0; c < ICH; ++c) {
+                        ca[c] = na[c];
+                        cb[c] = nb[c];
+                    }
+                    const R* nrow = Ts + min(jl + 1, jn - 1) * Nw;
+#pragma unroll
+                    for (int c = 0; c < ICH; ++c) {
+                        na[c] = nrow[ia[c]];
+                        if (KIND == 1) nb[c] = nrow[ib[c]];
+                    }
 #pragma unroll
                     for (int c = 0; c < ICH; ++c) {
                         if (g0 + 64 * c >= n_items) continue;
                         if (KIND == 0) {
-                            const R Tv = row[ia[c]];
+                            const R Tv = ca[c];
 #pragma unroll
                             for (int r = 0; r < SB; ++r) prod[c][r] *= (R)1 - sa[c][r] * tj[r] * Tv;
                         } else {
-                            const R ta = row[ia[c]], tb = row[ib[c]];
+                            const R ta = ca[c], tb = cb[c];
                             const R TT = (R)1 - ta * tb, Td = ta - tb;
 #pragma unroll
                             for (int r = 0; r < SB; ++r) prod[c][r] *= TT - sa[c][r] * tj[r] * Td;
