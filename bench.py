@@ -387,8 +387,11 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
     resident, in lock-step ticks (every resident run advances one SR step per
     tick; a step's latency is its tick's) and with asynchronous steps (each run
     starts its next step when its previous one ends; a step's latency is its
-    own); (3) Poisson arrivals at offered loads rho * mu, served in real time in
-    lock-step ticks.  Each pass reports aggregate local energies/s, p50/p99
+    own), and in lock-step ticks with every run's CG iterations in its own
+    launches instead of the grouped ones; the same two lock-step passes on
+    n_runs / 2 small runs (L ~ U{4..8}, 1024..4096 samples); (3) Poisson
+    arrivals at offered loads rho * mu, served in real time in lock-step
+    ticks.  Each pass reports aggregate local energies/s, p50/p99
     SR-step latency, queueing delay, time in system, mean residency and peak HBM
     footprint."""
     from paper_2112_10526_amd.serving import Server, requests_from_stream
@@ -426,6 +429,24 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
         passes[f"all_present_{mode}"] = summary(cap)
         print(f"[bench] serving all present, {mode}: {cap['wall_s']:.2f} s", file=sys.stderr,
               flush=True)
+    # lock-step ticks with every run's CG iterations in its own launches
+    own = Server(budget, max_slots=slots, grouping=False).serve(base, realtime=False,
+                                                                progress=progress)
+    passes["all_present_tick_own_launches"] = summary(own)
+    print(f"[bench] serving all present, tick, own CG launches: {own['wall_s']:.2f} s",
+          file=sys.stderr, flush=True)
+    # small runs only (L 4..8, 1024..4096 samples, every one of them small enough
+    # to group), grouped and in their own launches
+    small = [dataclasses.replace(r, arrival=0.0)
+             for r in requests_from_stream(n_runs // 2, seed, 1.0, n_steps=n_steps,
+                                           L_range=(4, 8), samples=(1024, 2048, 4096))]
+    for grouping in (True, False):
+        out = Server(budget, max_slots=slots, grouping=grouping).serve(small, realtime=False,
+                                                                       progress=progress)
+        key = "small_runs_tick" + ("" if grouping else "_own_launches")
+        passes[key] = summary(out)
+        print(f"[bench] serving small runs, tick, grouping={grouping}: {out['wall_s']:.2f} s",
+              file=sys.stderr, flush=True)
     for rho in loads:
         reqs = requests_from_stream(n_runs, seed, rho * mu, n_steps=n_steps)
         out = Server(budget, max_slots=slots).serve(reqs, realtime=True, progress=progress)

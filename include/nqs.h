@@ -484,6 +484,26 @@ int nqs_probe_rate(nqs_ctx* ctx, nqs_probe kind, double* per_second);
  * Drops a captured graph; synchronises the stream. */
 int nqs_set_cg_graphs(nqs_ctx* ctx, int enable);
 
+/* Grouped CG iterations in nqs_batch_step (section "Solving linear systems",
+ * on-the-fly QGT): with enable != 0 (the default) the on-the-fly CG of the
+ * small NQS_FP32 and NQS_BF16 contexts of one batched step that share a device
+ * (at least two of them; up to 32 per group, on a stream of the library's
+ * own) runs as one launch per kernel class and iteration for all of them,
+ * each run's blocks found through a device table of the runs' operands; with
+ * 0 this context runs its own launches (as with nqs_vmc_step).  Small: samples
+ * x round_up(n_hidden + 1, 16) x round_up(round_up(n_sites + 1, 16), 128) at
+ * most 2^27, where launch overhead dominates a run's own launches; larger
+ * contexts always run their own, side by side with the group.  Each run keeps
+ * its own blocks and fixed-order sums, so its results are identical either
+ * way.  Runs of one group advance in lock-step; a run that has stopped leaves
+ * the group's launches from the next batch of iterations on.  Contexts whose
+ * CG kernel classes are being timed (nqs_profile_enable) run their own
+ * launches.  The
+ * library keeps the tables, a stream and events per device until the process
+ * ends; batched steps on one device take their grouped part one at a time.
+ * Errors: NQS_EINVAL (null context). */
+int nqs_set_cg_grouping(nqs_ctx* ctx, int enable);
+
 /* Name of kernel class k, or NULL. */
 const char* nqs_profile_class_name(int k);
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "nqs_log_psi", "nqs_log_psi_vjp", "nqs_jacobian", "nqs_expect_and_grad", "nqs_sr_update",
     "nqs_vmc_step", "nqs_tdvp_step", "nqs_batch_step", "nqs_step_begin", "nqs_step_poll",
     "nqs_profile_enable", "nqs_profile_read",
-    "nqs_profile_class_name", "nqs_set_cg_graphs",
+    "nqs_profile_class_name", "nqs_set_cg_graphs", "nqs_set_cg_grouping",
 ]
 PROF_CLASSES = ["sample", "theta", "eloc", "stats", "qgt_w", "outer", "reduce", "cg_vec",
                 "jacobian", "gram", "dense_matvec", "update", "prepare"]
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
         "nqs_profile_read": (I, [V, V, V, I]),
         "nqs_profile_class_name": (ctypes.c_char_p, [I]),
         "nqs_set_cg_graphs": (I, [V, I]),
+        "nqs_set_cg_grouping": (I, [V, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

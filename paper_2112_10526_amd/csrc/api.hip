@@ -1,9 +1,12 @@
 // C ABI of libnqs (declared in include/nqs.h): context state, workspace
 // layout and the host-side orchestration of the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <set>
@@ -121,6 +124,8 @@ struct nqs_ctx {
     int64_t prof_count[NQS_PROF_CLASSES] = {};
     // a full batch of on-the-fly CG iterations captured as a HIP graph
     bool graphs = true;
+    // the batched step may run this context's CG iterations in grouped launches
+    bool grouping = true;
     hipGraphExec_t cg_graph = nullptr;
     hipGraphExec_t cg_graph_dense = nullptr;  // a batch of dense-form iterations
     hipStream_t cap_stream = nullptr;
@@ -829,6 +834,194 @@ struct CgRun {
         ++checked;
         progress = true;
         return NQS_OK;
+    }
+};
+
+// ---- grouped CG iterations of the batched step -----------------------------
+// The on-the-fly CG of several small BF16-form contexts on one device, one
+// launch per kernel class per iteration for all of them (cg_group_plan), on a
+// stream of the library's own.  Per device the library keeps slots (two
+// descriptor tables in device memory and their pinned host copies, stream,
+// events) until the process ends; one batched step at a time uses a device's
+// slots.
+namespace {
+
+// Contexts join a group when one CG iteration's contractions are small enough
+// for launch overhead to dominate their own launches: samples x augmented
+// hidden rows x site extent at most this (about two microseconds of work).
+constexpr double CG_GROUP_WORK = 134217728.0;
+bool group_small(const nqs_ctx* c) {
+    return (double)c->Ns * c->d.Ma * c->d.Kq <= CG_GROUP_WORK;
+}
+
+struct GroupSlot {
+    CgGroupTable* dev[2] = {nullptr, nullptr};
+    CgGroupTable* host[2] = {nullptr, nullptr};  // pinned
+    hipEvent_t copy_ev[2] = {nullptr, nullptr};  // after each table's upload
+    hipStream_t stream = nullptr;
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    hipEvent_t done_ev = nullptr;
+};
+struct GroupPool {
+    std::mutex m;
+    std::vector<std::unique_ptr<GroupSlot>> slots;
+};
+
+GroupPool& group_pool(int device) {
+    static std::mutex gm;
+    static std::map<int, std::unique_ptr<GroupPool>> pools;
+    std::lock_guard<std::mutex> l(gm);
+    std::unique_ptr<GroupPool>& p = pools[device];
+    if (!p) p.reset(new GroupPool);
+    return *p;
+}
+
+// slot k of the pool (created on first use, the device current); null on failure
+GroupSlot* group_slot(GroupPool& pool, size_t k, std::string& err) {
+    while (pool.slots.size() <= k) {
+        std::unique_ptr<GroupSlot> s(new GroupSlot);
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipMalloc((void**)&s->dev[i], sizeof(CgGroupTable));
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&s->host[i], sizeof(CgGroupTable), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev[i], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&s->flag_ev[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            err = std::string("grouped CG set-up: ") + hipGetErrorString(e);
+            return nullptr;  // (what was created stays with the process)
+        }
+        pool.slots.push_back(std::move(s));
+    }
+    return pool.slots[k].get();
+}
+
+}  // namespace
+
+// Drives the CG iterations of its members in lock-step: batches of `every`
+// grouped iterations, the members' stop flags read as batches finish (up to
+// two batches queued).  A member whose flag says it has stopped leaves the
+// table from the next batch issued on (the table is rebuilt in the slot's
+// other buffer; batches already queued still read the old one, and their
+// launches return at once for that member).
+struct CgGroup {
+    GroupSlot* s = nullptr;
+    std::vector<nqs_ctx*> all;      // every member (the streams to release)
+    std::vector<nqs_ctx*> members;  // those still iterating
+    CgGroupPlan plan{};
+    int cur = 0;  // table buffer the next batch reads
+    int every = 1, limit = 0;
+    bool stop = false;
+    int launched = 0, issued = 0, checked = 0;
+    std::string err;
+
+    bool ok(hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return false;
+    }
+    // fills table buffer cur from members and queues its upload
+    bool upload() {
+        hipError_t e = hipEventSynchronize(s->copy_ev[cur]);  // (its previous upload is done)
+        if (!ok(e, "grouped CG table")) return false;
+        CgGroupTable& t = *s->host[cur];
+        t.nrun = (int)members.size();
+        for (int r = 0; r < t.nrun; ++r) {
+            const nqs_ctx* c = members[r];
+            const Buffers& b = c->b;
+            CgGroupRun& R = t.run[r];
+            std::memset(&R, 0, sizeof(R));
+            R.d = c->d;
+            R.n = c->Ns;
+            R.Nsp = b.q.Nsp;
+            R.Sp = b.q.Sp;
+            R.St = b.q.St;
+            R.Tf = b.q.Tf;
+            R.Th = b.q.Th;
+            R.Rop = b.Pop;
+            R.w = b.wbuf;
+            R.wpart = b.q.wpart;
+            R.aux = b.rrp;
+            R.part = b.part;
+            R.papart = b.pap;
+            R.x = b.x;
+            R.r = b.r;
+            R.p = b.p;
+            R.p2 = b.p2;
+            R.sc = b.sc;
+            R.host_flag = &c->h_flag[0];
+            R.nbv = qgt_nbv(c->d, c->prec);
+            R.nbw = qgt_nbw(c->Ns, c->prec);
+            R.ks = qgt_ksplit(b.q);
+        }
+        cg_group_plan(t, plan);
+        e = hipMemcpyAsync(s->dev[cur], s->host[cur], sizeof(CgGroupTable),
+                           hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->copy_ev[cur], s->stream);
+        return ok(e, "grouped CG table");
+    }
+    // cfg_limit: the largest number of iterations any member may launch
+    bool start(int cfg_limit) {
+        all = members;
+        every = cg_check_interval();
+        limit = cfg_limit;
+        // the group's stream waits for each member's CG set-up (its flag_ev[0],
+        // recorded after the set-up was issued)
+        hipError_t e = hipStreamSynchronize(s->stream);  // (the slot's last use is over)
+        for (nqs_ctx* c : members)
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, c->flag_ev[0], 0);
+        return ok(e, "grouped CG start") && upload();
+    }
+    bool finished() const { return stop || (checked >= issued && launched >= limit); }
+    bool issue_batch() {
+        const int k = (limit - launched) < every ? (limit - launched) : every;
+        for (int i = 0; i < k; ++i)
+            launch_cg_group_iter(s->stream, s->dev[cur], plan, (launched + i) & 1, i + 1 == k);
+        launched += k;
+        if (!ok(hipGetLastError(), "grouped CG launch")) return false;
+        if (!ok(hipEventRecord(s->flag_ev[issued & 1], s->stream), "grouped CG event"))
+            return false;
+        ++issued;
+        return true;
+    }
+    bool top_up(int depth) {
+        while (!stop && launched < limit && issued - checked < depth)
+            if (!issue_batch()) return false;
+        return true;
+    }
+    // as CgRun::poll; CG has stopped when every member's flag says so
+    bool poll(bool block, bool& progress) {
+        progress = false;
+        if (checked >= issued) return true;
+        hipEvent_t ev = s->flag_ev[checked & 1];
+        if (block) {
+            if (!ok(hipEventSynchronize(ev), "grouped CG wait")) return false;
+        } else {
+            const hipError_t e = hipEventQuery(ev);
+            if (e == hipErrorNotReady) return true;
+            if (!ok(e, "grouped CG query")) return false;
+        }
+        ++checked;
+        progress = true;
+        std::vector<nqs_ctx*> left;
+        for (nqs_ctx* c : members)
+            if (c->h_flag[0] == 0) left.push_back(c);
+        stop = left.empty();
+        if (stop || left.size() == members.size()) return true;
+        members.swap(left);
+        cur ^= 1;
+        return upload();
+    }
+    // every member's stream waits for the group's work
+    bool finish() {
+        hipError_t e = hipEventRecord(s->done_ev, s->stream);
+        for (nqs_ctx* c : all)
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, s->done_ev, 0);
+        return ok(e, "grouped CG finish");
     }
 };
 
@@ -1886,18 +2079,45 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
             st[k] = fail(c, NQS_EINVAL, "the Cholesky solve steps one at a time");
         if (!st[k]) st[k] = set_device(c);
     }
-    // sampling, energies and gradients for every context, then CG init
-    for (int k = 0; k < n; ++k) {
-        if (st[k]) continue;
-        nqs_ctx* c = ctxs[k];
-        issue_sample(c, 0, nullptr);
-        issue_energy_grad(c);
-        mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
-        if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE)
-            issue_dense_setup(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
-        else issue_cg_init(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
-        st[k] = last_launch(c);
+    // contexts whose CG iterations may run grouped: small on-the-fly BF16-form
+    // contexts on one device (grouping on, no CG kernel class timed), at least two
+    std::vector<char> cand(n, 0);
+    int gdev = -1;
+    {
+        int nc = 0;
+        for (int k = 0; k < n; ++k) {
+            const nqs_ctx* c = ctxs[k];
+            if (st[k] || !c->grouping || c->prec == 0 || cfgs[k].qgt != NQS_QGT_ONTHEFLY ||
+                (c->prof_mask & CG_CLASSES) || !group_small(c))
+                continue;
+            if (gdev < 0) gdev = c->device;
+            if (c->device == gdev) {
+                cand[k] = 1;
+                ++nc;
+            }
+        }
+        if (nc < 2) std::fill(cand.begin(), cand.end(), 0);
     }
+    // sampling, energies and gradients for every context, then CG init: the
+    // grouping candidates first, each recording (flag_ev[0]) when its set-up is
+    // done, so that their grouped CG can start while the others still sample
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < n; ++k) {
+            if (st[k] || (cand[k] != 0) != (pass == 0)) continue;
+            nqs_ctx* c = ctxs[k];
+            issue_sample(c, 0, nullptr);
+            issue_energy_grad(c);
+            mi[k] = default_maxiter(c, cfgs[k].cg_maxiter);
+            if (cfgs[k].qgt == NQS_QGT_JACOBIAN_DENSE)
+                issue_dense_setup(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
+            else issue_cg_init(c, cfgs[k].cg_tol, mi[k], cfgs[k].diag_shift);
+            st[k] = last_launch(c);
+            if (!st[k] && cand[k]) {
+                const hipError_t e = hipEventRecord(c->flag_ev[0], c->stream);
+                if (e != hipSuccess)
+                    st[k] = fail(c, NQS_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+            }
+        }
     // CG on every context side by side: each keeps a batch of iterations queued
     // (two when it runs alone; graph replays where the context allows them) and
     // its stop flag is read as soon as a batch has finished; the host blocks
@@ -1908,15 +2128,57 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
         run[k].init(ctxs[k], cfgs[k].qgt, cfgs[k].diag_shift, mi[k]);
         if (run[k].limit <= 0) active[k] = 0;
     }
+    // the candidates that are still fine run their iterations in grouped
+    // launches, up to CG_GROUP_MAX per group (at least two); every other context
+    // runs its own
+    std::vector<CgGroup> groups;
+    std::vector<int> gdone;
+    std::unique_lock<std::mutex> glock;
+    {
+        std::vector<int> gk;
+        for (int k = 0; k < n; ++k)
+            if (cand[k] && !st[k] && active[k]) gk.push_back(k);
+        if (gk.size() >= 2) {
+            GroupPool& pool = group_pool(gdev);
+            glock = std::unique_lock<std::mutex>(pool.m);
+            const hipError_t e = hipSetDevice(gdev);
+            for (size_t i0 = 0; e == hipSuccess && i0 + 1 < gk.size(); i0 += CG_GROUP_MAX) {
+                const size_t i1 = std::min(gk.size(), i0 + (size_t)CG_GROUP_MAX);
+                if (i1 - i0 < 2) break;  // (a lone remainder runs its own)
+                CgGroup g;
+                g.s = group_slot(pool, groups.size(), g.err);
+                if (!g.s) break;  // (the remaining contexts run their own)
+                int lim = 0;
+                for (size_t i = i0; i < i1; ++i) {
+                    g.members.push_back(ctxs[gk[i]]);
+                    lim = std::max(lim, run[gk[i]].limit);
+                    active[gk[i]] = 0;  // driven by the group
+                }
+                const bool started = g.start(lim);
+                if (!started)
+                    for (size_t i = i0; i < i1; ++i) st[gk[i]] = fail(ctxs[gk[i]], NQS_EDEVICE, g.err);
+                groups.push_back(std::move(g));
+                gdone.push_back(started ? 0 : 1);
+            }
+        }
+    }
+    auto group_failed = [&](size_t q) {
+        for (nqs_ctx* c : groups[q].all)
+            for (int k = 0; k < n; ++k)
+                if (ctxs[k] == c) st[k] = fail(c, NQS_EDEVICE, groups[q].err);
+        gdone[q] = 1;
+    };
     bool any = true;
     while (any) {
         any = false;
         bool progress_any = false;
-        int wait_on = -1;
+        int wait_on = -1, wait_group = -1;
         for (int k = 0; k < n; ++k) {
             if (st[k] || !active[k]) continue;
             st[k] = run[k].top_up(n > 1 ? 1 : 2);
         }
+        for (size_t q = 0; q < groups.size(); ++q)
+            if (!gdone[q] && !groups[q].top_up(2)) group_failed(q);
         for (int k = 0; k < n; ++k) {
             if (st[k] || !active[k]) continue;
             bool progress = false;
@@ -1929,12 +2191,35 @@ int nqs_batch_step(nqs_ctx* const* ctxs, int n, const nqs_step_cfg* cfgs, nqs_st
             any = true;
             if (wait_on < 0) wait_on = k;
         }
+        for (size_t q = 0; q < groups.size(); ++q) {
+            if (gdone[q]) continue;
+            bool progress = false;
+            if (!groups[q].poll(false, progress)) {
+                group_failed(q);
+                continue;
+            }
+            progress_any = progress_any || progress;
+            if (groups[q].finished()) {
+                gdone[q] = 1;
+                continue;
+            }
+            any = true;
+            if (wait_group < 0) wait_group = (int)q;
+        }
         if (any && !progress_any && wait_on >= 0) {
             bool progress = false;
             st[wait_on] = run[wait_on].poll(true, progress);
             if (st[wait_on] || run[wait_on].finished()) active[wait_on] = 0;
+        } else if (any && !progress_any && wait_group >= 0) {
+            bool progress = false;
+            CgGroup& g = groups[wait_group];
+            if (!g.poll(true, progress)) group_failed(wait_group);
+            else if (g.finished()) gdone[wait_group] = 1;
         }
     }
+    // the members' streams wait for their group's iterations
+    for (size_t q = 0; q < groups.size(); ++q)
+        if (!groups[q].finish()) group_failed(q);
     for (int k = 0; k < n; ++k) {
         if (st[k]) continue;
         nqs_ctx* c = ctxs[k];
@@ -2158,6 +2443,12 @@ int nqs_set_cg_graphs(nqs_ctx* c, int enable) {
     if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     c->graphs = enable != 0;
+    return NQS_OK;
+}
+
+int nqs_set_cg_grouping(nqs_ctx* c, int enable) {
+    if (!c) return NQS_EINVAL;
+    c->grouping = enable != 0;
     return NQS_OK;
 }
 

@@ -170,6 +170,53 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
                      double* r, double* p, double* p2, void* Rop, double* aux0, double* w, long n,
                      double tol, int maxiter, double shift, CgScalars* sc);
 
+// Grouped on-the-fly CG iterations (BF16 forms): the three iteration kernels
+// of up to CG_GROUP_MAX independent runs, one launch per kernel class (the
+// head + contraction-1 kernel: one launch per block size).  Each run keeps
+// its own blocks and fixed-order sums, so its results are those of its own
+// launches.  The table lives in device memory; cg_group_plan fills it.
+constexpr int CG_GROUP_MAX = 32;
+struct CgGroupRun {
+    Dims d;
+    long n, Nsp;
+    const void* Sp;
+    const void* St;
+    const float* Tf;
+    const void* Th;
+    void* Rop;
+    double* w;       // w = J v (and the contraction-2 source)
+    double* wpart;   // contraction-1 block partials
+    double* aux;     // head partials: two sets of 3 nbv, alternating with the iteration
+    void* part;      // contraction-2 chunk partials
+    double* papart;  // p . G p chunk partials
+    double *x, *r, *p, *p2;  // p and p2 alternate as the old and new direction
+    CgScalars* sc;
+    int32_t* host_flag;  // pinned: the stop flag after the last iteration of a batch
+    int nbv, nbw, ks, pad;
+};
+struct CgGroupTable {
+    int nrun;
+    // each run's first block in the launch of each class, ascending in table
+    // order, INT_MAX past the last run (the contraction-1 launches, one per
+    // block size, number their blocks on from one another)
+    int first_w[CG_GROUP_MAX], first_o[CG_GROUP_MAX], first_u[CG_GROUP_MAX];
+    CgGroupRun run[CG_GROUP_MAX];
+};
+// the launches of one grouped iteration
+struct CgGroupPlan {
+    int nw;  // contraction-1 launches: first block, blocks, block size
+    int w_base[CG_GROUP_MAX], w_blocks[CG_GROUP_MAX], w_threads[CG_GROUP_MAX];
+    int o_blocks, u_blocks;
+};
+// The run entries of t (t.nrun of them, with their operands set) are put in
+// order of contraction-1 block size and the block offsets are filled in.
+void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan);
+// One grouped iteration; par = iteration & 1 (which direction buffer and head
+// partial set is the old one); write_flag: the update stores each run's stop
+// flag in its host_flag.
+void launch_cg_group_iter(hipStream_t st, const CgGroupTable* t_dev, const CgGroupPlan& plan,
+                          int par, int write_flag);
+
 // dense.hip
 void launch_jacobian_centred(hipStream_t st, const Dims& d, int prec, const int8_t* s,
                              const void* tact, long n, void* O, int P, long ld, double* cs,

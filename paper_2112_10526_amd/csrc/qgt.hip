@@ -31,6 +31,7 @@
 #include "kernels.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace nqs {
 
@@ -572,14 +573,14 @@ constexpr int W7_ROWS = 64;
 // CG head from the three sums: stop test, beta and p.p; block 0 publishes.
 // Returns false when CG stops.
 __device__ __forceinline__ bool head_decide(double rr, double rp, double ppo, const HeadIn& h,
-                                            CgScalars* sc, double& beta) {
+                                            CgScalars* sc, double& beta, bool lead_block) {
     const int it = h.it;
     const double rr0 = it == 0 ? rr : h.rr0;
     const double tol2 = h.tol * h.tol * rr0;
     const bool stop = !(rr > tol2) || it >= h.maxiter || !isfinite(rr);
     beta = it == 0 ? 0.0 : rr / h.rr_prev;
     const double pp = rr + 2.0 * beta * rp + beta * beta * ppo;
-    if (blockIdx.x == 0 && (threadIdx.x & 63) == 0) {
+    if (lead_block && (threadIdx.x & 63) == 0) {
         sc->rr = rr;
         sc->iters = it;
         sc->beta = beta;
@@ -596,12 +597,13 @@ __device__ __forceinline__ bool head_decide(double rr, double rp, double ppo, co
     return !stop;
 }
 
-__global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__ Sp,
-                                             const float* __restrict__ Tf, long n,
-                                             const uint16_t* __restrict__ Ph,
-                                             double* __restrict__ w, double* __restrict__ wpart,
-                                             const double* __restrict__ aux, int nbv,
-                                             CgScalars* sc) {
+// (blk: the block's index within its run's grid)
+__device__ __forceinline__ void w7_block(Dims d, const uint8_t* __restrict__ Sp,
+                                         const float* __restrict__ Tf, long n,
+                                         const uint16_t* __restrict__ Ph,
+                                         double* __restrict__ w, double* __restrict__ wpart,
+                                         const double* __restrict__ aux, int nbv, CgScalars* sc,
+                                         int blk) {
     constexpr int RT = W7_ROWS / 16;
     constexpr int HB = 4;  // head partials per lane issued up front, per sum
     // the stop flag; it is tested once the first loads are in flight
@@ -610,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nw = (blockDim.x >> 6) - 1;  // contraction waves; wave nw runs the head
     const int lr = lane & 15, lk = lane >> 4;
-    const long r0 = (long)blockIdx.x * W7_ROWS;
+    const long r0 = (long)blk * W7_ROWS;
     const int Kq = d.Kq, KB2 = d.Kq / 2, nct = d.Ma / 16, ng = d.Kq / 128;
     if (wave == nw) {
         // ---- the CG head: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the update's
@@ -636,7 +638,7 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
             t[k] = wave_sum(a);
         }
         double beta;
-        const bool go = head_decide(t[0], t[1], t[2], hin, sc, beta);
+        const bool go = head_decide(t[0], t[1], t[2], hin, sc, beta, blk == 0);
         __syncthreads();
         if (!go) return;
         double v = 0.0;
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
         const long k = r0 + lane;
         if (k < n) w[k] = v;
         const double s = wave_sum(k < n ? v : 0.0);
-        if (lane == 0) wpart[blockIdx.x] = s;
+        if (lane == 0) wpart[blk] = s;
         return;
     }
     const uint16_t* Pl = Ph + (size_t)d.Ma * Kq;
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
                 // the activations (needed after the MFMAs) behind the MFMA operands
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
-                    tv[rt] = *(const float4*)(Tf + ((((size_t)blockIdx.x * nct + ct) * RT + rt) * 64 + lane) * 4);
+                    tv[rt] = *(const float4*)(Tf + ((((size_t)blk * nct + ct) * RT + rt) * 64 + lane) * 4);
                 if (first) {
                     asm volatile("" ::: "memory");  // the loads above go out before the stop test
                     if (done) return;               // (uniform over the block, before any barrier)
@@ -716,6 +718,15 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
     __syncthreads();
 }
 
+__global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__ Sp,
+                                             const float* __restrict__ Tf, long n,
+                                             const uint16_t* __restrict__ Ph,
+                                             double* __restrict__ w, double* __restrict__ wpart,
+                                             const double* __restrict__ aux, int nbv,
+                                             CgScalars* sc) {
+    w7_block(d, Sp, Tf, n, Ph, w, wpart, aux, nbv, sc, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // contraction 2: part[q][j][i] = sum_{k in range q} t~_kj z_k s~_ki
 // v_mode 0: z_k = (w_k - mean w) / n with mean w from the contraction-1
@@ -731,8 +742,8 @@ constexpr int NXCD = 8;
 constexpr int O16_KC = 512, O16_KP = O16_KC + 8;
 
 // block -> (hidden tile, chunk), chunks grouped by XCD
-__device__ __forceinline__ void outer_block(int nj, int& jt, int& kc) {
-    const int L = blockIdx.x, x = L % NXCD, m = L / NXCD;
+__device__ __forceinline__ void outer_block(int L, int nj, int& jt, int& kc) {
+    const int x = L % NXCD, m = L / NXCD;
     jt = m % nj;
     kc = x + NXCD * (m / nj);
 }
@@ -971,13 +982,14 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
 // of w in the same order, so no barrier precedes the staging); for the
 // contraction, wave w takes site tiles w, w + 8, ...
 constexpr int O8_THREADS = 512;
-__global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8(Dims d, const uint8_t* __restrict__ St,
-                                                       const float* __restrict__ Th, long Nsp, long n,
-                                                       const double* __restrict__ v, int v_mode,
-                                                       const double* __restrict__ wpart, int nbw,
-                                                       float* __restrict__ part, int ksplit,
-                                                       double* __restrict__ papart,
-                                                       const CgScalars* __restrict__ sc) {
+// (blk: the block's index within its run's grid)
+__device__ __forceinline__ void outer8_block(Dims d, const uint8_t* __restrict__ St,
+                                             const float* __restrict__ Th, long Nsp, long n,
+                                             const double* __restrict__ v, int v_mode,
+                                             const double* __restrict__ wpart, int nbw,
+                                             float* __restrict__ part, int ksplit,
+                                             double* __restrict__ papart,
+                                             const CgScalars* __restrict__ sc, int blk) {
     // stop flag of the CG product, tested once the block's loads are in flight
     const int done = v_mode == 0 ? sc->done : 0;
     constexpr int KC = O16_KC, KP = O16_KP;
@@ -986,7 +998,7 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ double sh[NW];
     const int nj = d.Ma / 16;
     int jt, kc;
-    outer_block(nj, jt, kc);
+    outer_block(blk, nj, jt, kc);
     if (kc >= ksplit) return;  // no chunk for this block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -1071,6 +1083,16 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
         for (int q = 0; q < 4; ++q)
             out[(size_t)(jt * 16 + acc_row<float>(lk, q)) * d.Na + it * 16 + lr] = acc[q] + acc2[q];
     }
+}
+
+__global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8(Dims d, const uint8_t* __restrict__ St,
+                                                       const float* __restrict__ Th, long Nsp, long n,
+                                                       const double* __restrict__ v, int v_mode,
+                                                       const double* __restrict__ wpart, int nbw,
+                                                       float* __restrict__ part, int ksplit,
+                                                       double* __restrict__ papart,
+                                                       const CgScalars* __restrict__ sc) {
+    outer8_block(d, St, Th, Nsp, n, v, v_mode, wpart, nbw, part, ksplit, papart, sc, blockIdx.x);
 }
 
 // out[e] = sum_kc part[kc][e] + shift p[e] (parameter entries only); with p,
@@ -1220,15 +1242,16 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int
 // lane (FP32 chunk partial pairs; FP64 vectors as pairs), the residual
 // written to the contraction-1 operand as its two BF16 terms in fragment
 // order (pfrag_off).
-__global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int ksplit, double* x,
-                                                 double* r, const double* p_old, double* p_new,
-                                                 uint16_t* Rop, const double* papart, int npa,
-                                                 double* aux_next, int nbv, CgScalars* sc,
-                                                 volatile int32_t* host_flag) {
+// (blk: the block's index within its run's grid)
+__device__ __forceinline__ void update5_block(Dims d, const float* part, int ksplit, double* x,
+                                              double* r, const double* p_old, double* p_new,
+                                              uint16_t* Rop, const double* papart, int npa,
+                                              double* aux_next, int nbv, CgScalars* sc,
+                                              volatile int32_t* host_flag, int blk) {
     __shared__ double2 ws[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int total = d.Ma * d.Na;  // even (Na is a multiple of 16)
-    const int e = blockIdx.x * 128 + 2 * lane;
+    const int e = blk * 128 + 2 * lane;
     const int ec = e < total ? e : total - 2;
     // every load that does not depend on the scalars, issued up front
     const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
@@ -1245,7 +1268,7 @@ __global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int 
     const int done = sc->done;
     const double shift = sc->shift, rr = sc->rr, beta = sc->beta, pp = sc->pp;
     asm volatile("" ::: "memory");  // keep the loads above ahead of the stop test
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = blk == 0 && threadIdx.x == 0;
     if (done) {
         if (host_flag && lead) *host_flag = 1;
         return;
@@ -1318,8 +1341,62 @@ __global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int 
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double v = wave_sum(q[k]);
-        if (lane == 0) aux_next[(size_t)k * nbv + blockIdx.x] = v;
+        if (lane == 0) aux_next[(size_t)k * nbv + blk] = v;
     }
+}
+
+__global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int ksplit, double* x,
+                                                 double* r, const double* p_old, double* p_new,
+                                                 uint16_t* Rop, const double* papart, int npa,
+                                                 double* aux_next, int nbv, CgScalars* sc,
+                                                 volatile int32_t* host_flag) {
+    update5_block(d, part, ksplit, x, r, p_old, p_new, Rop, papart, npa, aux_next, nbv, sc,
+                  host_flag, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped CG iterations (BF16 forms): one launch of a kernel class runs the
+// blocks of several independent runs.  Block b of a launch belongs to the run
+// r with first[r] <= b < first[r + 1] and runs as block b - first[r] of that
+// run's own launch, on that run's operands (table entry r): every run keeps
+// its own blocks and its own fixed-order sums.  Contraction-2 block counts
+// are multiples of 8, so every run's blocks keep their XCD placement.  The
+// contraction-1 launches (one per block size) number their blocks on from
+// one another (base: the launch's first block).
+// ---------------------------------------------------------------------------
+// the run of block b (first[] ascending, padded with INT_MAX past the last
+// run; every entry is read, so the reads go out together)
+__device__ __forceinline__ int group_run(const int* __restrict__ first, int b) {
+    int r = 0;
+#pragma unroll
+    for (int i = 1; i < CG_GROUP_MAX; ++i) r += first[i] <= b ? 1 : 0;
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_w7_group(const CgGroupTable* __restrict__ t, int base,
+                                                   int par) {
+    const int b = base + (int)blockIdx.x;
+    const int r = group_run(t->first_w, b);
+    const CgGroupRun& R = t->run[r];
+    w7_block(R.d, (const uint8_t*)R.Sp, R.Tf, R.n, (const uint16_t*)R.Rop, R.w, R.wpart,
+             R.aux + (size_t)par * 3 * R.nbv, R.nbv, R.sc, b - t->first_w[r]);
+}
+
+__global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8_group(
+    const CgGroupTable* __restrict__ t) {
+    const int r = group_run(t->first_o, blockIdx.x);
+    const CgGroupRun& R = t->run[r];
+    outer8_block(R.d, (const uint8_t*)R.St, (const float*)R.Th, R.Nsp, R.n, R.w, 0, R.wpart,
+                 R.nbw, (float*)R.part, R.ks, R.papart, R.sc, blockIdx.x - t->first_o[r]);
+}
+
+__global__ __launch_bounds__(256) void k_update5_group(const CgGroupTable* __restrict__ t, int par,
+                                                       int write_flag) {
+    const int r = group_run(t->first_u, blockIdx.x);
+    const CgGroupRun& R = t->run[r];
+    update5_block(R.d, (const float*)R.part, R.ks, R.x, R.r, par ? R.p2 : R.p, par ? R.p : R.p2,
+                  (uint16_t*)R.Rop, R.papart, R.ks, R.aux + (size_t)(par ^ 1) * 3 * R.nbv, R.nbv,
+                  R.sc, write_flag ? R.host_flag : nullptr, blockIdx.x - t->first_u[r]);
 }
 
 // CG start (x0 = 0): r = f, both direction buffers 0, r in the contraction-1
@@ -1558,6 +1635,52 @@ void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& 
     else
         k_update5<<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new,
                                       (uint16_t*)Rop, papart, npa, aux_next, nb, sc, host_flag);
+}
+
+void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
+    const int n = t.nrun;
+    int th[CG_GROUP_MAX];
+    for (int r = 0; r < n; ++r) {
+        int waves, per;
+        wave_split(t.run[r].d.Ma / 16, 15, waves, per);
+        th[r] = 64 * (waves + 1);  // one more wave for the CG head
+    }
+    // runs in order of contraction-1 block size (stable: ties keep their order)
+    for (int r = 1; r < n; ++r)
+        for (int q = r; q > 0 && th[q - 1] > th[q]; --q) {
+            std::swap(th[q - 1], th[q]);
+            std::swap(t.run[q - 1], t.run[q]);
+        }
+    plan.nw = 0;
+    int bw = 0, bo = 0, bu = 0;
+    for (int r = 0; r < n; ++r) {
+        const CgGroupRun& R = t.run[r];
+        if (r == 0 || th[r] != th[r - 1]) {
+            plan.w_base[plan.nw] = bw;
+            plan.w_blocks[plan.nw] = 0;
+            plan.w_threads[plan.nw] = th[r];
+            ++plan.nw;
+        }
+        const int nb = qgt_nbw(R.n, 1);
+        t.first_w[r] = bw;
+        bw += nb;
+        plan.w_blocks[plan.nw - 1] += nb;
+        t.first_o[r] = bo;
+        bo += NXCD * (R.d.Ma / 16) * ((R.ks + NXCD - 1) / NXCD);
+        t.first_u[r] = bu;
+        bu += qgt_nbv(R.d, 1);
+    }
+    for (int r = n; r < CG_GROUP_MAX; ++r) t.first_w[r] = t.first_o[r] = t.first_u[r] = INT_MAX;
+    plan.o_blocks = bo;
+    plan.u_blocks = bu;
+}
+
+void launch_cg_group_iter(hipStream_t st, const CgGroupTable* t_dev, const CgGroupPlan& plan,
+                          int par, int write_flag) {
+    for (int g = 0; g < plan.nw; ++g)
+        k_w7_group<<<plan.w_blocks[g], plan.w_threads[g], 0, st>>>(t_dev, plan.w_base[g], par);
+    k_outer8_group<<<plan.o_blocks, O8_THREADS, 0, st>>>(t_dev);
+    k_update5_group<<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
 }
 
 }  // namespace nqs

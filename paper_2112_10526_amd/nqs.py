@@ -425,6 +425,16 @@ VMCState.profile_read = _profile_read
 VMCState.set_cg_graphs = _set_cg_graphs
 
 
+def _set_cg_grouping(self, enable: bool = True) -> None:
+    """Let batch_step run this run's on-the-fly CG iterations in launches
+    grouped with the other runs of the step (default; BF16 and FP32 forms) or
+    make it run its own launches.  The results are identical either way."""
+    self._check(self.lib.nqs_set_cg_grouping(self.ctx, 1 if enable else 0))
+
+
+VMCState.set_cg_grouping = _set_cg_grouping
+
+
 def _step_cfg(c: dict) -> NqsStepCfg:
     return NqsStepCfg(_lib.QGTS[c.get("qgt", "onthefly")], c.get("diag_shift", 0.01),
                       c.get("lr", 0.01), c.get("tol", 1e-6), c.get("maxiter", 0))

@@ -11,8 +11,10 @@ samples per step, number of SR steps).  The server
     own device workspace until the run finishes, then frees it;
   * advances the resident runs on their own HIP streams, so the runs' kernels
     overlap on the device.  Default (mode "tick"): all resident runs advance by
-    one SR step per tick with ``nqs_batch_step``; mode "async": every run starts
-    its next SR step as soon as its previous one has finished
+    one SR step per tick with ``nqs_batch_step``, whose on-the-fly CG runs the
+    iterations of all resident BF16/FP32-form runs as one launch per kernel
+    class (``grouping``; off: each run launches its own); mode "async": every
+    run starts its next SR step as soon as its previous one has finished
     (``nqs_step_begin`` / ``nqs_step_poll``), with no barrier between runs.
 
 Every run's arithmetic is independent of the others (its own Philox stream,
@@ -71,10 +73,11 @@ class Server:
                  precision: str = "bf16", device: int = 0, thermalize_segments: int = 20,
                  diag_shift: float = 0.01, lr: float = 0.01, cg_tol: float = 1e-6,
                  keep_params: bool = False, state_factory=None, step_fn=None, streams=None,
-                 mode: str = "tick", begin_fn=None, poll_fn=None):
+                 mode: str = "tick", begin_fn=None, poll_fn=None, grouping: bool = True):
         if mode not in ("async", "tick"):
             raise ValueError(f"unknown serving mode {mode!r}")
         self.mode = mode
+        self.grouping = grouping
         self.begin = begin_fn or step_begin
         self.poll = poll_fn or step_poll
         self.budget = int(hbm_budget)
@@ -183,6 +186,8 @@ class Server:
             req = pending[0]
             stream = self.streams[req.id % len(self.streams)]
             st = self.make_state(req, stream)
+            if not self.grouping:
+                st.set_cg_grouping(False)
             fp = st.workspace_bytes
             if fp > self.budget:
                 results[req.id].error = f"footprint {fp} B exceeds the budget {self.budget} B"

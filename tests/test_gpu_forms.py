@@ -123,6 +123,61 @@ def test_serving_result_same_alone_and_in_mix(precision):
     assert tight["peak_hbm_bytes"] <= max(x.footprint for x in alone.values()) + 1
 
 
+def _batch_run(reqs, precisions, steps, grouping):
+    """Every request as its own state (4 streams), `steps` batched SR steps;
+    per run: the step energies, CG iteration counts and final parameters."""
+    torch = _torch()
+    from paper_2112_10526_amd.nqs import VMCState, batch_step
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    sts = []
+    for k, (r, prec) in enumerate(zip(reqs, precisions)):
+        st = VMCState.from_workload(r.workload(prec), stream=streams[k % 4], allocate=False)
+        st.bind()
+        st.thermalize(3)
+        st.set_cg_grouping(grouping)
+        sts.append(st)
+    cfg = dict(diag_shift=0.01, lr=0.01, tol=1e-6)
+    out = [([], []) for _ in reqs]
+    for _ in range(steps):
+        for k, rep in enumerate(batch_step(sts, [cfg] * len(sts))):
+            out[k][0].append(rep.energy["mean"])
+            out[k][1].append(rep.sr.iterations)
+    res = [(e, it, st.get_params()) for (e, it), st in zip(out, sts)]
+    for st in sts:
+        st.close()
+    return res
+
+
+# grouped CG launches against each run's own launches: runs of five different
+# contraction-1 block sizes, with an FP64 run and a run too large to group
+# (10x10, alpha 2, 16,384 samples) among them, and 34 BF16 runs (two groups: 32
+# and 2)
+@pytest.mark.parametrize("case", ["mixed_shapes", "two_groups"])
+def test_grouped_cg_same_as_own_launches(case):
+    from paper_2112_10526_amd.serving import Request
+    if case == "mixed_shapes":
+        shapes = [(4, 1, 1024), (6, 2, 2048), (5, 4, 1024), (7, 1, 4096), (8, 4, 2048),
+                  (6, 2, 1024), (4, 4, 2048), (10, 2, 16384)]
+        precs = ["bf16", "bf16", "bf16", "bf16", "bf16", "fp64", "fp32", "bf16"]
+        steps = 3
+    else:
+        shapes = [(4 + k % 3, 1 + k % 2, 1024) for k in range(34)]
+        precs = ["bf16"] * 34
+        steps = 2
+    reqs = [Request(k, 0.0, L, 0.5 + 0.25 * k, a, ns, steps, 100 + k, 200 + k)
+            for k, (L, a, ns) in enumerate(shapes)]
+    print(f"[case] grouped CG {case}: {len(reqs)} runs", flush=True)
+    own = _batch_run(reqs, precs, steps, grouping=False)
+    grp = _batch_run(reqs, precs, steps, grouping=True)
+    iters = set()
+    for k, ((e0, i0, p0), (e1, i1, p1)) in enumerate(zip(own, grp)):
+        assert e1 == e0, k
+        assert i1 == i0, k
+        np.testing.assert_array_equal(p1, p0)
+        iters.update(i0)
+    assert len(iters) > 1  # the runs stop at different iterations
+
+
 @pytest.mark.parametrize("mode", ["tick", "async"])
 def test_serving_poisson_stream_smoke(mode):
     _torch()
