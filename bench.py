@@ -377,7 +377,7 @@ def precision_form_measure(torch, steps=5, warmup=1):
 
 
 def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), seed=7,
-                  budget_gib=32, slots=32):
+                  budget_gib=32, slots=32, only=None):
     """Serving form: a seeded stream of VMC runs (2D TFIM L x L, L ~ U{4..20},
     h ~ U[0.5, 4], alpha in {1, 2, 4}, 1024..16384 samples per step, BF16 form,
     n_steps SR steps each) through the continuous-batching server.
@@ -393,8 +393,13 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
     arrivals at offered loads rho * mu, served in real time in lock-step
     ticks.  Each pass reports aggregate local energies/s, p50/p99
     SR-step latency, queueing delay, time in system, mean residency and peak HBM
-    footprint."""
+    footprint.  only: names of the passes to run (all by default; the Poisson
+    passes need the one-at-a-time pass, which then runs too)."""
     from paper_2112_10526_amd.serving import Server, requests_from_stream
+    rho_names = [f"poisson_rho_{rho}" for rho in loads]
+
+    def want(name):
+        return only is None or name in only
     budget = budget_gib << 30
 
     def summary(out):
@@ -419,35 +424,45 @@ def serve_measure(torch, n_runs=256, n_steps=10, loads=(0.5, 0.9, 1.5, 3.0), see
             last[0] = now
             print(f"[bench] serving: {done}/{total} runs finished, {steps} SR steps",
                   file=sys.stderr, flush=True)
-    serial = Server(budget, max_slots=1).serve(base, realtime=False, progress=progress)
-    passes["one_at_a_time"] = summary(serial)
-    print(f"[bench] serving one at a time: {serial['wall_s']:.2f} s", file=sys.stderr, flush=True)
-    mu = n_runs / serial["wall_s"]
+    mu = None
+    if want("one_at_a_time") or any(want(x) for x in rho_names):
+        serial = Server(budget, max_slots=1).serve(base, realtime=False, progress=progress)
+        passes["one_at_a_time"] = summary(serial)
+        print(f"[bench] serving one at a time: {serial['wall_s']:.2f} s", file=sys.stderr,
+              flush=True)
+        mu = n_runs / serial["wall_s"]
     for mode in ("tick", "async"):
+        if not want(f"all_present_{mode}"):
+            continue
         cap = Server(budget, max_slots=slots, mode=mode).serve(base, realtime=False,
                                                                progress=progress)
         passes[f"all_present_{mode}"] = summary(cap)
         print(f"[bench] serving all present, {mode}: {cap['wall_s']:.2f} s", file=sys.stderr,
               flush=True)
     # lock-step ticks with every run's CG iterations in its own launches
-    own = Server(budget, max_slots=slots, grouping=False).serve(base, realtime=False,
-                                                                progress=progress)
-    passes["all_present_tick_own_launches"] = summary(own)
-    print(f"[bench] serving all present, tick, own CG launches: {own['wall_s']:.2f} s",
-          file=sys.stderr, flush=True)
+    if want("all_present_tick_own_launches"):
+        own = Server(budget, max_slots=slots, grouping=False).serve(base, realtime=False,
+                                                                    progress=progress)
+        passes["all_present_tick_own_launches"] = summary(own)
+        print(f"[bench] serving all present, tick, own CG launches: {own['wall_s']:.2f} s",
+              file=sys.stderr, flush=True)
     # small runs only (L 4..8, 1024..4096 samples, every one of them small enough
     # to group), grouped and in their own launches
     small = [dataclasses.replace(r, arrival=0.0)
              for r in requests_from_stream(n_runs // 2, seed, 1.0, n_steps=n_steps,
                                            L_range=(4, 8), samples=(1024, 2048, 4096))]
     for grouping in (True, False):
+        key = "small_runs_tick" + ("" if grouping else "_own_launches")
+        if not want(key):
+            continue
         out = Server(budget, max_slots=slots, grouping=grouping).serve(small, realtime=False,
                                                                        progress=progress)
-        key = "small_runs_tick" + ("" if grouping else "_own_launches")
         passes[key] = summary(out)
         print(f"[bench] serving small runs, tick, grouping={grouping}: {out['wall_s']:.2f} s",
               file=sys.stderr, flush=True)
-    for rho in loads:
+    for rho, name in zip(loads, rho_names):
+        if not want(name):
+            continue
         reqs = requests_from_stream(n_runs, seed, rho * mu, n_steps=n_steps)
         out = Server(budget, max_slots=slots).serve(reqs, realtime=True, progress=progress)
         passes[f"poisson_rho_{rho}"] = dict(summary(out), offered_rate_runs_per_s=rho * mu)
@@ -779,6 +794,8 @@ def main():
                     help="measure the continuous-batching server on a Poisson stream of runs")
     ap.add_argument("--serve-runs", type=int, default=256)
     ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-passes", default="",
+                    help="comma-separated serving passes to run (default: all)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -798,7 +815,9 @@ def main():
         print(json.dumps(precision_form_measure(torch)), flush=True)
         return
     if args.serve:
-        print(json.dumps(serve_measure(torch, args.serve_runs, args.serve_steps)), flush=True)
+        only = set(x for x in args.serve_passes.split(",") if x) or None
+        print(json.dumps(serve_measure(torch, args.serve_runs, args.serve_steps, only=only)),
+              flush=True)
         return
     if args.paper_workload:
         print(json.dumps(paper_workload_measure(torch)), flush=True)

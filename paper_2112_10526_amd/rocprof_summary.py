@@ -262,7 +262,25 @@ def summarize_stats(stats_csv, cmd, title):
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} | "
                    f"{c} | {m:.2f} |")
+    if os.path.exists(trace):
+        span, busy, n = _trace_span(trace)
+        out += ["", f"Trace: {n} launches; span from the first start to the last end "
+                    f"{span / 1e6:.1f} ms; kernel time summed over all streams {busy / 1e6:.1f} ms "
+                    f"({100.0 * busy / span:.0f} % of the span)."]
     print("\n".join(out))
+
+
+def _trace_span(trace_csv):
+    import csv
+    t0, t1, busy, n = None, None, 0, 0
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            t0 = a if t0 is None else min(t0, a)
+            t1 = b if t1 is None else max(t1, b)
+            busy += b - a
+            n += 1
+    return (t1 - t0 if n else 0), busy, n
 
 
 def main(argv=None):
