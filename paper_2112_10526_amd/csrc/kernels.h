@@ -207,6 +207,7 @@ struct CgGroupPlan {
     int nw;  // contraction-1 launches: first block, blocks, block size
     int w_base[CG_GROUP_MAX], w_blocks[CG_GROUP_MAX], w_threads[CG_GROUP_MAX];
     int o_blocks, u_blocks;
+    int u_sw;  // update: slot slabs per wave loaded up front (the largest the runs need)
 };
 // The run entries of t (t.nrun of them, with their operands set) are put in
 // order of contraction-1 block size and the block offsets are filled in.

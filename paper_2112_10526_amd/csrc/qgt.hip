@@ -31,6 +31,7 @@
 #include "kernels.h"
 
 #include <type_traits>
+#include <algorithm>
 #include <utility>
 
 namespace nqs {
@@ -1153,6 +1154,9 @@ __global__ __launch_bounds__(256) void k_reduce3(Dims d, const R* __restrict__ p
 // partials of r.r, r.p_it, p_it.p_it for the next head.  Block 0 advances the
 // iteration index and, when given a pinned host word, stores the stop flag
 // there (the last update of a batch of iterations does).
+// SW: slot slabs per wave loaded up front (at least ceil(ksplit / 4) where that
+// is at most 16; further slabs are read in the loop that follows)
+template <int SW>
 __global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int ksplit, double* x,
                                                  double* r, const double* p_old, double* p_new,
                                                  void* Rop, const double* papart, int npa,
@@ -1165,9 +1169,9 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int
     const int ec = e < total ? e : total - 1;
     // every load that does not depend on the scalars, issued up front
     const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
-    double xs[16];
+    double xs[SW];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
+    for (int u = 0; u < SW; ++u) xs[u] = part[(size_t)min(kb + u, ksplit - 1) * total + ec];
     const double xe = x[ec], re0 = r[ec], po = p_old[ec];
     double xa[4];  // p.Gp chunk partials lane, lane + 64, ... (summed by wave 0)
 #pragma unroll
@@ -1183,9 +1187,9 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int
     }
     double val = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < SW; ++u)
         if (kb + u < ke) val += (double)xs[u];
-    for (int kc = kb + 16; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
+    for (int kc = kb + SW; kc < ke; ++kc) val += (double)part[(size_t)kc * total + ec];
     ws[wave][lane] = val;
     __syncthreads();
     if (wave != 0) return;  // waves 1-3 only summed chunk slabs
@@ -1242,7 +1246,8 @@ __global__ __launch_bounds__(256) void k_update4(Dims d, const double* part, int
 // lane (FP32 chunk partial pairs; FP64 vectors as pairs), the residual
 // written to the contraction-1 operand as its two BF16 terms in fragment
 // order (pfrag_off).
-// (blk: the block's index within its run's grid)
+// (blk: the block's index within its run's grid; SW as for k_update4)
+template <int SW>
 __device__ __forceinline__ void update5_block(Dims d, const float* part, int ksplit, double* x,
                                               double* r, const double* p_old, double* p_new,
                                               uint16_t* Rop, const double* papart, int npa,
@@ -1255,9 +1260,9 @@ __device__ __forceinline__ void update5_block(Dims d, const float* part, int ksp
     const int ec = e < total ? e : total - 2;
     // every load that does not depend on the scalars, issued up front
     const int kb = wave * ksplit / 4, ke = (wave + 1) * ksplit / 4;
-    float2 xs[16];
+    float2 xs[SW];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < SW; ++u)
         xs[u] = *(const float2*)(part + (size_t)min(kb + u, ksplit - 1) * total + ec);
     const double2 xe = *(const double2*)(x + ec), re0 = *(const double2*)(r + ec),
                   po = *(const double2*)(p_old + ec);
@@ -1275,12 +1280,12 @@ __device__ __forceinline__ void update5_block(Dims d, const float* part, int ksp
     }
     double v0 = 0.0, v1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < SW; ++u)
         if (kb + u < ke) {
             v0 += (double)xs[u].x;
             v1 += (double)xs[u].y;
         }
-    for (int kc = kb + 16; kc < ke; ++kc) {
+    for (int kc = kb + SW; kc < ke; ++kc) {
         const float2 t = *(const float2*)(part + (size_t)kc * total + ec);
         v0 += (double)t.x;
         v1 += (double)t.y;
@@ -1345,13 +1350,14 @@ __device__ __forceinline__ void update5_block(Dims d, const float* part, int ksp
     }
 }
 
+template <int SW>
 __global__ __launch_bounds__(256) void k_update5(Dims d, const float* part, int ksplit, double* x,
                                                  double* r, const double* p_old, double* p_new,
                                                  uint16_t* Rop, const double* papart, int npa,
                                                  double* aux_next, int nbv, CgScalars* sc,
                                                  volatile int32_t* host_flag) {
-    update5_block(d, part, ksplit, x, r, p_old, p_new, Rop, papart, npa, aux_next, nbv, sc,
-                  host_flag, blockIdx.x);
+    update5_block<SW>(d, part, ksplit, x, r, p_old, p_new, Rop, papart, npa, aux_next, nbv, sc,
+                      host_flag, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1390,11 +1396,12 @@ __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
                  R.nbw, (float*)R.part, R.ks, R.papart, R.sc, blockIdx.x - t->first_o[r]);
 }
 
+template <int SW>
 __global__ __launch_bounds__(256) void k_update5_group(const CgGroupTable* __restrict__ t, int par,
                                                        int write_flag) {
     const int r = group_run(t->first_u, blockIdx.x);
     const CgGroupRun& R = t->run[r];
-    update5_block(R.d, (const float*)R.part, R.ks, R.x, R.r, par ? R.p2 : R.p, par ? R.p : R.p2,
+    update5_block<SW>(R.d, (const float*)R.part, R.ks, R.x, R.r, par ? R.p2 : R.p, par ? R.p : R.p2,
                   (uint16_t*)R.Rop, R.papart, R.ks, R.aux + (size_t)(par ^ 1) * 3 * R.nbv, R.nbv,
                   R.sc, write_flag ? R.host_flag : nullptr, blockIdx.x - t->first_u[r]);
 }
@@ -1624,17 +1631,37 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
 
 int qgt_nbo(const Dims& d, const QgtBatch& q) { return qgt_ksplit(q); }
 
+// slot slabs per wave the update loads up front for ks slots (4 waves)
+static int update_sw(int ks) {
+    const int per = (ks + 3) / 4;
+    return per <= 4 ? 4 : per <= 8 ? 8 : per <= 12 ? 12 : 16;
+}
+
 void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& q,
                        const void* part, double* x, double* r, const double* p_old,
                        double* p_new, void* Rop, const double* papart, double* aux_next,
                        CgScalars* sc, int32_t* host_flag) {
     const int nb = qgt_nbv(d, prec), ks = qgt_ksplit(q), npa = qgt_nbo(d, q);
-    if (prec == 0)
-        k_update4<<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop, papart,
-                                      npa, aux_next, nb, sc, host_flag);
-    else
-        k_update5<<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new,
-                                      (uint16_t*)Rop, papart, npa, aux_next, nb, sc, host_flag);
+#define U4(SW)                                                                                 \
+    k_update4<SW><<<nb, 256, 0, st>>>(d, (const double*)part, ks, x, r, p_old, p_new, Rop,   \
+                                      papart, npa, aux_next, nb, sc, host_flag)
+#define U5(SW)                                                                                 \
+    k_update5<SW><<<nb, 256, 0, st>>>(d, (const float*)part, ks, x, r, p_old, p_new,         \
+                                      (uint16_t*)Rop, papart, npa, aux_next, nb, sc, host_flag)
+    const int sw = update_sw(ks);
+    if (prec == 0) {
+        if (sw == 4) U4(4);
+        else if (sw == 8) U4(8);
+        else if (sw == 12) U4(12);
+        else U4(16);
+    } else {
+        if (sw == 4) U5(4);
+        else if (sw == 8) U5(8);
+        else if (sw == 12) U5(12);
+        else U5(16);
+    }
+#undef U4
+#undef U5
 }
 
 void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
@@ -1652,6 +1679,7 @@ void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
             std::swap(t.run[q - 1], t.run[q]);
         }
     plan.nw = 0;
+    plan.u_sw = 4;
     int bw = 0, bo = 0, bu = 0;
     for (int r = 0; r < n; ++r) {
         const CgGroupRun& R = t.run[r];
@@ -1669,6 +1697,7 @@ void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
         bo += NXCD * (R.d.Ma / 16) * ((R.ks + NXCD - 1) / NXCD);
         t.first_u[r] = bu;
         bu += qgt_nbv(R.d, 1);
+        plan.u_sw = std::max(plan.u_sw, update_sw(R.ks));
     }
     for (int r = n; r < CG_GROUP_MAX; ++r) t.first_w[r] = t.first_o[r] = t.first_u[r] = INT_MAX;
     plan.o_blocks = bo;
@@ -1680,7 +1709,10 @@ void launch_cg_group_iter(hipStream_t st, const CgGroupTable* t_dev, const CgGro
     for (int g = 0; g < plan.nw; ++g)
         k_w7_group<<<plan.w_blocks[g], plan.w_threads[g], 0, st>>>(t_dev, plan.w_base[g], par);
     k_outer8_group<<<plan.o_blocks, O8_THREADS, 0, st>>>(t_dev);
-    k_update5_group<<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
+    if (plan.u_sw == 4) k_update5_group<4><<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
+    else if (plan.u_sw == 8) k_update5_group<8><<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
+    else if (plan.u_sw == 12) k_update5_group<12><<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
+    else k_update5_group<16><<<plan.u_blocks, 256, 0, st>>>(t_dev, par, write_flag);
 }
 
 }  // namespace nqs
