@@ -147,10 +147,10 @@ def summarize_waves(counter_dir, cmd,
            "over waves.", "",
            "| kernel | waves | wave cycles / wave | wait (memory) % | wait (issue) % | active % |",
            "|---|---:|---:|---:|---:|---:|"]
-    for name in ["nqs::k_w7", "nqs::k_outer8", "nqs::k_update5",
+    for name in ["nqs::k_w7", "nqs::k_outer8", "nqs::k_update5<",
                  "nqs::k_sample<float, 4, 0, 2>", "nqs::k_sample<float, 16, 1, 1>",
                  "nqs::k_eloc<float, 0>", "nqs::k_eloc<float, 1>", "nqs::k_theta_bf16",
-                 "nqs::k_w5", "nqs::k_outer9<", "nqs::k_update4",
+                 "nqs::k_w5", "nqs::k_outer9<", "nqs::k_update4<",
                  "nqs::k_sample<double, 4, 0, 2>", "nqs::k_sample<double, 16, 1, 1>",
                  "nqs::k_eloc<double, 0>", "nqs::k_eloc<double, 1>", "nqs::k_theta<double>"]:
         # (a name ending in "<" stands for every instantiation of that template)
