@@ -77,7 +77,8 @@ def test_header_is_plain_c():
 def test_plain_c_program_links_and_calls(tmp_path):
     """A plain C program includes the header, links libnqs and calls it: without a
     device, nqs_create returns NQS_EINVAL and leaves the context null; the null-context
-    queries answer as documented."""
+    queries answer as documented, nqs_set_cg_grouping rejects a null context and an
+    empty batched step succeeds without touching a device."""
     import shutil
     import subprocess
     from paper_2112_10526_amd import _lib
@@ -94,6 +95,7 @@ def test_plain_c_program_links_and_calls(tmp_path):
         "    nqs_ctx* ctx = 0;\n"
         "    int st = nqs_create(&ctx, 0, 0);\n"
         '    printf("%d %d %s %zu\\n", st, ctx == 0, nqs_last_error(0), nqs_num_params(0));\n'
+        '    printf("%d %d\\n", nqs_set_cg_grouping(0, 1), nqs_batch_step(&ctx, 0, 0, 0));\n'
         "    return 0;\n}\n")
     libdir = os.path.dirname(_lib.LIB_PATH)
     exe = tmp_path / "main"
@@ -103,8 +105,10 @@ def test_plain_c_program_links_and_calls(tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
-    st, null_ctx, msg = r.stdout.split()[:3]
+    lines = r.stdout.strip().splitlines()
+    st, null_ctx, msg = lines[0].split()[:3]
     # no device visible here: NQS_EINVAL (a GPU machine would create the context)
     if st != "0":
         assert int(st) == _lib.NQS_EINVAL and null_ctx == "1"
-    assert r.stdout.strip().endswith("null context 0")
+    assert lines[0].endswith("null context 0")
+    assert lines[1].split() == [str(_lib.NQS_EINVAL), str(_lib.NQS_OK)]
