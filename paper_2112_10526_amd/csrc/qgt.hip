@@ -754,67 +754,72 @@ __device__ __forceinline__ void outer_block(int L, int nj, int& jt, int& kc) {
 // w + nwa, ...), and the q-th of ks near-equal ranges of 16-sample units (ks
 // chosen so that the blocks fill the CUs in one round, all with the same
 // work: two 512-thread blocks or one 1024-thread block per CU).
-// The range streams through LDS in sub-chunks of 128 samples: while the
-// matrix cores take a = t~ z of the current sub-chunk from LDS, the next
-// sub-chunk's t~ and z source and the spins are loaded; every wave keeps the
-// sums of its site tiles in registers over the whole range.  The FP64 MFMA
-// takes A = a and B = the int8 spins as +1 / -1 (0 on padding sites); within
-// 16 samples, k-step e of lane quad lk takes sample 4 lk + e.
-constexpr int O9_SC = 128;           // samples per sub-chunk
-constexpr int O9_LD = O9_SC + 1;     // doubles between staged rows (odd)
-constexpr int O9_NU = O9_SC / 16;    // 16-sample units per sub-chunk
-constexpr int O9_PIECES = 16 * O9_SC / 2;  // 16-byte staging units of a sub-chunk
+// The range streams through LDS in sub-chunks of SC samples (64 in 512-thread
+// blocks, 128 in 1,024-thread blocks: every thread stages at least one 16-byte
+// unit; shorter sub-chunks start the matrix cores sooner): while the matrix
+// cores take a = t~ z of the current sub-chunk from LDS, the next sub-chunk's
+// t~ and z source and the spins are loaded; every wave keeps the sums of its
+// site tiles in registers over the whole range.  The FP64 MFMA takes A = a and
+// B = the int8 spins as +1 / -1 (0 on padding sites); within 16 samples,
+// k-step e of lane quad lk takes sample 4 lk + e.
+template <int SC>
+struct O9 {
+    static constexpr int LD = SC + 1;       // doubles between staged rows (odd)
+    static constexpr int NU = SC / 16;      // 16-sample units per sub-chunk
+    static constexpr int PR = SC / 2;       // 16-byte staging units (sample pairs) per row
+    static constexpr int PIECES = 16 * PR;  // 16-byte staging units of a sub-chunk
+};
 
 struct O9Range {
     long k0, k1;  // the block's samples [k0, k1)
     int nsc;      // sub-chunks
 };
 
-// t~ and the z source of sub-chunk c (16-byte units: thread unit e is row e / 64,
-// samples 2 (e % 64) + {0, 1}), clamped into the block's range
-template <int NTH>
+// t~ and the z source of sub-chunk c (16-byte units: thread unit e is row
+// e / O9<SC>::PR, samples 2 (e % O9<SC>::PR) + {0, 1}), clamped into the block's range
+template <int SC, int NTH>
 __device__ __forceinline__ void o9_load(const double* __restrict__ Tj, const double* __restrict__ v,
                                         long Nsp, const O9Range& R, int c,
-                                        double2 (&ta)[O9_PIECES / NTH],
-                                        double2 (&va)[O9_PIECES / NTH]) {
+                                        double2 (&ta)[O9<SC>::PIECES / NTH],
+                                        double2 (&va)[O9<SC>::PIECES / NTH]) {
 #pragma unroll
-    for (int i = 0; i < O9_PIECES / NTH; ++i) {
+    for (int i = 0; i < O9<SC>::PIECES / NTH; ++i) {
         const int e = threadIdx.x + NTH * i;
-        const long k = min(R.k0 + (long)c * O9_SC + 2 * (e & 63), R.k1 - 2);
-        ta[i] = *(const double2*)(Tj + (size_t)(e >> 6) * Nsp + k);
+        const long k = min(R.k0 + (long)c * SC + 2 * (e % O9<SC>::PR), R.k1 - 2);
+        ta[i] = *(const double2*)(Tj + (size_t)(e / O9<SC>::PR) * Nsp + k);
         va[i] = *(const double2*)(v + k);
     }
 }
 // a = t~ z of sub-chunk c into LDS (zero past the range and past n); the
 // threads holding row 0 add up z_k (v_k - shift) (the p . G p partial)
-template <int NTH>
+template <int SC, int NTH>
 __device__ __forceinline__ void o9_stage(double* __restrict__ A, const O9Range& R, int c, long n,
                                          double shift, double scale,
-                                         const double2 (&ta)[O9_PIECES / NTH],
-                                         const double2 (&va)[O9_PIECES / NTH], double& zw) {
+                                         const double2 (&ta)[O9<SC>::PIECES / NTH],
+                                         const double2 (&va)[O9<SC>::PIECES / NTH], double& zw) {
 #pragma unroll
-    for (int i = 0; i < O9_PIECES / NTH; ++i) {
+    for (int i = 0; i < O9<SC>::PIECES / NTH; ++i) {
         const int e = threadIdx.x + NTH * i;
-        const int r = e >> 6, c2 = 2 * (e & 63);
-        const long k = R.k0 + (long)c * O9_SC + c2;
+        const int r = e / O9<SC>::PR, c2 = 2 * (e % O9<SC>::PR);
+        const long k = R.k0 + (long)c * SC + c2;
         const bool ok0 = k < R.k1 && k < n, ok1 = k + 1 < R.k1 && k + 1 < n;
         const double z0 = ok0 ? (va[i].x - shift) * scale : 0.0;
         const double z1 = ok1 ? (va[i].y - shift) * scale : 0.0;
-        A[r * O9_LD + c2] = ta[i].x * z0;
-        A[r * O9_LD + c2 + 1] = ta[i].y * z1;
+        A[r * O9<SC>::LD + c2] = ta[i].x * z0;
+        A[r * O9<SC>::LD + c2 + 1] = ta[i].y * z1;
         if (r == 0) zw += z0 * (va[i].x - shift) + z1 * (va[i].y - shift);
     }
 }
 // the spins of site tile it for sub-chunk c: one word (4 samples) per unit
-template <int PT>
+template <int SC, int PT>
 __device__ __forceinline__ void o9_spins(const int8_t* __restrict__ St, long Nsp, const O9Range& R,
                                          int c, const int (&its)[PT], int lr, int lk,
-                                         uint32_t (&sb)[PT][O9_NU]) {
+                                         uint32_t (&sb)[PT][O9<SC>::NU]) {
 #pragma unroll
     for (int p = 0; p < PT; ++p)
 #pragma unroll
-        for (int u = 0; u < O9_NU; ++u) {
-            const long k = min(R.k0 + (long)c * O9_SC + 16 * u, R.k1 - 16) + 4 * lk;
+        for (int u = 0; u < O9<SC>::NU; ++u) {
+            const long k = min(R.k0 + (long)c * SC + 16 * u, R.k1 - 16) + 4 * lk;
             sb[p][u] = *(const uint32_t*)(St + (size_t)(its[p] * 16 + lr) * Nsp + k);
         }
 }
@@ -822,16 +827,16 @@ __device__ __forceinline__ void o9_spins(const int8_t* __restrict__ St, long Nsp
 // the MFMAs of one sub-chunk for the wave's first NT site tiles: units of 16
 // samples (those past the range: none), the LDS operands of unit u + 1 read
 // while unit u's MFMAs run
-template <int NT, int PT, int CH>
+template <int SC, int NT, int PT, int CH>
 __device__ __forceinline__ void o9_units(const double* __restrict__ A, int nu,
-                                         const uint32_t (&sb)[PT][O9_NU], v4d (&acc)[PT][CH]) {
+                                         const uint32_t (&sb)[PT][O9<SC>::NU], v4d (&acc)[PT][CH]) {
     double a[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) a[e] = A[e];
 #pragma unroll
-    for (int u = 0; u < O9_NU; ++u) {
+    for (int u = 0; u < O9<SC>::NU; ++u) {
         double an[4];
-        if (u + 1 < O9_NU) {
+        if (u + 1 < O9<SC>::NU) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) an[e] = A[16 * (u + 1) + e];
         }
@@ -845,7 +850,7 @@ __device__ __forceinline__ void o9_units(const double* __restrict__ A, int nu,
                         __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b, acc[p][e % CH], 0, 0, 0);
                 }
         }
-        if (u + 1 < O9_NU) {
+        if (u + 1 < O9<SC>::NU) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) a[e] = an[e];
         }
@@ -861,12 +866,13 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
                                                 double* __restrict__ part, int ks, int tpp,
                                                 int nwa, double* __restrict__ papart,
                                                 const CgScalars* __restrict__ sc) {
-    constexpr int UT = O9_PIECES / NTH;  // staging units per thread
+    constexpr int SC = NTH == 512 ? 64 : 128;  // samples per sub-chunk
+    constexpr int UT = O9<SC>::PIECES / NTH;  // staging units per thread
     // stop flag of the CG product, tested once the block's loads are in flight
     const int done = v_mode == 0 ? sc->done : 0;
     constexpr int CH = PT == 1 ? 4 : 1;  // accumulation chains per site tile
     constexpr int BW = 2;                // mean-w partials per thread issued up front
-    __shared__ double As[2][16 * O9_LD];
+    __shared__ double As[2][16 * O9<SC>::LD];
     __shared__ double sh[16];
     const int nj = d.Ma / 16, ni = d.Na / 16;
     // work item (pass, q, jt), range-major, from the block index: XCD x (the
@@ -884,7 +890,7 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
     O9Range R;
     R.k0 = 16 * ((long)q * U / ks);
     R.k1 = 16 * (((long)q + 1) * U / ks);
-    R.nsc = (int)((R.k1 - R.k0 + O9_SC - 1) / O9_SC);
+    R.nsc = (int)((R.k1 - R.k0 + SC - 1) / SC);
     // this wave's site tiles (clamped to a valid one; nact of them count)
     const int t0 = pass * tpp, t1 = min(ni, t0 + tpp);
     int its[PT], nact = 0;
@@ -903,9 +909,9 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
         wp[u] = (v_mode == 0 && b < nbw) ? wpart[b] : 0.0;
     }
     double2 ta[UT], va[UT];
-    o9_load<NTH>(Tj, v, Nsp, R, 0, ta, va);
-    uint32_t sb[PT][O9_NU];
-    o9_spins<PT>(St, Nsp, R, 0, its, lr, lk, sb);
+    o9_load<SC, NTH>(Tj, v, Nsp, R, 0, ta, va);
+    uint32_t sb[PT][O9<SC>::NU];
+    o9_spins<SC, PT>(St, Nsp, R, 0, its, lr, lk, sb);
     asm volatile("" ::: "memory");  // the loads above go out before the stop test
     if (done) return;               // (uniform over the block, before any barrier)
     double shift = 0.0, scale = 1.0;
@@ -918,7 +924,7 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
         scale = 1.0 / (double)n;
     }
     double zw = 0.0;
-    o9_stage<NTH>(As[0], R, 0, n, shift, scale, ta, va, zw);
+    o9_stage<SC, NTH>(As[0], R, 0, n, shift, scale, ta, va, zw);
     __syncthreads();
     v4d acc[PT][CH];
 #pragma unroll
@@ -928,18 +934,18 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
     for (int c = 0; c < R.nsc; ++c) {
         // the next sub-chunk (this one again after the last: every load unconditional)
         const int cn = c + 1 < R.nsc ? c + 1 : c;
-        o9_load<NTH>(Tj, v, Nsp, R, cn, ta, va);
-        uint32_t sn[PT][O9_NU];
-        o9_spins<PT>(St, Nsp, R, cn, its, lr, lk, sn);
+        o9_load<SC, NTH>(Tj, v, Nsp, R, cn, ta, va);
+        uint32_t sn[PT][O9<SC>::NU];
+        o9_spins<SC, PT>(St, Nsp, R, cn, its, lr, lk, sn);
         __builtin_amdgcn_sched_barrier(0);  // those loads ahead of the MFMAs that hide them
-        const double* A = As[c & 1] + lr * O9_LD + 4 * lk;
-        const int nu = (int)min((long)O9_NU, (R.k1 - R.k0) / 16 - (long)c * O9_NU);
+        const double* A = As[c & 1] + lr * O9<SC>::LD + 4 * lk;
+        const int nu = (int)min((long)O9<SC>::NU, (R.k1 - R.k0) / 16 - (long)c * O9<SC>::NU);
         if (nact == PT)
-            o9_units<PT, PT, CH>(A, nu, sb, acc);
+            o9_units<SC, PT, PT, CH>(A, nu, sb, acc);
         else if (nact > 0)
-            o9_units<1, PT, CH>(A, nu, sb, acc);
+            o9_units<SC, 1, PT, CH>(A, nu, sb, acc);
         if (c + 1 < R.nsc) {
-            o9_stage<NTH>(As[(c + 1) & 1], R, c + 1, n, shift, scale, ta, va, zw);
+            o9_stage<SC, NTH>(As[(c + 1) & 1], R, c + 1, n, shift, scale, ta, va, zw);
         } else {  // a use of the repeat loads, which keeps them where they were issued
 #pragma unroll
             for (int i = 0; i < UT; ++i) asm volatile("" ::"v"(ta[i].x), "v"(va[i].x));
@@ -947,7 +953,7 @@ __global__ __launch_bounds__(NTH) void k_outer9(Dims d, const int8_t* __restrict
 #pragma unroll
         for (int p = 0; p < PT; ++p)
 #pragma unroll
-            for (int u = 0; u < O9_NU; ++u) sb[p][u] = sn[p][u];
+            for (int u = 0; u < O9<SC>::NU; ++u) sb[p][u] = sn[p][u];
         __syncthreads();
     }
     // p . G p = sum_k z_k (w_k - mean w) (G p = J^T z, w = J p): one partial per
