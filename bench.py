@@ -299,6 +299,41 @@ def dense_qgt_measure(torch, precision="fp32", repeats=2):
                 solve_wall_ms=wall * 1e3, kernels=best, data="synthetic")
 
 
+def same_batch_cg_iters(torch, stages=4, steps_between=20):
+    """CG iterations of the three forms on identical sample batches (10x10 TFIM):
+    an FP64 trajectory advances steps_between SR steps per stage; at each stage
+    its parameters and one freshly drawn batch are loaded into an FP64, an FP32
+    and a BF16 state, and each solves the SR system on it (shift 0.01, tol 1e-6)."""
+    from paper_2112_10526_amd.nqs import VMCState
+    w = synth.WORKLOADS["tfim2d_l10"]
+    ref = VMCState.from_workload(w, precision="fp64")
+    rows = []
+    for stage in range(stages):
+        for _ in range(0 if stage == 0 else steps_between):
+            ref.vmc_step(diag_shift=0.01, lr=0.01, tol=1e-6)
+        p = ref.get_params()
+        smp, _, _ = ref.sample()
+        s = smp.reshape(-1, w.n_sites)
+        row = dict(sr_steps=stage * steps_between)
+        for prec in ("fp64", "fp32", "bf16"):
+            st = VMCState.from_workload(w, precision=prec)
+            st.set_params(p)
+            st.load_samples(s)
+            st.expect_and_grad()
+            _, info = st.sr_update(diag_shift=0.01, lr=0.0, tol=1e-6, maxiter=4000)
+            row[prec] = dict(iterations=info.iterations, converged=bool(info.converged))
+            st.close()
+        rows.append(row)
+        print(f"[bench] same-batch CG iterations after {row['sr_steps']} steps: "
+              + ", ".join(f"{k} {row[k]['iterations']}" for k in ("fp64", "fp32", "bf16")),
+              file=sys.stderr, flush=True)
+    ref.close()
+    return dict(metric="CG iterations on identical sample batches, FP64 / FP32 / BF16 forms",
+                workload="tfim2d_l10: 2D TFIM 10x10, alpha 2, 16,384 samples; SR shift 0.01, "
+                         "CG tol 1e-6; parameters and samples from an FP64 trajectory",
+                stages=rows, data="synthetic")
+
+
 def precision_form_measure(torch, steps=5, warmup=1):
     """Precision form on the 16 x 16 Heisenberg workload (J1 = 1, periodic, Marshall
     rotated, zero magnetisation, exchange moves; alpha = 4, 1024 hidden units,
@@ -782,6 +817,8 @@ def main():
                     help="measure the dense Jacobian QGT kernels at the N=64 chain size instead")
     ap.add_argument("--precision-form", action="store_true",
                     help="measure the BF16 form against FP64 on the 16x16 Heisenberg workload")
+    ap.add_argument("--same-batch-iters", action="store_true",
+                    help="CG iterations of the FP64, FP32 and BF16 forms on identical batches")
     ap.add_argument("--plain", action="store_true",
                     help="SR steps on the N=10 TFIM chain: time and energy against the exact one")
     ap.add_argument("--paper-workload", action="store_true",
@@ -813,6 +850,9 @@ def main():
         return
     if args.precision_form:
         print(json.dumps(precision_form_measure(torch)), flush=True)
+        return
+    if args.same_batch_iters:
+        print(json.dumps(same_batch_cg_iters(torch)), flush=True)
         return
     if args.serve:
         only = set(x for x in args.serve_passes.split(",") if x) or None
