@@ -499,9 +499,11 @@ int nqs_set_cg_graphs(nqs_ctx* ctx, int enable);
  * way.  Runs of one group advance in lock-step; a run that has stopped leaves
  * the group's launches from the next batch of iterations on.  Contexts whose
  * CG kernel classes are being timed (nqs_profile_enable) run their own
- * launches.  The
- * library keeps the tables, a stream and events per device until the process
- * ends; batched steps on one device take their grouped part one at a time.
+ * launches.  The tables sit in a static device array (no device allocation;
+ * up to 8 groups, 256 runs, per device and call; further runs take their own
+ * launches); the library keeps their pinned host copies, a stream and events
+ * per device until the process ends; batched steps on one device take their
+ * grouped part one at a time.
  * Errors: NQS_EINVAL (null context). */
 int nqs_set_cg_grouping(nqs_ctx* ctx, int enable);
 

@@ -840,10 +840,15 @@ struct CgRun {
 // ---- grouped CG iterations of the batched step -----------------------------
 // The on-the-fly CG of several small BF16-form contexts on one device, one
 // launch per kernel class per iteration for all of them (cg_group_plan), on a
-// stream of the library's own.  Per device the library keeps slots (two
-// descriptor tables in device memory and their pinned host copies, stream,
-// events) until the process ends; one batched step at a time uses a device's
-// slots.
+// stream of the library's own.  Per device the library keeps up to
+// CG_GROUP_SLOTS slots (two descriptor tables, their pinned host copies, a
+// stream, events) until the process ends; one batched step at a time uses a
+// device's slots.  The tables sit in a static device array (no device
+// allocation): every GPU holds its own copy, and host code uses the address
+// hipGetSymbolAddress returns on that device, never the array's name.
+constexpr int CG_GROUP_SLOTS = 8;
+static __device__ __align__(256) CgGroupTable group_tables[2 * CG_GROUP_SLOTS];
+
 namespace {
 
 // Contexts join a group when one CG iteration's contractions are small enough
@@ -864,6 +869,7 @@ struct GroupSlot {
 };
 struct GroupPool {
     std::mutex m;
+    CgGroupTable* tables = nullptr;  // device address of group_tables on this device
     std::vector<std::unique_ptr<GroupSlot>> slots;
 };
 
@@ -876,15 +882,29 @@ GroupPool& group_pool(int device) {
     return *p;
 }
 
-// slot k of the pool (created on first use, the device current); null on failure
+// slot k of the pool (created on first use, the device current); null on
+// failure or past CG_GROUP_SLOTS
 GroupSlot* group_slot(GroupPool& pool, size_t k, std::string& err) {
+    if (k >= (size_t)CG_GROUP_SLOTS) {
+        err = "grouped CG: no free group slot";
+        return nullptr;
+    }
+    if (!pool.tables) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(group_tables)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            err = "grouped CG set-up: no address for the group tables";
+            return nullptr;
+        }
+        pool.tables = (CgGroupTable*)ptr;
+    }
     while (pool.slots.size() <= k) {
         std::unique_ptr<GroupSlot> s(new GroupSlot);
         hipError_t e = hipSuccess;
+        const size_t slot = pool.slots.size();
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-            e = hipMalloc((void**)&s->dev[i], sizeof(CgGroupTable));
-            if (e == hipSuccess)
-                e = hipHostMalloc((void**)&s->host[i], sizeof(CgGroupTable), hipHostMallocDefault);
+            s->dev[i] = pool.tables + 2 * slot + i;
+            e = hipHostMalloc((void**)&s->host[i], sizeof(CgGroupTable), hipHostMallocDefault);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev[i], hipEventDisableTiming);
         }
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
