@@ -172,7 +172,8 @@ void launch_qgt_init(hipStream_t st, const Dims& d, int prec, const double* f, d
 
 // Grouped on-the-fly CG iterations (BF16 forms): the three iteration kernels
 // of up to CG_GROUP_MAX independent runs, one launch per kernel class (the
-// head + contraction-1 kernel: one launch per block size).  Each run keeps
+// head + contraction-1 blocks sized for the run with the most contraction
+// waves; a smaller run's extra waves idle).  Each run keeps
 // its own blocks and fixed-order sums, so its results are those of its own
 // launches.  The table lives in device memory; cg_group_plan fills it.
 constexpr int CG_GROUP_MAX = 32;
@@ -192,7 +193,8 @@ struct CgGroupRun {
     double *x, *r, *p, *p2;  // p and p2 alternate as the old and new direction
     CgScalars* sc;
     int32_t* host_flag;  // pinned: the stop flag after the last iteration of a batch
-    int nbv, nbw, ks, pad;
+    int nbv, nbw, ks;
+    int nwc;  // contraction-1 waves of the run's own launch (set by cg_group_plan)
 };
 struct CgGroupTable {
     int nrun;
@@ -204,13 +206,13 @@ struct CgGroupTable {
 };
 // the launches of one grouped iteration
 struct CgGroupPlan {
-    int nw;  // contraction-1 launches: first block, blocks, block size
+    int nw;  // contraction-1 launches (one): first block, blocks, block size
     int w_base[CG_GROUP_MAX], w_blocks[CG_GROUP_MAX], w_threads[CG_GROUP_MAX];
     int o_blocks, u_blocks;
     int u_sw;  // update: slot slabs per wave loaded up front (the largest the runs need)
 };
-// The run entries of t (t.nrun of them, with their operands set) are put in
-// order of contraction-1 block size and the block offsets are filled in.
+// Fills in the block offsets (and each run's contraction-1 wave count) of the
+// run entries of t (t.nrun of them, with their operands set).
 void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan);
 // One grouped iteration; par = iteration & 1 (which direction buffer and head
 // partial set is the old one); write_flag: the update stores each run's stop

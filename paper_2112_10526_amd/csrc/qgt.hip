@@ -604,18 +604,20 @@ __device__ __forceinline__ void w7_block(Dims d, const uint8_t* __restrict__ Sp,
                                          const uint16_t* __restrict__ Ph,
                                          double* __restrict__ w, double* __restrict__ wpart,
                                          const double* __restrict__ aux, int nbv, CgScalars* sc,
-                                         int blk) {
+                                         int blk, int nwc) {
     constexpr int RT = W7_ROWS / 16;
     constexpr int HB = 4;  // head partials per lane issued up front, per sum
     // the stop flag; it is tested once the first loads are in flight
     const int done = sc->done;
     __shared__ double wsh[15][W7_ROWS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nw = (blockDim.x >> 6) - 1;  // contraction waves; wave nw runs the head
+    // waves 0 .. nwc - 1 take the hidden tiles, the last wave runs the head, and
+    // any waves between them (a grouped launch sized for a larger run) idle
+    const int nw = nwc, hw = (blockDim.x >> 6) - 1;
     const int lr = lane & 15, lk = lane >> 4;
     const long r0 = (long)blk * W7_ROWS;
     const int Kq = d.Kq, KB2 = d.Kq / 2, nct = d.Ma / 16, ng = d.Kq / 128;
-    if (wave == nw) {
+    if (wave == hw) {
         // ---- the CG head: r.r, r.p_{it-1}, p_{it-1}.p_{it-1} from the update's
         // block partials (lane stride 64, then the wave: the same order in every block)
         const HeadIn hin = head_in(sc);
@@ -651,6 +653,11 @@ __device__ __forceinline__ void w7_block(Dims d, const uint8_t* __restrict__ Sp,
         if (k < n) w[k] = v;
         const double s = wave_sum(k < n ? v : 0.0);
         if (lane == 0) wpart[blk] = s;
+        return;
+    }
+    if (wave >= nw) {  // an idle wave: the block's one barrier, or none once CG has stopped
+        if (done) return;  // (uniform over the block, before any barrier)
+        __syncthreads();
         return;
     }
     const uint16_t* Pl = Ph + (size_t)d.Ma * Kq;
@@ -725,7 +732,7 @@ __global__ __launch_bounds__(1024) void k_w7(Dims d, const uint8_t* __restrict__
                                              double* __restrict__ w, double* __restrict__ wpart,
                                              const double* __restrict__ aux, int nbv,
                                              CgScalars* sc) {
-    w7_block(d, Sp, Tf, n, Ph, w, wpart, aux, nbv, sc, blockIdx.x);
+    w7_block(d, Sp, Tf, n, Ph, w, wpart, aux, nbv, sc, blockIdx.x, (blockDim.x >> 6) - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1391,7 +1398,7 @@ __global__ __launch_bounds__(1024) void k_w7_group(const CgGroupTable* __restric
     const int r = group_run(t->first_w, b);
     const CgGroupRun& R = t->run[r];
     w7_block(R.d, (const uint8_t*)R.Sp, R.Tf, R.n, (const uint16_t*)R.Rop, R.w, R.wpart,
-             R.aux + (size_t)par * 3 * R.nbv, R.nbv, R.sc, b - t->first_w[r]);
+             R.aux + (size_t)par * 3 * R.nbv, R.nbv, R.sc, b - t->first_w[r], R.nwc);
 }
 
 __global__ __launch_bounds__(O8_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_outer8_group(
@@ -1672,33 +1679,24 @@ void launch_qgt_update(hipStream_t st, const Dims& d, int prec, const QgtBatch& 
 
 void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
     const int n = t.nrun;
-    int th[CG_GROUP_MAX];
+    // one contraction-1 launch for every run, its blocks sized for the run with
+    // the most contraction waves (plus the head wave); each run keeps its own
+    int maxw = 1;
     for (int r = 0; r < n; ++r) {
         int waves, per;
         wave_split(t.run[r].d.Ma / 16, 15, waves, per);
-        th[r] = 64 * (waves + 1);  // one more wave for the CG head
+        t.run[r].nwc = waves;
+        maxw = std::max(maxw, waves);
     }
-    // runs in order of contraction-1 block size (stable: ties keep their order)
-    for (int r = 1; r < n; ++r)
-        for (int q = r; q > 0 && th[q - 1] > th[q]; --q) {
-            std::swap(th[q - 1], th[q]);
-            std::swap(t.run[q - 1], t.run[q]);
-        }
-    plan.nw = 0;
+    plan.nw = 1;
+    plan.w_base[0] = 0;
+    plan.w_threads[0] = 64 * (maxw + 1);
     plan.u_sw = 4;
     int bw = 0, bo = 0, bu = 0;
     for (int r = 0; r < n; ++r) {
         const CgGroupRun& R = t.run[r];
-        if (r == 0 || th[r] != th[r - 1]) {
-            plan.w_base[plan.nw] = bw;
-            plan.w_blocks[plan.nw] = 0;
-            plan.w_threads[plan.nw] = th[r];
-            ++plan.nw;
-        }
-        const int nb = qgt_nbw(R.n, 1);
         t.first_w[r] = bw;
-        bw += nb;
-        plan.w_blocks[plan.nw - 1] += nb;
+        bw += qgt_nbw(R.n, 1);
         t.first_o[r] = bo;
         bo += NXCD * (R.d.Ma / 16) * ((R.ks + NXCD - 1) / NXCD);
         t.first_u[r] = bu;
@@ -1706,6 +1704,7 @@ void cg_group_plan(CgGroupTable& t, CgGroupPlan& plan) {
         plan.u_sw = std::max(plan.u_sw, update_sw(R.ks));
     }
     for (int r = n; r < CG_GROUP_MAX; ++r) t.first_w[r] = t.first_o[r] = t.first_u[r] = INT_MAX;
+    plan.w_blocks[0] = bw;
     plan.o_blocks = bo;
     plan.u_blocks = bu;
 }
