@@ -493,7 +493,7 @@ int nqs_set_cg_graphs(nqs_ctx* ctx, int enable);
  * each run's blocks found through a device table of the runs' operands; with
  * 0 this context runs its own launches (as with nqs_vmc_step).  Small: samples
  * x round_up(n_hidden + 1, 16) x round_up(round_up(n_sites + 1, 16), 128) at
- * most 2^27, where launch overhead dominates a run's own launches; larger
+ * most 2^28, where launch overhead dominates a run's own launches; larger
  * contexts always run their own, side by side with the group.  Each run keeps
  * its own blocks and fixed-order sums, so its results are identical either
  * way.  Runs of one group advance in lock-step; a run that has stopped leaves

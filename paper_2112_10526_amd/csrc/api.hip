@@ -853,8 +853,8 @@ namespace {
 
 // Contexts join a group when one CG iteration's contractions are small enough
 // for launch overhead to dominate their own launches: samples x augmented
-// hidden rows x site extent at most this (about two microseconds of work).
-constexpr double CG_GROUP_WORK = 134217728.0;
+// hidden rows x site extent at most this (2^28, a few microseconds of work).
+constexpr double CG_GROUP_WORK = 268435456.0;
 bool group_small(const nqs_ctx* c) {
     return (double)c->Ns * c->d.Ma * c->d.Kq <= CG_GROUP_WORK;
 }
